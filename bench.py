@@ -1,0 +1,200 @@
+"""Benchmark of the phase-field DUGKS step on one MI355X.
+
+Default workload: the coupled (Allen-Cahn + hydrodynamics) stationary bubble,
+128 x 128 periodic, R = 32, density ratio 1000, sigma = 1e-3, nu = 0.1,
+M = 0.1, FP32 step (Sec. IV.A of arXiv:1810.07802). One benchmark step is one
+DUGKS time step of the whole grid; `--steps` of them are timed after
+`--warmup` untimed ones, replayed from a HIP graph on the stream that the
+HIP events time. `value` is MLUPS = cells * steps / s / 1e6.
+
+The same JSON line carries:
+  roofline      HBM roofline of the step kernel at this workload (algorithmic
+                bytes: 160 B per cell and step in FP32)
+  large_grid    the same physics on 4096 x 4096 (R = 1024), where the working
+                set (2.8 GB) is far larger than the 256 MB Infinity Cache
+  batched       the spinodal batch (64 cases of 64^2..512^2): one graph of
+                batched launches vs one launch per case per step
+  cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+B_PER_CELL = {"fp32": 160.0, "fp64": 320.0}  # read + write of 18 populations + 2 history values
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--skip-extra", action="store_true", help="only the default workload")
+    ap.add_argument("--profile-kernel", action="store_true",
+                    help="run only the timed default workload (for profilers)")
+    return ap.parse_args()
+
+
+def timed_graph(torch, D, solvers, steps, warmup, chunk=1000):
+    """Replay `steps` steps of `solvers` (a batch) from HIP graphs of `chunk`
+    launches on torch's current stream; returns seconds measured by HIP events
+    on that stream."""
+    stream = torch.cuda.current_stream()
+    b = D.Batch(solvers)
+    b.set_stream(stream.cuda_stream)
+    chunk = max(1, min(chunk, steps))
+    w = warmup
+    while w > 0:
+        n = min(chunk, w)
+        b.step(n, use_graph=True)
+        w -= n
+    # make sure every graph used in the timed region is already instantiated
+    rest = steps % chunk
+    if rest:
+        b.step(rest, use_graph=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    left = steps
+    while left > 0:
+        n = min(chunk, left)
+        b.step(n, use_graph=True)
+        left -= n
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3, b
+
+
+def timed_eager(torch, D, solvers, steps):
+    """One launch per case per step (the plain per-case loop)."""
+    stream = torch.cuda.current_stream()
+    for s in solvers:
+        s.set_stream(stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for s in solvers:
+        s.step(steps)  # `steps` launches of the step kernel for this case
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def roofline(cells, steps, seconds, prec):
+    per_launch = B_PER_CELL[prec] * cells
+    t_launch = seconds / steps
+    achieved = per_launch / t_launch / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
+
+
+def cpu_baseline(budget_s):
+    import oracle
+    import workloads as W
+    c = W.bubble(L=128, R=32)
+    s = oracle.Sim(c["nx"], c["ny"], c["params"], "coupled")
+    s.init(c["phi"])
+    s.step(5)
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        s.step(50)
+        n += 50
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(c["nx"] * c["ny"] * n / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": cores, "kind": "oracle",
+            "sample": f"bubble 128x128 coupled FP64, {n} steps ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1810_07802_amd as D
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    c = W.bubble(L=128, R=32)
+    cells = c["nx"] * c["ny"]
+    s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    s.init(c["phi"])
+    secs, batch = timed_graph(torch, D, [s], args.steps, args.warmup)
+    mlups = cells * args.steps / secs / 1e6
+    rec = {
+        "metric": "MLUPS (coupled AC+hydro step, FP32) + %HBM peak; batched vs plain; p50/p99 solve latency",
+        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "stationary bubble 128x128, R=32, W=5, rho 1000:1, sigma=1e-3, "
+                               "nu=0.1, M=0.1, periodic, coupled FP32 step",
+                   "nx": c["nx"], "ny": c["ny"], "seg_rows": s.seg_rows,
+                   "launch": "HIP graph of 1000 step launches"},
+        "roofline": roofline(cells, args.steps, secs, "fp32"),
+    }
+    diag = s.diagnostics()
+    rec["check"] = {"nonfinite": diag["nonfinite"], "max_u": diag["max_u"]}
+    if args.profile_kernel:
+        print(json.dumps(rec), flush=True)
+        return
+    if not args.skip_extra:
+        # the same step launched one kernel at a time from the host
+        e_steps = min(args.steps, 2000)
+        t_e = timed_eager(torch, D, [s], e_steps)
+        rec["plain_launch_mlups"] = round(cells * e_steps / t_e / 1e6, 2)
+        # FP64 on the same workload
+        s64 = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp64")
+        s64.init(c["phi"])
+        t64, _ = timed_graph(torch, D, [s64], min(args.steps, 5000), 100)
+        rec["fp64_mlups"] = round(cells * min(args.steps, 5000) / t64 / 1e6, 2)
+        del s64
+        # large grid: HBM-resident working set
+        cl = W.bubble(L=4096, R=1024, steps=0)
+        sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32")
+        sl.init(cl["phi"])
+        tl, _ = timed_graph(torch, D, [sl], args.large_steps, 20, chunk=100)
+        ncl = cl["nx"] * cl["ny"]
+        rec["large_grid"] = {"workload": "stationary bubble 4096x4096, R=1024, coupled FP32",
+                             "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
+                             "steps": args.large_steps, "seg_rows": sl.seg_rows,
+                             "roofline": roofline(ncl, args.large_steps, tl, "fp32")}
+        del sl
+        # batched spinodal workload vs the per-case loop
+        cases = W.spinodal_batch(steps=0)
+        solvers = []
+        for cc in cases:
+            t = D.Solver(cc["nx"], cc["ny"], cc["params"], "coupled", "fp32")
+            t.init(cc["phi"])
+            solvers.append(t)
+        bc = sum(cc["nx"] * cc["ny"] for cc in cases)
+        tb, _ = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100)
+        tp = timed_eager(torch, D, solvers, args.batch_steps)
+        rec["batched"] = {"workload": "spinodal decomposition, 64 cases of 64^2..512^2 "
+                                      "(seed 1810), rho 1000:1, coupled FP32",
+                          "cells": bc, "steps": args.batch_steps,
+                          "batched_graph_mlups": round(bc * args.batch_steps / tb / 1e6, 1),
+                          "per_case_loop_mlups": round(bc * args.batch_steps / tp / 1e6, 1),
+                          "roofline": roofline(bc, args.batch_steps, tb, "fp32")}
+        del solvers
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * dugks.h — C ABI of the MI355X (gfx950) implementation of the phase-field
+ * discrete unified gas-kinetic scheme of Yang, Zhong & Zhuo,
+ * "A phase-field model for large-density-ratio two-phase flows based on
+ * discrete unified gas-kinetic scheme" (arXiv:1810.07802).
+ *
+ * One handle is one uniform 2-D D2Q9 grid of nx x ny unit cells (cell (i,j)
+ * centred at (i+1/2, j+1/2), row-major [ny][nx] in every host or device field
+ * passed through this ABI), x always periodic, y periodic or bounded by
+ * no-slip walls on the faces y = 0 and y = ny. It carries either
+ *   - the coupled model: conservative Allen-Cahn kinetic model f for the order
+ *     parameter phi plus the incompressible hydrodynamic model g for the
+ *     dynamic pressure p and the velocity u (Sec. II.A-II.B), or
+ *   - the interface-only model: f alone, advected by a prescribed velocity
+ *     field (Sec. III, Eqs. 40-43).
+ * The time step is the DUGKS update of Sec. II.B (Eqs. 21-33).
+ *
+ * Conventions
+ *   - Every call returns an int status: DUGKS_OK (0) or a negative DUGKS_E*
+ *     code; dugks_last_error() gives a message. Nothing aborts, no C++
+ *     exception crosses the ABI.
+ *   - The library owns all device memory of a handle. The caller owns every
+ *     pointer it passes; the library never keeps one after the call returns.
+ *   - Calls on one handle are not thread-safe; distinct handles are
+ *     independent. All device work of a handle is ordered on its stream
+ *     (default: the null stream; see dugks_set_stream()).
+ *   - Time is implicit: t = steps * dt with dt = CFL (grid spacing 1,
+ *     sqrt(3RT) = 1; Eq. 37).
+ */
+#ifndef DUGKS_H
+#define DUGKS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define DUGKS_OK 0
+#define DUGKS_EINVAL (-1)   /* bad argument or parameter */
+#define DUGKS_ENOMEM (-2)   /* device or host allocation failed */
+#define DUGKS_EDEVICE (-3)  /* HIP runtime error */
+#define DUGKS_ENUMERIC (-4) /* NaN/Inf found by the diagnostics */
+#define DUGKS_ESTATE (-5)   /* call out of order (e.g. step before init) */
+#define DUGKS_EBUSY (-6)    /* pool has no room for the request */
+
+enum { DUGKS_FP32 = 0, DUGKS_FP64 = 1 };
+enum { DUGKS_MODEL_AC = 0, DUGKS_MODEL_COUPLED = 1 };
+enum { DUGKS_VISC_UNIFORM_NU = 0, DUGKS_VISC_RECIPROCAL = 1, DUGKS_VISC_LINEAR = 2 };
+enum { DUGKS_GRAV_RHO_G = 0, DUGKS_GRAV_BUOYANCY = 1 };
+enum { DUGKS_BC_PERIODIC = 0, DUGKS_BC_WALLS = 1 };
+enum { DUGKS_VEL_UNIFORM = 0, DUGKS_VEL_ROTATION = 1, DUGKS_VEL_SHEAR = 2,
+       DUGKS_VEL_DEFORM = 3 };
+
+/* Physical and numerical parameters (Sec. II, III, IV of the paper).
+ *   phi_H, phi_L   order parameter of the heavy / light phase (Sec. II.A);
+ *                  the interface sits at their mean. Must differ.
+ *   rho_H, rho_L   densities, interpolated linearly in phi (Eq. 10); > 0.
+ *   mu_H, mu_L     dynamic viscosities for visc_mode RECIPROCAL (Eq. 35) or
+ *                  LINEAR (Eq. 36); > 0 when used.
+ *   nu             kinematic viscosity for visc_mode UNIFORM_NU; > 0.
+ *   sigma, W       surface tension (>= 0) and interface width (> 0); they set
+ *                  kappa and beta (Eq. 3, generalised so that width and
+ *                  tension hold for any phi_H - phi_L).
+ *   M_phi          mobility (>= 0); tau_f = M_phi / RT (Eq. 34).
+ *   gx, gy         gravitational acceleration; gravity_form RHO_G gives
+ *                  G = rho g, BUOYANCY gives G = (rho - (rho_H+rho_L)/2) g.
+ *   Gx, Gy         constant body-force density added to G (layered
+ *                  Poiseuille flow, Sec. IV.B).
+ *   cfl            CFL number in (0, 1]; dt = cfl, h = dt/2.
+ *   bc_y           DUGKS_BC_PERIODIC or DUGKS_BC_WALLS (coupled model only;
+ *                  needs ny >= 4).
+ *   vel_kind, U0, L0, T_period
+ *                  prescribed velocity of the interface-only model
+ *                  (Eqs. 40-43); ignored by the coupled model.
+ */
+typedef struct dugks_params {
+    double phi_H, phi_L;
+    double rho_H, rho_L;
+    double mu_H, mu_L;
+    double nu;
+    int visc_mode;
+    double sigma, W, M_phi;
+    double gx, gy;
+    int gravity_form;
+    double Gx, Gy;
+    double cfl;
+    int bc_y;
+    int vel_kind;
+    double U0, L0, T_period;
+} dugks_params;
+
+typedef struct dugks_handle dugks_handle;
+
+/* Create a grid of nx x ny cells (nx, ny >= 3) holding `model`
+ * (DUGKS_MODEL_*) in `precision` (DUGKS_FP32: distributions and arithmetic in
+ * float, density and relaxation-time interpolation in double; DUGKS_FP64: all
+ * double). Allocates the two state buffers on the current HIP device.
+ * Errors: EINVAL (sizes, enums), ENOMEM, EDEVICE. *out is NULL on error. */
+int dugks_create(int nx, int ny, int precision, int model, dugks_handle **out);
+
+/* Validate and set parameters. EINVAL on phi_H == phi_L, rho <= 0, a needed
+ * viscosity <= 0, M_phi < 0, cfl outside (0,1], W <= 0, sigma < 0, walls with
+ * the interface-only model or ny < 4. Resets nothing; takes effect from the
+ * next init or step. */
+int dugks_set_params(dugks_handle *h, const dugks_params *p);
+
+/* Use `stream` (a hipStream_t, NULL = null stream) for all later work. */
+int dugks_set_stream(dugks_handle *h, void *stream);
+
+/* Work decomposition of the step kernel: rows per segment of a 62-column
+ * strip (each (strip, segment) tile is one 64-lane wave). 0 = automatic
+ * (the longest segment that still gives >= 2048 waves). EINVAL outside
+ * [0, 4096]. dugks_get_tile returns the value in use (-1 for NULL). */
+int dugks_set_tile(dugks_handle *h, int seg_rows);
+int dugks_get_tile(const dugks_handle *h);
+
+/* Build the initial state from cell macros: host arrays [ny][nx] of double,
+ * copied during the call. u, v, p may be NULL (zero); the interface-only
+ * model ignores them and uses the prescribed velocity at t = 0. The tilde
+ * distributions start at psi^eq - (dt/2) S with a zero time derivative of
+ * phi u (Eqs. 23, 15-19). Resets the step counter. ESTATE before set_params. */
+int dugks_init_fields(dugks_handle *h, const double *phi, const double *u,
+                      const double *v, const double *p);
+
+/* As dugks_init_fields with device pointers (double, [ny][nx]), read on the
+ * handle's stream; asynchronous. */
+int dugks_init_fields_device(dugks_handle *h, const double *phi,
+                             const double *u, const double *v,
+                             const double *p);
+
+/* Enqueue nsteps >= 0 time steps (Sec. II.B: cell macros, bar-plus and
+ * tilde-plus auxiliaries, half-step face reconstruction, face macros and face
+ * distributions, microflux, cell update). Asynchronous; ESTATE before init. */
+int dugks_step(dugks_handle *h, int nsteps);
+
+/* Wait for the handle's stream. EDEVICE on a sticky device error. */
+int dugks_sync(dugks_handle *h);
+
+/* Cell macros of the current state (Eqs. 31-33 and Eq. 10): phi, u, v, p,
+ * rho into host arrays [ny][nx] of double; NULL skips a field. Synchronises
+ * the handle's stream. For the interface-only model u, v are the prescribed
+ * field at the current time and p = 0. */
+int dugks_get_macros(dugks_handle *h, double *phi, double *u, double *v,
+                     double *p, double *rho);
+
+/* As dugks_get_macros into device arrays; asynchronous on the stream. */
+int dugks_get_macros_device(dugks_handle *h, double *phi, double *u,
+                            double *v, double *p, double *rho);
+
+/* Diagnostics of the current state, accumulated in double on the device in
+ * a fixed order: out[0] = sum phi, out[1] = sum rho u, out[2] = sum rho v,
+ * out[3] = sum rho |u|^2 / 2, out[4] = max |u|, out[5] = sum rho,
+ * out[6] = number of non-finite cells, out[7] = time. Synchronises. Returns
+ * ENUMERIC (with out filled) when out[6] > 0. */
+int dugks_get_diagnostics(dugks_handle *h, double out[8]);
+
+/* Steps taken since init and the current time. */
+long long dugks_steps_done(const dugks_handle *h);
+double dugks_time(const dugks_handle *h);
+
+/* Checkpoint/resume: the state is the tilde distributions, the history
+ * (phi u)^(n-1), the phi plane and the step counter. dugks_state_bytes()
+ * gives the size of the host buffer; get/set copy it (synchronous). */
+size_t dugks_state_bytes(const dugks_handle *h);
+int dugks_get_state(dugks_handle *h, void *host_buf, size_t bytes,
+                    long long *steps);
+int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
+                    long long steps);
+
+/* Device bytes a handle of this shape holds (both state buffers). */
+size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
+
+/* Message of the last error on h (or of the last failed create when h is
+ * NULL). Never NULL. */
+const char *dugks_last_error(const dugks_handle *h);
+
+/* Release a handle; NULL is accepted. */
+int dugks_destroy(dugks_handle *h);
+
+/* ---------------------------------------------------------------- batches
+ * A batch advances several handles of the same precision and model together:
+ * one kernel launch per step covers all of them (work items are the (case,
+ * column strip, row segment) tiles of every case), and a step sequence can be
+ * recorded once in a HIP graph and replayed. The handles stay usable on their
+ * own (set_params, init, get_macros) between batch calls; the batch works on
+ * the batch's stream. Handles must outlive the batch. */
+typedef struct dugks_batch dugks_batch;
+
+int dugks_batch_create(int n, dugks_handle *const *cases, dugks_batch **out);
+
+/* Advance every active case by nsteps. use_graph = 1 records the sequence of
+ * nsteps launches in a HIP graph on first use (per distinct nsteps) and
+ * replays it. Cases with a step budget (dugks_batch_set_budget) stop when it
+ * runs out. Asynchronous on the batch stream. */
+int dugks_batch_step(dugks_batch *b, int nsteps, int use_graph);
+
+/* Limit case k to `steps` more steps (negative = unlimited); takes effect
+ * from the next dugks_batch_step. */
+int dugks_batch_set_budget(dugks_batch *b, int k, long long steps);
+
+int dugks_batch_set_stream(dugks_batch *b, void *stream);
+int dugks_batch_sync(dugks_batch *b);
+int dugks_batch_destroy(dugks_batch *b);
+
+/* Message of the last error on b (or of the last failed batch_create when b
+ * is NULL). Never NULL. */
+const char *dugks_batch_last_error(const dugks_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DUGKS_H */

@@ -40,7 +40,11 @@
  *       D) are the mean of the two adjacent cells at t_n; algebraic functions
  *       of phi (rho, theta, tau_g, gravity) are re-evaluated from the face phi.
  *   R6  Face macros use the cell formulas of Eq. 32-33 with dt/2 -> h/2.
- *   R7  n = 0 where |grad phi| = 0.
+ *   R7  n = grad phi / sqrt(|grad phi|^2 + eps^2), eps = 1e-6 |phi_H - phi_L|:
+ *       the unit normal where |grad phi| >> eps, zero for a uniform field, and
+ *       continuous at the saddle points of phi where the plain unit vector is
+ *       undefined (there theta n would otherwise follow the rounding of a
+ *       vanishing gradient).
  *   R8  grad phi: isotropic D2Q9-weighted difference (six non-zero points per
  *       component).
  *   R9  Laplacian: isotropic nine-point stencil.
@@ -298,15 +302,12 @@ void orc_stencils(int nx, int ny, int walls_y, const double *phi, double *gx,
         }
 }
 
-static void unit(double gx, double gy, double *nx, double *ny) {
-    double m = sqrt(gx * gx + gy * gy);
-    if (m > 0.0) {
-        *nx = gx / m;
-        *ny = gy / m;
-    } else { /* R7 */
-        *nx = 0.0;
-        *ny = 0.0;
-    }
+/* R7: regularised unit normal. */
+static void unit(const orc_sim *s, double gx, double gy, double *nx, double *ny) {
+    double eps = 1e-6 * s->Dphi;
+    double m = sqrt(gx * gx + gy * gy + eps * eps);
+    *nx = gx / m;
+    *ny = gy / m;
 }
 
 /* ------------------------------------------------------ allocation / API */
@@ -426,7 +427,7 @@ static void pass_a(orc_sim *s) {
 static void cell_eq_src(const orc_sim *s, size_t c, double *feq, double *sf,
                         double *geq, double *sg) {
     double nxv, nyv;
-    unit(s->gpx[c], s->gpy[c], &nxv, &nyv);
+    unit(s, s->gpx[c], s->gpy[c], &nxv, &nyv);
     orc_feq(s->phi[c], s->ux[c], s->uy[c], feq);
     orc_sf(s->theta[c], nxv, nyv, s->Dx[c], s->Dy[c], sf);
     if (s->coupled) {
@@ -497,7 +498,7 @@ static void face_df(const orc_sim *s, const face_in *in, const double *fb,
     for (int q = 0; q < 9; ++q) phif += fb[q];
     double rhof = rho_of(s, phif), thf = theta_of(s, phif);
     double nxv, nyv;
-    unit(in->gx, in->gy, &nxv, &nyv);
+    unit(s, in->gx, in->gy, &nxv, &nyv);
     double uf, vf;
     double feq[9], sf[9];
     if (s->coupled) {
@@ -548,7 +549,7 @@ static void wall_face(orc_sim *s, int i, int bottom) {
     double gxw = s->gpx[c], gyw = 0.0, muw = s->mu[c];
     double Dxw = s->Dx[c], Dyw = 0.0;
     double nxv, nyv;
-    unit(gxw, gyw, &nxv, &nyv);
+    unit(s, gxw, gyw, &nxv, &nyv);
     double Gx, Gy;
     gravity(s, rhow, &Gx, &Gy);
     double Fx = muw * gxw + Gx, Fy = muw * gyw + Gy;

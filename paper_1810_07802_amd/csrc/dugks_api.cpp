@@ -1,0 +1,628 @@
+// C ABI of libdugks (declared in include/dugks.h): handle life cycle,
+// parameter validation and derived constants, initialisation, stepping,
+// readout, diagnostics, checkpoints and batches (with HIP graphs).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dugks.h"
+#include "dugks_impl.h"
+
+using dugks::CaseDev;
+using dugks::Item;
+using dugks::StepArgs;
+
+namespace {
+
+constexpr double kRT = 1.0 / 3.0;
+constexpr int kDiagBlocks = 256;
+
+thread_local std::string g_create_error = "no error";
+
+}  // namespace
+
+struct dugks_handle {
+  int nx = 0, ny = 0, precision = 0, model = 0;
+  dugks_params params{};
+  bool has_params = false, has_state = false;
+  hipStream_t stream = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  size_t buf_bytes = 0;
+  CaseDev hc{};
+  CaseDev* dc = nullptr;
+  Item* items = nullptr;
+  int nitems = 0;
+  int seg_rows = 0;  // 0: automatic
+  long long* step_base = nullptr;  // device: steps done
+  long long steps = 0;             // host mirror
+  double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
+  std::string err = "no error";
+  bool dirty_case = true;
+
+  bool fp64() const { return precision == DUGKS_FP64; }
+  bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
+  size_t n() const { return (size_t)nx * ny; }
+  size_t elem() const { return fp64() ? 8 : 4; }
+};
+
+namespace {
+
+int fail(dugks_handle* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+int hip_fail(dugks_handle* h, hipError_t e, const char* what) {
+  return fail(h, DUGKS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(h, expr)                                   \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
+  } while (0)
+
+int auto_seg_rows(int nx, int ny) {
+  const int nstrips = (nx + dugks::kStripCols - 1) / dugks::kStripCols;
+  // Longest segments that still give >= 2048 waves (8 per CU); shorter
+  // segments repeat two halo rows of cell work per segment.
+  const int cand[] = {128, 64, 32, 16, 8, 4};
+  for (int s : cand) {
+    const long long waves = (long long)nstrips * ((ny + s - 1) / s);
+    if (waves >= 2048) return s;
+  }
+  return 2;
+}
+
+// Derived constants (Sec. II.B, Eqs. 3, 28-29, 34, 37) into the descriptor.
+void fill_case(dugks_handle* h) {
+  CaseDev& C = h->hc;
+  const dugks_params& P = h->params;
+  C.nx = h->nx;
+  C.ny = h->ny;
+  C.coupled = h->coupled() ? 1 : 0;
+  C.nstrips = (h->nx + dugks::kStripCols - 1) / dugks::kStripCols;
+  C.seg_rows = h->seg_rows > 0 ? h->seg_rows : auto_seg_rows(h->nx, h->ny);
+  C.nsegs = (h->ny + C.seg_rows - 1) / C.seg_rows;
+  C.walls = P.bc_y == DUGKS_BC_WALLS ? 1 : 0;
+  C.vel_kind = P.vel_kind;
+  C.visc_mode = P.visc_mode;
+  C.grav_form = P.gravity_form == DUGKS_GRAV_BUOYANCY ? 1 : 0;
+  C.plane = (long long)h->n();
+  C.set[0] = h->buf[0];
+  C.set[1] = h->buf[1];
+  C.dt = P.cfl;  // Eq. 37 with unit grid spacing and sqrt(3RT) = 1
+  C.h = 0.5 * C.dt;
+  C.t0 = 0.0;
+  const double D = P.phi_H - P.phi_L;
+  C.phi_H = P.phi_H;
+  C.phi_L = P.phi_L;
+  C.phibar = 0.5 * (P.phi_H + P.phi_L);
+  C.inv_dphi = 1.0 / D;
+  C.kappa = 1.5 * P.sigma * P.W / (D * D);
+  C.beta = 12.0 * P.sigma / (P.W * D * D * D * D);
+  C.theta_c = -4.0 / (P.W * D);
+  C.rho_H = P.rho_H;
+  C.rho_L = P.rho_L;
+  C.drho = (P.rho_H - P.rho_L) / D;
+  C.rho_mean = 0.5 * (P.rho_H + P.rho_L);
+  C.tau_f = P.M_phi / kRT;
+  C.tau_g_uniform = P.nu / kRT;
+  C.mu_H = P.mu_H;
+  C.mu_L = P.mu_L;
+  C.inv_mu_H = P.mu_H > 0 ? 1.0 / P.mu_H : 0.0;
+  C.inv_mu_L = P.mu_L > 0 ? 1.0 / P.mu_L : 0.0;
+  C.gx = P.gx;
+  C.gy = P.gy;
+  C.Gx = P.Gx;
+  C.Gy = P.Gy;
+  C.U0 = P.U0;
+  C.L0 = P.L0;
+  C.T_period = P.T_period;
+  C.eps_n2 = (1e-6 * D) * (1e-6 * D);
+  C.fb = 3.0 * C.h / (2.0 * C.tau_f + C.dt);
+  C.ffb = C.h / (2.0 * C.tau_f + C.h);
+  C.gb = 3.0 * C.h / (2.0 * C.tau_g_uniform + C.dt);
+  C.gfb = C.h / (2.0 * C.tau_g_uniform + C.h);
+  C.step0 = 0;
+  C.nsteps = LLONG_MAX;
+}
+
+int upload_case(dugks_handle* h) {
+  if (!h->dirty_case) return DUGKS_OK;
+  fill_case(h);
+  HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
+  std::vector<Item> it;
+  it.reserve((size_t)h->hc.nstrips * h->hc.nsegs);
+  for (int s = 0; s < h->hc.nsegs; ++s)
+    for (int x = 0; x < h->hc.nstrips; ++x) it.push_back(Item{0, x, s, 0});
+  if ((int)it.size() != h->nitems) {
+    if (h->items) (void)hipFree(h->items);
+    h->items = nullptr;
+    HIPCHK(h, hipMalloc(&h->items, it.size() * sizeof(Item)));
+    h->nitems = (int)it.size();
+  }
+  HIPCHK(h, hipMemcpyAsync(h->items, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice,
+                           h->stream));
+  // the pinned-host source of the copies above is a local: wait here
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->dirty_case = false;
+  return DUGKS_OK;
+}
+
+int validate(const dugks_handle* h, const dugks_params* p, std::string& why) {
+  auto bad = [&](const char* m) { why = m; return DUGKS_EINVAL; };
+  if (!(p->phi_H != p->phi_L)) return bad("phi_H must differ from phi_L");
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return bad("cfl must lie in (0, 1]");
+  if (!(p->W > 0.0)) return bad("W must be > 0");
+  if (!(p->sigma >= 0.0)) return bad("sigma must be >= 0");
+  if (!(p->M_phi >= 0.0)) return bad("M_phi must be >= 0");
+  if (p->bc_y != DUGKS_BC_PERIODIC && p->bc_y != DUGKS_BC_WALLS) return bad("bad bc_y");
+  if (h->model == DUGKS_MODEL_AC) {
+    if (p->bc_y == DUGKS_BC_WALLS) return bad("walls need the coupled model");
+    if (p->vel_kind < DUGKS_VEL_UNIFORM || p->vel_kind > DUGKS_VEL_DEFORM) return bad("bad vel_kind");
+    if (p->vel_kind != DUGKS_VEL_UNIFORM && !(p->L0 > 0.0)) return bad("L0 must be > 0");
+    if ((p->vel_kind == DUGKS_VEL_SHEAR || p->vel_kind == DUGKS_VEL_DEFORM) && !(p->T_period > 0.0))
+      return bad("T_period must be > 0");
+  } else {
+    if (!(p->rho_H > 0.0 && p->rho_L > 0.0)) return bad("densities must be > 0");
+    if (p->visc_mode == DUGKS_VISC_UNIFORM_NU) {
+      if (!(p->nu > 0.0)) return bad("nu must be > 0");
+    } else if (p->visc_mode == DUGKS_VISC_RECIPROCAL || p->visc_mode == DUGKS_VISC_LINEAR) {
+      if (!(p->mu_H > 0.0 && p->mu_L > 0.0)) return bad("viscosities must be > 0");
+    } else {
+      return bad("bad visc_mode");
+    }
+    if (p->gravity_form != DUGKS_GRAV_RHO_G && p->gravity_form != DUGKS_GRAV_BUOYANCY)
+      return bad("bad gravity_form");
+    if (p->bc_y == DUGKS_BC_WALLS && h->ny < 4) return bad("walls need ny >= 4");
+  }
+  return DUGKS_OK;
+}
+
+size_t state_set_bytes(int nx, int ny, int precision, int model) {
+  const size_t e = precision == DUGKS_FP64 ? 8 : 4;
+  return (size_t)dugks::num_planes(model == DUGKS_MODEL_COUPLED) * (size_t)nx * ny * e;
+}
+
+int ensure_scratch(dugks_handle* h) {
+  if (h->scratch) return DUGKS_OK;
+  const size_t bytes = (5 * h->n() + (size_t)kDiagBlocks * 7 + 16) * sizeof(double);
+  HIPCHK(h, hipMalloc(&h->scratch, bytes));
+  return DUGKS_OK;
+}
+
+int launch_steps(dugks_handle* h, int nsteps) {
+  StepArgs a;
+  a.cases = h->dc;
+  a.items = h->items;
+  a.nitems = h->nitems;
+  a.step_base = h->step_base;
+  for (int k = 0; k < nsteps; ++k) {
+    a.kofs = k;
+    HIPCHK(h, dugks::launch_step(h->fp64(), h->coupled(), a, h->stream));
+  }
+  HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
+  return DUGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dugks_create(int nx, int ny, int precision, int model, dugks_handle** out) {
+  if (!out) return fail(nullptr, DUGKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nx < 3 || ny < 3) return fail(nullptr, DUGKS_EINVAL, "nx and ny must be >= 3");
+  if ((long long)nx * ny > (1LL << 31) / 4) return fail(nullptr, DUGKS_EINVAL, "grid too large");
+  if (precision != DUGKS_FP32 && precision != DUGKS_FP64)
+    return fail(nullptr, DUGKS_EINVAL, "bad precision");
+  if (model != DUGKS_MODEL_AC && model != DUGKS_MODEL_COUPLED)
+    return fail(nullptr, DUGKS_EINVAL, "bad model");
+  dugks_handle* h = new (std::nothrow) dugks_handle;
+  if (!h) return fail(nullptr, DUGKS_ENOMEM, "host allocation failed");
+  h->nx = nx;
+  h->ny = ny;
+  h->precision = precision;
+  h->model = model;
+  h->buf_bytes = state_set_bytes(nx, ny, precision, model);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMalloc(&h->buf[k], h->buf_bytes);
+  if (e == hipSuccess) e = hipMalloc(&h->dc, sizeof(CaseDev));
+  if (e == hipSuccess) e = hipMalloc(&h->step_base, sizeof(long long));
+  if (e == hipSuccess) e = hipMemset(h->step_base, 0, sizeof(long long));
+  if (e != hipSuccess) {
+    std::string msg = std::string("device allocation failed: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    dugks_destroy(h);
+    return fail(nullptr, e == hipErrorOutOfMemory ? DUGKS_ENOMEM : DUGKS_EDEVICE, msg);
+  }
+  *out = h;
+  return DUGKS_OK;
+}
+
+int dugks_set_params(dugks_handle* h, const dugks_params* p) {
+  if (!h || !p) return fail(h, DUGKS_EINVAL, "NULL argument");
+  std::string why;
+  if (validate(h, p, why) != DUGKS_OK) return fail(h, DUGKS_EINVAL, why);
+  h->params = *p;
+  h->has_params = true;
+  h->dirty_case = true;
+  return upload_case(h);
+}
+
+int dugks_set_stream(dugks_handle* h, void* stream) {
+  if (!h) return DUGKS_EINVAL;
+  h->stream = static_cast<hipStream_t>(stream);
+  return DUGKS_OK;
+}
+
+// Rows per segment of the step kernel's work items (0 = automatic).
+int dugks_set_tile(dugks_handle* h, int seg_rows) {
+  if (!h || seg_rows < 0 || seg_rows > 4096) return fail(h, DUGKS_EINVAL, "bad seg_rows");
+  h->seg_rows = seg_rows;
+  h->dirty_case = true;
+  if (h->has_params) return upload_case(h);
+  return DUGKS_OK;
+}
+
+int dugks_get_tile(const dugks_handle* h) { return h ? h->hc.seg_rows : -1; }
+
+int dugks_init_fields_device(dugks_handle* h, const double* phi, const double* u, const double* v,
+                             const double* p) {
+  if (!h || !phi) return fail(h, DUGKS_EINVAL, "phi is NULL");
+  if (!h->has_params) return fail(h, DUGKS_ESTATE, "set_params first");
+  int rc = upload_case(h);
+  if (rc) return rc;
+  // local step 0 lives in buffer 0; the device step counter restarts at 0
+  h->hc.cur0 = 0;
+  h->hc.step0 = 0;
+  HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemsetAsync(h->step_base, 0, sizeof(long long), h->stream));
+  HIPCHK(h, dugks::launch_init(h->fp64(), h->dc, h->hc, phi, u, v, p, h->stream));
+  h->steps = 0;
+  h->has_state = true;
+  return DUGKS_OK;
+}
+
+int dugks_init_fields(dugks_handle* h, const double* phi, const double* u, const double* v,
+                      const double* p) {
+  if (!h || !phi) return fail(h, DUGKS_EINVAL, "phi is NULL");
+  if (!h->has_params) return fail(h, DUGKS_ESTATE, "set_params first");
+  int rc = ensure_scratch(h);
+  if (rc) return rc;
+  const size_t n = h->n(), b = n * sizeof(double);
+  double* d[4] = {h->scratch, h->scratch + n, h->scratch + 2 * n, h->scratch + 3 * n};
+  const double* src[4] = {phi, u, v, p};
+  for (int k = 0; k < 4; ++k)
+    if (src[k]) HIPCHK(h, hipMemcpyAsync(d[k], src[k], b, hipMemcpyHostToDevice, h->stream));
+  rc = dugks_init_fields_device(h, d[0], u ? d[1] : nullptr, v ? d[2] : nullptr, p ? d[3] : nullptr);
+  if (rc) return rc;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DUGKS_OK;
+}
+
+int dugks_step(dugks_handle* h, int nsteps) {
+  if (!h || nsteps < 0) return fail(h, DUGKS_EINVAL, "bad arguments");
+  if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  if (nsteps == 0) return DUGKS_OK;
+  int rc = launch_steps(h, nsteps);
+  if (rc) return rc;
+  h->steps += nsteps;
+  return DUGKS_OK;
+}
+
+int dugks_sync(dugks_handle* h) {
+  if (!h) return DUGKS_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DUGKS_OK;
+}
+
+int dugks_get_macros_device(dugks_handle* h, double* phi, double* u, double* v, double* p,
+                            double* rho) {
+  if (!h) return DUGKS_EINVAL;
+  if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  HIPCHK(h, dugks::launch_macros(h->fp64(), h->dc, h->hc, h->steps, phi, u, v, p, rho, h->stream));
+  return DUGKS_OK;
+}
+
+int dugks_get_macros(dugks_handle* h, double* phi, double* u, double* v, double* p, double* rho) {
+  if (!h) return DUGKS_EINVAL;
+  if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  int rc = ensure_scratch(h);
+  if (rc) return rc;
+  const size_t n = h->n(), b = n * sizeof(double);
+  double* d[5] = {h->scratch, h->scratch + n, h->scratch + 2 * n, h->scratch + 3 * n,
+                  h->scratch + 4 * n};
+  double* dst[5] = {phi, u, v, p, rho};
+  rc = dugks_get_macros_device(h, phi ? d[0] : nullptr, u ? d[1] : nullptr, v ? d[2] : nullptr,
+                               p ? d[3] : nullptr, rho ? d[4] : nullptr);
+  if (rc) return rc;
+  for (int k = 0; k < 5; ++k)
+    if (dst[k]) HIPCHK(h, hipMemcpyAsync(dst[k], d[k], b, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return DUGKS_OK;
+}
+
+int dugks_get_diagnostics(dugks_handle* h, double out[8]) {
+  if (!h || !out) return DUGKS_EINVAL;
+  if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  int rc = ensure_scratch(h);
+  if (rc) return rc;
+  const size_t n = h->n();
+  double* phi = h->scratch;
+  double* u = phi + n;
+  double* v = u + n;
+  double* rho = v + 2 * n;
+  double* part = h->scratch + 5 * n;
+  double* dout = part + (size_t)kDiagBlocks * 7;
+  rc = dugks_get_macros_device(h, phi, u, v, nullptr, rho);
+  if (rc) return rc;
+  HIPCHK(h, dugks::launch_diag(h->hc, phi, u, v, rho, part, kDiagBlocks, dout, h->stream));
+  double tmp[7];
+  HIPCHK(h, hipMemcpyAsync(tmp, dout, sizeof(tmp), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int k = 0; k < 7; ++k) out[k] = tmp[k];
+  out[7] = h->steps * h->params.cfl;
+  if (tmp[6] > 0) return fail(h, DUGKS_ENUMERIC, "non-finite values in the state");
+  return DUGKS_OK;
+}
+
+long long dugks_steps_done(const dugks_handle* h) { return h ? h->steps : -1; }
+double dugks_time(const dugks_handle* h) { return h ? h->steps * h->params.cfl : 0.0; }
+
+size_t dugks_state_bytes(const dugks_handle* h) { return h ? h->buf_bytes : 0; }
+
+int dugks_get_state(dugks_handle* h, void* host_buf, size_t bytes, long long* steps) {
+  if (!h || !host_buf || bytes != h->buf_bytes) return fail(h, DUGKS_EINVAL, "bad buffer");
+  if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  const int cur = (h->hc.cur0 + (int)(h->steps & 1)) & 1;
+  HIPCHK(h, hipMemcpyAsync(host_buf, h->buf[cur], bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (steps) *steps = h->steps;
+  return DUGKS_OK;
+}
+
+int dugks_set_state(dugks_handle* h, const void* host_buf, size_t bytes, long long steps) {
+  if (!h || !host_buf || bytes != h->buf_bytes || steps < 0)
+    return fail(h, DUGKS_EINVAL, "bad buffer");
+  if (!h->has_params) return fail(h, DUGKS_ESTATE, "set_params first");
+  int rc = upload_case(h);
+  if (rc) return rc;
+  h->hc.cur0 = (int)(steps & 1);  // local step `steps` lands in buffer 0
+  h->hc.step0 = 0;
+  HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->buf[0], host_buf, bytes, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, hipMemcpyAsync(h->step_base, &steps, sizeof(long long), hipMemcpyHostToDevice,
+                           h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->steps = steps;
+  h->has_state = true;
+  return DUGKS_OK;
+}
+
+size_t dugks_footprint_bytes(int nx, int ny, int precision, int model) {
+  if (nx < 1 || ny < 1) return 0;
+  return 2 * state_set_bytes(nx, ny, precision, model) + sizeof(CaseDev) + 64;
+}
+
+const char* dugks_last_error(const dugks_handle* h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int dugks_destroy(dugks_handle* h) {
+  if (!h) return DUGKS_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  for (int k = 0; k < 2; ++k)
+    if (h->buf[k]) (void)hipFree(h->buf[k]);
+  if (h->dc) (void)hipFree(h->dc);
+  if (h->items) (void)hipFree(h->items);
+  if (h->step_base) (void)hipFree(h->step_base);
+  if (h->scratch) (void)hipFree(h->scratch);
+  delete h;
+  return DUGKS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct dugks_batch {
+  std::vector<dugks_handle*> cases;
+  std::vector<long long> budget;  // remaining steps per case, < 0 = unlimited
+  bool fp64 = false, coupled = true;
+  hipStream_t stream = nullptr;
+  CaseDev* dcases = nullptr;
+  Item* items = nullptr;
+  int nitems = 0;
+  long long* step_base = nullptr;  // device: global step of the batch
+  long long gstep = 0;             // host mirror
+  std::vector<CaseDev> hcases;
+  std::map<int, hipGraphExec_t> graphs;
+  std::string err = "no error";
+};
+
+namespace {
+
+int bfail(dugks_batch* b, int code, const std::string& m) {
+  if (b) b->err = m;
+  else g_create_error = m;
+  return code;
+}
+
+#define BHIPCHK(b, expr)                                                        \
+  do {                                                                          \
+    hipError_t e_ = (expr);                                                     \
+    if (e_ != hipSuccess)                                                       \
+      return bfail((b), DUGKS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Bring the batch descriptors in line with the handles: local step n of
+// case k happens at global step gstep + (n - steps_k).
+int sync_descriptors(dugks_batch* b) {
+  for (size_t k = 0; k < b->cases.size(); ++k) {
+    dugks_handle* h = b->cases[k];
+    CaseDev c = h->hc;
+    c.step0 = b->gstep - h->steps;
+    c.nsteps = b->budget[k] < 0 ? LLONG_MAX : h->steps + b->budget[k];
+    b->hcases[k] = c;
+  }
+  BHIPCHK(b, hipMemcpyAsync(b->dcases, b->hcases.data(), b->hcases.size() * sizeof(CaseDev),
+                            hipMemcpyHostToDevice, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return DUGKS_OK;
+}
+
+int record_steps(dugks_batch* b, int nsteps) {
+  StepArgs a;
+  a.cases = b->dcases;
+  a.items = b->items;
+  a.nitems = b->nitems;
+  a.step_base = b->step_base;
+  for (int k = 0; k < nsteps; ++k) {
+    a.kofs = k;
+    BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, a, b->stream));
+  }
+  BHIPCHK(b, dugks::launch_advance(b->step_base, nsteps, b->stream));
+  return DUGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
+  if (!out || n <= 0 || !cases) return bfail(nullptr, DUGKS_EINVAL, "bad arguments");
+  *out = nullptr;
+  for (int k = 0; k < n; ++k) {
+    if (!cases[k]) return bfail(nullptr, DUGKS_EINVAL, "NULL case");
+    if (!cases[k]->has_params) return bfail(nullptr, DUGKS_ESTATE, "case without params");
+    if (cases[k]->precision != cases[0]->precision || cases[k]->model != cases[0]->model)
+      return bfail(nullptr, DUGKS_EINVAL, "cases must share precision and model");
+  }
+  dugks_batch* b = new (std::nothrow) dugks_batch;
+  if (!b) return bfail(nullptr, DUGKS_ENOMEM, "host allocation failed");
+  b->cases.assign(cases, cases + n);
+  b->budget.assign(n, -1);
+  b->hcases.resize(n);
+  b->fp64 = cases[0]->fp64();
+  b->coupled = cases[0]->coupled();
+  std::vector<Item> it;
+  for (int k = 0; k < n; ++k) {
+    if (upload_case(cases[k]) != DUGKS_OK) {
+      dugks_batch_destroy(b);
+      return bfail(nullptr, DUGKS_EDEVICE, cases[k]->err);
+    }
+    const CaseDev& c = cases[k]->hc;
+    for (int s = 0; s < c.nsegs; ++s)
+      for (int x = 0; x < c.nstrips; ++x) it.push_back(Item{k, x, s, 0});
+  }
+  b->nitems = (int)it.size();
+  hipError_t e = hipMalloc(&b->dcases, n * sizeof(CaseDev));
+  if (e == hipSuccess) e = hipMalloc(&b->items, it.size() * sizeof(Item));
+  if (e == hipSuccess) e = hipMalloc(&b->step_base, sizeof(long long));
+  if (e == hipSuccess) e = hipMemcpy(b->items, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(b->step_base, 0, sizeof(long long));
+  if (e != hipSuccess) {
+    std::string m = std::string("batch allocation failed: ") + hipGetErrorString(e);
+    dugks_batch_destroy(b);
+    return bfail(nullptr, DUGKS_ENOMEM, m);
+  }
+  *out = b;
+  return DUGKS_OK;
+}
+
+int dugks_batch_set_budget(dugks_batch* b, int k, long long steps) {
+  if (!b || k < 0 || k >= (int)b->cases.size()) return bfail(b, DUGKS_EINVAL, "bad case index");
+  b->budget[k] = steps < 0 ? -1 : steps;
+  return DUGKS_OK;
+}
+
+int dugks_batch_set_stream(dugks_batch* b, void* stream) {
+  if (!b) return DUGKS_EINVAL;
+  b->stream = static_cast<hipStream_t>(stream);
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+  return DUGKS_OK;
+}
+
+int dugks_batch_step(dugks_batch* b, int nsteps, int use_graph) {
+  if (!b || nsteps < 0) return bfail(b, DUGKS_EINVAL, "bad arguments");
+  for (auto* h : b->cases)
+    if (!h->has_state) return bfail(b, DUGKS_ESTATE, "a case has no state");
+  if (nsteps == 0) return DUGKS_OK;
+  // the handles' own work must be finished before the batch touches them
+  for (auto* h : b->cases)
+    if (h->stream != b->stream) BHIPCHK(b, hipStreamSynchronize(h->stream));
+  int rc = sync_descriptors(b);
+  if (rc) return rc;
+  if (use_graph && b->stream) {
+    auto itg = b->graphs.find(nsteps);
+    if (itg == b->graphs.end()) {
+      hipGraph_t g;
+      BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      rc = record_steps(b, nsteps);
+      hipError_t e = hipStreamEndCapture(b->stream, &g);
+      if (rc) return rc;
+      if (e != hipSuccess) return bfail(b, DUGKS_EDEVICE, hipGetErrorString(e));
+      hipGraphExec_t ex;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return bfail(b, DUGKS_EDEVICE, hipGetErrorString(e));
+      itg = b->graphs.emplace(nsteps, ex).first;
+    }
+    BHIPCHK(b, hipGraphLaunch(itg->second, b->stream));
+  } else {
+    rc = record_steps(b, nsteps);
+    if (rc) return rc;
+  }
+  b->gstep += nsteps;
+  // advance every case's own counters by the steps it actually took
+  for (size_t k = 0; k < b->cases.size(); ++k) {
+    dugks_handle* h = b->cases[k];
+    long long took = nsteps;
+    if (b->budget[k] >= 0) {
+      took = std::min<long long>(nsteps, b->budget[k]);
+      b->budget[k] -= took;
+    }
+    if (took > 0) {
+      BHIPCHK(b, dugks::launch_advance(h->step_base, took, b->stream));
+      h->steps += took;
+    }
+  }
+  return DUGKS_OK;
+}
+
+int dugks_batch_sync(dugks_batch* b) {
+  if (!b) return DUGKS_EINVAL;
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return DUGKS_OK;
+}
+
+int dugks_batch_destroy(dugks_batch* b) {
+  if (!b) return DUGKS_OK;
+  (void)hipStreamSynchronize(b->stream);
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  if (b->dcases) (void)hipFree(b->dcases);
+  if (b->items) (void)hipFree(b->items);
+  if (b->step_base) (void)hipFree(b->step_base);
+  delete b;
+  return DUGKS_OK;
+}
+
+const char* dugks_batch_last_error(const dugks_batch* b) {
+  return b ? b->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Internal types shared by the kernels and the C-ABI layer of libdugks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dugks {
+
+// Interior columns per strip: a strip is one 64-lane wave whose lanes 0 and
+// 63 hold the halo columns on either side.
+constexpr int kStripCols = 62;
+constexpr int kWave = 64;
+
+// Plane order inside one state buffer (each plane is nx*ny values):
+//   f0..f8, [g0..g8], hist_x, hist_y, phi
+// where hist = (phi u) of the previous step and phi = sum_q f.
+__host__ __device__ constexpr int plane_f(int q) { return q; }
+__host__ __device__ constexpr int plane_g(int q) { return 9 + q; }
+__host__ __device__ constexpr int plane_hist(bool coupled, int c) {
+  return (coupled ? 18 : 9) + c;
+}
+__host__ __device__ constexpr int plane_phi(bool coupled) { return coupled ? 20 : 11; }
+__host__ __device__ constexpr int num_planes(bool coupled) { return coupled ? 21 : 12; }
+
+// Everything a kernel needs about one case. Lives in device memory (an array
+// for batches, one entry for a plain handle). Constants are kept in double;
+// kernels narrow them to their working precision.
+struct CaseDev {
+  // geometry and work decomposition
+  int nx, ny;
+  int nstrips;   // ceil(nx / kStripCols)
+  int seg_rows;  // rows per segment
+  int nsegs;     // ceil(ny / seg_rows)
+  int walls;     // 1: no-slip walls on y = 0 and y = ny
+  int coupled;
+  int vel_kind, visc_mode, grav_form;
+  int cur0;              // state buffer holding local step 0
+  long long step0;       // global step index of local step 0
+  long long nsteps;      // local steps allowed (active window)
+  long long plane;       // values per plane
+  void* set[2];          // the two state buffers
+  // time
+  double dt, h, t0;
+  // phase field
+  double phi_H, phi_L, phibar, inv_dphi, kappa, beta, theta_c;
+  double eps_n2;  // regularisation of the unit normal: (1e-6 |phi_H - phi_L|)^2
+  double rho_H, rho_L, drho, rho_mean;
+  double tau_f;
+  // viscosity
+  double tau_g_uniform;  // used when visc_mode == uniform nu
+  double mu_H, mu_L, inv_mu_H, inv_mu_L;
+  // forcing
+  double gx, gy, Gx, Gy;
+  // prescribed velocity
+  double U0, L0, T_period;
+  // equilibrium weights of the relaxation: cell (Eq. 29) 3h/(2tau+dt), face
+  // (Eq. 28) h/(2tau+h); for f, and for g when tau_g is uniform
+  double fb, ffb, gb, gfb;
+};
+
+enum VelKind { kVelUniform = 0, kVelRotation = 1, kVelShear = 2, kVelDeform = 3 };
+enum ViscMode { kViscUniformNu = 0, kViscReciprocal = 1, kViscLinear = 2 };
+
+// Work item of the step kernel: which case, which column strip, which row
+// segment.
+struct Item {
+  int c, strip, seg, pad;
+};
+
+// Launch arguments of the step kernel.
+struct StepArgs {
+  const CaseDev* cases;
+  const Item* items;
+  int nitems;
+  int kofs;                    // offset of this launch inside a step sequence
+  const long long* step_base;  // device counter: global step of kofs = 0
+};
+
+// host-side launchers (dugks_kernels.hip)
+hipError_t launch_step(bool fp64, bool coupled, const StepArgs& a, hipStream_t s);
+hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);
+hipError_t launch_init(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
+                       const double* phi, const double* u, const double* v,
+                       const double* p, hipStream_t s);
+hipError_t launch_macros(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
+                         long long local_step, double* phi, double* u,
+                         double* v, double* p, double* rho, hipStream_t s);
+hipError_t launch_diag(const CaseDev& hcase, const double* phi, const double* u,
+                       const double* v, const double* rho, double* partial,
+                       int npartial, double* out, hipStream_t s);
+
+}  // namespace dugks

@@ -1,0 +1,879 @@
+// HIP kernels of the phase-field DUGKS step for gfx950 (MI355X).
+//
+// Paper: Yang, Zhong & Zhuo, arXiv:1810.07802. Section and equation numbers
+// below refer to it.
+//
+// Step kernel layout. One 64-lane wave owns a strip of 62 interior columns
+// (lanes 1..62; lanes 0 and 63 carry the halo columns) and a segment of rows,
+// and marches up the rows. For each new row r it runs the cell stage (macros
+// at t_n, equilibria and sources, bar-plus and tilde-plus, Eqs. 15-19, 29-33)
+// once; the three most recent rows stay in registers, so every cell stage is
+// done once per segment except two halo rows. The x-neighbours' values needed
+// by the face reconstruction come through cross-lane permutes, not memory.
+// Faces are reconstructed from the bar-plus values of the adjacent cells
+// (central scheme: mean, normal difference, mean of the tangential central
+// differences, Eq. 27), including the face moments used for the face macros,
+// which are linear in the populations and therefore reconstructed from the
+// cell moments. The face distributions (Eq. 28) give the microflux (Eq. 22)
+// and the cell update (Eq. 24) is written together with phi = sum f and the
+// history (phi u) for the next step's time derivative.
+//
+// Working precision T is float or double. In the float path the density,
+// its reciprocal and the relaxation time of g (interpolated across the
+// interface) are evaluated in double and narrowed.
+
+#include <hip/hip_runtime.h>
+
+#include "dugks_impl.h"
+
+namespace dugks {
+namespace {
+
+__device__ constexpr int EX[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
+__device__ constexpr int EY[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+
+// D2Q9 weights (Eq. 14). In float the nine stored weights are chosen within
+// one ulp of 4/9, 1/9, 1/36 so that they sum to exactly 1 (w1 = 4 w2 and
+// w0 = 1 - 4 w1 - 4 w2 are exact); with the rounded weights the zeroth moment
+// of every equilibrium would carry a 7e-9 bias per step into sum phi.
+template <typename T>
+__device__ __forceinline__ constexpr T wq(int q);
+template <>
+__device__ __forceinline__ constexpr float wq<float>(int q) {
+  return q == 0 ? 0x1.c71c74p-2f : ((q & 1) ? 0x1.c71c70p-4f : 0x1.c71c70p-6f);
+}
+template <>
+__device__ __forceinline__ constexpr double wq<double>(int q) {
+  return q == 0 ? 4.0 / 9.0 : ((q & 1) ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+
+__device__ __forceinline__ int wrap(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+// Row index of a (possibly ghost) row: periodic wrap, or mirror about the
+// walls (neutral wetting ghost values for the phi stencils).
+__device__ __forceinline__ int row_of(int r, int ny, int walls) {
+  if (walls) {
+    if (r < 0) r = -1 - r;
+    if (r >= ny) r = 2 * ny - 1 - r;
+    return r;
+  }
+  return wrap(r, ny);
+}
+
+// Cross-lane moves inside the wave: value of lane l-1 / l+1 (wrapping; the
+// wrapped values only reach the halo lanes, whose results are discarded).
+__device__ __forceinline__ float perm(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double perm(int addr, double v) {
+  int2 w = *reinterpret_cast<int2*>(&v);
+  w.x = __builtin_amdgcn_ds_bpermute(addr, w.x);
+  w.y = __builtin_amdgcn_ds_bpermute(addr, w.y);
+  return *reinterpret_cast<double*>(&w);
+}
+
+__device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
+
+// 1/rho in double. The float path refines a float reciprocal with one
+// Newton-Raphson step (relative error ~1e-14); the double path divides.
+template <typename T>
+__device__ __forceinline__ double inv_rho(double r);
+template <>
+__device__ __forceinline__ double inv_rho<float>(double r) {
+  double y = (double)__builtin_amdgcn_rcpf((float)r);
+  return y * (2.0 - r * y);
+}
+template <>
+__device__ __forceinline__ double inv_rho<double>(double r) {
+  return 1.0 / r;
+}
+
+// Density (Eq. 10) with s clamped to [0,1], in double.
+__device__ __forceinline__ double rho_of(const CaseDev& C, double phi) {
+  double s = (phi - C.phi_L) * C.inv_dphi;
+  s = fmin(fmax(s, 0.0), 1.0);
+  return C.rho_L + (C.rho_H - C.rho_L) * s;
+}
+
+// Relaxation of g for a local tau_g (Eqs. 34-36), in double. Returns the
+// equilibrium weight b and tau: cell (Eq. 29) b = 3h/(2tau+dt), face (Eq. 28)
+// b = h/(2tau+h); the source weight is tau b in both, and the weight of the
+// distribution itself is 1 - b, which the kernels use in the increment form
+// psi + b (psi^eq + tau S - psi).
+template <bool FACE>
+__device__ __forceinline__ void g_relax(const CaseDev& C, double phi, double rho,
+                                        double& b, double& tau) {
+  if (C.visc_mode == kViscUniformNu) {
+    tau = C.tau_g_uniform;
+    b = FACE ? C.gfb : C.gb;
+    return;
+  }
+  double s = (phi - C.phi_L) * C.inv_dphi;
+  s = fmin(fmax(s, 0.0), 1.0);
+  double mu = (C.visc_mode == kViscReciprocal)
+                  ? 1.0 / (s * C.inv_mu_H + (1.0 - s) * C.inv_mu_L)
+                  : s * C.mu_H + (1.0 - s) * C.mu_L;
+  tau = 3.0 * mu / rho;
+  b = FACE ? C.h / (2.0 * tau + C.h) : 3.0 * C.h / (2.0 * tau + C.dt);
+}
+
+// Unit normal n = grad phi / sqrt(|grad phi|^2 + eps^2): zero for a uniform
+// field, the plain unit vector wherever |grad phi| >> eps.
+template <typename T>
+__device__ __forceinline__ void normal(const CaseDev& C, T gx, T gy, T& nx, T& ny) {
+  const T inv = rsqrt_t(gx * gx + gy * gy + T(C.eps_n2));
+  nx = gx * inv;
+  ny = gy * inv;
+}
+
+// Prescribed velocity of the interface-only tests (Eqs. 40-43).
+template <typename T>
+__device__ __forceinline__ void presc_vel(const CaseDev& C, double x, double y,
+                                          double t, T& u, T& v) {
+  const double pi = 3.14159265358979323846;
+  double U0 = C.U0, L0 = C.L0;
+  switch (C.vel_kind) {
+    case kVelUniform: u = T(U0); v = T(U0); break;
+    case kVelRotation:
+      u = T(-U0 * pi / L0 * (y - 0.5 * L0));
+      v = T(U0 * pi / L0 * (x - 0.5 * L0));
+      break;
+    case kVelShear: {
+      double sg = (t < 0.5 * C.T_period) ? 1.0 : -1.0;
+      u = T(sg * U0 * pi * sin(pi * x / L0) * cos(pi * y / L0));
+      v = T(-sg * U0 * pi * cos(pi * x / L0) * sin(pi * y / L0));
+      break;
+    }
+    default: {
+      double c = cos(pi * t / C.T_period);
+      u = T(-U0 * sin(4.0 * pi * x / L0) * sin(4.0 * pi * y / L0) * c);
+      v = T(-U0 * cos(4.0 * pi * x / L0) * cos(4.0 * pi * y / L0) * c);
+    }
+  }
+}
+
+// ------------------------------------------------------------- cell stage
+
+template <typename T>
+struct Cell {
+  T fb[9], gb[9];  // bar-plus, Eq. 29
+  T gx, gy, mu, Dx, Dy;  // inputs averaged onto faces
+  T phi, p;              // for wall faces
+  T hx, hy;              // phi u at t_n (history of the next step)
+  // moments of bar-plus: f: sum, sum e_x, sum e_y;
+  // g: sum over q != 0, sum e_x, sum e_y, sum e_x^2, sum e_x e_y, sum e_y^2
+  T M0, Mx, My, N0, Jx, Jy, Pxx, Pxy, Pyy;
+};
+
+// Cell macros at t_n (Eqs. 31-33, 4, 6, 10), equilibria and sources
+// (Eqs. 15-19), bar-plus (Eq. 29) and tilde-plus (Eq. 30). ph[r][c] is phi on
+// rows (r-1, r, r+1) and columns (left, own, right). The tilde-plus values go
+// to `tp` (18 values, f then g).
+template <typename T, bool CPL>
+__device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3],
+                                           const T (&ft)[9], const T (&gt)[9],
+                                           T hist_x, T hist_y, double xc, double yc,
+                                           double tn, Cell<T>& o, T (&tp)[18]) {
+  const T c = ph[1][1];
+  const T E = ph[1][2], Wv = ph[1][0], N = ph[2][1], S = ph[0][1];
+  const T NE = ph[2][2], NW = ph[2][0], SE = ph[0][2], SW = ph[0][0];
+  // R8/R9: isotropic gradient and nine-point Laplacian
+  const T gx = (T(4) * (E - Wv) + (NE - NW) + (SE - SW)) * T(1.0 / 12.0);
+  const T gy = (T(4) * (N - S) + (NE - SE) + (NW - SW)) * T(1.0 / 12.0);
+  // differences first: near equilibrium mu_phi is a small residual of two
+  // O(beta) terms, so the Laplacian must not lose the ulps of phi
+  const T lap = T(2.0 / 3.0) * (((E - c) + (Wv - c)) + ((N - c) + (S - c))) +
+                T(1.0 / 6.0) * (((NE - c) + (NW - c)) + ((SE - c) + (SW - c)));
+  const T phi = c;
+  const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
+  const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;  // Eq. 4
+  const T theta = T(C.theta_c) * dA * dB;                                            // Eq. 6
+  T nxv, nyv;
+  normal<T>(C, gx, gy, nxv, nyv);
+  const T dt = T(C.dt);
+
+  T u, v, p = T(0);
+  double rhoD = rho_of(C, (double)phi);
+  if (CPL) {
+    const T rho = T(rhoD);
+    const T irho = T(inv_rho<T>(rhoD));
+    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
+    const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
+    const T mx = (gt[1] + gt[2] + gt[8]) - (gt[4] + gt[5] + gt[6]);
+    const T my = (gt[2] + gt[3] + gt[4]) - (gt[6] + gt[7] + gt[8]);
+    const T m0 = ((gt[1] + gt[2]) + (gt[3] + gt[4])) + ((gt[5] + gt[6]) + (gt[7] + gt[8]));
+    u = (mx + T(0.5) * dt * Fx) * irho;  // Eq. 32
+    v = (my + T(0.5) * dt * Fy) * irho;
+    const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
+    const T uu = u * u + v * v;
+    p = T(0.6) * m0 + T(0.3) * dt * (u * drx + v * dry) - T(0.4) * rho * uu;  // Eq. 33
+    // g: equilibrium (Eq. 17) and source (Eq. 19), bar-plus and tilde-plus
+    double gbD, tauD;
+    g_relax<false>(C, (double)phi, rhoD, gbD, tauD);
+    const T gb = T(gbD), tau = T(tauD);
+    const T a0 = u * drx + v * dry, b0 = u * Fx + v * Fy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const T e = T(EX[q]) * u + T(EY[q]) * v;
+      const T Gh = e * (T(3) + T(4.5) * e) - T(1.5) * uu;  // (Gamma_q(u) - w_q) / w_q
+      const T aq = T(EX[q]) * drx + T(EY[q]) * dry;
+      const T bq = T(EX[q]) * Fx + T(EY[q]) * Fy;
+      const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
+      T geq = wq<T>(q) * (T(3) * p + rho * Gh);
+      if (q == 0) geq -= T(3) * p;
+      // Eq. 29-30 as increments: bar+ = g + d, tilde+ = g + (4/3) d
+      const T d = gb * (geq + tau * Sg - gt[q]);
+      o.gb[q] = gt[q] + d;
+      tp[9 + q] = gt[q] + T(4.0 / 3.0) * d;
+    }
+  } else {
+    presc_vel<T>(C, xc, yc, tn, u, v);
+  }
+  // f: equilibrium (Eq. 15) and source (Eq. 16) with D = d_t(phi u) (R10)
+  const T hx = phi * u, hy = phi * v;
+  const T Dx = (hx - hist_x) * T(1.0 / C.dt), Dy = (hy - hist_y) * T(1.0 / C.dt);
+  {
+    // f^eq + tau_f S^f = w (phi + xi . V) with V = 3 phi u + tau_f (theta n + 3 D)
+    const T fbc = T(C.fb), tauf = T(C.tau_f);
+    const T Vx = T(3) * phi * u + tauf * (theta * nxv + T(3) * Dx);
+    const T Vy = T(3) * phi * v + tauf * (theta * nyv + T(3) * Dy);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const T d = fbc * (wq<T>(q) * (phi + (T(EX[q]) * Vx + T(EY[q]) * Vy)) - ft[q]);
+      o.fb[q] = ft[q] + d;
+      tp[q] = ft[q] + T(4.0 / 3.0) * d;
+    }
+  }
+  o.gx = gx; o.gy = gy; o.mu = mu; o.Dx = Dx; o.Dy = Dy;
+  o.phi = phi; o.p = p; o.hx = hx; o.hy = hy;
+  // moments of bar-plus
+  const T* f = o.fb;
+  o.M0 = (f[0] + ((f[1] + f[2]) + (f[3] + f[4]))) + ((f[5] + f[6]) + (f[7] + f[8]));
+  o.Mx = (f[1] + f[2] + f[8]) - (f[4] + f[5] + f[6]);
+  o.My = (f[2] + f[3] + f[4]) - (f[6] + f[7] + f[8]);
+  if (CPL) {
+    const T* g = o.gb;
+    o.N0 = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
+    o.Jx = (g[1] + g[2] + g[8]) - (g[4] + g[5] + g[6]);
+    o.Jy = (g[2] + g[3] + g[4]) - (g[6] + g[7] + g[8]);
+    const T dg = (g[2] + g[4]) + (g[6] + g[8]);
+    o.Pxx = (g[1] + g[5]) + dg;
+    o.Pyy = (g[3] + g[7]) + dg;
+    o.Pxy = (g[2] - g[4]) + (g[6] - g[8]);
+  }
+}
+
+// ------------------------------------------------------- face distribution
+
+// Face macros (R5, R6; Eqs. 31-33 with dt/2 -> h/2) and face original
+// distributions (Eq. 28) for the populations crossing a face of normal DIR
+// (0: x, 1: y). fbar/gbar hold the reconstructed bar values.
+template <typename T, bool CPL, int DIR>
+__device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, T Jyf,
+                                        T gxf, T gyf, T muf, T Dxf, T Dyf,
+                                        const T (&fbar)[9], const T (&gbar)[9],
+                                        double xf, double yf, double tf,
+                                        T (&fo)[9], T (&go)[9]) {
+  const T h = T(C.h);
+  const T theta = T(C.theta_c) * (phif - T(C.phi_H)) * (phif - T(C.phi_L));
+  T nxv, nyv;
+  normal<T>(C, gxf, gyf, nxv, nyv);
+  T u, v;
+  if (CPL) {
+    const double rhoD = rho_of(C, (double)phif);
+    const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
+    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T Fx = muf * gxf + (T(C.Gx) + rg * T(C.gx));
+    const T Fy = muf * gyf + (T(C.Gy) + rg * T(C.gy));
+    u = (Jxf + T(0.5) * h * Fx) * irho;
+    v = (Jyf + T(0.5) * h * Fy) * irho;
+    const T drx = T(C.drho) * gxf, dry = T(C.drho) * gyf;
+    const T uu = u * u + v * v;
+    const T p = T(0.6) * N0f + T(0.3) * h * (u * drx + v * dry) - T(0.4) * rho * uu;
+    double gbD, tauD;
+    g_relax<true>(C, (double)phif, rhoD, gbD, tauD);
+    const T gb = T(gbD), tau = T(tauD);
+    const T a0 = u * drx + v * dry, b0 = u * Fx + v * Fy;
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if ((DIR == 0 ? EX[q] : EY[q]) == 0) continue;
+      const T e = T(EX[q]) * u + T(EY[q]) * v;
+      const T Gh = e * (T(3) + T(4.5) * e) - T(1.5) * uu;
+      const T aq = T(EX[q]) * drx + T(EY[q]) * dry;
+      const T bq = T(EX[q]) * Fx + T(EY[q]) * Fy;
+      const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
+      const T geq = wq<T>(q) * (T(3) * p + rho * Gh);
+      go[q] = gbar[q] + gb * (geq + tau * Sg - gbar[q]);  // Eq. 28, increment form
+    }
+  } else {
+    presc_vel<T>(C, xf, yf, tf, u, v);
+  }
+  const T fbc = T(C.ffb), tauf = T(C.tau_f);
+  const T Vx = T(3) * phif * u + tauf * (theta * nxv + T(3) * Dxf);
+  const T Vy = T(3) * phif * v + tauf * (theta * nyv + T(3) * Dyf);
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    if ((DIR == 0 ? EX[q] : EY[q]) == 0) continue;
+    fo[q] = fbar[q] + fbc * (wq<T>(q) * (phif + (T(EX[q]) * Vx + T(EY[q]) * Vy)) - fbar[q]);
+  }
+}
+
+// No-slip wall on the face below row 0 (BOTTOM) or above row ny-1 (R15).
+// `c` is the adjacent cell, `cn` the next cell inward, txf/txg the x central
+// differences of the adjacent cell's bar-plus values (diagonal populations).
+template <typename T, bool BOTTOM>
+__device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
+                                          const Cell<T>& cn, const T (&txf)[9],
+                                          const T (&txg)[9], T (&fo)[9], T (&go)[9]) {
+  const T h = T(C.h);
+  const T dyw = BOTTOM ? T(-0.5) : T(0.5);
+  const T phiw = c.phi;
+  const double rhoD = rho_of(C, (double)phiw);
+  const T theta = T(C.theta_c) * (phiw - T(C.phi_H)) * (phiw - T(C.phi_L));
+  const T gxw = c.gx;
+  T nxv, nyv;
+  normal<T>(C, gxw, T(0), nxv, nyv);
+  const T rg = C.grav_form ? T(rhoD - C.rho_mean) : T(rhoD);
+  const T Fx = c.mu * gxw + (T(C.Gx) + rg * T(C.gx));
+  const T Fy = T(C.Gy) + rg * T(C.gy);
+  double gbD, tauD;
+  g_relax<true>(C, (double)phiw, rhoD, gbD, tauD);
+  const T gb = T(gbD), tau = T(tauD);
+  const T fbc = T(C.ffb), tauf = T(C.tau_f);
+  const T Vx = tauf * (theta * nxv + T(3) * c.Dx);
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const bool out = BOTTOM ? (EY[q] < 0) : (EY[q] > 0);
+    if (!out) continue;
+    const T dx = -h * T(EX[q]), dy = dyw - h * T(EY[q]);
+    const T sgn = BOTTOM ? T(1) : T(-1);
+    const T syf = sgn * (cn.fb[q] - c.fb[q]);
+    const T syg = sgn * (cn.gb[q] - c.gb[q]);
+    T fbar = c.fb[q] + dy * syf;
+    T gbar = c.gb[q] + dy * syg;
+    if (EX[q] != 0) {
+      fbar += dx * T(0.5) * txf[q];
+      gbar += dx * T(0.5) * txg[q];
+    }
+    // u = 0: f^eq = w phi, S^f = w e_x (theta n_x + 3 D_x); g^eq = 3 w p,
+    // S^g = 3 w (e . F)
+    const T fval = fbar + fbc * (wq<T>(q) * (phiw + T(EX[q]) * Vx) - fbar);
+    const T bq = T(EX[q]) * Fx + T(EY[q]) * Fy;
+    const T gval = gbar + gb * (wq<T>(q) * T(3) * (c.p + tau * bq) - gbar);
+    const int qo = ((q + 3) % 8) + 1;  // opposite direction: bounce-back
+    fo[q] = fval; go[q] = gval;
+    fo[qo] = fval; go[qo] = gval;
+  }
+}
+
+// ----------------------------------------------------------- step kernel
+
+template <typename T, bool CPL>
+struct RowData {
+  Cell<T> cell;
+  T txf[9], txg[9];  // x central differences (diagonal pops)
+  T txMx, txJx, txPxx, txPxy;
+};
+
+template <typename T, bool CPL>
+__device__ __forceinline__ void x_diffs(int aL, int aR, RowData<T, CPL>& r) {
+  const int diag[4] = {2, 4, 6, 8};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int q = diag[k];
+    r.txf[q] = perm(aR, r.cell.fb[q]) - perm(aL, r.cell.fb[q]);
+    if (CPL) r.txg[q] = perm(aR, r.cell.gb[q]) - perm(aL, r.cell.gb[q]);
+  }
+  r.txMx = perm(aR, r.cell.Mx) - perm(aL, r.cell.Mx);
+  if (CPL) {
+    r.txJx = perm(aR, r.cell.Jx) - perm(aL, r.cell.Jx);
+    r.txPxx = perm(aR, r.cell.Pxx) - perm(aL, r.cell.Pxx);
+    r.txPxy = perm(aR, r.cell.Pxy) - perm(aL, r.cell.Pxy);
+  }
+}
+
+// y-face between row D (below) and row U (above), own column.
+template <typename T, bool CPL>
+__device__ __forceinline__ void y_face(const CaseDev& C, const RowData<T, CPL>& D,
+                                       const RowData<T, CPL>& U, double xf, double yf,
+                                       double tf, T (&fo)[9], T (&go)[9]) {
+  const T h = T(C.h), hq = T(0.25) * T(C.h);
+  T fbar[9], gbar[9];
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    if (EY[q] == 0) continue;
+    const T ey = T(EY[q]), ex = T(EX[q]);
+    T vf = T(0.5) * (D.cell.fb[q] + U.cell.fb[q]) - h * ey * (U.cell.fb[q] - D.cell.fb[q]);
+    if (EX[q] != 0) vf -= hq * ex * (D.txf[q] + U.txf[q]);
+    fbar[q] = vf;
+    if (CPL) {
+      T vg = T(0.5) * (D.cell.gb[q] + U.cell.gb[q]) - h * ey * (U.cell.gb[q] - D.cell.gb[q]);
+      if (EX[q] != 0) vg -= hq * ex * (D.txg[q] + U.txg[q]);
+      gbar[q] = vg;
+    }
+  }
+  const Cell<T>& a = D.cell;
+  const Cell<T>& b = U.cell;
+  const T phif = T(0.5) * (a.M0 + b.M0) - h * (b.My - a.My) - hq * (D.txMx + U.txMx);
+  T N0f = T(0), Jxf = T(0), Jyf = T(0);
+  if (CPL) {
+    N0f = T(0.5) * (a.N0 + b.N0) - h * (b.Jy - a.Jy) - hq * (D.txJx + U.txJx);
+    Jxf = T(0.5) * (a.Jx + b.Jx) - h * (b.Pxy - a.Pxy) - hq * (D.txPxx + U.txPxx);
+    Jyf = T(0.5) * (a.Jy + b.Jy) - h * (b.Pyy - a.Pyy) - hq * (D.txPxy + U.txPxy);
+  }
+  face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, T(0.5) * (a.gx + b.gx), T(0.5) * (a.gy + b.gy),
+                     T(0.5) * (a.mu + b.mu), T(0.5) * (a.Dx + b.Dx), T(0.5) * (a.Dy + b.Dy),
+                     fbar, gbar, xf, yf, tf, fo, go);
+}
+
+template <typename T, bool CPL>
+__global__ __launch_bounds__(64) void k_step(StepArgs A) {
+  const int nb = gridDim.x;
+  const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (idx >= A.nitems) return;
+  const Item it = A.items[idx];
+  const CaseDev& C = A.cases[it.c];
+  const long long n = *A.step_base + A.kofs - C.step0;
+  if (n < 0 || n >= C.nsteps) return;
+
+  const int lane = threadIdx.x;
+  const int nx = C.nx, ny = C.ny, walls = C.walls;
+  const int i0 = it.strip * kStripCols;
+  const int col = i0 - 1 + lane;
+  const int ci = wrap(col, nx);
+  const int cx = lane == 0 ? wrap(col - 1, nx) : (lane == 63 ? wrap(col + 1, nx) : ci);
+  const bool store = lane >= 1 && lane <= kStripCols && col < nx;
+  const int aL = ((lane + 63) & 63) << 2, aR = ((lane + 1) & 63) << 2;
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  const T* __restrict__ in = static_cast<const T*>(C.set[cur]);
+  T* __restrict__ out = static_cast<T*>(C.set[cur ^ 1]);
+  const long long P = C.plane;
+  const T* __restrict__ phiP = in + plane_phi(CPL) * P;
+  const double tn = C.t0 + (double)n * C.dt;
+  const double xc = (double)ci + 0.5;  // wrapped: halo lanes see their true cell
+  const int j0 = it.seg * C.seg_rows;
+  const int j1 = min(j0 + C.seg_rows, ny);
+
+  __shared__ T stash[2][18][64];
+
+  // phi of one row for the own column and its two neighbours
+  auto phi_row = [&](int r, T (&o)[3]) {
+    const long long base = (long long)row_of(r, ny, walls) * nx;
+    const T own = phiP[base + ci];
+    const T ext = phiP[base + cx];
+    T left = perm(aL, own), right = perm(aR, own);
+    if (lane == 0) left = ext;
+    if (lane == 63) right = ext;
+    o[0] = left; o[1] = own; o[2] = right;
+  };
+  auto stage = [&](int r, const T (&pm)[3], const T (&p0)[3], const T (&pp)[3],
+                   RowData<T, CPL>& rd) {
+    const long long base = (long long)row_of(r, ny, walls) * nx + ci;
+    T ft[9], gt[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ft[q] = in[plane_f(q) * P + base];
+    if (CPL) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) gt[q] = in[plane_g(q) * P + base];
+    }
+    const T hx = in[plane_hist(CPL, 0) * P + base];
+    const T hy = in[plane_hist(CPL, 1) * P + base];
+    T ph[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { ph[0][k] = pm[k]; ph[1][k] = p0[k]; ph[2][k] = pp[k]; }
+    T tp[18];
+    cell_stage<T, CPL>(C, ph, ft, gt, hx, hy, xc, (double)row_of(r, ny, walls) + 0.5, tn,
+                       rd.cell, tp);
+    const int slot = r & 1;
+#pragma unroll
+    for (int q = 0; q < 18; ++q) stash[slot][q][lane] = tp[q];
+    x_diffs<T, CPL>(aL, aR, rd);
+  };
+
+  // The loop runs from k = j0 - 2: the first two passes only stage rows
+  // j0 - 1 and j0 and form the south face of row j0, so that every row goes
+  // through the same code (bitwise identical results for any segmentation).
+  T pa[3], pb[3], pc[3];  // phi rows k, k+1, k+2 at the top of iteration k
+  RowData<T, CPL> prv, cur_r, nxt;
+  T fs_f[9], fs_g[9];  // face distributions of the south face of row k
+  phi_row(j0 - 2, pa);
+  phi_row(j0 - 1, pb);
+
+  for (int k = j0 - 2; k < j1; ++k) {
+    const int rs = k + 1;  // row staged in this pass
+    const bool top_wall = walls && k == ny - 1;
+    const bool bot_wall = walls && k == 0;
+    // the phi ring advances every pass (ghost rows mirror into the grid), the
+    // cell stage runs only for rows that exist
+    phi_row(rs + 1, pc);
+    if (!(walls && (rs < 0 || rs >= ny))) stage(rs, pa, pb, pc, nxt);
+    // y-face between rows k and k+1 (the north face of row k)
+    T fn_f[9], fn_g[9];
+    const bool yface = k >= j0 - 1 && !(walls && (k < 0 || k >= ny - 1));
+    if (yface) {
+      const int kr = row_of(k, ny, walls);
+      y_face<T, CPL>(C, cur_r, nxt, xc, (double)kr + 1.0, tn + C.h, fn_f, fn_g);
+    }
+    if (k >= j0) {
+      // tangential (y) differences at row k for the x-face
+      T tyf[9], tyg[9], tyMy, tyJy, tyPxy, tyPyy;
+      {
+        const int diag[4] = {2, 4, 6, 8};
+        // one-sided next to a wall: 2 (next - cur) or 2 (cur - prev)
+        const RowData<T, CPL>& up = top_wall ? cur_r : nxt;
+        const RowData<T, CPL>& dn = bot_wall ? cur_r : prv;
+        const T sc = (top_wall || bot_wall) ? T(2) : T(1);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int q = diag[m];
+          tyf[q] = sc * (up.cell.fb[q] - dn.cell.fb[q]);
+          if (CPL) tyg[q] = sc * (up.cell.gb[q] - dn.cell.gb[q]);
+        }
+        tyMy = sc * (up.cell.My - dn.cell.My);
+        tyJy = sc * (up.cell.Jy - dn.cell.Jy);
+        tyPxy = sc * (up.cell.Pxy - dn.cell.Pxy);
+        tyPyy = sc * (up.cell.Pyy - dn.cell.Pyy);
+      }
+      // x-face east of the own cell: L = own lane, R = lane + 1
+      T fx_f[9], fx_g[9];
+      {
+        const Cell<T>& L = cur_r.cell;
+        const T h = T(C.h), hq = T(0.25) * T(C.h);
+        T fbar[9], gbar[9];
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+          if (EX[q] == 0) continue;
+          const T ex = T(EX[q]), ey = T(EY[q]);
+          const T Rf = perm(aR, L.fb[q]);
+          T vf = T(0.5) * (L.fb[q] + Rf) - h * ex * (Rf - L.fb[q]);
+          if (EY[q] != 0) vf -= hq * ey * (tyf[q] + perm(aR, tyf[q]));
+          fbar[q] = vf;
+          if (CPL) {
+            const T Rg = perm(aR, L.gb[q]);
+            T vg = T(0.5) * (L.gb[q] + Rg) - h * ex * (Rg - L.gb[q]);
+            if (EY[q] != 0) vg -= hq * ey * (tyg[q] + perm(aR, tyg[q]));
+            gbar[q] = vg;
+          }
+        }
+        const T phif = T(0.5) * (L.M0 + perm(aR, L.M0)) - h * (perm(aR, L.Mx) - L.Mx) -
+                       hq * (tyMy + perm(aR, tyMy));
+        T N0f = T(0), Jxf = T(0), Jyf = T(0);
+        if (CPL) {
+          N0f = T(0.5) * (L.N0 + perm(aR, L.N0)) - h * (perm(aR, L.Jx) - L.Jx) -
+                hq * (tyJy + perm(aR, tyJy));
+          Jxf = T(0.5) * (L.Jx + perm(aR, L.Jx)) - h * (perm(aR, L.Pxx) - L.Pxx) -
+                hq * (tyPxy + perm(aR, tyPxy));
+          Jyf = T(0.5) * (L.Jy + perm(aR, L.Jy)) - h * (perm(aR, L.Pxy) - L.Pxy) -
+                hq * (tyPyy + perm(aR, tyPyy));
+        }
+        const T gxf = T(0.5) * (L.gx + perm(aR, L.gx));
+        const T gyf = T(0.5) * (L.gy + perm(aR, L.gy));
+        const T muf = T(0.5) * (L.mu + perm(aR, L.mu));
+        const T Dxf = T(0.5) * (L.Dx + perm(aR, L.Dx));
+        const T Dyf = T(0.5) * (L.Dy + perm(aR, L.Dy));
+        const int kr = row_of(k, ny, walls);
+        face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
+                           (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
+      }
+      if (top_wall) wall_face<T, false>(C, cur_r.cell, prv.cell, cur_r.txf, cur_r.txg, fn_f, fn_g);
+      if (bot_wall) wall_face<T, true>(C, cur_r.cell, nxt.cell, cur_r.txf, cur_r.txg, fs_f, fs_g);
+      // update (Eq. 24) and store
+      {
+        const int kr = row_of(k, ny, walls);
+        const long long base = (long long)kr * nx + ci;
+        const int slot = k & 1;
+        const T dt = T(C.dt);
+        T phin = T(0);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          T J = T(0);
+          if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - perm(aL, fx_f[q]));
+          if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
+          const T val = stash[slot][q][lane] - dt * J;
+          phin += val;
+          if (store) out[plane_f(q) * P + base] = val;
+        }
+        if (CPL) {
+#pragma unroll
+          for (int q = 0; q < 9; ++q) {
+            T J = T(0);
+            if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - perm(aL, fx_g[q]));
+            if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
+            const T val = stash[slot][9 + q][lane] - dt * J;
+            if (store) out[plane_g(q) * P + base] = val;
+          }
+        }
+        if (store) {
+          out[plane_hist(CPL, 0) * P + base] = cur_r.cell.hx;
+          out[plane_hist(CPL, 1) * P + base] = cur_r.cell.hy;
+          out[plane_phi(CPL) * P + base] = phin;
+        }
+      }
+    }
+    // rotate
+#pragma unroll
+    for (int q = 0; q < 9; ++q) { fs_f[q] = fn_f[q]; fs_g[q] = fn_g[q]; }
+    prv = cur_r;
+    cur_r = nxt;
+    pa[0] = pb[0]; pa[1] = pb[1]; pa[2] = pb[2];
+    pb[0] = pc[0]; pb[1] = pc[1]; pb[2] = pc[2];
+  }
+}
+
+__global__ void k_advance(long long* step_base, long long by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) step_base[0] += by;
+}
+
+// ------------------------------------------------------------ init / macros
+
+// phi on the 3x3 neighbourhood of cell (i, j) from a row-major field.
+template <typename S, typename T>
+__device__ __forceinline__ void gather3x3(const S* __restrict__ f, int i, int j, int nx,
+                                          int ny, int walls, T (&ph)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int r = row_of(j + a - 1, ny, walls);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) ph[a][b] = T(f[(long long)r * nx + wrap(i + b - 1, nx)]);
+  }
+}
+
+// Initial state (R11): tilde = psi^eq - (dt/2) S with d_t(phi u) = 0, from
+// the macros phi, u, v, p (double, [ny][nx]); hist = phi u; phi plane.
+template <typename T, bool CPL>
+__global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __restrict__ phi0,
+                       const double* __restrict__ u0, const double* __restrict__ v0,
+                       const double* __restrict__ p0) {
+  const CaseDev& C = *Cd;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= C.nx || j >= C.ny) return;
+  const long long c = (long long)j * C.nx + i, P = C.plane;
+  T* __restrict__ st = static_cast<T*>(C.set[buf]);
+  T ph[3][3];
+  gather3x3<double, T>(phi0, i, j, C.nx, C.ny, C.walls, ph);
+  const T gx = (T(4) * (ph[1][2] - ph[1][0]) + (ph[2][2] - ph[2][0]) + (ph[0][2] - ph[0][0])) * T(1.0 / 12.0);
+  const T gy = (T(4) * (ph[2][1] - ph[0][1]) + (ph[2][2] - ph[0][2]) + (ph[2][0] - ph[0][0])) * T(1.0 / 12.0);
+  const T cc = ph[1][1];
+  const T lap = T(2.0 / 3.0) * (((ph[1][2] - cc) + (ph[1][0] - cc)) + ((ph[2][1] - cc) + (ph[0][1] - cc))) +
+                T(1.0 / 6.0) * (((ph[2][2] - cc) + (ph[2][0] - cc)) + ((ph[0][2] - cc) + (ph[0][0] - cc)));
+  const T phi = cc;
+  const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
+  const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
+  const T theta = T(C.theta_c) * dA * dB;
+  T nxv, nyv;
+  normal<T>(C, gx, gy, nxv, nyv);
+  const T hdt = T(0.5 * C.dt);
+  T u, v;
+  if (CPL) {
+    u = u0 ? T(u0[c]) : T(0);
+    v = v0 ? T(v0[c]) : T(0);
+    const T p = p0 ? T(p0[c]) : T(0);
+    const double rhoD = rho_of(C, (double)phi);
+    const T rho = T(rhoD);
+    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
+    const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
+    const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
+    const T uu = u * u + v * v;
+    const T a0 = u * drx + v * dry, b0 = u * Fx + v * Fy;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const T e = T(EX[q]) * u + T(EY[q]) * v;
+      const T Gh = e * (T(3) + T(4.5) * e) - T(1.5) * uu;
+      const T aq = T(EX[q]) * drx + T(EY[q]) * dry;
+      const T bq = T(EX[q]) * Fx + T(EY[q]) * Fy;
+      const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
+      T geq = wq<T>(q) * (T(3) * p + rho * Gh);
+      if (q == 0) geq -= T(3) * p;
+      st[plane_g(q) * P + c] = geq - hdt * Sg;
+    }
+  } else {
+    presc_vel<T>(C, i + 0.5, j + 0.5, 0.0, u, v);
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    const T en = T(EX[q]) * nxv + T(EY[q]) * nyv;
+    const T feq = wq<T>(q) * phi * (T(1) + T(3) * (T(EX[q]) * u + T(EY[q]) * v));
+    const T Sf = wq<T>(q) * theta * en;
+    st[plane_f(q) * P + c] = feq - hdt * Sf;
+  }
+  st[plane_hist(CPL, 0) * P + c] = phi * u;
+  st[plane_hist(CPL, 1) * P + c] = phi * v;
+  // phi plane = sum of the stored f (the same sum the step kernel forms)
+  T s = T(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) s += st[plane_f(q) * P + c];
+  st[plane_phi(CPL) * P + c] = s;
+}
+
+// Cell macros of a state (Eqs. 31-33, 10) into double arrays.
+template <typename T, bool CPL>
+__global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
+                         double* __restrict__ ophi, double* __restrict__ ou,
+                         double* __restrict__ ov, double* __restrict__ op,
+                         double* __restrict__ orho) {
+  const CaseDev& C = *Cd;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= C.nx || j >= C.ny) return;
+  const long long c = (long long)j * C.nx + i, P = C.plane;
+  const T* __restrict__ st = static_cast<const T*>(C.set[buf]);
+  T ph[3][3];
+  gather3x3<T, T>(st + plane_phi(CPL) * P, i, j, C.nx, C.ny, C.walls, ph);
+  const T phi = ph[1][1];
+  const double rhoD = rho_of(C, (double)phi);
+  T u, v, p = T(0);
+  if (CPL) {
+    const T gx = (T(4) * (ph[1][2] - ph[1][0]) + (ph[2][2] - ph[2][0]) + (ph[0][2] - ph[0][0])) * T(1.0 / 12.0);
+    const T gy = (T(4) * (ph[2][1] - ph[0][1]) + (ph[2][2] - ph[0][2]) + (ph[2][0] - ph[0][0])) * T(1.0 / 12.0);
+    const T cc = ph[1][1];
+    const T lap = T(2.0 / 3.0) * (((ph[1][2] - cc) + (ph[1][0] - cc)) + ((ph[2][1] - cc) + (ph[0][1] - cc))) +
+                  T(1.0 / 6.0) * (((ph[2][2] - cc) + (ph[2][0] - cc)) + ((ph[0][2] - cc) + (ph[0][0] - cc)));
+    const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
+    const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
+    const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
+    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
+    const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
+    T g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) g[q] = st[plane_g(q) * P + c];
+    const T mx = (g[1] + g[2] + g[8]) - (g[4] + g[5] + g[6]);
+    const T my = (g[2] + g[3] + g[4]) - (g[6] + g[7] + g[8]);
+    const T m0 = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
+    const T dt = T(C.dt);
+    u = (mx + T(0.5) * dt * Fx) * irho;
+    v = (my + T(0.5) * dt * Fy) * irho;
+    const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
+    p = T(0.6) * m0 + T(0.3) * dt * (u * drx + v * dry) - T(0.4) * rho * (u * u + v * v);
+  } else {
+    presc_vel<T>(C, i + 0.5, j + 0.5, t, u, v);
+  }
+  if (ophi) ophi[c] = (double)phi;
+  if (ou) ou[c] = (double)u;
+  if (ov) ov[c] = (double)v;
+  if (op) op[c] = (double)p;
+  if (orho) orho[c] = rhoD;
+}
+
+// Diagnostics in double, in a fixed order: per-block partial sums over rows,
+// then one block folds the partials. out: sum phi, sum rho u, sum rho v,
+// sum rho |u|^2 / 2, max |u|, sum rho, #non-finite.
+constexpr int kDiagThreads = 256;
+constexpr int kDiagQ = 7;
+
+__global__ void k_diag_partial(int nx, int ny, const double* __restrict__ phi,
+                               const double* __restrict__ u, const double* __restrict__ v,
+                               const double* __restrict__ rho, double* __restrict__ part) {
+  __shared__ double sh[kDiagQ][kDiagThreads];
+  double a[kDiagQ] = {0, 0, 0, 0, 0, 0, 0};
+  const long long n = (long long)nx * ny;
+  for (long long c = (long long)blockIdx.x * kDiagThreads + threadIdx.x; c < n;
+       c += (long long)gridDim.x * kDiagThreads) {
+    const double r = rho[c], uu = u[c], vv = v[c], ph = phi[c];
+    a[0] += ph;
+    a[1] += r * uu;
+    a[2] += r * vv;
+    a[3] += 0.5 * r * (uu * uu + vv * vv);
+    a[4] = fmax(a[4], sqrt(uu * uu + vv * vv));
+    a[5] += r;
+    const bool bad = !isfinite(ph) || !isfinite(uu) || !isfinite(vv) || !isfinite(r);
+    a[6] += bad ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kDiagQ; ++k) sh[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < kDiagQ; ++k) {
+        if (k == 4) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + s]);
+        else sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kDiagQ) part[(long long)blockIdx.x * kDiagQ + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_diag_final(int nblocks, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double a[kDiagQ] = {0, 0, 0, 0, 0, 0, 0};
+  for (int b = 0; b < nblocks; ++b)
+    for (int k = 0; k < kDiagQ; ++k) {
+      const double x = part[(long long)b * kDiagQ + k];
+      if (k == 4) a[k] = fmax(a[k], x);
+      else a[k] += x;
+    }
+  for (int k = 0; k < kDiagQ; ++k) out[k] = a[k];
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- launchers
+
+hipError_t launch_step(bool fp64, bool coupled, const StepArgs& a, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  const int per = (a.nitems + 7) / 8;
+  dim3 grid(per * 8), block(kWave);
+  if (fp64) {
+    if (coupled) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<double, false>), grid, block, 0, s, a);
+  } else {
+    if (coupled) hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<float, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(long long* step_base, long long by, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, step_base, by);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(bool fp64, const CaseDev* dcase, const CaseDev& hc, const double* phi,
+                       const double* u, const double* v, const double* p, hipStream_t s) {
+  dim3 block(128), grid((hc.nx + 127) / 128, hc.ny);
+  const int buf = hc.cur0;
+  if (fp64) {
+    if (hc.coupled) hipLaunchKernelGGL((k_init<double, true>), grid, block, 0, s, dcase, buf, phi, u, v, p);
+    else hipLaunchKernelGGL((k_init<double, false>), grid, block, 0, s, dcase, buf, phi, u, v, p);
+  } else {
+    if (hc.coupled) hipLaunchKernelGGL((k_init<float, true>), grid, block, 0, s, dcase, buf, phi, u, v, p);
+    else hipLaunchKernelGGL((k_init<float, false>), grid, block, 0, s, dcase, buf, phi, u, v, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_macros(bool fp64, const CaseDev* dcase, const CaseDev& hc, long long local_step,
+                         double* phi, double* u, double* v, double* p, double* rho, hipStream_t s) {
+  dim3 block(128), grid((hc.nx + 127) / 128, hc.ny);
+  const int buf = (hc.cur0 + (int)(local_step & 1)) & 1;
+  const double t = hc.t0 + (double)local_step * hc.dt;
+  if (fp64) {
+    if (hc.coupled) hipLaunchKernelGGL((k_macros<double, true>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+    else hipLaunchKernelGGL((k_macros<double, false>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+  } else {
+    if (hc.coupled) hipLaunchKernelGGL((k_macros<float, true>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+    else hipLaunchKernelGGL((k_macros<float, false>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const CaseDev& hc, const double* phi, const double* u, const double* v,
+                       const double* rho, double* partial, int npartial, double* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_partial, dim3(npartial), dim3(kDiagThreads), 0, s, hc.nx, hc.ny, phi,
+                     u, v, rho, partial);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, npartial, partial, out);
+  return hipGetLastError();
+}
+
+}  // namespace dugks

@@ -1,0 +1,59 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+that include/dugks.h declares, and its GPU-free calls behave."""
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1810_07802_amd as D
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dugks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dugks_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared()
+    assert "dugks_create" in names and "dugks_step" in names and "dugks_destroy" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", D.build.LIB], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (dugks_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = D.lib()
+    for n in names:
+        assert hasattr(L, n)
+
+
+def test_footprint_matches_layout():
+    # coupled: 21 planes (9 f + 9 g + 2 history + phi) per state buffer, two buffers
+    n = 1000 * 700
+    fp = D.footprint_bytes(1000, 700, D.FP32, D.MODEL_COUPLED)
+    assert 2 * 21 * n * 4 <= fp < 2 * 21 * n * 4 + 4096
+    fp = D.footprint_bytes(1000, 700, D.FP64, D.MODEL_AC)
+    assert 2 * 12 * n * 8 <= fp < 2 * 12 * n * 8 + 4096
+
+
+def test_null_and_bad_arguments_do_not_crash():
+    L = D.lib()
+    assert L.dugks_destroy(None) == 0
+    assert L.dugks_step(None, 1) == D.EINVAL
+    assert L.dugks_last_error(None) is not None
+    with pytest.raises(D.DugksError) as e:
+        D.create(2, 16)
+    assert e.value.code == D.EINVAL
+    with pytest.raises(D.DugksError) as e:
+        D.create(16, 16, precision=7)
+    assert e.value.code == D.EINVAL
+
+
+def test_params_marshalling_rejects_unknown_keys():
+    with pytest.raises(KeyError):
+        D.make_params(dict(bogus=1.0))
+    p = D.make_params(dict(visc="reciprocal", walls_y=True, vel="deform", M=0.3))
+    assert p.visc_mode == 1 and p.bc_y == 1 and p.vel_kind == 3 and p.M_phi == 0.3

@@ -1,0 +1,159 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on
+generic synthetic cases, plus the GPU-side invariants (tiling, checkpoint,
+batch, diagnostics).
+
+FP64 tolerance: relative L2 norm ||gpu - oracle|| / ||oracle|| <= 1e-12 for
+every field after hundreds of steps; both sides evaluate the same double
+formulas in a different order, so the difference is accumulated rounding.
+Sizes span several 62-column strips with a ragged last strip and several row
+segments, and cover periodic and wall-bounded y. The benchmark configurations
+at full size, and the FP32 path, are in test_gpu_configs.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1810_07802_amd as D
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def run_both(case, steps, precision, seg_rows=None):
+    s = D.Solver(case["nx"], case["ny"], case["params"], case["model"], precision, seg_rows)
+    s.init(case["phi"], case["u"], case["v"], case["p"])
+    s.step(steps)
+    g = s.macros()
+    o = oracle.Sim(case["nx"], case["ny"], case["params"], case["model"])
+    o.init(case["phi"], case["u"], case["v"], case["p"])
+    o.step(steps)
+    r = o.macros()
+    return g, r, s
+
+
+def _report(tag, g, r):
+    errs = {k: rel(g[k], r[k]) for k in ("phi", "u", "v", "p")}
+    print(tag, " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    return errs
+
+
+@pytest.mark.parametrize("seg", [4, 16])
+def test_fp64_coupled_periodic(seg):
+    c = W.random_coupled(100, 40, seed=3, rho_ratio=100.0)
+    g, r, _ = run_both(c, 300, "fp64", seg)
+    e = _report(f"fp64 periodic seg={seg}", g, r)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+def test_fp64_coupled_walls():
+    c = W.random_coupled(70, 36, seed=4, rho_ratio=10.0, walls_y=True)
+    g, r, _ = run_both(c, 300, "fp64", 8)
+    e = _report("fp64 walls", g, r)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+@pytest.mark.parametrize("vel", ["uniform", "rotation", "shear", "deform"])
+def test_fp64_interface_only(vel):
+    c = W.smoothed_deformation(L0=96, Pe=96, M=0.02)
+    c["params"] = dict(c["params"], vel=vel, T_period=400.0, U0=0.02)
+    g, r, _ = run_both(c, 400, "fp64", 16)
+    e = _report(f"fp64 ac {vel}", g, r)
+    assert e["phi"] < 1e-12
+    assert e["u"] < 1e-14 and e["v"] < 1e-14
+
+
+def test_fp64_density_ratio_1000_driven_flow():
+    """A well-conditioned flow (|u| ~ 1e-2) across a 1000:1 interface."""
+    c = W.random_coupled(100, 40, seed=5, rho_ratio=1000.0, U=0.01)
+    g, r, _ = run_both(c, 100, "fp64", 8)
+    e = _report("fp64 ratio1000", g, r)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+def test_tiling_does_not_change_bits():
+    c = W.random_coupled(130, 50, seed=7, rho_ratio=50.0)
+    states = []
+    for seg in (2, 7, 64):
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32", seg)
+        s.init(c["phi"], c["u"], c["v"])
+        s.step(50)
+        states.append(s.get_state()[0])
+    assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_checkpoint_resume_bitwise(prec):
+    c = W.random_coupled(70, 36, seed=8, rho_ratio=10.0, walls_y=True)
+    a = D.Solver(c["nx"], c["ny"], c["params"], "coupled", prec)
+    a.init(c["phi"])
+    a.step(31)
+    buf, st = a.get_state()
+    a.step(30)
+    b = D.Solver(c["nx"], c["ny"], c["params"], "coupled", prec)
+    b.set_state(buf, st)
+    b.step(30)
+    assert b.steps_done == a.steps_done == 61
+    assert np.array_equal(a.get_state()[0], b.get_state()[0])
+
+
+def test_batch_matches_single_cases_bitwise():
+    cases = [W.spinodal(L=L, seed=10 + k, steps=0) for k, L in enumerate((64, 100, 37))]
+    alone, solvers = [], []
+    for c in cases:
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        s.init(c["phi"])
+        s.step(40)
+        alone.append(s.get_state()[0])
+        t = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        t.init(c["phi"])
+        solvers.append(t)
+    import torch
+    stream = torch.cuda.Stream()
+    b = D.Batch(solvers)
+    b.set_stream(stream.cuda_stream)
+    b.step(15, use_graph=False)
+    b.step(25, use_graph=True)
+    b.sync()
+    for k, s in enumerate(solvers):
+        assert s.steps_done == 40
+        assert np.array_equal(s.get_state()[0], alone[k]), k
+
+
+def test_batch_budget_stops_a_case():
+    cases = [W.spinodal(L=48, seed=20 + k, steps=0) for k in range(2)]
+    solvers = []
+    for c in cases:
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        s.init(c["phi"])
+        solvers.append(s)
+    ref = D.Solver(cases[1]["nx"], cases[1]["ny"], cases[1]["params"], "coupled", "fp32")
+    ref.init(cases[1]["phi"])
+    ref.step(7)
+    b = D.Batch(solvers)
+    b.set_budget(1, 7)
+    b.step(20)
+    b.sync()
+    assert solvers[0].steps_done == 20 and solvers[1].steps_done == 7
+    assert np.array_equal(solvers[1].get_state()[0], ref.get_state()[0])
+
+
+def test_diagnostics_match_oracle_sums():
+    c = W.random_coupled(100, 40, seed=9, rho_ratio=100.0)
+    g, r, s = run_both(c, 100, "fp64")
+    d = s.diagnostics()
+    assert d["status"] == 0 and d["nonfinite"] == 0
+    assert d["sum_phi"] == pytest.approx(r["phi"].sum(), rel=1e-12)
+    # the momentum sums cancel; compare against the sum of magnitudes
+    scale_u = np.abs(r["rho"] * r["u"]).sum()
+    assert abs(d["sum_rho_u"] - (r["rho"] * r["u"]).sum()) < 1e-12 * scale_u
+    assert d["sum_rho"] == pytest.approx(r["rho"].sum(), rel=1e-12)
+    assert d["max_u"] == pytest.approx(np.hypot(r["u"], r["v"]).max(), rel=1e-10)
+    assert d["time"] == pytest.approx(100 * c["params"]["cfl"])

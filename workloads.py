@@ -248,8 +248,9 @@ def random_coupled(nx, ny, seed=0, rho_ratio=10.0, sigma=1e-3, U=0.01,
         phi = tanh_profile(Y - 0.5 * ny - wave, 4.0, 1.0, 0.0)
     else:  # a wavy band of heavy fluid, smooth across the periodic seam
         phi = tanh_profile(0.25 * ny - np.abs(Y - 0.5 * ny - wave), 4.0, 1.0, 0.0)
-    if walls_y:
-        u = v = None
+    if walls_y:  # a smooth shear flow that vanishes at the walls
+        u = smooth_field(nx, ny, seed + 1, amp=U, offset=U) * np.sin(np.pi * Y / ny)
+        v = None
     else:
         u = smooth_field(nx, ny, seed + 1, amp=U)
         v = smooth_field(nx, ny, seed + 2, amp=U)
