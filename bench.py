@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--skip-extra", action="store_true", help="only the default workload")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="run only the timed default workload (for profilers)")
+    ap.add_argument("--profile-large", action="store_true",
+                    help="run only the timed 4096x4096 workload (for profilers)")
     return ap.parse_args()
 
 
@@ -130,6 +132,16 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.profile_large:
+        cl = W.bubble(L=4096, R=1024, steps=0)
+        sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32")
+        sl.init(cl["phi"])
+        tl, _ = timed_graph(torch, D, [sl], args.large_steps, 5, chunk=args.large_steps)
+        ncl = cl["nx"] * cl["ny"]
+        print(json.dumps({"workload": "bubble 4096x4096 coupled FP32", "steps": args.large_steps,
+                          "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
+                          "roofline": roofline(ncl, args.large_steps, tl, "fp32")}), flush=True)
+        return
     c = W.bubble(L=128, R=32)
     cells = c["nx"] * c["ny"]
     s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")

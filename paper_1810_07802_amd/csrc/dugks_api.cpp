@@ -72,16 +72,26 @@ int hip_fail(dugks_handle* h, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
   } while (0)
 
-int auto_seg_rows(int nx, int ny) {
-  const int nstrips = (nx + dugks::kStripCols - 1) / dugks::kStripCols;
-  // Longest segments that still give >= 2048 waves (8 per CU); shorter
-  // segments repeat two halo rows of cell work per segment.
-  const int cand[] = {128, 64, 32, 16, 8, 4};
-  for (int s : cand) {
-    const long long waves = (long long)nstrips * ((ny + s - 1) / s);
-    if (waves >= 2048) return s;
+// Resident step waves on the current device (CUs x waves per CU).
+int wave_capacity(bool fp64, bool coupled, bool walls) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 2048;
   }
-  return 2;
+  return prop.multiProcessorCount * dugks::step_waves_per_cu(fp64, coupled, walls);
+}
+
+// Rows per segment so that `strip_rows` rows of strips (sum over cases of
+// strips x rows) make about one generation of resident waves: every wave
+// then starts at once and none is left to run alone at the end. Segments
+// are at least 2 rows (each segment repeats the cell work of 2 halo rows).
+int seg_rows_for(long long strip_rows, int capacity) {
+  long long s = (strip_rows + capacity - 1) / capacity;
+  if (s < 2) s = 2;
+  if (s > 4096) s = 4096;
+  return (int)s;
 }
 
 // Derived constants (Sec. II.B, Eqs. 3, 28-29, 34, 37) into the descriptor.
@@ -92,7 +102,11 @@ void fill_case(dugks_handle* h) {
   C.ny = h->ny;
   C.coupled = h->coupled() ? 1 : 0;
   C.nstrips = (h->nx + dugks::kStripCols - 1) / dugks::kStripCols;
-  C.seg_rows = h->seg_rows > 0 ? h->seg_rows : auto_seg_rows(h->nx, h->ny);
+  C.walls = P.bc_y == DUGKS_BC_WALLS ? 1 : 0;
+  C.seg_rows = h->seg_rows > 0
+                   ? h->seg_rows
+                   : seg_rows_for((long long)C.nstrips * h->ny,
+                                  wave_capacity(h->fp64(), h->coupled(), C.walls != 0));
   C.nsegs = (h->ny + C.seg_rows - 1) / C.seg_rows;
   C.walls = P.bc_y == DUGKS_BC_WALLS ? 1 : 0;
   C.vel_kind = P.vel_kind;
@@ -210,7 +224,7 @@ int launch_steps(dugks_handle* h, int nsteps) {
   a.step_base = h->step_base;
   for (int k = 0; k < nsteps; ++k) {
     a.kofs = k;
-    HIPCHK(h, dugks::launch_step(h->fp64(), h->coupled(), a, h->stream));
+    HIPCHK(h, dugks::launch_step(h->fp64(), h->coupled(), h->hc.walls != 0, a, h->stream));
   }
   HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
   return DUGKS_OK;
@@ -444,8 +458,9 @@ struct dugks_batch {
   bool fp64 = false, coupled = true;
   hipStream_t stream = nullptr;
   CaseDev* dcases = nullptr;
-  Item* items = nullptr;
-  int nitems = 0;
+  Item* items[2] = {nullptr, nullptr};  // work items: periodic cases, wall cases
+  int nitems[2] = {0, 0};
+  std::vector<int> seg;                 // rows per segment used for each case
   long long* step_base = nullptr;  // device: global step of the batch
   long long gstep = 0;             // host mirror
   std::vector<CaseDev> hcases;
@@ -474,6 +489,8 @@ int sync_descriptors(dugks_batch* b) {
   for (size_t k = 0; k < b->cases.size(); ++k) {
     dugks_handle* h = b->cases[k];
     CaseDev c = h->hc;
+    c.seg_rows = b->seg[k];
+    c.nsegs = (c.ny + c.seg_rows - 1) / c.seg_rows;
     c.step0 = b->gstep - h->steps;
     c.nsteps = b->budget[k] < 0 ? LLONG_MAX : h->steps + b->budget[k];
     b->hcases[k] = c;
@@ -487,12 +504,15 @@ int sync_descriptors(dugks_batch* b) {
 int record_steps(dugks_batch* b, int nsteps) {
   StepArgs a;
   a.cases = b->dcases;
-  a.items = b->items;
-  a.nitems = b->nitems;
   a.step_base = b->step_base;
   for (int k = 0; k < nsteps; ++k) {
     a.kofs = k;
-    BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, a, b->stream));
+    for (int w = 0; w < 2; ++w) {
+      if (b->nitems[w] == 0) continue;
+      a.items = b->items[w];
+      a.nitems = b->nitems[w];
+      BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, w == 1, a, b->stream));
+    }
   }
   BHIPCHK(b, dugks::launch_advance(b->step_base, nsteps, b->stream));
   return DUGKS_OK;
@@ -518,21 +538,39 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
   b->hcases.resize(n);
   b->fp64 = cases[0]->fp64();
   b->coupled = cases[0]->coupled();
-  std::vector<Item> it;
+  b->seg.assign(n, 2);
+  // one segment length per boundary group, sized to the whole group
+  long long strip_rows[2] = {0, 0};
   for (int k = 0; k < n; ++k) {
     if (upload_case(cases[k]) != DUGKS_OK) {
+      std::string m = cases[k]->err;
       dugks_batch_destroy(b);
-      return bfail(nullptr, DUGKS_EDEVICE, cases[k]->err);
+      return bfail(nullptr, DUGKS_EDEVICE, m);
     }
     const CaseDev& c = cases[k]->hc;
-    for (int s = 0; s < c.nsegs; ++s)
-      for (int x = 0; x < c.nstrips; ++x) it.push_back(Item{k, x, s, 0});
+    strip_rows[c.walls ? 1 : 0] += (long long)c.nstrips * c.ny;
   }
-  b->nitems = (int)it.size();
+  int segw[2];
+  for (int w = 0; w < 2; ++w)
+    segw[w] = seg_rows_for(strip_rows[w], wave_capacity(b->fp64, b->coupled, w == 1));
+  std::vector<Item> it[2];
+  for (int k = 0; k < n; ++k) {
+    const CaseDev& c = cases[k]->hc;
+    const int w = c.walls ? 1 : 0;
+    b->seg[k] = segw[w];
+    const int nsegs = (c.ny + segw[w] - 1) / segw[w];
+    for (int s = 0; s < nsegs; ++s)
+      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{k, x, s, 0});
+  }
   hipError_t e = hipMalloc(&b->dcases, n * sizeof(CaseDev));
-  if (e == hipSuccess) e = hipMalloc(&b->items, it.size() * sizeof(Item));
+  for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+    b->nitems[w] = (int)it[w].size();
+    if (it[w].empty()) continue;
+    e = hipMalloc(&b->items[w], it[w].size() * sizeof(Item));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->items[w], it[w].data(), it[w].size() * sizeof(Item), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMalloc(&b->step_base, sizeof(long long));
-  if (e == hipSuccess) e = hipMemcpy(b->items, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(b->step_base, 0, sizeof(long long));
   if (e != hipSuccess) {
     std::string m = std::string("batch allocation failed: ") + hipGetErrorString(e);
@@ -615,7 +653,8 @@ int dugks_batch_destroy(dugks_batch* b) {
   (void)hipStreamSynchronize(b->stream);
   for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
   if (b->dcases) (void)hipFree(b->dcases);
-  if (b->items) (void)hipFree(b->items);
+  for (int w = 0; w < 2; ++w)
+    if (b->items[w]) (void)hipFree(b->items[w]);
   if (b->step_base) (void)hipFree(b->step_base);
   delete b;
   return DUGKS_OK;

@@ -78,7 +78,8 @@ struct StepArgs {
 };
 
 // host-side launchers (dugks_kernels.hip)
-hipError_t launch_step(bool fp64, bool coupled, const StepArgs& a, hipStream_t s);
+hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
+int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);
 hipError_t launch_init(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
                        const double* phi, const double* u, const double* v,

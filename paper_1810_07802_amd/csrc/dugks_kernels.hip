@@ -156,6 +156,38 @@ __device__ __forceinline__ void presc_vel(const CaseDev& C, double x, double y,
   }
 }
 
+// ------------------------------------------- equilibria + sources, by pairs
+
+// For the g model the relaxation needs g^eq_q + tau S^g_q (Eqs. 17-19). For a
+// direction q and its opposite -q, e = xi.u, a = xi.grad rho and b = xi.F
+// change sign, so Gamma_q(u)/w_q - 1 = E2 +- 3e with E2 = 4.5 e^2 - 1.5 |u|^2,
+// and g^eq + tau S^g = w (Qe +- Qo) with
+//   Qe = 3p + rho E2 + tau [3ae - a0 E2 + 3 (3be - b0 (1 + E2))]
+//   Qo = 3 rho e + tau [a E2 - 3 a0 e + 3 (b (1 + E2) - 3 b0 e)]
+// (a0 = u.grad rho, b0 = u.F): one evaluation serves both directions.
+template <typename T>
+struct GTerms {
+  T u, v, uu, p, rho, tau, drx, dry, Fx, Fy, a0, b0;
+};
+template <typename T>
+__device__ __forceinline__ void g_pair(const GTerms<T>& s, int ex, int ey, T& qe, T& qo) {
+  const T e = T(ex) * s.u + T(ey) * s.v;
+  const T a = T(ex) * s.drx + T(ey) * s.dry;
+  const T b = T(ex) * s.Fx + T(ey) * s.Fy;
+  const T E2 = T(4.5) * e * e - T(1.5) * s.uu;
+  const T S_e = T(3) * a * e - s.a0 * E2 + T(3) * (T(3) * b * e - s.b0 * (T(1) + E2));
+  const T S_o = a * E2 - T(3) * s.a0 * e + T(3) * (b * (T(1) + E2) - T(3) * s.b0 * e);
+  qe = T(3) * s.p + s.rho * E2 + s.tau * S_e;
+  qo = T(3) * s.rho * e + s.tau * S_o;
+}
+// rest population: e = a = b = 0, and g^eq_0 carries -3p (Eq. 17)
+template <typename T>
+__device__ __forceinline__ T g_rest(const GTerms<T>& s) {
+  const T E2 = T(-1.5) * s.uu;
+  const T S0 = -s.a0 * E2 - T(3) * s.b0 * (T(1) + E2);
+  return wq<T>(0) * (T(3) * s.p + s.rho * E2 + s.tau * S0) - T(3) * s.p;
+}
+
 // ------------------------------------------------------------- cell stage
 
 template <typename T>
@@ -215,21 +247,22 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
     // g: equilibrium (Eq. 17) and source (Eq. 19), bar-plus and tilde-plus
     double gbD, tauD;
     g_relax<false>(C, (double)phi, rhoD, gbD, tauD);
-    const T gb = T(gbD), tau = T(tauD);
-    const T a0 = u * drx + v * dry, b0 = u * Fx + v * Fy;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const T e = T(EX[q]) * u + T(EY[q]) * v;
-      const T Gh = e * (T(3) + T(4.5) * e) - T(1.5) * uu;  // (Gamma_q(u) - w_q) / w_q
-      const T aq = T(EX[q]) * drx + T(EY[q]) * dry;
-      const T bq = T(EX[q]) * Fx + T(EY[q]) * Fy;
-      const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
-      T geq = wq<T>(q) * (T(3) * p + rho * Gh);
-      if (q == 0) geq -= T(3) * p;
-      // Eq. 29-30 as increments: bar+ = g + d, tilde+ = g + (4/3) d
-      const T d = gb * (geq + tau * Sg - gt[q]);
+    const T gb = T(gbD);
+    const GTerms<T> s{u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy, u * drx + v * dry, u * Fx + v * Fy};
+    // Eq. 29-30 as increments: bar+ = g + d, tilde+ = g + (4/3) d with
+    // d = b (g^eq + tau S - g)
+    auto relax = [&](int q, T target) {
+      const T d = gb * (target - gt[q]);
       o.gb[q] = gt[q] + d;
       tp[9 + q] = gt[q] + T(4.0 / 3.0) * d;
+    };
+    relax(0, g_rest<T>(s));
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+      T qe, qo;
+      g_pair<T>(s, EX[q], EY[q], qe, qo);
+      relax(q, wq<T>(q) * (qe + qo));
+      relax(q + 4, wq<T>(q) * (qe - qo));
     }
   } else {
     presc_vel<T>(C, xc, yc, tn, u, v);
@@ -242,11 +275,17 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
     const T fbc = T(C.fb), tauf = T(C.tau_f);
     const T Vx = T(3) * phi * u + tauf * (theta * nxv + T(3) * Dx);
     const T Vy = T(3) * phi * v + tauf * (theta * nyv + T(3) * Dy);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      const T d = fbc * (wq<T>(q) * (phi + (T(EX[q]) * Vx + T(EY[q]) * Vy)) - ft[q]);
+    auto relax = [&](int q, T target) {
+      const T d = fbc * (target - ft[q]);
       o.fb[q] = ft[q] + d;
       tp[q] = ft[q] + T(4.0 / 3.0) * d;
+    };
+    relax(0, wq<T>(0) * phi);
+#pragma unroll
+    for (int q = 1; q <= 4; ++q) {
+      const T xv = T(EX[q]) * Vx + T(EY[q]) * Vy;
+      relax(q, wq<T>(q) * (phi + xv));
+      relax(q + 4, wq<T>(q) * (phi - xv));
     }
   }
   o.gx = gx; o.gy = gy; o.mu = mu; o.Dx = Dx; o.Dy = Dy;
@@ -297,18 +336,16 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
     const T p = T(0.6) * N0f + T(0.3) * h * (u * drx + v * dry) - T(0.4) * rho * uu;
     double gbD, tauD;
     g_relax<true>(C, (double)phif, rhoD, gbD, tauD);
-    const T gb = T(gbD), tau = T(tauD);
-    const T a0 = u * drx + v * dry, b0 = u * Fx + v * Fy;
+    const T gb = T(gbD);
+    const GTerms<T> s{u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy, u * drx + v * dry, u * Fx + v * Fy};
+    // Eq. 28 in increment form, for the pairs of directions crossing the face
 #pragma unroll
-    for (int q = 1; q < 9; ++q) {
+    for (int q = 1; q <= 4; ++q) {
       if ((DIR == 0 ? EX[q] : EY[q]) == 0) continue;
-      const T e = T(EX[q]) * u + T(EY[q]) * v;
-      const T Gh = e * (T(3) + T(4.5) * e) - T(1.5) * uu;
-      const T aq = T(EX[q]) * drx + T(EY[q]) * dry;
-      const T bq = T(EX[q]) * Fx + T(EY[q]) * Fy;
-      const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
-      const T geq = wq<T>(q) * (T(3) * p + rho * Gh);
-      go[q] = gbar[q] + gb * (geq + tau * Sg - gbar[q]);  // Eq. 28, increment form
+      T qe, qo;
+      g_pair<T>(s, EX[q], EY[q], qe, qo);
+      go[q] = gbar[q] + gb * (wq<T>(q) * (qe + qo) - gbar[q]);
+      go[q + 4] = gbar[q + 4] + gb * (wq<T>(q) * (qe - qo) - gbar[q + 4]);
     }
   } else {
     presc_vel<T>(C, xf, yf, tf, u, v);
@@ -317,9 +354,11 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
   const T Vx = T(3) * phif * u + tauf * (theta * nxv + T(3) * Dxf);
   const T Vy = T(3) * phif * v + tauf * (theta * nyv + T(3) * Dyf);
 #pragma unroll
-  for (int q = 1; q < 9; ++q) {
+  for (int q = 1; q <= 4; ++q) {
     if ((DIR == 0 ? EX[q] : EY[q]) == 0) continue;
-    fo[q] = fbar[q] + fbc * (wq<T>(q) * (phif + (T(EX[q]) * Vx + T(EY[q]) * Vy)) - fbar[q]);
+    const T xv = T(EX[q]) * Vx + T(EY[q]) * Vy;
+    fo[q] = fbar[q] + fbc * (wq<T>(q) * (phif + xv) - fbar[q]);
+    fo[q + 4] = fbar[q + 4] + fbc * (wq<T>(q) * (phif - xv) - fbar[q + 4]);
   }
 }
 
@@ -373,11 +412,37 @@ __device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
 
 // ----------------------------------------------------------- step kernel
 
+// Global-memory access through a uniform base pointer (SGPRs) plus a 32-bit
+// byte offset (one VGPR), which maps to the saddr form of global loads and
+// stores and keeps 64-bit address arithmetic out of the loop.
+typedef __attribute__((address_space(1))) char gchar;
+template <typename T>
+struct GMem {
+  typedef __attribute__((address_space(1))) T type;
+};
+template <typename T>
+__device__ __forceinline__ T gload(const char* base, unsigned off) {
+  return *(const typename GMem<T>::type*)((const gchar*)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void gstore(char* base, unsigned off, T v) {
+  *(typename GMem<T>::type*)((gchar*)base + off) = v;
+}
+
+// Row index of a row in [-2, ny + 2): one period (periodic) or one
+// reflection about the wall (walls) brings it into the grid.
+__device__ __forceinline__ int row_idx(int r, int ny, int walls) {
+  if (r < 0) return walls ? -1 - r : r + ny;
+  if (r >= ny) return walls ? 2 * ny - 1 - r : r - ny;
+  return r;
+}
+
 template <typename T, bool CPL>
 struct RowData {
   Cell<T> cell;
   T txf[9], txg[9];  // x central differences (diagonal pops)
   T txMx, txJx, txPxx, txPxy;
+  T fnf[9], fng[9];  // face distributions of the face above this row
 };
 
 template <typename T, bool CPL>
@@ -431,8 +496,31 @@ __device__ __forceinline__ void y_face(const CaseDev& C, const RowData<T, CPL>& 
                      fbar, gbar, xf, yf, tf, fo, go);
 }
 
+// Tangential (y) differences of the diagonal populations and moments at the
+// own cell for its x-face: next - prev, or twice the one-sided difference
+// next to a wall.
 template <typename T, bool CPL>
-__global__ __launch_bounds__(64) void k_step(StepArgs A) {
+struct Ty {
+  T f[9], g[9], My, Jy, Pxy, Pyy;
+};
+template <typename T, bool CPL>
+__device__ __forceinline__ void y_diffs(const RowData<T, CPL>& up, const RowData<T, CPL>& dn,
+                                        T sc, Ty<T, CPL>& t) {
+  const int diag[4] = {2, 4, 6, 8};
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int q = diag[m];
+    t.f[q] = sc * (up.cell.fb[q] - dn.cell.fb[q]);
+    if (CPL) t.g[q] = sc * (up.cell.gb[q] - dn.cell.gb[q]);
+  }
+  t.My = sc * (up.cell.My - dn.cell.My);
+  t.Jy = sc * (up.cell.Jy - dn.cell.Jy);
+  t.Pxy = sc * (up.cell.Pxy - dn.cell.Pxy);
+  t.Pyy = sc * (up.cell.Pyy - dn.cell.Pyy);
+}
+
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A) {
   const int nb = gridDim.x;
   const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
   const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
@@ -443,7 +531,8 @@ __global__ __launch_bounds__(64) void k_step(StepArgs A) {
   if (n < 0 || n >= C.nsteps) return;
 
   const int lane = threadIdx.x;
-  const int nx = C.nx, ny = C.ny, walls = C.walls;
+  const int nx = C.nx, ny = C.ny;
+  constexpr int walls = WALLS ? 1 : 0;
   const int i0 = it.strip * kStripCols;
   const int col = i0 - 1 + lane;
   const int ci = wrap(col, nx);
@@ -451,10 +540,11 @@ __global__ __launch_bounds__(64) void k_step(StepArgs A) {
   const bool store = lane >= 1 && lane <= kStripCols && col < nx;
   const int aL = ((lane + 63) & 63) << 2, aR = ((lane + 1) & 63) << 2;
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
-  const T* __restrict__ in = static_cast<const T*>(C.set[cur]);
-  T* __restrict__ out = static_cast<T*>(C.set[cur ^ 1]);
-  const long long P = C.plane;
-  const T* __restrict__ phiP = in + plane_phi(CPL) * P;
+  const char* in = static_cast<const char*>(C.set[cur]);
+  char* out = static_cast<char*>(C.set[cur ^ 1]);
+  const long long PB = C.plane * (long long)sizeof(T);  // bytes per plane
+  const char* phiP = in + plane_phi(CPL) * PB;
+  const unsigned es = sizeof(T);
   const double tn = C.t0 + (double)n * C.dt;
   const double xc = (double)ci + 0.5;  // wrapped: halo lanes see their true cell
   const int j0 = it.seg * C.seg_rows;
@@ -462,167 +552,177 @@ __global__ __launch_bounds__(64) void k_step(StepArgs A) {
 
   __shared__ T stash[2][18][64];
 
-  // phi of one row for the own column and its two neighbours
-  auto phi_row = [&](int r, T (&o)[3]) {
-    const long long base = (long long)row_of(r, ny, walls) * nx;
-    const T own = phiP[base + ci];
-    const T ext = phiP[base + cx];
+  // Raw inputs of the cell stage of row r (tilde f, g, history) and phi of
+  // row r+1 (own column and the halo lanes' extra column). They are loaded
+  // one pass ahead of use, so that a whole pass of arithmetic covers the
+  // memory latency.
+  struct Raw {
+    T f[9], g[9], hx, hy, po, pe;
+  };
+  auto fetch = [&](int r, Raw& R) {
+    const unsigned off = ((unsigned)row_idx(r, ny, walls) * (unsigned)nx + ci) * es;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R.f[q] = gload<T>(in + plane_f(q) * PB, off);
+    if (CPL) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) R.g[q] = gload<T>(in + plane_g(q) * PB, off);
+    }
+    R.hx = gload<T>(in + plane_hist(CPL, 0) * PB, off);
+    R.hy = gload<T>(in + plane_hist(CPL, 1) * PB, off);
+    const unsigned rb = (unsigned)row_idx(r + 1, ny, walls) * (unsigned)nx;
+    R.po = gload<T>(phiP, (rb + ci) * es);
+    R.pe = gload<T>(phiP, (rb + cx) * es);
+  };
+  // phi of one row for (left, own, right) columns from own and extra values
+  auto phi_lr = [&](T own, T ext, T (&o)[3]) {
     T left = perm(aL, own), right = perm(aR, own);
     if (lane == 0) left = ext;
     if (lane == 63) right = ext;
     o[0] = left; o[1] = own; o[2] = right;
   };
-  auto stage = [&](int r, const T (&pm)[3], const T (&p0)[3], const T (&pp)[3],
+  auto phi_row = [&](int r, T (&o)[3]) {
+    const unsigned rb = (unsigned)row_idx(r, ny, walls) * (unsigned)nx;
+    phi_lr(gload<T>(phiP, (rb + ci) * es), gload<T>(phiP, (rb + cx) * es), o);
+  };
+  auto stage = [&](int r, const Raw& R, const T (&pm)[3], const T (&p0)[3], const T (&pp)[3],
                    RowData<T, CPL>& rd) {
-    const long long base = (long long)row_of(r, ny, walls) * nx + ci;
-    T ft[9], gt[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) ft[q] = in[plane_f(q) * P + base];
-    if (CPL) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) gt[q] = in[plane_g(q) * P + base];
-    }
-    const T hx = in[plane_hist(CPL, 0) * P + base];
-    const T hy = in[plane_hist(CPL, 1) * P + base];
+    const int rr = row_idx(r, ny, walls);
     T ph[3][3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) { ph[0][k] = pm[k]; ph[1][k] = p0[k]; ph[2][k] = pp[k]; }
     T tp[18];
-    cell_stage<T, CPL>(C, ph, ft, gt, hx, hy, xc, (double)row_of(r, ny, walls) + 0.5, tn,
-                       rd.cell, tp);
+    cell_stage<T, CPL>(C, ph, R.f, R.g, R.hx, R.hy, xc, (double)rr + 0.5, tn, rd.cell, tp);
     const int slot = r & 1;
 #pragma unroll
     for (int q = 0; q < 18; ++q) stash[slot][q][lane] = tp[q];
     x_diffs<T, CPL>(aL, aR, rd);
   };
 
-  // The loop runs from k = j0 - 2: the first two passes only stage rows
-  // j0 - 1 and j0 and form the south face of row j0, so that every row goes
-  // through the same code (bitwise identical results for any segmentation).
-  T pa[3], pb[3], pc[3];  // phi rows k, k+1, k+2 at the top of iteration k
-  RowData<T, CPL> prv, cur_r, nxt;
-  T fs_f[9], fs_g[9];  // face distributions of the south face of row k
-  phi_row(j0 - 2, pa);
-  phi_row(j0 - 1, pb);
-
-  for (int k = j0 - 2; k < j1; ++k) {
-    const int rs = k + 1;  // row staged in this pass
+  // One pass of the march for output row k. It stages row k+1 into `nxt`,
+  // forms the face above row k, and (for k >= j0) the x-face east of row k
+  // and the update of row k. Passes start at k = j0 - 2 so that every row,
+  // halo rows included, goes through the same code: results do not depend on
+  // the segmentation, bit for bit.
+  Raw pre;  // inputs of the next pass, in flight
+  auto pass = [&](int k, RowData<T, CPL>& prv, RowData<T, CPL>& cur_r, RowData<T, CPL>& nxt,
+                  const T (&pa)[3], const T (&pb)[3], T (&pc)[3]) {
+    const int rs = k + 1;
     const bool top_wall = walls && k == ny - 1;
     const bool bot_wall = walls && k == 0;
+    const Raw raw = pre;
+    fetch(rs + 1, pre);
     // the phi ring advances every pass (ghost rows mirror into the grid), the
     // cell stage runs only for rows that exist
-    phi_row(rs + 1, pc);
-    if (!(walls && (rs < 0 || rs >= ny))) stage(rs, pa, pb, pc, nxt);
-    // y-face between rows k and k+1 (the north face of row k)
-    T fn_f[9], fn_g[9];
-    const bool yface = k >= j0 - 1 && !(walls && (k < 0 || k >= ny - 1));
-    if (yface) {
-      const int kr = row_of(k, ny, walls);
-      y_face<T, CPL>(C, cur_r, nxt, xc, (double)kr + 1.0, tn + C.h, fn_f, fn_g);
+    phi_lr(raw.po, raw.pe, pc);
+    if (!(walls && (rs < 0 || rs >= ny))) stage(rs, raw, pa, pb, pc, nxt);
+    // face above row k
+    if (k >= j0 - 1 && !(walls && (k < 0 || k >= ny - 1))) {
+      const int kr = row_idx(k, ny, walls);
+      y_face<T, CPL>(C, cur_r, nxt, xc, (double)kr + 1.0, tn + C.h, cur_r.fnf, cur_r.fng);
     }
-    if (k >= j0) {
-      // tangential (y) differences at row k for the x-face
-      T tyf[9], tyg[9], tyMy, tyJy, tyPxy, tyPyy;
-      {
-        const int diag[4] = {2, 4, 6, 8};
-        // one-sided next to a wall: 2 (next - cur) or 2 (cur - prev)
-        const RowData<T, CPL>& up = top_wall ? cur_r : nxt;
-        const RowData<T, CPL>& dn = bot_wall ? cur_r : prv;
-        const T sc = (top_wall || bot_wall) ? T(2) : T(1);
+    if (k < j0) return;
+    Ty<T, CPL> ty;
+    if (WALLS && top_wall) y_diffs<T, CPL>(cur_r, prv, T(2), ty);
+    else if (WALLS && bot_wall) y_diffs<T, CPL>(nxt, cur_r, T(2), ty);
+    else y_diffs<T, CPL>(nxt, prv, T(1), ty);
+    // x-face east of the own cell: L = own lane, R = lane + 1
+    T fx_f[9], fx_g[9];
+    {
+      const Cell<T>& L = cur_r.cell;
+      const T h = T(C.h), hq = T(0.25) * T(C.h);
+      T fbar[9], gbar[9];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int q = diag[m];
-          tyf[q] = sc * (up.cell.fb[q] - dn.cell.fb[q]);
-          if (CPL) tyg[q] = sc * (up.cell.gb[q] - dn.cell.gb[q]);
-        }
-        tyMy = sc * (up.cell.My - dn.cell.My);
-        tyJy = sc * (up.cell.Jy - dn.cell.Jy);
-        tyPxy = sc * (up.cell.Pxy - dn.cell.Pxy);
-        tyPyy = sc * (up.cell.Pyy - dn.cell.Pyy);
-      }
-      // x-face east of the own cell: L = own lane, R = lane + 1
-      T fx_f[9], fx_g[9];
-      {
-        const Cell<T>& L = cur_r.cell;
-        const T h = T(C.h), hq = T(0.25) * T(C.h);
-        T fbar[9], gbar[9];
-#pragma unroll
-        for (int q = 1; q < 9; ++q) {
-          if (EX[q] == 0) continue;
-          const T ex = T(EX[q]), ey = T(EY[q]);
-          const T Rf = perm(aR, L.fb[q]);
-          T vf = T(0.5) * (L.fb[q] + Rf) - h * ex * (Rf - L.fb[q]);
-          if (EY[q] != 0) vf -= hq * ey * (tyf[q] + perm(aR, tyf[q]));
-          fbar[q] = vf;
-          if (CPL) {
-            const T Rg = perm(aR, L.gb[q]);
-            T vg = T(0.5) * (L.gb[q] + Rg) - h * ex * (Rg - L.gb[q]);
-            if (EY[q] != 0) vg -= hq * ey * (tyg[q] + perm(aR, tyg[q]));
-            gbar[q] = vg;
-          }
-        }
-        const T phif = T(0.5) * (L.M0 + perm(aR, L.M0)) - h * (perm(aR, L.Mx) - L.Mx) -
-                       hq * (tyMy + perm(aR, tyMy));
-        T N0f = T(0), Jxf = T(0), Jyf = T(0);
+      for (int q = 1; q < 9; ++q) {
+        if (EX[q] == 0) continue;
+        const T ex = T(EX[q]), ey = T(EY[q]);
+        const T Rf = perm(aR, L.fb[q]);
+        T vf = T(0.5) * (L.fb[q] + Rf) - h * ex * (Rf - L.fb[q]);
+        if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + perm(aR, ty.f[q]));
+        fbar[q] = vf;
         if (CPL) {
-          N0f = T(0.5) * (L.N0 + perm(aR, L.N0)) - h * (perm(aR, L.Jx) - L.Jx) -
-                hq * (tyJy + perm(aR, tyJy));
-          Jxf = T(0.5) * (L.Jx + perm(aR, L.Jx)) - h * (perm(aR, L.Pxx) - L.Pxx) -
-                hq * (tyPxy + perm(aR, tyPxy));
-          Jyf = T(0.5) * (L.Jy + perm(aR, L.Jy)) - h * (perm(aR, L.Pxy) - L.Pxy) -
-                hq * (tyPyy + perm(aR, tyPyy));
+          const T Rg = perm(aR, L.gb[q]);
+          T vg = T(0.5) * (L.gb[q] + Rg) - h * ex * (Rg - L.gb[q]);
+          if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + perm(aR, ty.g[q]));
+          gbar[q] = vg;
         }
-        const T gxf = T(0.5) * (L.gx + perm(aR, L.gx));
-        const T gyf = T(0.5) * (L.gy + perm(aR, L.gy));
-        const T muf = T(0.5) * (L.mu + perm(aR, L.mu));
-        const T Dxf = T(0.5) * (L.Dx + perm(aR, L.Dx));
-        const T Dyf = T(0.5) * (L.Dy + perm(aR, L.Dy));
-        const int kr = row_of(k, ny, walls);
-        face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
-                           (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
       }
-      if (top_wall) wall_face<T, false>(C, cur_r.cell, prv.cell, cur_r.txf, cur_r.txg, fn_f, fn_g);
-      if (bot_wall) wall_face<T, true>(C, cur_r.cell, nxt.cell, cur_r.txf, cur_r.txg, fs_f, fs_g);
-      // update (Eq. 24) and store
-      {
-        const int kr = row_of(k, ny, walls);
-        const long long base = (long long)kr * nx + ci;
-        const int slot = k & 1;
-        const T dt = T(C.dt);
-        T phin = T(0);
+      const T phif = T(0.5) * (L.M0 + perm(aR, L.M0)) - h * (perm(aR, L.Mx) - L.Mx) -
+                     hq * (ty.My + perm(aR, ty.My));
+      T N0f = T(0), Jxf = T(0), Jyf = T(0);
+      if (CPL) {
+        N0f = T(0.5) * (L.N0 + perm(aR, L.N0)) - h * (perm(aR, L.Jx) - L.Jx) -
+              hq * (ty.Jy + perm(aR, ty.Jy));
+        Jxf = T(0.5) * (L.Jx + perm(aR, L.Jx)) - h * (perm(aR, L.Pxx) - L.Pxx) -
+              hq * (ty.Pxy + perm(aR, ty.Pxy));
+        Jyf = T(0.5) * (L.Jy + perm(aR, L.Jy)) - h * (perm(aR, L.Pxy) - L.Pxy) -
+              hq * (ty.Pyy + perm(aR, ty.Pyy));
+      }
+      const T gxf = T(0.5) * (L.gx + perm(aR, L.gx));
+      const T gyf = T(0.5) * (L.gy + perm(aR, L.gy));
+      const T muf = T(0.5) * (L.mu + perm(aR, L.mu));
+      const T Dxf = T(0.5) * (L.Dx + perm(aR, L.Dx));
+      const T Dyf = T(0.5) * (L.Dy + perm(aR, L.Dy));
+      const int kr = row_idx(k, ny, walls);
+      face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
+                         (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
+    }
+    if (WALLS) {
+      if (top_wall) wall_face<T, false>(C, cur_r.cell, prv.cell, cur_r.txf, cur_r.txg, cur_r.fnf, cur_r.fng);
+      if (bot_wall) wall_face<T, true>(C, cur_r.cell, nxt.cell, cur_r.txf, cur_r.txg, prv.fnf, prv.fng);
+    }
+    // update (Eq. 24) and store; the face below row k is the face above k-1
+    const T(&fn_f)[9] = cur_r.fnf;
+    const T(&fn_g)[9] = cur_r.fng;
+    const T(&fs_f)[9] = prv.fnf;
+    const T(&fs_g)[9] = prv.fng;
+    const int kr = row_idx(k, ny, walls);
+    const unsigned off = ((unsigned)kr * (unsigned)nx + ci) * es;
+    const int slot = k & 1;
+    const T dt = T(C.dt);
+    T phin = T(0);
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-          T J = T(0);
-          if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - perm(aL, fx_f[q]));
-          if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
-          const T val = stash[slot][q][lane] - dt * J;
-          phin += val;
-          if (store) out[plane_f(q) * P + base] = val;
-        }
-        if (CPL) {
+    for (int q = 0; q < 9; ++q) {
+      T J = T(0);
+      if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - perm(aL, fx_f[q]));
+      if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
+      const T val = stash[slot][q][lane] - dt * J;
+      phin += val;
+      if (store) gstore<T>(out + plane_f(q) * PB, off, val);
+    }
+    if (CPL) {
 #pragma unroll
-          for (int q = 0; q < 9; ++q) {
-            T J = T(0);
-            if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - perm(aL, fx_g[q]));
-            if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
-            const T val = stash[slot][9 + q][lane] - dt * J;
-            if (store) out[plane_g(q) * P + base] = val;
-          }
-        }
-        if (store) {
-          out[plane_hist(CPL, 0) * P + base] = cur_r.cell.hx;
-          out[plane_hist(CPL, 1) * P + base] = cur_r.cell.hy;
-          out[plane_phi(CPL) * P + base] = phin;
-        }
+      for (int q = 0; q < 9; ++q) {
+        T J = T(0);
+        if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - perm(aL, fx_g[q]));
+        if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
+        const T val = stash[slot][9 + q][lane] - dt * J;
+        if (store) gstore<T>(out + plane_g(q) * PB, off, val);
       }
     }
-    // rotate
+    if (store) {
+      gstore<T>(out + plane_hist(CPL, 0) * PB, off, cur_r.cell.hx);
+      gstore<T>(out + plane_hist(CPL, 1) * PB, off, cur_r.cell.hy);
+      gstore<T>(out + plane_phi(CPL) * PB, off, phin);
+    }
+  };
+
+  // The three row records and the three phi rows rotate after each pass. (A
+  // loop unrolled by three, rotating by renaming instead of copies, needs
+  // ~285 registers and ran 40% slower on gfx950: spills, or one wave per SIMD.)
+  RowData<T, CPL> R0, R1, R2;
+  T P0[3], P1[3], P2[3];
+  phi_row(j0 - 2, P0);
+  phi_row(j0 - 1, P1);
+  fetch(j0 - 1, pre);
+  for (int k = j0 - 2; k < j1; ++k) {
+    pass(k, R0, R1, R2, P0, P1, P2);
+    R0 = R1;
+    R1 = R2;
 #pragma unroll
-    for (int q = 0; q < 9; ++q) { fs_f[q] = fn_f[q]; fs_g[q] = fn_g[q]; }
-    prv = cur_r;
-    cur_r = nxt;
-    pa[0] = pb[0]; pa[1] = pb[1]; pa[2] = pb[2];
-    pb[0] = pc[0]; pb[1] = pc[1]; pb[2] = pc[2];
+    for (int m = 0; m < 3; ++m) {
+      P0[m] = P1[m];
+      P1[m] = P2[m];
+    }
   }
 }
 
@@ -819,18 +919,37 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
 
 // ----------------------------------------------------------------- launchers
 
-hipError_t launch_step(bool fp64, bool coupled, const StepArgs& a, hipStream_t s) {
+hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s) {
   if (a.nitems <= 0) return hipSuccess;
   const int per = (a.nitems + 7) / 8;
   dim3 grid(per * 8), block(kWave);
+  if (walls && !coupled) return hipErrorInvalidValue;
   if (fp64) {
-    if (coupled) hipLaunchKernelGGL((k_step<double, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step<double, false>), grid, block, 0, s, a);
+    if (!coupled) hipLaunchKernelGGL((k_step<double, false, false>), grid, block, 0, s, a);
+    else if (walls) hipLaunchKernelGGL((k_step<double, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<double, true, false>), grid, block, 0, s, a);
   } else {
-    if (coupled) hipLaunchKernelGGL((k_step<float, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step<float, false>), grid, block, 0, s, a);
+    if (!coupled) hipLaunchKernelGGL((k_step<float, false, false>), grid, block, 0, s, a);
+    else if (walls) hipLaunchKernelGGL((k_step<float, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<float, true, false>), grid, block, 0, s, a);
   }
   return hipGetLastError();
+}
+
+// Resident waves per CU of the step kernel (one wave per work group).
+int step_waves_per_cu(bool fp64, bool coupled, bool walls) {
+  int nb = 0;
+  hipError_t e;
+  if (fp64) {
+    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<double, false, false>, kWave, 0);
+    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<double, true, true>, kWave, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<double, true, false>, kWave, 0);
+  } else {
+    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, false, false>, kWave, 0);
+    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, true, true>, kWave, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, true, false>, kWave, 0);
+  }
+  return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s) {
