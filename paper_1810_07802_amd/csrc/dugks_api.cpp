@@ -129,7 +129,7 @@ void fill_case(dugks_handle* h) {
   C.rho_H = P.rho_H;
   C.rho_L = P.rho_L;
   C.drho = (P.rho_H - P.rho_L) / D;
-  C.rho_mean = 0.5 * (P.rho_H + P.rho_L);
+  C.rho_ref = C.grav_form ? 0.5 * (P.rho_H + P.rho_L) : 0.0;
   C.tau_f = P.M_phi / kRT;
   C.tau_g_uniform = P.nu / kRT;
   C.mu_H = P.mu_H;

@@ -45,7 +45,10 @@ struct CaseDev {
   // phase field
   double phi_H, phi_L, phibar, inv_dphi, kappa, beta, theta_c;
   double eps_n2;  // regularisation of the unit normal: (1e-6 |phi_H - phi_L|)^2
-  double rho_H, rho_L, drho, rho_mean;
+  double rho_H, rho_L, drho;
+  // density subtracted in the gravity force: the mean density (buoyancy
+  // form) or 0 (rho g form), so that both forms are one expression
+  double rho_ref;
   double tau_f;
   // viscosity
   double tau_g_uniform;  // used when visc_mode == uniform nu

@@ -233,7 +233,7 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
   if (CPL) {
     const T rho = T(rhoD);
     const T irho = T(inv_rho<T>(rhoD));
-    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T rg = T(rhoD - C.rho_ref);
     const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
     const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
     const T mx = (gt[1] + gt[2] + gt[8]) - (gt[4] + gt[5] + gt[6]);
@@ -326,7 +326,7 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
   if (CPL) {
     const double rhoD = rho_of(C, (double)phif);
     const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
-    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T rg = T(rhoD - C.rho_ref);
     const T Fx = muf * gxf + (T(C.Gx) + rg * T(C.gx));
     const T Fy = muf * gyf + (T(C.Gy) + rg * T(C.gy));
     u = (Jxf + T(0.5) * h * Fx) * irho;
@@ -377,7 +377,7 @@ __device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
   const T gxw = c.gx;
   T nxv, nyv;
   normal<T>(C, gxw, T(0), nxv, nyv);
-  const T rg = C.grav_form ? T(rhoD - C.rho_mean) : T(rhoD);
+  const T rg = T(rhoD - C.rho_ref);
   const T Fx = c.mu * gxw + (T(C.Gx) + rg * T(C.gx));
   const T Fy = T(C.Gy) + rg * T(C.gy);
   double gbD, tauD;
@@ -526,7 +526,11 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (idx >= A.nitems) return;
   const Item it = A.items[idx];
-  const CaseDev& C = A.cases[it.c];
+  // The case constants are copied into registers once: read through the
+  // descriptor pointer, they would be re-read after every store of the march
+  // (the stores could alias them as far as the compiler knows).
+  const CaseDev* Cg = A.cases + it.c;
+  const CaseDev C = *Cg;
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
 
@@ -540,8 +544,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   const bool store = lane >= 1 && lane <= kStripCols && col < nx;
   const int aL = ((lane + 63) & 63) << 2, aR = ((lane + 1) & 63) << 2;
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
-  const char* in = static_cast<const char*>(C.set[cur]);
-  char* out = static_cast<char*>(C.set[cur ^ 1]);
+  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
   const long long PB = C.plane * (long long)sizeof(T);  // bytes per plane
   const char* phiP = in + plane_phi(CPL) * PB;
   const unsigned es = sizeof(T);
@@ -679,15 +683,15 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     const unsigned off = ((unsigned)kr * (unsigned)nx + ci) * es;
     const int slot = k & 1;
     const T dt = T(C.dt);
+    T nv[CPL ? 21 : 12];  // new tilde f, tilde g, history, phi
     T phin = T(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       T J = T(0);
       if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - perm(aL, fx_f[q]));
       if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
-      const T val = stash[slot][q][lane] - dt * J;
-      phin += val;
-      if (store) gstore<T>(out + plane_f(q) * PB, off, val);
+      nv[plane_f(q)] = stash[slot][q][lane] - dt * J;
+      phin += nv[plane_f(q)];
     }
     if (CPL) {
 #pragma unroll
@@ -695,14 +699,16 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
         T J = T(0);
         if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - perm(aL, fx_g[q]));
         if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
-        const T val = stash[slot][9 + q][lane] - dt * J;
-        if (store) gstore<T>(out + plane_g(q) * PB, off, val);
+        nv[plane_g(q)] = stash[slot][9 + q][lane] - dt * J;
       }
     }
+    nv[plane_hist(CPL, 0)] = cur_r.cell.hx;
+    nv[plane_hist(CPL, 1)] = cur_r.cell.hy;
+    nv[plane_phi(CPL)] = phin;
+    // one masked region for all stores of the row
     if (store) {
-      gstore<T>(out + plane_hist(CPL, 0) * PB, off, cur_r.cell.hx);
-      gstore<T>(out + plane_hist(CPL, 1) * PB, off, cur_r.cell.hy);
-      gstore<T>(out + plane_phi(CPL) * PB, off, phin);
+#pragma unroll
+      for (int m = 0; m < num_planes(CPL); ++m) gstore<T>(out + m * PB, off, nv[m]);
     }
   };
 
@@ -777,7 +783,7 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
     const T p = p0 ? T(p0[c]) : T(0);
     const double rhoD = rho_of(C, (double)phi);
     const T rho = T(rhoD);
-    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T rg = T(rhoD - C.rho_ref);
     const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
     const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
     const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
@@ -839,7 +845,7 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
     const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
     const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
     const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
-    const T rg = C.grav_form ? T(rhoD - C.rho_mean) : rho;
+    const T rg = T(rhoD - C.rho_ref);
     const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
     const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
     T g[9];
