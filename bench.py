@@ -45,6 +45,9 @@ def parse():
                     help="run only the timed default workload (for profilers)")
     ap.add_argument("--profile-large", action="store_true",
                     help="run only the timed 4096x4096 workload (for profilers)")
+    ap.add_argument("--profile-copy", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (calibrates the "
+                         "HBM byte counters)")
     return ap.parse_args()
 
 
@@ -93,12 +96,34 @@ def timed_eager(torch, D, solvers, steps):
     return e0.elapsed_time(e1) / 1e3
 
 
-def roofline(cells, steps, seconds, prec):
+def counter_traffic(workload):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
+    reading), or None when the kernel sources differ from the profiled ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_step_hbm_counters.txt")
+    if workload is None or not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("dugks_kernels.hip", "dugks_impl.h"):
+        with open(os.path.join(ROOT, "paper_1810_07802_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha, val = None, None
+    for line in open(path):
+        w = line.split()
+        if len(w) >= 2 and w[0] == "kernel_source_sha256":
+            sha = w[1]
+        if len(w) >= 2 and w[0] == "workload" and w[1] == workload:
+            val = float(w[w.index("bytes_per_launch") + 1])
+    return val if sha == h.hexdigest() else None
+
+
+def roofline(cells, steps, seconds, prec, workload=None):
     per_launch = B_PER_CELL[prec] * cells
     t_launch = seconds / steps
     achieved = per_launch / t_launch / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(workload),
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
 
 
@@ -132,6 +157,21 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.profile_copy:
+        n = 1 << 28  # float32 elements: 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / 1e3 / 5
+        print(json.dumps({"workload": "device copy 1 GiB", "bytes_read": 4 * n, "bytes_written": 4 * n,
+                          "copy_GBps": round(8 * n / t / 1e9, 1)}), flush=True)
+        return
     if args.profile_large:
         cl = W.bubble(L=4096, R=1024, steps=0)
         sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32")
@@ -140,7 +180,7 @@ def main():
         ncl = cl["nx"] * cl["ny"]
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32", "steps": args.large_steps,
                           "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
-                          "roofline": roofline(ncl, args.large_steps, tl, "fp32")}), flush=True)
+                          "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}), flush=True)
         return
     c = W.bubble(L=128, R=32)
     cells = c["nx"] * c["ny"]
@@ -158,7 +198,7 @@ def main():
                                "nu=0.1, M=0.1, periodic, coupled FP32 step",
                    "nx": c["nx"], "ny": c["ny"], "seg_rows": s.seg_rows,
                    "launch": "HIP graph of 1000 step launches"},
-        "roofline": roofline(cells, args.steps, secs, "fp32"),
+        "roofline": roofline(cells, args.steps, secs, "fp32", "bubble128"),
     }
     diag = s.diagnostics()
     rec["check"] = {"nonfinite": diag["nonfinite"], "max_u": diag["max_u"]}
@@ -185,7 +225,7 @@ def main():
         rec["large_grid"] = {"workload": "stationary bubble 4096x4096, R=1024, coupled FP32",
                              "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
                              "steps": args.large_steps, "seg_rows": sl.seg_rows,
-                             "roofline": roofline(ncl, args.large_steps, tl, "fp32")}
+                             "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}
         del sl
         # batched spinodal workload vs the per-case loop
         cases = W.spinodal_batch(steps=0)
