@@ -97,6 +97,8 @@ typedef struct dugks_handle dugks_handle;
  * (DUGKS_MODEL_*) in `precision` (DUGKS_FP32: distributions and arithmetic in
  * float, density and relaxation-time interpolation in double; DUGKS_FP64: all
  * double). Allocates the two state buffers on the current HIP device.
+ * nx * ny may not exceed 2^32 / (4 * value bytes): 2^28 cells in FP32, 2^27
+ * in FP64 (the step kernel uses 32-bit byte offsets within a group plane).
  * Errors: EINVAL (sizes, enums), ENOMEM, EDEVICE. *out is NULL on error. */
 int dugks_create(int nx, int ny, int precision, int model, dugks_handle **out);
 
@@ -111,8 +113,10 @@ int dugks_set_stream(dugks_handle *h, void *stream);
 
 /* Work decomposition of the step kernel: rows per segment of a 62-column
  * strip (each (strip, segment) tile is one 64-lane wave). 0 = automatic
- * (the longest segment that still gives >= 2048 waves). EINVAL outside
- * [0, 4096]. dugks_get_tile returns the value in use (-1 for NULL). */
+ * (segments just long enough that all tiles are resident on the device at
+ * once). Results do not depend on it, bit for bit. A batch uses a case's
+ * explicit value, and its own automatic choice for cases left at 0. EINVAL
+ * outside [0, 4096]. dugks_get_tile returns the value in use (-1 for NULL). */
 int dugks_set_tile(dugks_handle *h, int seg_rows);
 int dugks_get_tile(const dugks_handle *h);
 
@@ -162,7 +166,11 @@ double dugks_time(const dugks_handle *h);
 
 /* Checkpoint/resume: the state is the tilde distributions, the history
  * (phi u)^(n-1), the phi plane and the step counter. dugks_state_bytes()
- * gives the size of the host buffer; get/set copy it (synchronous). */
+ * gives the size of the host buffer; get/set copy it (synchronous). Layout
+ * (values of the handle's precision, n = nx * ny cells, cell c = y nx + x):
+ * the values f0..f8, [g0..g8], hist_x, hist_y in groups of four consecutive
+ * values, each group cell-interleaved ([n][4]; a last partial group of w
+ * values is [n][w]), then phi [n]. */
 size_t dugks_state_bytes(const dugks_handle *h);
 int dugks_get_state(dugks_handle *h, void *host_buf, size_t bytes,
                     long long *steps);

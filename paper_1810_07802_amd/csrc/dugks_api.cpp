@@ -206,7 +206,7 @@ int validate(const dugks_handle* h, const dugks_params* p, std::string& why) {
 
 size_t state_set_bytes(int nx, int ny, int precision, int model) {
   const size_t e = precision == DUGKS_FP64 ? 8 : 4;
-  return (size_t)dugks::num_planes(model == DUGKS_MODEL_COUPLED) * (size_t)nx * ny * e;
+  return (size_t)dugks::num_values(model == DUGKS_MODEL_COUPLED) * (size_t)nx * ny * e;
 }
 
 int ensure_scratch(dugks_handle* h) {
@@ -238,9 +238,12 @@ int dugks_create(int nx, int ny, int precision, int model, dugks_handle** out) {
   if (!out) return fail(nullptr, DUGKS_EINVAL, "out is NULL");
   *out = nullptr;
   if (nx < 3 || ny < 3) return fail(nullptr, DUGKS_EINVAL, "nx and ny must be >= 3");
-  if ((long long)nx * ny > (1LL << 31) / 4) return fail(nullptr, DUGKS_EINVAL, "grid too large");
   if (precision != DUGKS_FP32 && precision != DUGKS_FP64)
     return fail(nullptr, DUGKS_EINVAL, "bad precision");
+  // the step kernel addresses a group of four values of a cell with a 32-bit
+  // byte offset: 4 * sizeof(value) * cells must stay within 2^32
+  if ((long long)nx * ny > (1LL << 32) / (4 * (precision == DUGKS_FP64 ? 8 : 4)))
+    return fail(nullptr, DUGKS_EINVAL, "grid too large (cells > 2^32 / (4 * value bytes))");
   if (model != DUGKS_MODEL_AC && model != DUGKS_MODEL_COUPLED)
     return fail(nullptr, DUGKS_EINVAL, "bad model");
   dugks_handle* h = new (std::nothrow) dugks_handle;

@@ -12,16 +12,31 @@ namespace dugks {
 constexpr int kStripCols = 62;
 constexpr int kWave = 64;
 
-// Plane order inside one state buffer (each plane is nx*ny values):
+// Values held per cell, in this order:
 //   f0..f8, [g0..g8], hist_x, hist_y, phi
 // where hist = (phi u) of the previous step and phi = sum_q f.
-__host__ __device__ constexpr int plane_f(int q) { return q; }
-__host__ __device__ constexpr int plane_g(int q) { return 9 + q; }
-__host__ __device__ constexpr int plane_hist(bool coupled, int c) {
-  return (coupled ? 18 : 9) + c;
+__host__ __device__ constexpr int val_f(int q) { return q; }
+__host__ __device__ constexpr int val_g(int q) { return 9 + q; }
+__host__ __device__ constexpr int val_hist(bool coupled, int c) { return (coupled ? 18 : 9) + c; }
+__host__ __device__ constexpr int val_phi(bool coupled) { return coupled ? 20 : 11; }
+__host__ __device__ constexpr int num_values(bool coupled) { return coupled ? 21 : 12; }
+// Values stored in groups (all but phi).
+__host__ __device__ constexpr int num_grouped(bool coupled) { return num_values(coupled) - 1; }
+
+// Layout of one state buffer of n cells. The grouped values are split into
+// groups of four consecutive values; each group is stored cell-interleaved
+// ([n][4], so that one 16-byte access per cell moves a group; a last partial
+// group of w values is [n][w]). The phi plane [n] follows. A group occupies
+// 4 n values, so group g starts at 4 g n and the phi plane at num_grouped n.
+__host__ __device__ constexpr long long value_index(int v, long long c, long long n,
+                                                    bool coupled) {
+  return v == num_grouped(coupled)
+             ? (long long)num_grouped(coupled) * n + c
+             : 4LL * (v >> 2) * n +
+                   c * (num_grouped(coupled) - 4 * (v >> 2) < 4 ? num_grouped(coupled) - 4 * (v >> 2)
+                                                                 : 4) +
+                   (v & 3);
 }
-__host__ __device__ constexpr int plane_phi(bool coupled) { return coupled ? 20 : 11; }
-__host__ __device__ constexpr int num_planes(bool coupled) { return coupled ? 21 : 12; }
 
 // Everything a kernel needs about one case. Lives in device memory (an array
 // for batches, one entry for a plain handle). Constants are kept in double;
@@ -38,7 +53,7 @@ struct CaseDev {
   int cur0;              // state buffer holding local step 0
   long long step0;       // global step index of local step 0
   long long nsteps;      // local steps allowed (active window)
-  long long plane;       // values per plane
+  long long plane;       // cells (values per plane)
   void* set[2];          // the two state buffers
   // time
   double dt, h, t0;

@@ -429,6 +429,39 @@ __device__ __forceinline__ void gstore(char* base, unsigned off, T v) {
   *(typename GMem<T>::type*)((gchar*)base + off) = v;
 }
 
+// The grouped values of one cell (all but phi; layout in value_index()):
+// one 4-wide vector access per full group, scalar accesses for a last
+// partial group. `c` is the cell, PB the bytes of one plane (n values).
+template <typename T>
+using Vec4 = T __attribute__((ext_vector_type(4)));
+template <typename T, int NV>
+__device__ __forceinline__ void load_groups(const char* base, long long PB, unsigned c,
+                                            T (&v)[NV]) {
+#pragma unroll
+  for (int g = 0; g < NV / 4; ++g) {
+    const Vec4<T> x = gload<Vec4<T>>(base + 4 * g * PB, c * (4u * sizeof(T)));
+    v[4 * g] = x.x; v[4 * g + 1] = x.y; v[4 * g + 2] = x.z; v[4 * g + 3] = x.w;
+  }
+  constexpr int w = NV % 4;
+#pragma unroll
+  for (int k = 0; k < w; ++k)
+    v[NV - w + k] = gload<T>(base + (NV - w) * PB, (c * w + k) * (unsigned)sizeof(T));
+}
+template <typename T, int NV>
+__device__ __forceinline__ void store_groups(char* base, long long PB, unsigned c,
+                                             const T (&v)[NV]) {
+#pragma unroll
+  for (int g = 0; g < NV / 4; ++g) {
+    Vec4<T> x;
+    x.x = v[4 * g]; x.y = v[4 * g + 1]; x.z = v[4 * g + 2]; x.w = v[4 * g + 3];
+    gstore<Vec4<T>>(base + 4 * g * PB, c * (4u * sizeof(T)), x);
+  }
+  constexpr int w = NV % 4;
+#pragma unroll
+  for (int k = 0; k < w; ++k)
+    gstore<T>(base + (NV - w) * PB, (c * w + k) * (unsigned)sizeof(T), v[NV - w + k]);
+}
+
 // Row index of a row in [-2, ny + 2): one period (periodic) or one
 // reflection about the wall (walls) brings it into the grid.
 __device__ __forceinline__ int row_idx(int r, int ny, int walls) {
@@ -547,7 +580,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
   const long long PB = C.plane * (long long)sizeof(T);  // bytes per plane
-  const char* phiP = in + plane_phi(CPL) * PB;
+  constexpr int NV = num_grouped(CPL);
+  const char* phiP = in + NV * PB;
   const unsigned es = sizeof(T);
   const double tn = C.t0 + (double)n * C.dt;
   const double xc = (double)ci + 0.5;  // wrapped: halo lanes see their true cell
@@ -557,22 +591,24 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   __shared__ T stash[2][18][64];
 
   // Raw inputs of the cell stage of row r (tilde f, g, history) and phi of
-  // row r+1 (own column and the halo lanes' extra column). They are loaded
-  // one pass ahead of use, so that a whole pass of arithmetic covers the
+  // row r+1 (own column and the halo lanes' extra column). Two sets are in
+  // flight: a pass consumes one set in its cell stage and then reloads it for
+  // the pass after next, so that more than a pass of arithmetic covers the
   // memory latency.
   struct Raw {
     T f[9], g[9], hx, hy, po, pe;
   };
   auto fetch = [&](int r, Raw& R) {
-    const unsigned off = ((unsigned)row_idx(r, ny, walls) * (unsigned)nx + ci) * es;
+    T v[NV];
+    load_groups<T, NV>(in, PB, (unsigned)row_idx(r, ny, walls) * (unsigned)nx + ci, v);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) R.f[q] = gload<T>(in + plane_f(q) * PB, off);
+    for (int q = 0; q < 9; ++q) R.f[q] = v[val_f(q)];
     if (CPL) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) R.g[q] = gload<T>(in + plane_g(q) * PB, off);
+      for (int q = 0; q < 9; ++q) R.g[q] = v[val_g(q)];
     }
-    R.hx = gload<T>(in + plane_hist(CPL, 0) * PB, off);
-    R.hy = gload<T>(in + plane_hist(CPL, 1) * PB, off);
+    R.hx = v[val_hist(CPL, 0)];
+    R.hy = v[val_hist(CPL, 1)];
     const unsigned rb = (unsigned)row_idx(r + 1, ny, walls) * (unsigned)nx;
     R.po = gload<T>(phiP, (rb + ci) * es);
     R.pe = gload<T>(phiP, (rb + cx) * es);
@@ -607,18 +643,18 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   // and the update of row k. Passes start at k = j0 - 2 so that every row,
   // halo rows included, goes through the same code: results do not depend on
   // the segmentation, bit for bit.
-  Raw pre;  // inputs of the next pass, in flight
-  auto pass = [&](int k, RowData<T, CPL>& prv, RowData<T, CPL>& cur_r, RowData<T, CPL>& nxt,
-                  const T (&pa)[3], const T (&pb)[3], T (&pc)[3]) {
+  auto pass = [&](int k, Raw& raw, RowData<T, CPL>& prv, RowData<T, CPL>& cur_r,
+                  RowData<T, CPL>& nxt, const T (&pa)[3], const T (&pb)[3], T (&pc)[3]) {
     const int rs = k + 1;
     const bool top_wall = walls && k == ny - 1;
     const bool bot_wall = walls && k == 0;
-    const Raw raw = pre;
-    fetch(rs + 1, pre);
     // the phi ring advances every pass (ghost rows mirror into the grid), the
     // cell stage runs only for rows that exist
     phi_lr(raw.po, raw.pe, pc);
     if (!(walls && (rs < 0 || rs >= ny))) stage(rs, raw, pa, pb, pc, nxt);
+    // inputs of pass k + 2 (row k + 3); rows past j1 + 1 are never staged,
+    // so the fetch stays on the rows the segment reads anyway
+    fetch(min(k + 3, j1 + 1), raw);
     // face above row k
     if (k >= j0 - 1 && !(walls && (k < 0 || k >= ny - 1))) {
       const int kr = row_idx(k, ny, walls);
@@ -680,18 +716,18 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     const T(&fs_f)[9] = prv.fnf;
     const T(&fs_g)[9] = prv.fng;
     const int kr = row_idx(k, ny, walls);
-    const unsigned off = ((unsigned)kr * (unsigned)nx + ci) * es;
+    const unsigned cell = (unsigned)kr * (unsigned)nx + ci;
     const int slot = k & 1;
     const T dt = T(C.dt);
-    T nv[CPL ? 21 : 12];  // new tilde f, tilde g, history, phi
+    T nv[NV];  // new tilde f, tilde g, history
     T phin = T(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       T J = T(0);
       if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - perm(aL, fx_f[q]));
       if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
-      nv[plane_f(q)] = stash[slot][q][lane] - dt * J;
-      phin += nv[plane_f(q)];
+      nv[val_f(q)] = stash[slot][q][lane] - dt * J;
+      phin += nv[val_f(q)];
     }
     if (CPL) {
 #pragma unroll
@@ -699,16 +735,15 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
         T J = T(0);
         if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - perm(aL, fx_g[q]));
         if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
-        nv[plane_g(q)] = stash[slot][9 + q][lane] - dt * J;
+        nv[val_g(q)] = stash[slot][9 + q][lane] - dt * J;
       }
     }
-    nv[plane_hist(CPL, 0)] = cur_r.cell.hx;
-    nv[plane_hist(CPL, 1)] = cur_r.cell.hy;
-    nv[plane_phi(CPL)] = phin;
+    nv[val_hist(CPL, 0)] = cur_r.cell.hx;
+    nv[val_hist(CPL, 1)] = cur_r.cell.hy;
     // one masked region for all stores of the row
     if (store) {
-#pragma unroll
-      for (int m = 0; m < num_planes(CPL); ++m) gstore<T>(out + m * PB, off, nv[m]);
+      store_groups<T, NV>(out, PB, cell, nv);
+      gstore<T>(out + NV * PB, cell * es, phin);
     }
   };
 
@@ -717,17 +752,26 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   // ~285 registers and ran 40% slower on gfx950: spills, or one wave per SIMD.)
   RowData<T, CPL> R0, R1, R2;
   T P0[3], P1[3], P2[3];
-  phi_row(j0 - 2, P0);
-  phi_row(j0 - 1, P1);
-  fetch(j0 - 1, pre);
-  for (int k = j0 - 2; k < j1; ++k) {
-    pass(k, R0, R1, R2, P0, P1, P2);
+  auto rotate = [&]() {
     R0 = R1;
     R1 = R2;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       P0[m] = P1[m];
       P1[m] = P2[m];
+    }
+  };
+  Raw ra, rb;  // inputs of the even and odd passes (counted from j0 - 2)
+  phi_row(j0 - 2, P0);
+  phi_row(j0 - 1, P1);
+  fetch(j0 - 1, ra);
+  fetch(j0, rb);
+  for (int k = j0 - 2; k < j1; k += 2) {
+    pass(k, ra, R0, R1, R2, P0, P1, P2);
+    rotate();
+    if (k + 1 < j1) {
+      pass(k + 1, rb, R0, R1, R2, P0, P1, P2);
+      rotate();
     }
   }
 }
@@ -798,7 +842,7 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
       const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
       T geq = wq<T>(q) * (T(3) * p + rho * Gh);
       if (q == 0) geq -= T(3) * p;
-      st[plane_g(q) * P + c] = geq - hdt * Sg;
+      st[value_index(val_g(q), c, P, CPL)] = geq - hdt * Sg;
     }
   } else {
     presc_vel<T>(C, i + 0.5, j + 0.5, 0.0, u, v);
@@ -808,15 +852,15 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
     const T en = T(EX[q]) * nxv + T(EY[q]) * nyv;
     const T feq = wq<T>(q) * phi * (T(1) + T(3) * (T(EX[q]) * u + T(EY[q]) * v));
     const T Sf = wq<T>(q) * theta * en;
-    st[plane_f(q) * P + c] = feq - hdt * Sf;
+    st[value_index(val_f(q), c, P, CPL)] = feq - hdt * Sf;
   }
-  st[plane_hist(CPL, 0) * P + c] = phi * u;
-  st[plane_hist(CPL, 1) * P + c] = phi * v;
+  st[value_index(val_hist(CPL, 0), c, P, CPL)] = phi * u;
+  st[value_index(val_hist(CPL, 1), c, P, CPL)] = phi * v;
   // phi plane = sum of the stored f (the same sum the step kernel forms)
   T s = T(0);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) s += st[plane_f(q) * P + c];
-  st[plane_phi(CPL) * P + c] = s;
+  for (int q = 0; q < 9; ++q) s += st[value_index(val_f(q), c, P, CPL)];
+  st[value_index(val_phi(CPL), c, P, CPL)] = s;
 }
 
 // Cell macros of a state (Eqs. 31-33, 10) into double arrays.
@@ -832,7 +876,7 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
   const long long c = (long long)j * C.nx + i, P = C.plane;
   const T* __restrict__ st = static_cast<const T*>(C.set[buf]);
   T ph[3][3];
-  gather3x3<T, T>(st + plane_phi(CPL) * P, i, j, C.nx, C.ny, C.walls, ph);
+  gather3x3<T, T>(st + value_index(val_phi(CPL), 0, P, CPL), i, j, C.nx, C.ny, C.walls, ph);
   const T phi = ph[1][1];
   const double rhoD = rho_of(C, (double)phi);
   T u, v, p = T(0);
@@ -850,7 +894,7 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
     const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
     T g[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = st[plane_g(q) * P + c];
+    for (int q = 0; q < 9; ++q) g[q] = st[value_index(val_g(q), c, P, CPL)];
     const T mx = (g[1] + g[2] + g[8]) - (g[4] + g[5] + g[6]);
     const T my = (g[2] + g[3] + g[4]) - (g[6] + g[7] + g[8]);
     const T m0 = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
