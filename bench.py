@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--large-seg", type=int, default=0,
+                    help="tile (rows per segment) of the 4096x4096 leg; 0: the library's autotuner")
     ap.add_argument("--batch-steps", type=int, default=500)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-extra", action="store_true", help="only the default workload")
@@ -174,12 +176,13 @@ def main():
         return
     if args.profile_large:
         cl = W.bubble(L=4096, R=1024, steps=0)
-        sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32")
+        sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32", args.large_seg or None)
         sl.init(cl["phi"])
+        seg = sl.seg_rows if args.large_seg else sl.autotune(10)[0]
         tl, _ = timed_graph(torch, D, [sl], args.large_steps, 5, chunk=args.large_steps)
         ncl = cl["nx"] * cl["ny"]
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32", "steps": args.large_steps,
-                          "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
+                          "seg_rows": seg, "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
                           "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}), flush=True)
         return
     c = W.bubble(L=128, R=32)
@@ -220,11 +223,17 @@ def main():
         cl = W.bubble(L=4096, R=1024, steps=0)
         sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32")
         sl.init(cl["phi"])
+        auto_seg = sl.seg_rows
+        if args.large_seg:
+            sl.set_tile(args.large_seg)
+        else:
+            sl.autotune(10)  # tile chosen by the library's autotuner (outside the timed region)
         tl, _ = timed_graph(torch, D, [sl], args.large_steps, 20, chunk=100)
         ncl = cl["nx"] * cl["ny"]
         rec["large_grid"] = {"workload": "stationary bubble 4096x4096, R=1024, coupled FP32",
                              "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
                              "steps": args.large_steps, "seg_rows": sl.seg_rows,
+                             "auto_seg_rows": auto_seg,
                              "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}
         del sl
         # batched spinodal workload vs the per-case loop

@@ -113,8 +113,9 @@ int dugks_set_stream(dugks_handle *h, void *stream);
 
 /* Work decomposition of the step kernel: rows per segment of a 62-column
  * strip (each (strip, segment) tile is one 64-lane wave). 0 = automatic
- * (segments just long enough that all tiles are resident on the device at
- * once). Results do not depend on it, bit for bit. A batch uses a case's
+ * (the shortest segments whose tiles are all resident on the device at
+ * once; if those would exceed 64 rows, the shortest that fit eight rounds).
+ * Results do not depend on it, bit for bit. A batch uses a case's
  * explicit value, and its own automatic choice for cases left at 0. EINVAL
  * outside [0, 4096]. dugks_get_tile returns the value in use (-1 for NULL). */
 int dugks_set_tile(dugks_handle *h, int seg_rows);
@@ -176,6 +177,18 @@ int dugks_get_state(dugks_handle *h, void *host_buf, size_t bytes,
                     long long *steps);
 int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
                     long long steps);
+
+/* Tile autotuner: times probe_steps (1..1000) steps for each of a few
+ * segment lengths (1 and 2 rows, for the lowest latency per step, and for
+ * k = 1..8, 12, 16 the shortest segment whose tiles fit k rounds of the
+ * device's resident waves) on the handle's current state, keeps the fastest as the
+ * handle's tile (dugks_set_tile) and puts the state and step counter back as
+ * they were. Results do not depend on the tile, bit for bit. Synchronous;
+ * holds one extra copy of the state on the device while it runs. Outputs
+ * (NULL to skip): the chosen seg_rows and its time per step in microseconds.
+ * ESTATE before init; on EDEVICE the state is undefined. */
+int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
+                   double *us_per_step);
 
 /* Device bytes a handle of this shape holds (both state buffers). */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);

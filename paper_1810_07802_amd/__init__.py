@@ -106,6 +106,7 @@ def lib():
             "dugks_set_stream": (i, [vp, vp]),
             "dugks_set_tile": (i, [vp, i]),
             "dugks_get_tile": (i, [vp]),
+            "dugks_autotune": (i, [vp, i, C.POINTER(i), dp]),
             "dugks_init_fields": (i, [vp, dp, dp, dp, dp]),
             "dugks_init_fields_device": (i, [vp, vp, vp, vp, vp]),
             "dugks_step": (i, [vp, i]),
@@ -241,7 +242,10 @@ class Solver:
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            destroy(h)
+            try:
+                destroy(h)
+            except Exception:  # interpreter shutdown: module globals may be gone
+                pass
             self.h = None
 
     def set_stream(self, stream):
@@ -288,6 +292,13 @@ class Solver:
     def set_tile(self, seg_rows):
         set_tile(self.h, seg_rows)
 
+    def autotune(self, probe_steps=20):
+        """Time a few tiles on the current state, keep the fastest (the state
+        is put back); returns (seg_rows, microseconds per step)."""
+        seg, us = C.c_int(0), C.c_double(0.0)
+        _check(lib().dugks_autotune(self.h, int(probe_steps), C.byref(seg), C.byref(us)), self.h)
+        return int(seg.value), float(us.value)
+
     def get_state(self):
         n = int(lib().dugks_state_bytes(self.h))
         buf = np.empty(n, dtype=np.uint8)
@@ -314,7 +325,10 @@ class Batch:
     def __del__(self):
         b = getattr(self, "b", None)
         if b:
-            lib().dugks_batch_destroy(b)
+            try:
+                lib().dugks_batch_destroy(b)
+            except Exception:  # interpreter shutdown: module globals may be gone
+                pass
             self.b = None
 
     def set_stream(self, stream):

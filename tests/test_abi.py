@@ -50,6 +50,13 @@ def test_null_and_bad_arguments_do_not_crash():
     with pytest.raises(D.DugksError) as e:
         D.create(16, 16, precision=7)
     assert e.value.code == D.EINVAL
+    assert L.dugks_autotune(None, 10, None, None) == D.EINVAL
+    # 32-bit group offsets: at most 2^28 cells in FP32 and 2^27 in FP64
+    # (rejected before any device allocation)
+    for nx, ny, prec in ((1 << 15, 1 << 14, D.FP32), (1 << 14, 1 << 14, D.FP64)):
+        with pytest.raises(D.DugksError) as e:
+            D.create(nx, ny, precision=prec)
+        assert e.value.code == D.EINVAL and "too large" in str(e.value)
 
 
 def test_params_marshalling_rejects_unknown_keys():

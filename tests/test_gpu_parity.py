@@ -104,6 +104,23 @@ def test_checkpoint_resume_bitwise(prec):
     assert np.array_equal(a.get_state()[0], b.get_state()[0])
 
 
+def test_autotune_restores_state_and_keeps_bits():
+    c = W.random_coupled(130, 50, seed=11, rho_ratio=50.0)
+    ref = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    ref.init(c["phi"], c["u"], c["v"])
+    ref.step(25)
+    s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    s.init(c["phi"], c["u"], c["v"])
+    s.step(10)
+    before, n0 = s.get_state()
+    seg, us = s.autotune(5)
+    after, n1 = s.get_state()
+    assert n0 == n1 == 10 and np.array_equal(before, after)
+    assert s.seg_rows == seg and seg >= 1 and us > 0
+    s.step(15)
+    assert np.array_equal(s.get_state()[0], ref.get_state()[0])
+
+
 def test_batch_matches_single_cases_bitwise():
     cases = [W.spinodal(L=L, seed=10 + k, steps=0) for k, L in enumerate((64, 100, 37))]
     alone, solvers = [], []
