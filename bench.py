@@ -14,6 +14,9 @@ The same JSON line carries:
                 set (2.8 GB) is far larger than the 256 MB Infinity Cache
   batched       the spinodal batch (64 cases of 64^2..512^2): one graph of
                 batched launches vs one launch per case per step
+  served        the served request stream through the continuous-batching
+                pool: p50 / p99 time to solution at 80 % load, aggregate
+                MLUPS, vs the plain sequential per-case loop
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -41,6 +44,8 @@ def parse():
     ap.add_argument("--large-seg", type=int, default=0,
                     help="tile (rows per segment) of the 4096x4096 leg; 0: the library's autotuner")
     ap.add_argument("--batch-steps", type=int, default=500)
+    ap.add_argument("--serve-requests", type=int, default=60,
+                    help="requests of the served stream (0: skip the serving leg)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-extra", action="store_true", help="only the default workload")
     ap.add_argument("--profile-kernel", action="store_true",
@@ -127,6 +132,51 @@ def roofline(cells, steps, seconds, prec, workload=None):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(workload),
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
+
+
+def served_stream(torch, D, W, n_req):
+    """The served request stream: closed-loop capacity, then Poisson arrivals
+    at 80 % of it (p50 / p99 time to solution, aggregate MLUPS), then the
+    plain sequential per-case loop on the same requests."""
+    import numpy as np
+    from paper_1810_07802_amd import serve
+    cases = W.served_stream(n=n_req)
+    lups = [c["nx"] * c["ny"] * c["steps"] for c in cases]
+    mean_lups = float(np.mean(lups))
+
+    def pool():
+        p = D.Pool(8 << 30, max_cases=32, max_cells=1024 * 1024)
+        p.set_stream(torch.cuda.current_stream().cuda_stream)
+        return p
+
+    warm = [serve.Request(0, W.bubble(L=64, steps=0), 200, 0.0)]
+    serve.run(pool(), warm, chunk=100)
+    # closed loop: everything queued at t = 0
+    reqs = [serve.Request(k, c, c["steps"], 0.0) for k, c in enumerate(cases)]
+    closed = serve.summary(serve.run(pool(), reqs, chunk=200))
+    cap = closed["mlups"] * 1e6  # LUP/s
+    rate = 0.8 * cap / mean_lups  # requests per second
+    arr = np.cumsum(np.random.default_rng(7802).exponential(1.0 / rate, size=len(cases)))
+    reqs = [serve.Request(k, c, c["steps"], float(arr[k])) for k, c in enumerate(cases)]
+    opened = serve.summary(serve.run(pool(), reqs, chunk=200))
+    # the plain sequential per-case loop: create, init, step, read out, one case at a time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in cases:
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        s.init(c["phi"], c.get("u"), c.get("v"), c.get("p"))
+        s.step(c["steps"])
+        s.macros()
+        del s
+    seq = time.perf_counter() - t0
+    return {"workload": f"{len(cases)} requests: layered Poiseuille (mu ratio 100, nx 64, ny 64..1024) "
+                        "and stationary bubbles (64^2..1024^2), 1k-20k steps each (seed 7802), FP32, "
+                        "pool of 32 slots and an 8 GiB arena",
+            "closed_loop_mlups": round(closed["mlups"], 1),
+            "arrival_rate_per_s": round(rate, 3), "load": 0.8,
+            "served_mlups": round(opened["mlups"], 1),
+            "p50_s": round(opened["p50_s"], 4), "p99_s": round(opened["p99_s"], 4),
+            "sequential_mlups": round(sum(lups) / seq / 1e6, 1)}
 
 
 def cpu_baseline(budget_s):
@@ -253,6 +303,8 @@ def main():
                           "per_case_loop_mlups": round(bc * args.batch_steps / tp / 1e6, 1),
                           "roofline": roofline(bc, args.batch_steps, tb, "fp32")}
         del solvers
+        if args.serve_requests > 0:
+            rec["served"] = served_stream(torch, D, W, args.serve_requests)
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 

@@ -229,6 +229,54 @@ int dugks_batch_destroy(dugks_batch *b);
  * is NULL). Never NULL. */
 const char *dugks_batch_last_error(const dugks_batch *b);
 
+/* ------------------------------------------------------------ serving pool
+ * Continuous batching of solve requests (cases) of one precision and model.
+ * The pool owns one device arena of hbm_bytes for case states and a table of
+ * max_cases slots. A case is admitted while others run if a slot is free and
+ * its state (dugks_pool_case_bytes) fits in the arena; otherwise admission
+ * returns EBUSY and changes nothing. Every admitted case runs its own number
+ * of steps: dugks_pool_step advances all cases that still have steps left,
+ * in batched launches, and a case stops at its target. A retired case's
+ * memory returns to the arena once the pool's stream has passed the
+ * retirement. Results do not depend on the other cases in the pool, bit for
+ * bit (the step of a case reads only its own state). Not thread-safe. */
+typedef struct dugks_pool dugks_pool;
+
+/* max_cells bounds the cells of one case (it sizes the staging area for
+ * init and readout: 5 max_cells doubles). EINVAL, ENOMEM, EDEVICE. */
+int dugks_pool_create(size_t hbm_bytes, int max_cases, long long max_cells,
+                      int precision, int model, dugks_pool **out);
+/* Stream of all pool work (hipStream_t, NULL = null stream). */
+int dugks_pool_set_stream(dugks_pool *p, void *stream);
+/* Arena bytes a case of this shape takes (two state buffers). */
+size_t dugks_pool_case_bytes(int nx, int ny, int precision, int model);
+/* Admit a case: parameters as dugks_set_params, initial fields as
+ * dugks_init_fields (host [ny][nx] doubles, copied during the call; u, v, p
+ * may be NULL), and its number of steps. The initial state is built on the
+ * pool's stream. *slot receives the case's slot. EBUSY: no free slot or no
+ * room in the arena. EINVAL: bad sizes or parameters. */
+int dugks_pool_admit(dugks_pool *p, int nx, int ny, const dugks_params *prm,
+                     const double *phi, const double *u, const double *v,
+                     const double *pr, long long nsteps, int *slot);
+/* Enqueue nsteps pool steps: every case with steps left advances by
+ * min(nsteps, steps left). use_graph: replay a captured HIP graph while the
+ * set of running cases does not change. Asynchronous. */
+int dugks_pool_step(dugks_pool *p, int nsteps, int use_graph);
+/* Steps done and steps left of a slot (host bookkeeping, -1 for a free slot). */
+long long dugks_pool_steps_done(const dugks_pool *p, int slot);
+long long dugks_pool_remaining(const dugks_pool *p, int slot);
+/* Cell macros of a slot's current state, as dugks_get_macros (synchronous:
+ * waits for the work queued on the pool's stream). */
+int dugks_pool_get_macros(dugks_pool *p, int slot, double *phi, double *u,
+                          double *v, double *pr, double *rho);
+/* Free a slot; its arena block is reused once the stream passes this point. */
+int dugks_pool_retire(dugks_pool *p, int slot);
+/* Free arena bytes (blocks whose retirement the stream has passed). */
+size_t dugks_pool_bytes_free(dugks_pool *p);
+int dugks_pool_sync(dugks_pool *p);
+const char *dugks_pool_last_error(const dugks_pool *p);
+int dugks_pool_destroy(dugks_pool *p);
+
 #ifdef __cplusplus
 }
 #endif

@@ -129,6 +129,19 @@ def lib():
             "dugks_batch_sync": (i, [vp]),
             "dugks_batch_destroy": (i, [vp]),
             "dugks_batch_last_error": (C.c_char_p, [vp]),
+            "dugks_pool_create": (i, [sz, i, ll, i, i, C.POINTER(vp)]),
+            "dugks_pool_set_stream": (i, [vp, vp]),
+            "dugks_pool_case_bytes": (sz, [i, i, i, i]),
+            "dugks_pool_admit": (i, [vp, i, i, C.POINTER(Params), dp, dp, dp, dp, ll, C.POINTER(i)]),
+            "dugks_pool_step": (i, [vp, i, i]),
+            "dugks_pool_steps_done": (ll, [vp, i]),
+            "dugks_pool_remaining": (ll, [vp, i]),
+            "dugks_pool_get_macros": (i, [vp, i, dp, dp, dp, dp, dp]),
+            "dugks_pool_retire": (i, [vp, i]),
+            "dugks_pool_bytes_free": (sz, [vp]),
+            "dugks_pool_sync": (i, [vp]),
+            "dugks_pool_last_error": (C.c_char_p, [vp]),
+            "dugks_pool_destroy": (i, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -343,3 +356,77 @@ class Batch:
 
     def sync(self):
         _check(lib().dugks_batch_sync(self.b), self.b, batch=True)
+
+
+class Pool:
+    """Serving pool (continuous batching): cases admitted by arena footprint
+    while others run, advanced together, read out and retired one by one."""
+
+    def __init__(self, hbm_bytes, max_cases, max_cells, precision="fp32", model="coupled"):
+        self.precision = FP64 if precision == "fp64" else FP32
+        self.model = MODEL_COUPLED if model == "coupled" else MODEL_AC
+        p = C.c_void_p()
+        rc = lib().dugks_pool_create(int(hbm_bytes), int(max_cases), int(max_cells),
+                                     self.precision, self.model, C.byref(p))
+        if rc != OK:
+            raise DugksError(rc, (lib().dugks_pool_last_error(None) or b"").decode())
+        self.p = p
+        self.shapes = {}
+
+    def _check(self, rc):
+        if rc != OK:
+            raise DugksError(rc, (lib().dugks_pool_last_error(self.p) or b"").decode())
+
+    def __del__(self):
+        p = getattr(self, "p", None)
+        if p:
+            try:
+                lib().dugks_pool_destroy(p)
+            except Exception:  # interpreter shutdown: module globals may be gone
+                pass
+            self.p = None
+
+    def set_stream(self, stream):
+        self._check(lib().dugks_pool_set_stream(self.p, C.c_void_p(stream)))
+
+    def case_bytes(self, nx, ny):
+        return int(lib().dugks_pool_case_bytes(int(nx), int(ny), self.precision, self.model))
+
+    def admit(self, case, nsteps):
+        """Admit a case dict (workloads format); returns its slot, or None
+        when the pool has no free slot or no room (EBUSY)."""
+        shape = (case["ny"], case["nx"])
+        prm = make_params(case["params"])
+        arrs = [_host(case.get(k), shape) for k in ("phi", "u", "v", "p")]
+        slot = C.c_int(-1)
+        rc = lib().dugks_pool_admit(self.p, case["nx"], case["ny"], C.byref(prm),
+                                    *[_dptr(a) for a in arrs], int(nsteps), C.byref(slot))
+        if rc == EBUSY:
+            return None
+        self._check(rc)
+        self.shapes[slot.value] = shape
+        return slot.value
+
+    def step(self, nsteps, use_graph=True):
+        self._check(lib().dugks_pool_step(self.p, int(nsteps), 1 if use_graph else 0))
+
+    def steps_done(self, slot):
+        return int(lib().dugks_pool_steps_done(self.p, int(slot)))
+
+    def remaining(self, slot):
+        return int(lib().dugks_pool_remaining(self.p, int(slot)))
+
+    def macros(self, slot):
+        out = [np.empty(self.shapes[slot]) for _ in range(5)]
+        self._check(lib().dugks_pool_get_macros(self.p, int(slot), *[_dptr(a) for a in out]))
+        return dict(zip(("phi", "u", "v", "p", "rho"), out))
+
+    def retire(self, slot):
+        self._check(lib().dugks_pool_retire(self.p, int(slot)))
+        self.shapes.pop(slot, None)
+
+    def bytes_free(self):
+        return int(lib().dugks_pool_bytes_free(self.p))
+
+    def sync(self):
+        self._check(lib().dugks_pool_sync(self.p))

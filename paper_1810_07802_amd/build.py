@@ -9,7 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdugks.so")
-SOURCES = [os.path.join(CSRC, "dugks_kernels.hip"), os.path.join(CSRC, "dugks_api.cpp")]
+SOURCES = [os.path.join(CSRC, "dugks_kernels.hip"), os.path.join(CSRC, "dugks_api.cpp"),
+           os.path.join(CSRC, "dugks_pool.cpp")]
 HEADERS = [os.path.join(CSRC, "dugks_impl.h"),
            os.path.join(os.path.dirname(HERE), "include", "dugks.h")]
 

@@ -14,47 +14,17 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dugks.h"
-#include "dugks_impl.h"
+
+#include "dugks_host.h"
 
 using dugks::CaseDev;
 using dugks::Item;
 using dugks::StepArgs;
 
-namespace {
-
-constexpr double kRT = 1.0 / 3.0;
-constexpr int kDiagBlocks = 256;
+namespace dugks {
+namespace host {
 
 thread_local std::string g_create_error = "no error";
-
-}  // namespace
-
-struct dugks_handle {
-  int nx = 0, ny = 0, precision = 0, model = 0;
-  dugks_params params{};
-  bool has_params = false, has_state = false;
-  hipStream_t stream = nullptr;
-  void* buf[2] = {nullptr, nullptr};
-  size_t buf_bytes = 0;
-  CaseDev hc{};
-  CaseDev* dc = nullptr;
-  Item* items = nullptr;
-  int nitems = 0;
-  int seg_rows = 0;  // 0: automatic
-  long long* step_base = nullptr;  // device: steps done
-  long long steps = 0;             // host mirror
-  double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
-  std::string err = "no error";
-  bool dirty_case = true;
-
-  bool fp64() const { return precision == DUGKS_FP64; }
-  bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
-  size_t n() const { return (size_t)nx * ny; }
-  size_t elem() const { return fp64() ? 8 : 4; }
-};
-
-namespace {
 
 int fail(dugks_handle* h, int code, const std::string& msg) {
   if (h) h->err = msg;
@@ -66,12 +36,6 @@ int hip_fail(dugks_handle* h, hipError_t e, const char* what) {
   return fail(h, DUGKS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIPCHK(h, expr)                                   \
-  do {                                                    \
-    hipError_t e_ = (expr);                               \
-    if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
-  } while (0)
-
 // Resident step waves on the current device (CUs x waves per CU).
 int wave_capacity(bool fp64, bool coupled, bool walls) {
   int dev = 0;
@@ -82,11 +46,6 @@ int wave_capacity(bool fp64, bool coupled, bool walls) {
   }
   return prop.multiProcessorCount * dugks::step_waves_per_cu(fp64, coupled, walls);
 }
-
-// Shape of the step work of one case: strips of 62 columns, and rows.
-struct StripShape {
-  int nstrips, ny;
-};
 
 // Waves (tiles) of a list of cases cut into segments of `seg` rows.
 long long tile_count(const std::vector<StripShape>& cs, int seg) {
@@ -184,6 +143,10 @@ int upload_case(dugks_handle* h) {
   if (!h->dirty_case) return DUGKS_OK;
   fill_case(h);
   HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
+  if (h->borrowed) {  // a pool case: the pool launches it with its own items, and
+    h->dirty_case = false;  // h->hc, the source of the copy, lives as long as the case
+    return DUGKS_OK;
+  }
   std::vector<Item> it;
   it.reserve((size_t)h->hc.nstrips * h->hc.nsegs);
   for (int s = 0; s < h->hc.nsegs; ++s)
@@ -258,7 +221,10 @@ int launch_steps(dugks_handle* h, int nsteps) {
   return DUGKS_OK;
 }
 
-}  // namespace
+}  // namespace host
+}  // namespace dugks
+
+using namespace dugks::host;
 
 extern "C" {
 
@@ -542,6 +508,7 @@ const char* dugks_last_error(const dugks_handle* h) {
 
 int dugks_destroy(dugks_handle* h) {
   if (!h) return DUGKS_OK;
+  if (h->borrowed) return fail(h, DUGKS_EINVAL, "a pool case is retired through its pool");
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   for (int k = 0; k < 2; ++k)

@@ -1,0 +1,80 @@
+// Host-side internals of libdugks shared by the handle API (dugks_api.cpp)
+// and the serving pool (dugks_pool.cpp): the handle, and the helpers that
+// fill and upload a case descriptor and launch its steps.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dugks.h"
+#include "dugks_impl.h"
+
+struct dugks_handle {
+  int nx = 0, ny = 0, precision = 0, model = 0;
+  dugks_params params{};
+  bool has_params = false, has_state = false;
+  hipStream_t stream = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  size_t buf_bytes = 0;
+  dugks::CaseDev hc{};
+  dugks::CaseDev* dc = nullptr;
+  dugks::Item* items = nullptr;
+  int nitems = 0;
+  int seg_rows = 0;  // 0: automatic
+  long long* step_base = nullptr;  // device: steps done
+  long long steps = 0;             // host mirror
+  double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
+  std::string err = "no error";
+  bool dirty_case = true;
+  // a case of a serving pool: its buffers, descriptor, counter and scratch
+  // belong to the pool, which also launches its steps
+  bool borrowed = false;
+
+  bool fp64() const { return precision == DUGKS_FP64; }
+  bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
+  size_t n() const { return (size_t)nx * ny; }
+  size_t elem() const { return fp64() ? 8 : 4; }
+};
+
+namespace dugks {
+namespace host {
+
+constexpr double kRT = 1.0 / 3.0;
+constexpr int kDiagBlocks = 256;
+
+// error of the last failed create (no handle to hold it)
+extern thread_local std::string g_create_error;
+
+int fail(dugks_handle* h, int code, const std::string& msg);
+int hip_fail(dugks_handle* h, hipError_t e, const char* what);
+
+#define HIPCHK(h, expr)                                    \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
+  } while (0)
+
+// Resident step waves on the current device (CUs x waves per CU).
+int wave_capacity(bool fp64, bool coupled, bool walls);
+
+// Shape of the step work of one case: strips of 62 columns, and rows.
+struct StripShape {
+  int nstrips, ny;
+};
+long long tile_count(const std::vector<StripShape>& cs, int seg);
+int fit_seg_rows(const std::vector<StripShape>& cs, long long budget);
+int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity);
+
+// Derived constants of the handle's parameters into h->hc, and the upload of
+// the descriptor (and, for a plain handle, of its work items).
+void fill_case(dugks_handle* h);
+int upload_case(dugks_handle* h);
+int validate(const dugks_handle* h, const dugks_params* p, std::string& why);
+size_t state_set_bytes(int nx, int ny, int precision, int model);
+int ensure_scratch(dugks_handle* h);
+int launch_steps(dugks_handle* h, int nsteps);
+
+}  // namespace host
+}  // namespace dugks
