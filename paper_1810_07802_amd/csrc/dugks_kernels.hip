@@ -65,15 +65,25 @@ __device__ __forceinline__ int row_of(int r, int ny, int walls) {
 
 // Cross-lane moves inside the wave: value of lane l-1 / l+1 (wrapping; the
 // wrapped values only reach the halo lanes, whose results are discarded).
-__device__ __forceinline__ float perm(int addr, float v) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+// Neighbour lanes by DPP wavefront rotates, fused into the consuming ALU
+// instruction where the encoding allows: right = lane + 1 (wave_rol:1), left
+// = lane - 1 (wave_ror:1), both wrapping around the 64 lanes (every lane
+// receives a value, so no lane keeps an old one).
+template <int CTRL>
+__device__ __forceinline__ float rot(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
-__device__ __forceinline__ double perm(int addr, double v) {
+template <int CTRL>
+__device__ __forceinline__ double rot(double v) {
   int2 w = *reinterpret_cast<int2*>(&v);
-  w.x = __builtin_amdgcn_ds_bpermute(addr, w.x);
-  w.y = __builtin_amdgcn_ds_bpermute(addr, w.y);
+  w.x = __builtin_amdgcn_mov_dpp(w.x, CTRL, 0xF, 0xF, true);
+  w.y = __builtin_amdgcn_mov_dpp(w.y, CTRL, 0xF, 0xF, true);
   return *reinterpret_cast<double*>(&w);
 }
+template <typename T>
+__device__ __forceinline__ T nbr_r(T v) { return rot<0x134>(v); }  // value of lane + 1
+template <typename T>
+__device__ __forceinline__ T nbr_l(T v) { return rot<0x13C>(v); }  // value of lane - 1
 
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
@@ -479,19 +489,19 @@ struct RowData {
 };
 
 template <typename T, bool CPL>
-__device__ __forceinline__ void x_diffs(int aL, int aR, RowData<T, CPL>& r) {
+__device__ __forceinline__ void x_diffs(RowData<T, CPL>& r) {
   const int diag[4] = {2, 4, 6, 8};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int q = diag[k];
-    r.txf[q] = perm(aR, r.cell.fb[q]) - perm(aL, r.cell.fb[q]);
-    if (CPL) r.txg[q] = perm(aR, r.cell.gb[q]) - perm(aL, r.cell.gb[q]);
+    r.txf[q] = nbr_r(r.cell.fb[q]) - nbr_l(r.cell.fb[q]);
+    if (CPL) r.txg[q] = nbr_r(r.cell.gb[q]) - nbr_l(r.cell.gb[q]);
   }
-  r.txMx = perm(aR, r.cell.Mx) - perm(aL, r.cell.Mx);
+  r.txMx = nbr_r(r.cell.Mx) - nbr_l(r.cell.Mx);
   if (CPL) {
-    r.txJx = perm(aR, r.cell.Jx) - perm(aL, r.cell.Jx);
-    r.txPxx = perm(aR, r.cell.Pxx) - perm(aL, r.cell.Pxx);
-    r.txPxy = perm(aR, r.cell.Pxy) - perm(aL, r.cell.Pxy);
+    r.txJx = nbr_r(r.cell.Jx) - nbr_l(r.cell.Jx);
+    r.txPxx = nbr_r(r.cell.Pxx) - nbr_l(r.cell.Pxx);
+    r.txPxy = nbr_r(r.cell.Pxy) - nbr_l(r.cell.Pxy);
   }
 }
 
@@ -575,7 +585,6 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   const int ci = wrap(col, nx);
   const int cx = lane == 0 ? wrap(col - 1, nx) : (lane == 63 ? wrap(col + 1, nx) : ci);
   const bool store = lane >= 1 && lane <= kStripCols && col < nx;
-  const int aL = ((lane + 63) & 63) << 2, aR = ((lane + 1) & 63) << 2;
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
@@ -615,7 +624,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   };
   // phi of one row for (left, own, right) columns from own and extra values
   auto phi_lr = [&](T own, T ext, T (&o)[3]) {
-    T left = perm(aL, own), right = perm(aR, own);
+    T left = nbr_l(own), right = nbr_r(own);
     if (lane == 0) left = ext;
     if (lane == 63) right = ext;
     o[0] = left; o[1] = own; o[2] = right;
@@ -635,7 +644,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     const int slot = r & 1;
 #pragma unroll
     for (int q = 0; q < 18; ++q) stash[slot][q][lane] = tp[q];
-    x_diffs<T, CPL>(aL, aR, rd);
+    x_diffs<T, CPL>(rd);
   };
 
   // One pass of the march for output row k. It stages row k+1 into `nxt`,
@@ -675,33 +684,33 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
       for (int q = 1; q < 9; ++q) {
         if (EX[q] == 0) continue;
         const T ex = T(EX[q]), ey = T(EY[q]);
-        const T Rf = perm(aR, L.fb[q]);
+        const T Rf = nbr_r(L.fb[q]);
         T vf = T(0.5) * (L.fb[q] + Rf) - h * ex * (Rf - L.fb[q]);
-        if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + perm(aR, ty.f[q]));
+        if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + nbr_r(ty.f[q]));
         fbar[q] = vf;
         if (CPL) {
-          const T Rg = perm(aR, L.gb[q]);
+          const T Rg = nbr_r(L.gb[q]);
           T vg = T(0.5) * (L.gb[q] + Rg) - h * ex * (Rg - L.gb[q]);
-          if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + perm(aR, ty.g[q]));
+          if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + nbr_r(ty.g[q]));
           gbar[q] = vg;
         }
       }
-      const T phif = T(0.5) * (L.M0 + perm(aR, L.M0)) - h * (perm(aR, L.Mx) - L.Mx) -
-                     hq * (ty.My + perm(aR, ty.My));
+      const T phif = T(0.5) * (L.M0 + nbr_r(L.M0)) - h * (nbr_r(L.Mx) - L.Mx) -
+                     hq * (ty.My + nbr_r(ty.My));
       T N0f = T(0), Jxf = T(0), Jyf = T(0);
       if (CPL) {
-        N0f = T(0.5) * (L.N0 + perm(aR, L.N0)) - h * (perm(aR, L.Jx) - L.Jx) -
-              hq * (ty.Jy + perm(aR, ty.Jy));
-        Jxf = T(0.5) * (L.Jx + perm(aR, L.Jx)) - h * (perm(aR, L.Pxx) - L.Pxx) -
-              hq * (ty.Pxy + perm(aR, ty.Pxy));
-        Jyf = T(0.5) * (L.Jy + perm(aR, L.Jy)) - h * (perm(aR, L.Pxy) - L.Pxy) -
-              hq * (ty.Pyy + perm(aR, ty.Pyy));
+        N0f = T(0.5) * (L.N0 + nbr_r(L.N0)) - h * (nbr_r(L.Jx) - L.Jx) -
+              hq * (ty.Jy + nbr_r(ty.Jy));
+        Jxf = T(0.5) * (L.Jx + nbr_r(L.Jx)) - h * (nbr_r(L.Pxx) - L.Pxx) -
+              hq * (ty.Pxy + nbr_r(ty.Pxy));
+        Jyf = T(0.5) * (L.Jy + nbr_r(L.Jy)) - h * (nbr_r(L.Pxy) - L.Pxy) -
+              hq * (ty.Pyy + nbr_r(ty.Pyy));
       }
-      const T gxf = T(0.5) * (L.gx + perm(aR, L.gx));
-      const T gyf = T(0.5) * (L.gy + perm(aR, L.gy));
-      const T muf = T(0.5) * (L.mu + perm(aR, L.mu));
-      const T Dxf = T(0.5) * (L.Dx + perm(aR, L.Dx));
-      const T Dyf = T(0.5) * (L.Dy + perm(aR, L.Dy));
+      const T gxf = T(0.5) * (L.gx + nbr_r(L.gx));
+      const T gyf = T(0.5) * (L.gy + nbr_r(L.gy));
+      const T muf = T(0.5) * (L.mu + nbr_r(L.mu));
+      const T Dxf = T(0.5) * (L.Dx + nbr_r(L.Dx));
+      const T Dyf = T(0.5) * (L.Dy + nbr_r(L.Dy));
       const int kr = row_idx(k, ny, walls);
       face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
                          (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
@@ -724,7 +733,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       T J = T(0);
-      if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - perm(aL, fx_f[q]));
+      if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - nbr_l(fx_f[q]));
       if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
       nv[val_f(q)] = stash[slot][q][lane] - dt * J;
       phin += nv[val_f(q)];
@@ -733,7 +742,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         T J = T(0);
-        if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - perm(aL, fx_g[q]));
+        if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - nbr_l(fx_g[q]));
         if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
         nv[val_g(q)] = stash[slot][9 + q][lane] - dt * J;
       }
