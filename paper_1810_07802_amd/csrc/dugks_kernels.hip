@@ -175,27 +175,50 @@ __device__ __forceinline__ void presc_vel(const CaseDev& C, double x, double y,
 //   Qe = 3p + rho E2 + tau [3ae - a0 E2 + 3 (3be - b0 (1 + E2))]
 //   Qo = 3 rho e + tau [a E2 - 3 a0 e + 3 (b (1 + E2) - 3 b0 e)]
 // (a0 = u.grad rho, b0 = u.F): one evaluation serves both directions.
+// With G = grad rho + 3F, A = xi.G and A0 = u.G the brackets regroup into
+//   Qe = (3p - 3 tau b0) + E2 (rho - tau A0) + 3 tau e A
+//   Qo = 3e (rho - tau A0) + tau (E2 A + 3b)
+// whose point terms (in parentheses) are shared by all pairs.
 template <typename T>
 struct GTerms {
-  T u, v, uu, p, rho, tau, drx, dry, Fx, Fy, a0, b0;
+  T u, v, m15uu;  // velocity and -1.5 |u|^2
+  T Gx, Gy;       // grad rho + 3F
+  T F3x, F3y;     // 3F
+  T Pp;           // 3p - 3 tau b0
+  T Rp, Rp3;      // rho - tau A0 and three times it
+  T tau, tau3;
 };
+template <typename T>
+__device__ __forceinline__ GTerms<T> g_terms(T u, T v, T uu, T p, T rho, T tau, T drx, T dry,
+                                             T Fx, T Fy) {
+  GTerms<T> s;
+  s.u = u;
+  s.v = v;
+  s.m15uu = T(-1.5) * uu;
+  s.F3x = T(3) * Fx;
+  s.F3y = T(3) * Fy;
+  s.Gx = drx + s.F3x;
+  s.Gy = dry + s.F3y;
+  s.tau = tau;
+  s.tau3 = T(3) * tau;
+  s.Pp = T(3) * p - s.tau3 * (u * Fx + v * Fy);
+  s.Rp = rho - tau * (u * s.Gx + v * s.Gy);
+  s.Rp3 = T(3) * s.Rp;
+  return s;
+}
 template <typename T>
 __device__ __forceinline__ void g_pair(const GTerms<T>& s, int ex, int ey, T& qe, T& qo) {
   const T e = T(ex) * s.u + T(ey) * s.v;
-  const T a = T(ex) * s.drx + T(ey) * s.dry;
-  const T b = T(ex) * s.Fx + T(ey) * s.Fy;
-  const T E2 = T(4.5) * e * e - T(1.5) * s.uu;
-  const T S_e = T(3) * a * e - s.a0 * E2 + T(3) * (T(3) * b * e - s.b0 * (T(1) + E2));
-  const T S_o = a * E2 - T(3) * s.a0 * e + T(3) * (b * (T(1) + E2) - T(3) * s.b0 * e);
-  qe = T(3) * s.p + s.rho * E2 + s.tau * S_e;
-  qo = T(3) * s.rho * e + s.tau * S_o;
+  const T A = T(ex) * s.Gx + T(ey) * s.Gy;
+  const T b3 = T(ex) * s.F3x + T(ey) * s.F3y;
+  const T E2 = T(4.5) * e * e + s.m15uu;
+  qe = s.Pp + E2 * s.Rp + s.tau3 * e * A;
+  qo = e * s.Rp3 + s.tau * (E2 * A + b3);
 }
-// rest population: e = a = b = 0, and g^eq_0 carries -3p (Eq. 17)
+// rest population: e = A = b = 0, and g^eq_0 carries -3p (Eq. 17)
 template <typename T>
-__device__ __forceinline__ T g_rest(const GTerms<T>& s) {
-  const T E2 = T(-1.5) * s.uu;
-  const T S0 = -s.a0 * E2 - T(3) * s.b0 * (T(1) + E2);
-  return wq<T>(0) * (T(3) * s.p + s.rho * E2 + s.tau * S0) - T(3) * s.p;
+__device__ __forceinline__ T g_rest(const GTerms<T>& s, T p) {
+  return wq<T>(0) * (s.Pp + s.m15uu * s.Rp) - T(3) * p;
 }
 
 // ------------------------------------------------------------- cell stage
@@ -258,7 +281,7 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
     double gbD, tauD;
     g_relax<false>(C, (double)phi, rhoD, gbD, tauD);
     const T gb = T(gbD);
-    const GTerms<T> s{u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy, u * drx + v * dry, u * Fx + v * Fy};
+    const GTerms<T> s = g_terms<T>(u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy);
     // Eq. 29-30 as increments: bar+ = g + d, tilde+ = g + (4/3) d with
     // d = b (g^eq + tau S - g)
     auto relax = [&](int q, T target) {
@@ -266,7 +289,7 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
       o.gb[q] = gt[q] + d;
       tp[9 + q] = gt[q] + T(4.0 / 3.0) * d;
     };
-    relax(0, g_rest<T>(s));
+    relax(0, g_rest<T>(s, p));
 #pragma unroll
     for (int q = 1; q <= 4; ++q) {
       T qe, qo;
@@ -347,7 +370,7 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
     double gbD, tauD;
     g_relax<true>(C, (double)phif, rhoD, gbD, tauD);
     const T gb = T(gbD);
-    const GTerms<T> s{u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy, u * drx + v * dry, u * Fx + v * Fy};
+    const GTerms<T> s = g_terms<T>(u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy);
     // Eq. 28 in increment form, for the pairs of directions crossing the face
 #pragma unroll
     for (int q = 1; q <= 4; ++q) {
@@ -511,16 +534,20 @@ __device__ __forceinline__ void y_face(const CaseDev& C, const RowData<T, CPL>& 
                                        const RowData<T, CPL>& U, double xf, double yf,
                                        double tf, T (&fo)[9], T (&go)[9]) {
   const T h = T(C.h), hq = T(0.25) * T(C.h);
+  // mean minus h e_y times the normal slope, as weights of the two cells:
+  // (1/2 + h e_y) below + (1/2 - h e_y) above
+  const T cp = T(0.5) + h, cm = T(0.5) - h;
   T fbar[9], gbar[9];
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
     if (EY[q] == 0) continue;
-    const T ey = T(EY[q]), ex = T(EX[q]);
-    T vf = T(0.5) * (D.cell.fb[q] + U.cell.fb[q]) - h * ey * (U.cell.fb[q] - D.cell.fb[q]);
+    const T ex = T(EX[q]);
+    const T cD = EY[q] > 0 ? cp : cm, cU = EY[q] > 0 ? cm : cp;
+    T vf = cD * D.cell.fb[q] + cU * U.cell.fb[q];
     if (EX[q] != 0) vf -= hq * ex * (D.txf[q] + U.txf[q]);
     fbar[q] = vf;
     if (CPL) {
-      T vg = T(0.5) * (D.cell.gb[q] + U.cell.gb[q]) - h * ey * (U.cell.gb[q] - D.cell.gb[q]);
+      T vg = cD * D.cell.gb[q] + cU * U.cell.gb[q];
       if (EX[q] != 0) vg -= hq * ex * (D.txg[q] + U.txg[q]);
       gbar[q] = vg;
     }
@@ -679,18 +706,20 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     {
       const Cell<T>& L = cur_r.cell;
       const T h = T(C.h), hq = T(0.25) * T(C.h);
+      // (1/2 + h e_x) own + (1/2 - h e_x) right neighbour (mean minus h e_x
+      // times the normal slope)
+      const T cp = T(0.5) + h, cm = T(0.5) - h;
       T fbar[9], gbar[9];
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
         if (EX[q] == 0) continue;
-        const T ex = T(EX[q]), ey = T(EY[q]);
-        const T Rf = nbr_r(L.fb[q]);
-        T vf = T(0.5) * (L.fb[q] + Rf) - h * ex * (Rf - L.fb[q]);
+        const T ey = T(EY[q]);
+        const T cL = EX[q] > 0 ? cp : cm, cR = EX[q] > 0 ? cm : cp;
+        T vf = cL * L.fb[q] + cR * nbr_r(L.fb[q]);
         if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + nbr_r(ty.f[q]));
         fbar[q] = vf;
         if (CPL) {
-          const T Rg = nbr_r(L.gb[q]);
-          T vg = T(0.5) * (L.gb[q] + Rg) - h * ex * (Rg - L.gb[q]);
+          T vg = cL * L.gb[q] + cR * nbr_r(L.gb[q]);
           if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + nbr_r(ty.g[q]));
           gbar[q] = vg;
         }
