@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdugks.so")
 SOURCES = [os.path.join(CSRC, "dugks_kernels.hip"), os.path.join(CSRC, "dugks_api.cpp"),
            os.path.join(CSRC, "dugks_pool.cpp")]
-HEADERS = [os.path.join(CSRC, "dugks_impl.h"),
+HEADERS = [os.path.join(CSRC, "dugks_impl.h"), os.path.join(CSRC, "dugks_host.h"),
            os.path.join(os.path.dirname(HERE), "include", "dugks.h")]
 
 
@@ -26,6 +26,11 @@ def command(out: str = LIB, extra=()) -> list[str]:
     return [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions stay off (see the design notes)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # multiply-adds are fused within a source expression only, never
+            # across statements: the same expression then rounds the same way
+            # in every kernel that inlines it (the one-row kernel and the
+            # march give the same bits)
+            "-ffp-contract=on",
             "-Wno-unused-command-line-argument", *extra, "-o", out, *SOURCES]
 
 

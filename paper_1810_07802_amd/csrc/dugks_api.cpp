@@ -208,11 +208,12 @@ int ensure_scratch(dugks_handle* h) {
 }
 
 int launch_steps(dugks_handle* h, int nsteps) {
-  StepArgs a;
+  StepArgs a{};
   a.cases = h->dc;
   a.items = h->items;
   a.nitems = h->nitems;
   a.step_base = h->step_base;
+  a.one_row = h->hc.seg_rows == 1 ? 1 : 0;
   for (int k = 0; k < nsteps; ++k) {
     a.kofs = k;
     HIPCHK(h, dugks::launch_step(h->fp64(), h->coupled(), h->hc.walls != 0, a, h->stream));
@@ -533,6 +534,7 @@ struct dugks_batch {
   CaseDev* dcases = nullptr;
   Item* items[2] = {nullptr, nullptr};  // work items: periodic cases, wall cases
   int nitems[2] = {0, 0};
+  int one_row[2] = {1, 1};              // every case of the group has one-row tiles
   std::vector<int> seg;                 // rows per segment used for each case
   long long* step_base = nullptr;  // device: global step of the batch
   long long gstep = 0;             // host mirror
@@ -575,7 +577,7 @@ int sync_descriptors(dugks_batch* b) {
 }
 
 int record_steps(dugks_batch* b, int nsteps) {
-  StepArgs a;
+  StepArgs a{};
   a.cases = b->dcases;
   a.step_base = b->step_base;
   for (int k = 0; k < nsteps; ++k) {
@@ -584,6 +586,7 @@ int record_steps(dugks_batch* b, int nsteps) {
       if (b->nitems[w] == 0) continue;
       a.items = b->items[w];
       a.nitems = b->nitems[w];
+      a.one_row = b->one_row[w];
       BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, w == 1, a, b->stream));
     }
   }
@@ -634,6 +637,7 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
     const int w = c.walls ? 1 : 0;
     // a case's explicit tile wins over the group's automatic one
     b->seg[k] = cases[k]->seg_rows > 0 ? cases[k]->seg_rows : segw[w];
+    if (b->seg[k] != 1) b->one_row[w] = 0;
     const int nsegs = (c.ny + b->seg[k] - 1) / b->seg[k];
     for (int s = 0; s < nsegs; ++s)
       for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{k, x, s, 0});

@@ -93,6 +93,7 @@ struct StepArgs {
   int nitems;
   int kofs;                    // offset of this launch inside a step sequence
   const long long* step_base;  // device counter: global step of kofs = 0
+  int one_row;                 // every item is one row (seg_rows == 1): row kernel
 };
 
 // host-side launchers (dugks_kernels.hip)

@@ -589,6 +589,114 @@ __device__ __forceinline__ void y_diffs(const RowData<T, CPL>& up, const RowData
   t.Pyy = sc * (up.cell.Pyy - dn.cell.Pyy);
 }
 
+// x-face east of each cell of output row k and the wall faces of that row
+// (R15), from the records of rows k-1 (prv), k (cur) and k+1 (nxt); a bottom
+// wall face lands in prv.fnf/fng (the face below row k), a top one in
+// cur.fnf/fng (the face above).
+template <typename T, bool CPL, bool WALLS>
+__device__ __forceinline__ void row_xface(const CaseDev& C, int k, int ny, int ci, double tn,
+                                          RowData<T, CPL>& prv, RowData<T, CPL>& cur_r,
+                                          const RowData<T, CPL>& nxt, T (&fx_f)[9], T (&fx_g)[9]) {
+  constexpr int walls = WALLS ? 1 : 0;
+  const bool top_wall = walls && k == ny - 1;
+  const bool bot_wall = walls && k == 0;
+  Ty<T, CPL> ty;
+  if (WALLS && top_wall) y_diffs<T, CPL>(cur_r, prv, T(2), ty);
+  else if (WALLS && bot_wall) y_diffs<T, CPL>(nxt, cur_r, T(2), ty);
+  else y_diffs<T, CPL>(nxt, prv, T(1), ty);
+  // x-face east of the own cell: L = own lane, R = lane + 1
+  {
+    const Cell<T>& L = cur_r.cell;
+    const T h = T(C.h), hq = T(0.25) * T(C.h);
+    // (1/2 + h e_x) own + (1/2 - h e_x) right neighbour (mean minus h e_x
+    // times the normal slope)
+    const T cp = T(0.5) + h, cm = T(0.5) - h;
+    T fbar[9], gbar[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (EX[q] == 0) continue;
+      const T ey = T(EY[q]);
+      const T cL = EX[q] > 0 ? cp : cm, cR = EX[q] > 0 ? cm : cp;
+      T vf = cL * L.fb[q] + cR * nbr_r(L.fb[q]);
+      if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + nbr_r(ty.f[q]));
+      fbar[q] = vf;
+      if (CPL) {
+        T vg = cL * L.gb[q] + cR * nbr_r(L.gb[q]);
+        if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + nbr_r(ty.g[q]));
+        gbar[q] = vg;
+      }
+    }
+    const T phif = T(0.5) * (L.M0 + nbr_r(L.M0)) - h * (nbr_r(L.Mx) - L.Mx) -
+                   hq * (ty.My + nbr_r(ty.My));
+    T N0f = T(0), Jxf = T(0), Jyf = T(0);
+    if (CPL) {
+      N0f = T(0.5) * (L.N0 + nbr_r(L.N0)) - h * (nbr_r(L.Jx) - L.Jx) -
+            hq * (ty.Jy + nbr_r(ty.Jy));
+      Jxf = T(0.5) * (L.Jx + nbr_r(L.Jx)) - h * (nbr_r(L.Pxx) - L.Pxx) -
+            hq * (ty.Pxy + nbr_r(ty.Pxy));
+      Jyf = T(0.5) * (L.Jy + nbr_r(L.Jy)) - h * (nbr_r(L.Pxy) - L.Pxy) -
+            hq * (ty.Pyy + nbr_r(ty.Pyy));
+    }
+    const T gxf = T(0.5) * (L.gx + nbr_r(L.gx));
+    const T gyf = T(0.5) * (L.gy + nbr_r(L.gy));
+    const T muf = T(0.5) * (L.mu + nbr_r(L.mu));
+    const T Dxf = T(0.5) * (L.Dx + nbr_r(L.Dx));
+    const T Dyf = T(0.5) * (L.Dy + nbr_r(L.Dy));
+    const int kr = row_idx(k, ny, walls);
+    face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
+                       (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
+  }
+  if (WALLS) {
+    if (top_wall) wall_face<T, false>(C, cur_r.cell, prv.cell, cur_r.txf, cur_r.txg, cur_r.fnf, cur_r.fng);
+    if (bot_wall) wall_face<T, true>(C, cur_r.cell, nxt.cell, cur_r.txf, cur_r.txg, prv.fnf, prv.fng);
+  }
+}
+
+// Update of output row k (Eq. 24) and its stores. cur.fnf/fng hold the face
+// above the row, prv.fnf/fng the face below, fx the x-faces east of each
+// cell (the west face is the left lane's), tp(q) the tilde-plus values.
+template <typename T, bool CPL, typename TP>
+__device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int nx, int walls,
+                                           int ci, bool store, char* out, long long PB,
+                                           const RowData<T, CPL>& prv, const RowData<T, CPL>& cur_r,
+                                           const T (&fx_f)[9], const T (&fx_g)[9], TP tp) {
+  constexpr int NV = num_grouped(CPL);
+  const unsigned es = sizeof(T);
+  const T(&fn_f)[9] = cur_r.fnf;
+  const T(&fn_g)[9] = cur_r.fng;
+  const T(&fs_f)[9] = prv.fnf;
+  const T(&fs_g)[9] = prv.fng;
+  const int kr = row_idx(k, ny, walls);
+  const unsigned cell = (unsigned)kr * (unsigned)nx + ci;
+  const T dt = T(C.dt);
+  T nv[NV];  // new tilde f, tilde g, history
+  T phin = T(0);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    T J = T(0);
+    if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - nbr_l(fx_f[q]));
+    if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
+    nv[val_f(q)] = tp(q) - dt * J;
+    phin += nv[val_f(q)];
+  }
+  if (CPL) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      T J = T(0);
+      if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - nbr_l(fx_g[q]));
+      if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
+      nv[val_g(q)] = tp(9 + q) - dt * J;
+    }
+  }
+  nv[val_hist(CPL, 0)] = cur_r.cell.hx;
+  nv[val_hist(CPL, 1)] = cur_r.cell.hy;
+  // one masked region for all stores of the row
+  if (store) {
+    store_groups<T, NV>(out, PB, cell, nv);
+    gstore<T>(out + NV * PB, cell * es, phin);
+  }
+}
+
 template <typename T, bool CPL, bool WALLS>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A) {
   const int nb = gridDim.x;
@@ -682,8 +790,6 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   auto pass = [&](int k, Raw& raw, RowData<T, CPL>& prv, RowData<T, CPL>& cur_r,
                   RowData<T, CPL>& nxt, const T (&pa)[3], const T (&pb)[3], T (&pc)[3]) {
     const int rs = k + 1;
-    const bool top_wall = walls && k == ny - 1;
-    const bool bot_wall = walls && k == 0;
     // the phi ring advances every pass (ghost rows mirror into the grid), the
     // cell stage runs only for rows that exist
     phi_lr(raw.po, raw.pe, pc);
@@ -697,92 +803,11 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
       y_face<T, CPL>(C, cur_r, nxt, xc, (double)kr + 1.0, tn + C.h, cur_r.fnf, cur_r.fng);
     }
     if (k < j0) return;
-    Ty<T, CPL> ty;
-    if (WALLS && top_wall) y_diffs<T, CPL>(cur_r, prv, T(2), ty);
-    else if (WALLS && bot_wall) y_diffs<T, CPL>(nxt, cur_r, T(2), ty);
-    else y_diffs<T, CPL>(nxt, prv, T(1), ty);
-    // x-face east of the own cell: L = own lane, R = lane + 1
     T fx_f[9], fx_g[9];
-    {
-      const Cell<T>& L = cur_r.cell;
-      const T h = T(C.h), hq = T(0.25) * T(C.h);
-      // (1/2 + h e_x) own + (1/2 - h e_x) right neighbour (mean minus h e_x
-      // times the normal slope)
-      const T cp = T(0.5) + h, cm = T(0.5) - h;
-      T fbar[9], gbar[9];
-#pragma unroll
-      for (int q = 1; q < 9; ++q) {
-        if (EX[q] == 0) continue;
-        const T ey = T(EY[q]);
-        const T cL = EX[q] > 0 ? cp : cm, cR = EX[q] > 0 ? cm : cp;
-        T vf = cL * L.fb[q] + cR * nbr_r(L.fb[q]);
-        if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + nbr_r(ty.f[q]));
-        fbar[q] = vf;
-        if (CPL) {
-          T vg = cL * L.gb[q] + cR * nbr_r(L.gb[q]);
-          if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + nbr_r(ty.g[q]));
-          gbar[q] = vg;
-        }
-      }
-      const T phif = T(0.5) * (L.M0 + nbr_r(L.M0)) - h * (nbr_r(L.Mx) - L.Mx) -
-                     hq * (ty.My + nbr_r(ty.My));
-      T N0f = T(0), Jxf = T(0), Jyf = T(0);
-      if (CPL) {
-        N0f = T(0.5) * (L.N0 + nbr_r(L.N0)) - h * (nbr_r(L.Jx) - L.Jx) -
-              hq * (ty.Jy + nbr_r(ty.Jy));
-        Jxf = T(0.5) * (L.Jx + nbr_r(L.Jx)) - h * (nbr_r(L.Pxx) - L.Pxx) -
-              hq * (ty.Pxy + nbr_r(ty.Pxy));
-        Jyf = T(0.5) * (L.Jy + nbr_r(L.Jy)) - h * (nbr_r(L.Pxy) - L.Pxy) -
-              hq * (ty.Pyy + nbr_r(ty.Pyy));
-      }
-      const T gxf = T(0.5) * (L.gx + nbr_r(L.gx));
-      const T gyf = T(0.5) * (L.gy + nbr_r(L.gy));
-      const T muf = T(0.5) * (L.mu + nbr_r(L.mu));
-      const T Dxf = T(0.5) * (L.Dx + nbr_r(L.Dx));
-      const T Dyf = T(0.5) * (L.Dy + nbr_r(L.Dy));
-      const int kr = row_idx(k, ny, walls);
-      face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
-                         (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
-    }
-    if (WALLS) {
-      if (top_wall) wall_face<T, false>(C, cur_r.cell, prv.cell, cur_r.txf, cur_r.txg, cur_r.fnf, cur_r.fng);
-      if (bot_wall) wall_face<T, true>(C, cur_r.cell, nxt.cell, cur_r.txf, cur_r.txg, prv.fnf, prv.fng);
-    }
-    // update (Eq. 24) and store; the face below row k is the face above k-1
-    const T(&fn_f)[9] = cur_r.fnf;
-    const T(&fn_g)[9] = cur_r.fng;
-    const T(&fs_f)[9] = prv.fnf;
-    const T(&fs_g)[9] = prv.fng;
-    const int kr = row_idx(k, ny, walls);
-    const unsigned cell = (unsigned)kr * (unsigned)nx + ci;
+    row_xface<T, CPL, WALLS>(C, k, ny, ci, tn, prv, cur_r, nxt, fx_f, fx_g);
     const int slot = k & 1;
-    const T dt = T(C.dt);
-    T nv[NV];  // new tilde f, tilde g, history
-    T phin = T(0);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      T J = T(0);
-      if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - nbr_l(fx_f[q]));
-      if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
-      nv[val_f(q)] = stash[slot][q][lane] - dt * J;
-      phin += nv[val_f(q)];
-    }
-    if (CPL) {
-#pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        T J = T(0);
-        if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - nbr_l(fx_g[q]));
-        if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
-        nv[val_g(q)] = stash[slot][9 + q][lane] - dt * J;
-      }
-    }
-    nv[val_hist(CPL, 0)] = cur_r.cell.hx;
-    nv[val_hist(CPL, 1)] = cur_r.cell.hy;
-    // one masked region for all stores of the row
-    if (store) {
-      store_groups<T, NV>(out, PB, cell, nv);
-      gstore<T>(out + NV * PB, cell * es, phin);
-    }
+    row_update<T, CPL>(C, k, ny, nx, walls, ci, store, out, PB, prv, cur_r, fx_f, fx_g,
+                       [&](int q) { return stash[slot][q][lane]; });
   };
 
   // The three row records and the three phi rows rotate after each pass. (A
@@ -811,6 +836,157 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
       pass(k + 1, rb, R0, R1, R2, P0, P1, P2);
       rotate();
     }
+  }
+}
+
+// --------------------------------------------------- one-row step kernel
+
+// The fields of a row record that the faces and slopes of the neighbouring
+// rows read (y_face, y_diffs, wall_face): the populations that cross a
+// y-face, the x differences of the diagonal ones, the moments and the face
+// inputs. kRec values per lane.
+constexpr int kRec = 36;
+template <typename T, bool CPL, bool PUT>
+__device__ __forceinline__ void move_record(T (*X)[64], int lane, RowData<T, CPL>& r) {
+  int m = 0;
+  auto mv = [&](T& v) {
+    if (PUT) X[m][lane] = v;
+    else v = X[m][lane];
+    ++m;
+  };
+  const int ycross[6] = {2, 3, 4, 6, 7, 8};
+  const int diag[4] = {2, 4, 6, 8};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    mv(r.cell.fb[ycross[k]]);
+    if (CPL) mv(r.cell.gb[ycross[k]]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    mv(r.txf[diag[k]]);
+    if (CPL) mv(r.txg[diag[k]]);
+  }
+  mv(r.cell.M0); mv(r.cell.My); mv(r.txMx);
+  if (CPL) {
+    mv(r.cell.N0); mv(r.cell.Jx); mv(r.cell.Jy); mv(r.cell.Pxy); mv(r.cell.Pyy);
+    mv(r.txJx); mv(r.txPxx); mv(r.txPxy);
+  }
+  mv(r.cell.gx); mv(r.cell.gy); mv(r.cell.mu); mv(r.cell.Dx); mv(r.cell.Dy);
+}
+
+// One output row j of one 62-column strip per work group of three waves,
+// for tiles of one row (seg_rows == 1), where a single wave marching three
+// rows would be latency-bound. Wave w stages row j - 1 + w; the row records
+// meet in LDS; wave 0 forms the face between rows j - 1 and j while wave 1
+// forms the face above row j and the x-faces of row j; wave 1 then updates
+// row j. Every quantity goes through the same functions, with the same
+// inputs, as in the march of k_step, so the results are the same bit for bit.
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepArgs A) {
+  const int nb = gridDim.x;
+  const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (idx >= A.nitems) return;  // uniform over the work group
+  const Item it = A.items[idx];
+  const CaseDev C = A.cases[it.c];
+  const long long n = *A.step_base + A.kofs - C.step0;
+  if (n < 0 || n >= C.nsteps) return;  // uniform over the work group
+
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int nx = C.nx, ny = C.ny;
+  constexpr int walls = WALLS ? 1 : 0;
+  const int i0 = it.strip * kStripCols;
+  const int col = i0 - 1 + lane;
+  const int ci = wrap(col, nx);
+  const int cx = lane == 0 ? wrap(col - 1, nx) : (lane == 63 ? wrap(col + 1, nx) : ci);
+  const bool store = lane >= 1 && lane <= kStripCols && col < nx;
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  const long long PB = C.plane * (long long)sizeof(T);
+  constexpr int NV = num_grouped(CPL);
+  const char* phiP = in + NV * PB;
+  const unsigned es = sizeof(T);
+  const double tn = C.t0 + (double)n * C.dt;
+  const double xc = (double)ci + 0.5;
+  const int j = it.seg;  // tiles of one row: segment index = row
+  const int r = j - 1 + w;
+  const bool exists = !(walls && (r < 0 || r >= ny));
+
+  __shared__ T rec[3][kRec][64];
+  __shared__ T below[18][64];  // face between rows j - 1 and j (f, g)
+  __shared__ T tplus[18][64];  // tilde-plus of row j
+
+  RowData<T, CPL> rd;
+  if (exists) {
+    T v[NV];
+    load_groups<T, NV>(in, PB, (unsigned)row_idx(r, ny, walls) * (unsigned)nx + ci, v);
+    T f[9], g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      f[q] = v[val_f(q)];
+      g[q] = CPL ? v[val_g(q)] : T(0);
+    }
+    T ph[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const unsigned rb = (unsigned)row_idx(r - 1 + a, ny, walls) * (unsigned)nx;
+      const T own = gload<T>(phiP, (rb + ci) * es), ext = gload<T>(phiP, (rb + cx) * es);
+      T left = nbr_l(own), right = nbr_r(own);
+      if (lane == 0) left = ext;
+      if (lane == 63) right = ext;
+      ph[a][0] = left; ph[a][1] = own; ph[a][2] = right;
+    }
+    T tp[18];
+    cell_stage<T, CPL>(C, ph, f, g, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], xc,
+                       (double)row_idx(r, ny, walls) + 0.5, tn, rd.cell, tp);
+    if (w == 1) {
+#pragma unroll
+      for (int q = 0; q < 18; ++q) tplus[q][lane] = tp[q];
+    }
+    x_diffs<T, CPL>(rd);
+    move_record<T, CPL, true>(rec[w], lane, rd);
+  }
+  __syncthreads();
+  const bool bot_wall = walls && j == 0;
+  const bool top_wall = walls && j == ny - 1;
+  T fx_f[9], fx_g[9];
+  RowData<T, CPL> prv;
+  if (w == 0) {
+    // the face above row j - 1 (below row j)
+    if (exists && !(walls && r >= ny - 1)) {
+      RowData<T, CPL> up;
+      move_record<T, CPL, false>(rec[1], lane, up);
+      y_face<T, CPL>(C, rd, up, xc, (double)row_idx(r, ny, walls) + 1.0, tn + C.h, rd.fnf, rd.fng);
+#pragma unroll
+      for (int q = 1; q < 9; ++q) {
+        if (EY[q] == 0) continue;
+        below[q][lane] = rd.fnf[q];
+        if (CPL) below[9 + q][lane] = rd.fng[q];
+      }
+    }
+  } else if (w == 1) {
+    RowData<T, CPL> nxt;
+    if (!(walls && j - 1 < 0)) move_record<T, CPL, false>(rec[0], lane, prv);
+    if (!(walls && j + 1 >= ny)) move_record<T, CPL, false>(rec[2], lane, nxt);
+    if (!(walls && j >= ny - 1))
+      y_face<T, CPL>(C, rd, nxt, xc, (double)row_idx(j, ny, walls) + 1.0, tn + C.h, rd.fnf, rd.fng);
+    row_xface<T, CPL, WALLS>(C, j, ny, ci, tn, prv, rd, nxt, fx_f, fx_g);
+  }
+  __syncthreads();
+  if (w == 1) {
+    if (!bot_wall) {
+#pragma unroll
+      for (int q = 1; q < 9; ++q) {
+        if (EY[q] == 0) continue;
+        prv.fnf[q] = below[q][lane];
+        if (CPL) prv.fng[q] = below[9 + q][lane];
+      }
+    }
+    (void)top_wall;
+    row_update<T, CPL>(C, j, ny, nx, walls, ci, store, out, PB, prv, rd, fx_f, fx_g,
+                       [&](int q) { return tplus[q][lane]; });
   }
 }
 
@@ -1010,8 +1186,21 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s) {
   if (a.nitems <= 0) return hipSuccess;
   const int per = (a.nitems + 7) / 8;
-  dim3 grid(per * 8), block(kWave);
   if (walls && !coupled) return hipErrorInvalidValue;
+  if (a.one_row) {  // three waves per one-row tile
+    dim3 grid(per * 8), block(3 * kWave);
+    if (fp64) {
+      if (!coupled) hipLaunchKernelGGL((k_step_row<double, false, false>), grid, block, 0, s, a);
+      else if (walls) hipLaunchKernelGGL((k_step_row<double, true, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_step_row<double, true, false>), grid, block, 0, s, a);
+    } else {
+      if (!coupled) hipLaunchKernelGGL((k_step_row<float, false, false>), grid, block, 0, s, a);
+      else if (walls) hipLaunchKernelGGL((k_step_row<float, true, true>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((k_step_row<float, true, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+  }
+  dim3 grid(per * 8), block(kWave);
   if (fp64) {
     if (!coupled) hipLaunchKernelGGL((k_step<double, false, false>), grid, block, 0, s, a);
     else if (walls) hipLaunchKernelGGL((k_step<double, true, true>), grid, block, 0, s, a);

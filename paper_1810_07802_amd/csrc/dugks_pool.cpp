@@ -52,6 +52,7 @@ struct dugks_pool {
   Item* items[2] = {nullptr, nullptr};
   size_t items_cap[2] = {0, 0};
   int nitems[2] = {0, 0};
+  int seg[2] = {1, 1};        // rows per segment of each group
   std::vector<char> running;  // slot in the current items
   bool dirty = true;
   std::map<int, hipGraphExec_t> graphs;
@@ -136,7 +137,7 @@ int rebuild(dugks_pool* p) {
     shapes[h->hc.walls ? 1 : 0].push_back(StripShape{h->hc.nstrips, h->ny});
   }
   if (!p->dirty && run == p->running) return DUGKS_OK;
-  int seg[2];
+  int* seg = p->seg;
   for (int w = 0; w < 2; ++w)
     seg[w] = shapes[w].empty() ? 1 : auto_seg_rows(shapes[w], wave_capacity(p->fp64(), p->coupled(), w == 1));
   std::vector<Item> it[2];
@@ -184,7 +185,7 @@ int rebuild(dugks_pool* p) {
 }
 
 int record(dugks_pool* p, int nsteps) {
-  StepArgs a;
+  StepArgs a{};
   a.cases = p->dcases;
   a.step_base = p->step_base;
   for (int k = 0; k < nsteps; ++k) {
@@ -193,6 +194,7 @@ int record(dugks_pool* p, int nsteps) {
       if (p->nitems[w] == 0) continue;
       a.items = p->items[w];
       a.nitems = p->nitems[w];
+      a.one_row = p->seg[w] == 1 ? 1 : 0;
       PHIPCHK(p, dugks::launch_step(p->fp64(), p->coupled(), w == 1, a, p->stream));
     }
   }

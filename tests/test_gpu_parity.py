@@ -42,7 +42,7 @@ def _report(tag, g, r):
     return errs
 
 
-@pytest.mark.parametrize("seg", [4, 16])
+@pytest.mark.parametrize("seg", [1, 4, 16])
 def test_fp64_coupled_periodic(seg):
     c = W.random_coupled(100, 40, seed=3, rho_ratio=100.0)
     g, r, _ = run_both(c, 300, "fp64", seg)
@@ -51,9 +51,10 @@ def test_fp64_coupled_periodic(seg):
         assert e[k] < 1e-12, (k, e[k])
 
 
-def test_fp64_coupled_walls():
+@pytest.mark.parametrize("seg", [1, 8])
+def test_fp64_coupled_walls(seg):
     c = W.random_coupled(70, 36, seed=4, rho_ratio=10.0, walls_y=True)
-    g, r, _ = run_both(c, 300, "fp64", 8)
+    g, r, _ = run_both(c, 300, "fp64", seg)
     e = _report("fp64 walls", g, r)
     for k in ("phi", "u", "v", "p"):
         assert e[k] < 1e-12, (k, e[k])
@@ -78,15 +79,32 @@ def test_fp64_density_ratio_1000_driven_flow():
         assert e[k] < 1e-12, (k, e[k])
 
 
-def test_tiling_does_not_change_bits():
-    c = W.random_coupled(130, 50, seed=7, rho_ratio=50.0)
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_tiling_does_not_change_bits(walls, prec):
+    """Segments of 2, 7 and 64 rows (one wave marching each) and of 1 row
+    (the three-wave row kernel) give the same state bit for bit."""
+    c = W.random_coupled(130, 50, seed=7, rho_ratio=50.0, walls_y=walls)
     states = []
-    for seg in (2, 7, 64):
-        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32", seg)
+    for seg in (2, 1, 7, 64):
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", prec, seg)
         s.init(c["phi"], c["u"], c["v"])
         s.step(50)
         states.append(s.get_state()[0])
-    assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
+    for k in range(1, 4):
+        assert np.array_equal(states[0], states[k]), k
+
+
+def test_row_kernel_interface_only_bits():
+    c = W.smoothed_deformation(L0=96, Pe=96, M=0.02)
+    c["params"] = dict(c["params"], vel="shear", T_period=400.0, U0=0.02)
+    states = []
+    for seg in (3, 1):
+        s = D.Solver(c["nx"], c["ny"], c["params"], "ac", "fp64", seg)
+        s.init(c["phi"])
+        s.step(120)
+        states.append(s.get_state()[0])
+    assert np.array_equal(states[0], states[1])
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
