@@ -50,6 +50,9 @@
  *   R9  Laplacian: isotropic nine-point stencil.
  *   R10 d_t(phi u) = [(phi u)^n - (phi u)^(n-1)] / dt, zero on the first step.
  *   R11 Initial tilde distributions: psi^eq - (dt/2) S with D = 0.
+ *   R12 Viscosity: a uniform nu gives tau_g = nu / RT everywhere; unequal
+ *       mu_H, mu_L are interpolated in s reciprocally (1/mu = s/mu_H +
+ *       (1-s)/mu_L) or linearly, and tau_g = mu / (rho RT).
  *   R13 s = (phi - phi_L)/Delta is clamped to [0,1] inside rho, mu and tau_g
  *       only; grad rho = rho' grad phi is not clamped.
  *   R15 No-slip walls on the faces y = 0 and y = ny (see wall_face()).

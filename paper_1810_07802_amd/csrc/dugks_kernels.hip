@@ -246,7 +246,8 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
   const T c = ph[1][1];
   const T E = ph[1][2], Wv = ph[1][0], N = ph[2][1], S = ph[0][1];
   const T NE = ph[2][2], NW = ph[2][0], SE = ph[0][2], SW = ph[0][0];
-  // R8/R9: isotropic gradient and nine-point Laplacian
+  // isotropic D2Q9-weighted gradient (six non-zero points per component) and
+  // nine-point Laplacian, the stencils named before Eq. 37
   const T gx = (T(4) * (E - Wv) + (NE - NW) + (SE - SW)) * T(1.0 / 12.0);
   const T gy = (T(4) * (N - S) + (NE - SE) + (NW - SW)) * T(1.0 / 12.0);
   // differences first: near equilibrium mu_phi is a small residual of two
@@ -300,7 +301,8 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
   } else {
     presc_vel<T>(C, xc, yc, tn, u, v);
   }
-  // f: equilibrium (Eq. 15) and source (Eq. 16) with D = d_t(phi u) (R10)
+  // f: equilibrium (Eq. 15) and source (Eq. 16) with D = d_t(phi u) taken as
+  // [(phi u)^n - (phi u)^(n-1)] / dt (zero on the first step)
   const T hx = phi * u, hy = phi * v;
   const T Dx = (hx - hist_x) * T(1.0 / C.dt), Dy = (hy - hist_y) * T(1.0 / C.dt);
   {
@@ -342,7 +344,8 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
 
 // ------------------------------------------------------- face distribution
 
-// Face macros (R5, R6; Eqs. 31-33 with dt/2 -> h/2) and face original
+// Face macros (Eqs. 31-33 with dt/2 -> h/2; gradient-type inputs are the mean
+// of the two cells, functions of phi are re-evaluated from the face phi) and face original
 // distributions (Eq. 28) for the populations crossing a face of normal DIR
 // (0: x, 1: y). fbar/gbar hold the reconstructed bar values.
 template <typename T, bool CPL, int DIR>
@@ -395,7 +398,10 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
   }
 }
 
-// No-slip wall on the face below row 0 (BOTTOM) or above row ny-1 (R15).
+// No-slip wall on the face below row 0 (BOTTOM) or above row ny-1: face
+// bounce-back. Populations leaving the fluid are reconstructed one-sidedly from
+// the wall cell, the entering ones take the value of their opposite; u = 0,
+// p and phi are the wall cell's, and the normal parts of grad phi and D vanish.
 // `c` is the adjacent cell, `cn` the next cell inward, txf/txg the x central
 // differences of the adjacent cell's bar-plus values (diagonal populations).
 template <typename T, bool BOTTOM>
@@ -590,7 +596,8 @@ __device__ __forceinline__ void y_diffs(const RowData<T, CPL>& up, const RowData
 }
 
 // x-face east of each cell of output row k and the wall faces of that row
-// (R15), from the records of rows k-1 (prv), k (cur) and k+1 (nxt); a bottom
+// (face bounce-back, wall_face()), from the records of rows k-1 (prv), k (cur)
+// and k+1 (nxt); a bottom
 // wall face lands in prv.fnf/fng (the face below row k), a top one in
 // cur.fnf/fng (the face above).
 template <typename T, bool CPL, bool WALLS>
@@ -1008,7 +1015,7 @@ __device__ __forceinline__ void gather3x3(const S* __restrict__ f, int i, int j,
   }
 }
 
-// Initial state (R11): tilde = psi^eq - (dt/2) S with d_t(phi u) = 0, from
+// Initial state: tilde = psi^eq - (dt/2) S with d_t(phi u) = 0, from
 // the macros phi, u, v, p (double, [ny][nx]); hist = phi u; phi plane.
 template <typename T, bool CPL>
 __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __restrict__ phi0,

@@ -298,7 +298,7 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
   h->scratch = p->staging;
   int rc = dugks_set_params(h, prm);
   if (rc == DUGKS_OK) {
-    // host fields into the staging area, then the initial state (R11); all
+    // host fields into the staging area, then the initial state; all
     // on the pool stream, so the staging area is reused in order
     const size_t n = h->n(), b = n * sizeof(double);
     const double* src[4] = {phi, u, v, pr};
