@@ -180,21 +180,46 @@ def served_stream(torch, D, W, n_req):
 
 
 def cpu_baseline(budget_s):
+    """The FP64 oracle on the host: the bubble 128^2 for about 3/4 of the
+    budget on all OpenMP threads, then about 1/4 on one thread."""
+    import ctypes
     import oracle
     import workloads as W
     c = W.bubble(L=128, R=32)
     s = oracle.Sim(c["nx"], c["ny"], c["params"], "coupled")
     s.init(c["phi"])
     s.step(5)
-    n, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        s.step(50)
-        n += 50
-    dt = time.perf_counter() - t0
+
+    def rate(seconds):
+        n, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            s.step(10)
+            n += 10
+        dt = time.perf_counter() - t0
+        return c["nx"] * c["ny"] * n / dt / 1e6, n, dt
+
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(c["nx"] * c["ny"] * n / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": cores, "kind": "oracle",
-            "sample": f"bubble 128x128 coupled FP64, {n} steps ({dt:.1f} s)"}
+    v, n, dt = rate(0.75 * budget_s)
+    one = None
+    try:  # the oracle library links the OpenMP runtime
+        omp = ctypes.CDLL(oracle._LIB_PATH)
+        omp.omp_set_num_threads(1)
+        one = rate(0.25 * budget_s)[0]
+        omp.omp_set_num_threads(cores)
+    except (OSError, AttributeError):
+        pass
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(v, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"bubble 128x128 coupled FP64, {n} steps ({dt:.1f} s) on {cores} threads",
+            "single_thread_value": None if one is None else round(one, 3),
+            "cpu_model": model}
 
 
 def main():
