@@ -58,13 +58,15 @@ def parse():
     return ap.parse_args()
 
 
-def timed_graph(torch, D, solvers, steps, warmup, chunk=1000):
+def timed_graph(torch, D, solvers, steps, warmup, chunk=1000, autotune=False):
     """Replay `steps` steps of `solvers` (a batch) from HIP graphs of `chunk`
     launches on torch's current stream; returns seconds measured by HIP events
-    on that stream."""
+    on that stream. With `autotune`, the batch's tiles are picked by the
+    library's autotuner first (outside the timed region)."""
     stream = torch.cuda.current_stream()
     b = D.Batch(solvers)
     b.set_stream(stream.cuda_stream)
+    b.tiles = b.autotune(5) if autotune else None
     chunk = max(1, min(chunk, steps))
     w = warmup
     while w > 0:
@@ -319,12 +321,15 @@ def main():
             t.init(cc["phi"])
             solvers.append(t)
         bc = sum(cc["nx"] * cc["ny"] for cc in cases)
-        tb, _ = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100)
+        tb_auto, _ = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100)
+        tb, bt = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100, autotune=True)
         tp = timed_eager(torch, D, solvers, args.batch_steps)
         rec["batched"] = {"workload": "spinodal decomposition, 64 cases of 64^2..512^2 "
                                       "(seed 1810), rho 1000:1, coupled FP32",
                           "cells": bc, "steps": args.batch_steps,
                           "batched_graph_mlups": round(bc * args.batch_steps / tb / 1e6, 1),
+                          "batched_graph_auto_tile_mlups": round(bc * args.batch_steps / tb_auto / 1e6, 1),
+                          "tile_seg_rows": bt.tiles,
                           "per_case_loop_mlups": round(bc * args.batch_steps / tp / 1e6, 1),
                           "roofline": roofline(bc, args.batch_steps, tb, "fp32")}
         del solvers

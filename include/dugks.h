@@ -225,6 +225,18 @@ int dugks_batch_set_stream(dugks_batch *b, void *stream);
 int dugks_batch_sync(dugks_batch *b);
 int dugks_batch_destroy(dugks_batch *b);
 
+/* Tile autotuner of a batch: for each boundary group (periodic cases, wall
+ * cases) in turn, times probe_steps (1..1000) batch steps for the same
+ * candidate segment lengths as dugks_autotune, computed over the whole group,
+ * keeps the fastest for every case of the group, and puts every case's state
+ * and the batch's step counter back as they were (results do not depend on
+ * the tile, bit for bit). Synchronous; holds one extra copy of every case's
+ * state while it runs. Outputs (NULL to skip): the chosen segment length of
+ * each group (0 for an empty group). ESTATE if a case has no state; on
+ * EDEVICE the states are undefined. */
+int dugks_batch_autotune(dugks_batch *b, int probe_steps, int *seg_periodic,
+                         int *seg_walls);
+
 /* Message of the last error on b (or of the last failed batch_create when b
  * is NULL). Never NULL. */
 const char *dugks_batch_last_error(const dugks_batch *b);

@@ -129,6 +129,7 @@ def lib():
             "dugks_batch_sync": (i, [vp]),
             "dugks_batch_destroy": (i, [vp]),
             "dugks_batch_last_error": (C.c_char_p, [vp]),
+            "dugks_batch_autotune": (i, [vp, i, C.POINTER(i), C.POINTER(i)]),
             "dugks_pool_create": (i, [sz, i, ll, i, i, C.POINTER(vp)]),
             "dugks_pool_set_stream": (i, [vp, vp]),
             "dugks_pool_case_bytes": (sz, [i, i, i, i]),
@@ -349,6 +350,14 @@ class Batch:
 
     def set_budget(self, k, steps):
         _check(lib().dugks_batch_set_budget(self.b, int(k), int(steps)), self.b, batch=True)
+
+    def autotune(self, probe_steps=10):
+        """Pick each boundary group's segment length by timing (states are
+        put back); returns (periodic, walls) segment lengths (0: no case)."""
+        a, w = C.c_int(0), C.c_int(0)
+        _check(lib().dugks_batch_autotune(self.b, int(probe_steps), C.byref(a), C.byref(w)),
+               self.b, batch=True)
+        return int(a.value), int(w.value)
 
     def step(self, nsteps=1, use_graph=False):
         _check(lib().dugks_batch_step(self.b, int(nsteps), int(bool(use_graph))), self.b,

@@ -576,6 +576,34 @@ int sync_descriptors(dugks_batch* b) {
   return DUGKS_OK;
 }
 
+// Work items of both boundary groups from the segment length of each case
+// (b->seg); (re)allocates the item arrays.
+hipError_t build_items(dugks_batch* b) {
+  std::vector<Item> it[2];
+  b->one_row[0] = b->one_row[1] = 1;
+  for (size_t k = 0; k < b->cases.size(); ++k) {
+    const CaseDev& c = b->cases[k]->hc;
+    const int w = c.walls ? 1 : 0;
+    if (b->seg[k] != 1) b->one_row[w] = 0;
+    const int nsegs = (c.ny + b->seg[k] - 1) / b->seg[k];
+    for (int s = 0; s < nsegs; ++s)
+      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{(int)k, x, s, 0});
+  }
+  for (int w = 0; w < 2; ++w) {
+    if (b->items[w]) (void)hipFree(b->items[w]);
+    b->items[w] = nullptr;
+    b->nitems[w] = (int)it[w].size();
+    if (it[w].empty()) continue;
+    hipError_t e = hipMalloc(&b->items[w], it[w].size() * sizeof(Item));
+    if (e == hipSuccess)
+      e = hipMemcpy(b->items[w], it[w].data(), it[w].size() * sizeof(Item), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
+  b->graphs.clear();
+  return hipSuccess;
+}
+
 int record_steps(dugks_batch* b, int nsteps) {
   StepArgs a{};
   a.cases = b->dcases;
@@ -631,25 +659,13 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
     segw[w] = shapes[w].empty()
                   ? 1
                   : auto_seg_rows(shapes[w], wave_capacity(b->fp64, b->coupled, w == 1));
-  std::vector<Item> it[2];
   for (int k = 0; k < n; ++k) {
-    const CaseDev& c = cases[k]->hc;
-    const int w = c.walls ? 1 : 0;
+    const int w = cases[k]->hc.walls ? 1 : 0;
     // a case's explicit tile wins over the group's automatic one
     b->seg[k] = cases[k]->seg_rows > 0 ? cases[k]->seg_rows : segw[w];
-    if (b->seg[k] != 1) b->one_row[w] = 0;
-    const int nsegs = (c.ny + b->seg[k] - 1) / b->seg[k];
-    for (int s = 0; s < nsegs; ++s)
-      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{k, x, s, 0});
   }
   hipError_t e = hipMalloc(&b->dcases, n * sizeof(CaseDev));
-  for (int w = 0; w < 2 && e == hipSuccess; ++w) {
-    b->nitems[w] = (int)it[w].size();
-    if (it[w].empty()) continue;
-    e = hipMalloc(&b->items[w], it[w].size() * sizeof(Item));
-    if (e == hipSuccess)
-      e = hipMemcpy(b->items[w], it[w].data(), it[w].size() * sizeof(Item), hipMemcpyHostToDevice);
-  }
+  if (e == hipSuccess) e = build_items(b);
   if (e == hipSuccess) e = hipMalloc(&b->step_base, sizeof(long long));
   if (e == hipSuccess) e = hipMemset(b->step_base, 0, sizeof(long long));
   if (e != hipSuccess) {
@@ -664,6 +680,101 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
 int dugks_batch_set_budget(dugks_batch* b, int k, long long steps) {
   if (!b || k < 0 || k >= (int)b->cases.size()) return bfail(b, DUGKS_EINVAL, "bad case index");
   b->budget[k] = steps < 0 ? -1 : steps;
+  return DUGKS_OK;
+}
+
+int dugks_batch_autotune(dugks_batch* b, int probe_steps, int* seg_periodic, int* seg_walls) {
+  if (!b || probe_steps < 1 || probe_steps > 1000) return bfail(b, DUGKS_EINVAL, "bad arguments");
+  for (auto* h : b->cases)
+    if (!h->has_state) return bfail(b, DUGKS_ESTATE, "a case has no state");
+  for (auto* h : b->cases)
+    if (h->stream != b->stream) BHIPCHK(b, hipStreamSynchronize(h->stream));
+  const size_t n = b->cases.size();
+  // the current state of every case, put back after each probe
+  std::vector<void*> saved(n, nullptr);
+  std::vector<int> curbuf(n);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipSuccess;
+  for (size_t k = 0; k < n && e == hipSuccess; ++k) {
+    dugks_handle* h = b->cases[k];
+    curbuf[k] = (h->hc.cur0 + (int)(h->steps & 1)) & 1;
+    e = hipMalloc(&saved[k], h->buf_bytes);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(saved[k], h->buf[curbuf[k]], h->buf_bytes, hipMemcpyDeviceToDevice, b->stream);
+  }
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  auto restore = [&]() -> hipError_t {
+    hipError_t r = hipSuccess;
+    for (size_t k = 0; k < n && r == hipSuccess; ++k)
+      r = hipMemcpyAsync(b->cases[k]->buf[curbuf[k]], saved[k], b->cases[k]->buf_bytes,
+                         hipMemcpyDeviceToDevice, b->stream);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(b->step_base, &b->gstep, sizeof(long long), hipMemcpyHostToDevice, b->stream);
+    if (r == hipSuccess) r = hipStreamSynchronize(b->stream);
+    return r;
+  };
+  // time `probe_steps` batch steps with the current items (state put back after)
+  auto probe = [&](float& ms) -> int {
+    int rc = sync_descriptors(b);
+    if (rc) return rc;
+    rc = record_steps(b, 1);  // warm-up
+    if (rc) return rc;
+    BHIPCHK(b, hipEventRecord(e0, b->stream));
+    rc = record_steps(b, probe_steps);
+    if (rc) return rc;
+    BHIPCHK(b, hipEventRecord(e1, b->stream));
+    BHIPCHK(b, hipEventSynchronize(e1));
+    BHIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+    BHIPCHK(b, restore());
+    return DUGKS_OK;
+  };
+  int rc = e == hipSuccess ? DUGKS_OK : bfail(b, DUGKS_EDEVICE, hipGetErrorString(e));
+  int best[2] = {0, 0};
+  // one group at a time, the other at its current segment length
+  for (int w = 0; w < 2 && rc == DUGKS_OK; ++w) {
+    std::vector<StripShape> shapes;
+    for (size_t k = 0; k < n; ++k)
+      if ((b->cases[k]->hc.walls ? 1 : 0) == w)
+        shapes.push_back(StripShape{b->cases[k]->hc.nstrips, b->cases[k]->ny});
+    if (shapes.empty()) continue;
+    const long long cap = wave_capacity(b->fp64, b->coupled, w == 1);
+    std::vector<int> cand = {1, 2};
+    for (int r : {1, 2, 3, 4, 5, 6, 7, 8, 12, 16}) {
+      const int c = fit_seg_rows(shapes, r * cap);
+      if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
+    }
+    float best_ms = -1.0f;
+    for (int c : cand) {
+      for (size_t k = 0; k < n; ++k)
+        if ((b->cases[k]->hc.walls ? 1 : 0) == w) b->seg[k] = c;
+      e = build_items(b);
+      if (e != hipSuccess) {
+        rc = bfail(b, DUGKS_EDEVICE, hipGetErrorString(e));
+        break;
+      }
+      float ms = 0.0f;
+      rc = probe(ms);
+      if (rc) break;
+      if (best_ms < 0.0f || ms < best_ms) {
+        best_ms = ms;
+        best[w] = c;
+      }
+    }
+    if (rc) break;
+    for (size_t k = 0; k < n; ++k)
+      if ((b->cases[k]->hc.walls ? 1 : 0) == w) b->seg[k] = best[w];
+    e = build_items(b);
+    if (e != hipSuccess) rc = bfail(b, DUGKS_EDEVICE, hipGetErrorString(e));
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(b->stream);
+  for (void* q : saved)
+    if (q) (void)hipFree(q);
+  if (rc) return rc;
+  if (seg_periodic) *seg_periodic = best[0];
+  if (seg_walls) *seg_walls = best[1];
   return DUGKS_OK;
 }
 

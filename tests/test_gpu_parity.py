@@ -162,6 +162,36 @@ def test_batch_matches_single_cases_bitwise():
         assert np.array_equal(s.get_state()[0], alone[k]), k
 
 
+def test_batch_autotune_restores_states_and_keeps_bits():
+    cases = [W.spinodal(L=64, seed=30, steps=0), W.random_coupled(70, 36, seed=31, walls_y=True),
+             W.spinodal(L=100, seed=32, steps=0), W.random_coupled(130, 50, seed=33, walls_y=True)]
+    solvers, alone = [], []
+    for c in cases:
+        a = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        a.init(c["phi"], c.get("u"), c.get("v"))
+        a.step(30)
+        alone.append(a.get_state()[0])
+        t = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        t.init(c["phi"], c.get("u"), c.get("v"))
+        solvers.append(t)
+    import torch
+    stream = torch.cuda.Stream()
+    b = D.Batch(solvers)
+    b.set_stream(stream.cuda_stream)
+    b.step(10, use_graph=False)
+    b.sync()
+    before = [s.get_state()[0] for s in solvers]
+    seg_p, seg_w = b.autotune(3)
+    assert seg_p >= 1 and seg_w >= 1
+    for k, s in enumerate(solvers):
+        assert s.steps_done == 10
+        assert np.array_equal(s.get_state()[0], before[k]), k
+    b.step(20, use_graph=True)
+    b.sync()
+    for k, s in enumerate(solvers):
+        assert np.array_equal(s.get_state()[0], alone[k]), k
+
+
 def test_batch_budget_stops_a_case():
     cases = [W.spinodal(L=48, seed=20 + k, steps=0) for k in range(2)]
     solvers = []
