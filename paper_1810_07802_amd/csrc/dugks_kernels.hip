@@ -849,10 +849,10 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
 // --------------------------------------------------- one-row step kernel
 
 // The fields of a row record that the faces and slopes of the neighbouring
-// rows read (y_face, y_diffs, wall_face): the populations that cross a
-// y-face, the x differences of the diagonal ones, the moments and the face
-// inputs. kRec values per lane.
-constexpr int kRec = 36;
+// rows read (y_face, y_diffs, wall_face) and that the x-faces of the row
+// read (row_xface): the populations that cross a face, the x differences of
+// the diagonal ones, the moments and the face inputs. kRec values per lane.
+constexpr int kRec = 42;
 template <typename T, bool CPL, bool PUT>
 __device__ __forceinline__ void move_record(T (*X)[64], int lane, RowData<T, CPL>& r) {
   int m = 0;
@@ -861,21 +861,21 @@ __device__ __forceinline__ void move_record(T (*X)[64], int lane, RowData<T, CPL
     else v = X[m][lane];
     ++m;
   };
-  const int ycross[6] = {2, 3, 4, 6, 7, 8};
+  const int cross[8] = {1, 2, 3, 4, 5, 6, 7, 8};
   const int diag[4] = {2, 4, 6, 8};
 #pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    mv(r.cell.fb[ycross[k]]);
-    if (CPL) mv(r.cell.gb[ycross[k]]);
+  for (int k = 0; k < 8; ++k) {
+    mv(r.cell.fb[cross[k]]);
+    if (CPL) mv(r.cell.gb[cross[k]]);
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     mv(r.txf[diag[k]]);
     if (CPL) mv(r.txg[diag[k]]);
   }
-  mv(r.cell.M0); mv(r.cell.My); mv(r.txMx);
+  mv(r.cell.M0); mv(r.cell.Mx); mv(r.cell.My); mv(r.txMx);
   if (CPL) {
-    mv(r.cell.N0); mv(r.cell.Jx); mv(r.cell.Jy); mv(r.cell.Pxy); mv(r.cell.Pyy);
+    mv(r.cell.N0); mv(r.cell.Jx); mv(r.cell.Jy); mv(r.cell.Pxx); mv(r.cell.Pxy); mv(r.cell.Pyy);
     mv(r.txJx); mv(r.txPxx); mv(r.txPxy);
   }
   mv(r.cell.gx); mv(r.cell.gy); mv(r.cell.mu); mv(r.cell.Dx); mv(r.cell.Dy);
@@ -884,10 +884,11 @@ __device__ __forceinline__ void move_record(T (*X)[64], int lane, RowData<T, CPL
 // One output row j of one 62-column strip per work group of three waves,
 // for tiles of one row (seg_rows == 1), where a single wave marching three
 // rows would be latency-bound. Wave w stages row j - 1 + w; the row records
-// meet in LDS; wave 0 forms the face between rows j - 1 and j while wave 1
-// forms the face above row j and the x-faces of row j; wave 1 then updates
-// row j. Every quantity goes through the same functions, with the same
-// inputs, as in the march of k_step, so the results are the same bit for bit.
+// meet in LDS; at the same time wave 0 forms the face between rows j - 1 and
+// j, wave 1 the face above row j and wave 2 the x-faces of row j (wave 1 when
+// a wall bounds the row); wave 1 then updates row j. Every quantity goes
+// through the same functions, with the same inputs, as in the march of
+// k_step, so the results are the same bit for bit.
 template <typename T, bool CPL, bool WALLS>
 __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepArgs A) {
   const int nb = gridDim.x;
@@ -923,6 +924,7 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
 
   __shared__ T rec[3][kRec][64];
   __shared__ T below[18][64];  // face between rows j - 1 and j (f, g)
+  __shared__ T east[18][64];   // x-faces east of the cells of row j (f, g)
   __shared__ T tplus[18][64];  // tilde-plus of row j
 
   RowData<T, CPL> rd;
@@ -958,8 +960,22 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
   __syncthreads();
   const bool bot_wall = walls && j == 0;
   const bool top_wall = walls && j == ny - 1;
+  const bool wall_row = bot_wall || top_wall;  // wave 1 forms the x-faces itself
   T fx_f[9], fx_g[9];
   RowData<T, CPL> prv;
+  if (w == 2 && !wall_row) {
+    // x-faces of row j: rows j - 1 and j from LDS, row j + 1 is this wave's
+    RowData<T, CPL> pj, cj;
+    move_record<T, CPL, false>(rec[0], lane, pj);
+    move_record<T, CPL, false>(rec[1], lane, cj);
+    row_xface<T, CPL, WALLS>(C, j, ny, ci, tn, pj, cj, rd, fx_f, fx_g);
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (EX[q] == 0) continue;
+      east[q][lane] = fx_f[q];
+      if (CPL) east[9 + q][lane] = fx_g[q];
+    }
+  }
   if (w == 0) {
     // the face above row j - 1 (below row j)
     if (exists && !(walls && r >= ny - 1)) {
@@ -979,10 +995,18 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
     if (!(walls && j + 1 >= ny)) move_record<T, CPL, false>(rec[2], lane, nxt);
     if (!(walls && j >= ny - 1))
       y_face<T, CPL>(C, rd, nxt, xc, (double)row_idx(j, ny, walls) + 1.0, tn + C.h, rd.fnf, rd.fng);
-    row_xface<T, CPL, WALLS>(C, j, ny, ci, tn, prv, rd, nxt, fx_f, fx_g);
+    if (wall_row) row_xface<T, CPL, WALLS>(C, j, ny, ci, tn, prv, rd, nxt, fx_f, fx_g);
   }
   __syncthreads();
   if (w == 1) {
+    if (!wall_row) {
+#pragma unroll
+      for (int q = 1; q < 9; ++q) {
+        if (EX[q] == 0) continue;
+        fx_f[q] = east[q][lane];
+        if (CPL) fx_g[q] = east[9 + q][lane];
+      }
+    }
     if (!bot_wall) {
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
@@ -991,7 +1015,6 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
         if (CPL) prv.fng[q] = below[9 + q][lane];
       }
     }
-    (void)top_wall;
     row_update<T, CPL>(C, j, ny, nx, walls, ci, store, out, PB, prv, rd, fx_f, fx_g,
                        [&](int q) { return tplus[q][lane]; });
   }
