@@ -23,6 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 VISC = {"uniform_nu": 0, "reciprocal": 1, "linear": 2}
 GRAV = {"rho_g": 0, "buoyancy": 1}
 VEL = {"uniform": 0, "rotation": 1, "shear": 2, "deform": 3}
+RECON = {"central": 0, "upwind": 1}
 
 
 class OrcParams(C.Structure):
@@ -40,6 +41,7 @@ class OrcParams(C.Structure):
         ("walls_y", C.c_int),
         ("vel_kind", C.c_int),
         ("U0", C.c_double), ("L0", C.c_double), ("T_period", C.c_double),
+        ("recon", C.c_int),
     ]
 
 
@@ -47,7 +49,7 @@ PARAM_DEFAULTS = dict(
     phi_H=1.0, phi_L=0.0, rho_H=1.0, rho_L=1.0, mu_H=0.1, mu_L=0.1, nu=0.1,
     visc="uniform_nu", sigma=0.0, W=4.0, M=0.1, gx=0.0, gy=0.0,
     gravity="rho_g", Gx=0.0, Gy=0.0, cfl=0.5, walls_y=False,
-    vel="uniform", U0=0.0, L0=1.0, T_period=1.0,
+    vel="uniform", U0=0.0, L0=1.0, T_period=1.0, recon="central",
 )
 
 
@@ -94,6 +96,7 @@ def lib():
         L.orc_bar_plus.argtypes = [C.c_double, C.c_double, dp, dp, dp, dp, dp]
         L.orc_face_df.argtypes = [C.c_double, C.c_double, dp, dp, dp, dp]
         L.orc_stencils.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp]
+        L.orc_recon.argtypes = [C.c_int] * 4 + [C.c_double, C.c_int, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -123,6 +126,7 @@ def make_params(d: dict) -> OrcParams:
     s.gravity_form = GRAV[p["gravity"]]
     s.walls_y = int(bool(p["walls_y"]))
     s.vel_kind = VEL[p["vel"]]
+    s.recon = RECON[p["recon"]]
     return s
 
 
@@ -236,6 +240,16 @@ def face_df(tau, h, bar, eq, S):
     out = np.empty(9)
     lib().orc_face_df(tau, h, _ptr(bar), _ptr(eq), _ptr(S), _ptr(out))
     return out
+
+
+def recon(a, q, h, mode="central", walls_y=False):
+    """Bar values of population q of the cell field ``a`` ([ny][nx]) at the
+    x-faces (east of each cell) and y-faces (north of each cell)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    ny, nx = a.shape
+    xf, yf = np.empty_like(a), np.empty_like(a)
+    lib().orc_recon(nx, ny, int(walls_y), RECON[mode], float(h), int(q), _ptr(a), _ptr(xf), _ptr(yf))
+    return xf, yf
 
 
 def stencils(phi, walls_y=False):

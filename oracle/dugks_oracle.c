@@ -59,6 +59,14 @@
  *   R16 Gravity either rho g or (rho - (rho_H + rho_L)/2) g, plus a constant
  *       body-force density.
  *   R22 Pressure follows Eq. 33 exactly as printed.
+ *   Upwind mode (recon = ORC_RECON_UPWIND; the paper names an upwind, limited
+ *       reconstruction as the cure for the dissipation of the central one):
+ *       a population crossing a face is traced back from the face by h xi
+ *       into its upwind cell and evaluated there with the cell's van Leer
+ *       limited slopes, VL(a, b) = 2ab / (a + b) if ab > 0, else 0, of the
+ *       backward and forward differences (one-sided next to a wall); a
+ *       population along the face takes the mean of the two cells and the
+ *       mean of their limited tangential slopes.
  */
 #include "dugks_oracle.h"
 
@@ -487,6 +495,102 @@ static double slope_x(const orc_sim *s, const double *a, int i, int j) {
                   a[(size_t)j * nx + wrapi(i - 1, nx)]);
 }
 
+/* Upwind mode: van Leer limited slope of two one-sided differences. */
+static double van_leer(double a, double b) {
+    return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
+}
+
+/* Limited x and y slopes of a cell field (one-sided next to a wall in y). */
+static double lim_x(const orc_sim *s, const double *a, int i, int j) {
+    int nx = s->nx;
+    size_t c = (size_t)j * nx + i;
+    return van_leer(a[c] - a[(size_t)j * nx + wrapi(i - 1, nx)],
+                    a[(size_t)j * nx + wrapi(i + 1, nx)] - a[c]);
+}
+static double lim_y(const orc_sim *s, const double *a, int i, int j) {
+    int nx = s->nx, ny = s->ny;
+    if (s->P.walls_y) {
+        if (j == 0) return a[(size_t)1 * nx + i] - a[i];
+        if (j == ny - 1) return a[(size_t)(ny - 1) * nx + i] - a[(size_t)(ny - 2) * nx + i];
+    }
+    size_t c = (size_t)j * nx + i;
+    return van_leer(a[c] - a[(size_t)wrapi(j - 1, ny) * nx + i],
+                    a[(size_t)wrapi(j + 1, ny) * nx + i] - a[c]);
+}
+
+/* Bar value of population q at the x-face between L = (i,j) and R = (ir,j)
+   (upwind mode): x_f - h xi lies in the upwind cell at (1/2 - h e_x, -h e_y)
+   from its centre (mirrored for e_x < 0). */
+static double upwind_x(const orc_sim *s, const double *a, int q, int i, int ir, int j) {
+    int nx = s->nx;
+    size_t L = (size_t)j * nx + i, R = (size_t)j * nx + ir;
+    double h = s->h;
+    if (EX[q] > 0)
+        return a[L] + (0.5 - h) * lim_x(s, a, i, j) - h * EY[q] * lim_y(s, a, i, j);
+    if (EX[q] < 0)
+        return a[R] - (0.5 - h) * lim_x(s, a, ir, j) - h * EY[q] * lim_y(s, a, ir, j);
+    return 0.5 * (a[L] + a[R]) - h * EY[q] * 0.5 * (lim_y(s, a, i, j) + lim_y(s, a, ir, j));
+}
+
+/* Same at the y-face between D = (i,jd) and U = (i,ju). */
+static double upwind_y(const orc_sim *s, const double *a, int q, int i, int jd, int ju) {
+    int nx = s->nx;
+    size_t Dn = (size_t)jd * nx + i, Up = (size_t)ju * nx + i;
+    double h = s->h;
+    if (EY[q] > 0)
+        return a[Dn] + (0.5 - h) * lim_y(s, a, i, jd) - h * EX[q] * lim_x(s, a, i, jd);
+    if (EY[q] < 0)
+        return a[Up] - (0.5 - h) * lim_y(s, a, i, ju) - h * EX[q] * lim_x(s, a, i, ju);
+    return 0.5 * (a[Dn] + a[Up]) - h * EX[q] * 0.5 * (lim_x(s, a, i, jd) + lim_x(s, a, i, ju));
+}
+
+/* Bar value of population q at the x-face between L = (i,j) and R = (ir,j)
+   with the central reconstruction of R4: a - h (e_qx d_n + e_qy d_t). */
+static double central_x(const orc_sim *s, const double *a, int q, int i, int ir, int j) {
+    size_t L = (size_t)j * s->nx + i, R = (size_t)j * s->nx + ir;
+    double avg = 0.5 * (a[L] + a[R]), dn = a[R] - a[L];
+    double dtg = 0.5 * (slope_y(s, a, i, j) + slope_y(s, a, ir, j));
+    return avg - s->h * (EX[q] * dn + EY[q] * dtg);
+}
+
+/* Same at the y-face between D = (i,jd) and U = (i,ju). */
+static double central_y(const orc_sim *s, const double *a, int q, int i, int jd, int ju) {
+    size_t Dn = (size_t)jd * s->nx + i, Up = (size_t)ju * s->nx + i;
+    double avg = 0.5 * (a[Dn] + a[Up]), dn = a[Up] - a[Dn];
+    double dtg = 0.5 * (slope_x(s, a, i, jd) + slope_x(s, a, i, ju));
+    return avg - s->h * (EY[q] * dn + EX[q] * dtg);
+}
+
+/* Face value in the reconstruction the parameters select. */
+static double recon_x(const orc_sim *s, const double *a, int q, int i, int ir, int j) {
+    return s->P.recon == ORC_RECON_UPWIND ? upwind_x(s, a, q, i, ir, j)
+                                          : central_x(s, a, q, i, ir, j);
+}
+static double recon_y(const orc_sim *s, const double *a, int q, int i, int jd, int ju) {
+    return s->P.recon == ORC_RECON_UPWIND ? upwind_y(s, a, q, i, jd, ju)
+                                          : central_y(s, a, q, i, jd, ju);
+}
+
+/* Bar values of population q on every x-face (east of each cell) and every
+   y-face (north of each cell; rows 0 .. ny-2 with walls) for a cell field a,
+   in the reconstruction recon selects, with the functions Pass C uses. */
+void orc_recon(int nx, int ny, int walls_y, int recon, double h, int q, const double *a,
+               double *xface, double *yface) {
+    orc_sim tmp;
+    memset(&tmp, 0, sizeof tmp);
+    tmp.nx = nx;
+    tmp.ny = ny;
+    tmp.h = h;
+    tmp.P.walls_y = walls_y;
+    tmp.P.recon = recon;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            size_t c = (size_t)j * nx + i;
+            xface[c] = recon_x(&tmp, a, q, i, wrapi(i + 1, nx), j);
+            yface[c] = (walls_y && j == ny - 1) ? 0.0 : recon_y(&tmp, a, q, i, j, wrapi(j + 1, ny));
+        }
+}
+
 /* Face macros and the face original distributions (Eq. 28) from the bar
    distributions at the face (R5, R6). The averaged gradient-type inputs come
    in as arguments. */
@@ -595,9 +699,8 @@ static void pass_c(orc_sim *s) {
     int nx = s->nx, ny = s->ny;
     size_t n = (size_t)nx * ny, n1 = (size_t)nx * (ny + 1);
 
-    /* x-faces: face east of cell (i,j), between L = (i,j) and R = (i+1,j).
-       Eq. 27 with the central reconstruction of R4:
-       bar psi_q = a - h (e_qx d_n + e_qy d_t). */
+    /* x-faces: face east of cell (i,j), between L = (i,j) and R = (i+1,j);
+       the bar values at the face (Eq. 27) in the selected reconstruction. */
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
@@ -605,16 +708,8 @@ static void pass_c(orc_sim *s) {
             size_t L = (size_t)j * nx + i, R = (size_t)j * nx + ir;
             double fb[9], gb[9], fo[9], go[9];
             for (int q = 0; q < 9; ++q) {
-                const double *a = s->fbp + q * n;
-                double avg = 0.5 * (a[L] + a[R]), dn = a[R] - a[L];
-                double dtg = 0.5 * (slope_y(s, a, i, j) + slope_y(s, a, ir, j));
-                fb[q] = avg - s->h * (EX[q] * dn + EY[q] * dtg);
-                if (s->coupled) {
-                    const double *b = s->gbp + q * n;
-                    double avgb = 0.5 * (b[L] + b[R]), dnb = b[R] - b[L];
-                    double dtb = 0.5 * (slope_y(s, b, i, j) + slope_y(s, b, ir, j));
-                    gb[q] = avgb - s->h * (EX[q] * dnb + EY[q] * dtb);
-                }
+                fb[q] = recon_x(s, s->fbp + q * n, q, i, ir, j);
+                if (s->coupled) gb[q] = recon_x(s, s->gbp + q * n, q, i, ir, j);
             }
             face_in in;
             in.gx = 0.5 * (s->gpx[L] + s->gpx[R]);
@@ -641,16 +736,8 @@ static void pass_c(orc_sim *s) {
             size_t Dn = (size_t)jd * nx + i, Up = (size_t)ju * nx + i;
             double fb[9], gb[9], fo[9], go[9];
             for (int q = 0; q < 9; ++q) {
-                const double *a = s->fbp + q * n;
-                double avg = 0.5 * (a[Dn] + a[Up]), dn = a[Up] - a[Dn];
-                double dtg = 0.5 * (slope_x(s, a, i, jd) + slope_x(s, a, i, ju));
-                fb[q] = avg - s->h * (EY[q] * dn + EX[q] * dtg);
-                if (s->coupled) {
-                    const double *b = s->gbp + q * n;
-                    double avgb = 0.5 * (b[Dn] + b[Up]), dnb = b[Up] - b[Dn];
-                    double dtb = 0.5 * (slope_x(s, b, i, jd) + slope_x(s, b, i, ju));
-                    gb[q] = avgb - s->h * (EY[q] * dnb + EX[q] * dtb);
-                }
+                fb[q] = recon_y(s, s->fbp + q * n, q, i, jd, ju);
+                if (s->coupled) gb[q] = recon_y(s, s->gbp + q * n, q, i, jd, ju);
             }
             face_in in;
             in.gx = 0.5 * (s->gpx[Dn] + s->gpx[Up]);

@@ -16,6 +16,7 @@ extern "C" {
 enum { ORC_VISC_UNIFORM_NU = 0, ORC_VISC_RECIPROCAL = 1, ORC_VISC_LINEAR = 2 };
 enum { ORC_GRAV_RHO_G = 0, ORC_GRAV_BUOYANCY = 1 };
 enum { ORC_VEL_UNIFORM = 0, ORC_VEL_ROTATION = 1, ORC_VEL_SHEAR = 2, ORC_VEL_DEFORM = 3 };
+enum { ORC_RECON_CENTRAL = 0, ORC_RECON_UPWIND = 1 };
 
 typedef struct {
     double phi_H, phi_L;   /* order parameter of the heavy / light phase */
@@ -31,6 +32,7 @@ typedef struct {
     int walls_y;           /* 0: periodic in y, 1: no-slip walls at y=0, ny */
     int vel_kind;          /* interface-only model: prescribed velocity */
     double U0, L0, T_period;
+    int recon;             /* ORC_RECON_*: face reconstruction of Eq. 27 */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -64,6 +66,10 @@ void orc_bar_plus(double tau, double dt, const double *tl, const double *eq,
                   const double *S, double *bp, double *tp);
 void orc_face_df(double tau, double h, const double *bar, const double *eq,
                  const double *S, double *out);
+/* Bar values of population q at the faces (Eq. 27, both reconstructions):
+   xface[j nx + i] east of cell (i,j), yface[j nx + i] north of it. */
+void orc_recon(int nx, int ny, int walls_y, int recon, double h, int q, const double *a,
+               double *xface, double *yface);
 void orc_stencils(int nx, int ny, int walls_y, const double *phi, double *gx,
                   double *gy, double *lap);
 
