@@ -52,6 +52,7 @@ enum { DUGKS_GRAV_RHO_G = 0, DUGKS_GRAV_BUOYANCY = 1 };
 enum { DUGKS_BC_PERIODIC = 0, DUGKS_BC_WALLS = 1 };
 enum { DUGKS_VEL_UNIFORM = 0, DUGKS_VEL_ROTATION = 1, DUGKS_VEL_SHEAR = 2,
        DUGKS_VEL_DEFORM = 3 };
+enum { DUGKS_RECON_CENTRAL = 0, DUGKS_RECON_UPWIND = 1 };
 
 /* Physical and numerical parameters (Sec. II, III, IV of the paper).
  *   phi_H, phi_L   order parameter of the heavy / light phase (Sec. II.A);
@@ -74,6 +75,22 @@ enum { DUGKS_VEL_UNIFORM = 0, DUGKS_VEL_ROTATION = 1, DUGKS_VEL_SHEAR = 2,
  *   vel_kind, U0, L0, T_period
  *                  prescribed velocity of the interface-only model
  *                  (Eqs. 40-43); ignored by the coupled model.
+ *   recon          face reconstruction of the bar distributions (Eq. 27):
+ *                  DUGKS_RECON_CENTRAL (0, default) is the central one of the
+ *                  paper's runs: mean of the two cells, their difference as
+ *                  the normal slope, central differences along the face.
+ *                  DUGKS_RECON_UPWIND (1) is the upwind, limited
+ *                  reconstruction that Sec. III names against the central
+ *                  one's Peclet-number error growth: the population crossing
+ *                  a face is evaluated in its upwind cell at the point it
+ *                  left from, x_face - h xi, with that cell's van Leer limited
+ *                  slopes (2ab/(a+b) of the one-sided differences a, b if
+ *                  ab > 0, else 0; one-sided and unlimited next to a wall);
+ *                  populations along the face take the mean of both cells.
+ *                  Upwind runs on single handles only (EINVAL in batches and
+ *                  pools), and takes (18 + 6 + 2 * 12) * n values of device
+ *                  scratch (coupled; 9 + 6 + 2 * 6 for interface-only),
+ *                  allocated by dugks_set_params.
  */
 typedef struct dugks_params {
     double phi_H, phi_L;
@@ -89,6 +106,7 @@ typedef struct dugks_params {
     int bc_y;
     int vel_kind;
     double U0, L0, T_period;
+    int recon;
 } dugks_params;
 
 typedef struct dugks_handle dugks_handle;

@@ -161,6 +161,11 @@ class Sim:
         self._keep = arrs
         lib().orc_init(self._h, *[_ptr(a) for a in arrs])
 
+    def set_params(self, params: dict):
+        """New parameters from the next step on (the state is kept)."""
+        self._p = make_params(params)
+        lib().orc_set_params(self._h, C.byref(self._p))
+
     def step(self, nsteps: int = 1):
         lib().orc_step(self._h, int(nsteps))
 

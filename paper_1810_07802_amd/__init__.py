@@ -21,6 +21,7 @@ MODEL_AC, MODEL_COUPLED = 0, 1
 _VISC = {"uniform_nu": 0, "reciprocal": 1, "linear": 2}
 _GRAV = {"rho_g": 0, "buoyancy": 1}
 _VEL = {"uniform": 0, "rotation": 1, "shear": 2, "deform": 3}
+_RECON = {"central": 0, "upwind": 1}
 
 
 class DugksError(RuntimeError):
@@ -44,13 +45,14 @@ class Params(C.Structure):
         ("bc_y", C.c_int),
         ("vel_kind", C.c_int),
         ("U0", C.c_double), ("L0", C.c_double), ("T_period", C.c_double),
+        ("recon", C.c_int),
     ]
 
 
 _DEFAULTS = dict(phi_H=1.0, phi_L=0.0, rho_H=1.0, rho_L=1.0, mu_H=0.1, mu_L=0.1,
                  nu=0.1, visc="uniform_nu", sigma=0.0, W=4.0, M=0.1, gx=0.0, gy=0.0,
                  gravity="rho_g", Gx=0.0, Gy=0.0, cfl=0.5, walls_y=False,
-                 vel="uniform", U0=0.0, L0=1.0, T_period=1.0)
+                 vel="uniform", U0=0.0, L0=1.0, T_period=1.0, recon="central")
 
 
 def make_params(d: dict) -> Params:
@@ -68,6 +70,7 @@ def make_params(d: dict) -> Params:
     s.gravity_form = _GRAV[p["gravity"]]
     s.bc_y = 1 if p["walls_y"] else 0
     s.vel_kind = _VEL[p["vel"]]
+    s.recon = _RECON[p["recon"]]
     return s
 
 
@@ -264,6 +267,10 @@ class Solver:
 
     def set_stream(self, stream):
         set_stream(self.h, stream)
+
+    def set_params(self, params):
+        """New parameters from the next step on (the state is kept)."""
+        set_params(self.h, params)
 
     def init(self, phi, u=None, v=None, p=None):
         init_fields(self.h, self.shape, phi, u, v, p)

@@ -173,6 +173,9 @@ int validate(const dugks_handle* h, const dugks_params* p, std::string& why) {
   if (!(p->sigma >= 0.0)) return bad("sigma must be >= 0");
   if (!(p->M_phi >= 0.0)) return bad("M_phi must be >= 0");
   if (p->bc_y != DUGKS_BC_PERIODIC && p->bc_y != DUGKS_BC_WALLS) return bad("bad bc_y");
+  if (p->recon != DUGKS_RECON_CENTRAL && p->recon != DUGKS_RECON_UPWIND) return bad("bad recon");
+  if (p->recon == DUGKS_RECON_UPWIND && h->borrowed)
+    return bad("the upwind reconstruction runs on single handles only");
   if (h->model == DUGKS_MODEL_AC) {
     if (p->bc_y == DUGKS_BC_WALLS) return bad("walls need the coupled model");
     if (p->vel_kind < DUGKS_VEL_UNIFORM || p->vel_kind > DUGKS_VEL_DEFORM) return bad("bad vel_kind");
@@ -208,6 +211,16 @@ int ensure_scratch(dugks_handle* h) {
 }
 
 int launch_steps(dugks_handle* h, int nsteps) {
+  if (h->upwind()) {
+    UpArgs u{h->dc, h->step_base, 0, h->up};
+    for (int k = 0; k < nsteps; ++k) {
+      u.kofs = k;
+      HIPCHK(h, dugks::launch_step_upwind(h->fp64(), h->coupled(), h->hc.walls != 0, h->nx, h->ny,
+                                          u, h->stream));
+    }
+    HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
+    return DUGKS_OK;
+  }
   StepArgs a{};
   a.cases = h->dc;
   a.items = h->items;
@@ -267,6 +280,16 @@ int dugks_set_params(dugks_handle* h, const dugks_params* p) {
   if (!h || !p) return fail(h, DUGKS_EINVAL, "NULL argument");
   std::string why;
   if (validate(h, p, why) != DUGKS_OK) return fail(h, DUGKS_EINVAL, why);
+  if (p->recon == DUGKS_RECON_UPWIND && !h->up) {
+    const size_t b = (size_t)dugks::up_scratch_values((long long)h->n(), h->nx, h->coupled()) * h->elem();
+    hipError_t e = hipMalloc(&h->up, b);
+    if (e != hipSuccess) {
+      h->up = nullptr;
+      (void)hipGetLastError();
+      return fail(h, e == hipErrorOutOfMemory ? DUGKS_ENOMEM : DUGKS_EDEVICE,
+                  std::string("upwind scratch allocation failed: ") + hipGetErrorString(e));
+    }
+  }
   h->params = *p;
   h->has_params = true;
   h->dirty_case = true;
@@ -426,6 +449,7 @@ int dugks_set_state(dugks_handle* h, const void* host_buf, size_t bytes, long lo
 int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* out_us) {
   if (!h || probe_steps < 1 || probe_steps > 1000) return fail(h, DUGKS_EINVAL, "bad arguments");
   if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  if (h->upwind()) return fail(h, DUGKS_EINVAL, "the upwind reconstruction has no tiles to tune");
   // candidates: the shortest segments (lowest latency per step), and for
   // k = 1..8, 12, 16 the shortest segment whose tiles fit k rounds of resident waves
   // (more rounds: finer load balance, more repeated halo work)
@@ -518,6 +542,7 @@ int dugks_destroy(dugks_handle* h) {
   if (h->items) (void)hipFree(h->items);
   if (h->step_base) (void)hipFree(h->step_base);
   if (h->scratch) (void)hipFree(h->scratch);
+  if (h->up) (void)hipFree(h->up);
   delete h;
   return DUGKS_OK;
 }
@@ -563,6 +588,8 @@ int bfail(dugks_batch* b, int code, const std::string& m) {
 int sync_descriptors(dugks_batch* b) {
   for (size_t k = 0; k < b->cases.size(); ++k) {
     dugks_handle* h = b->cases[k];
+    if (h->upwind())  // parameters changed after the batch was made
+      return bfail(b, DUGKS_EINVAL, "the upwind reconstruction runs on single handles only");
     CaseDev c = h->hc;
     c.seg_rows = b->seg[k];
     c.nsegs = (c.ny + c.seg_rows - 1) / c.seg_rows;
@@ -634,6 +661,8 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
     if (!cases[k]->has_params) return bfail(nullptr, DUGKS_ESTATE, "case without params");
     if (cases[k]->precision != cases[0]->precision || cases[k]->model != cases[0]->model)
       return bfail(nullptr, DUGKS_EINVAL, "cases must share precision and model");
+    if (cases[k]->upwind())
+      return bfail(nullptr, DUGKS_EINVAL, "the upwind reconstruction runs on single handles only");
   }
   dugks_batch* b = new (std::nothrow) dugks_batch;
   if (!b) return bfail(nullptr, DUGKS_ENOMEM, "host allocation failed");

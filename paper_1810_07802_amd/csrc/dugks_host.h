@@ -26,6 +26,7 @@ struct dugks_handle {
   long long* step_base = nullptr;  // device: steps done
   long long steps = 0;             // host mirror
   double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
+  void* up = nullptr;              // scratch planes of the upwind reconstruction
   std::string err = "no error";
   bool dirty_case = true;
   // a case of a serving pool: its buffers, descriptor, counter and scratch
@@ -33,6 +34,7 @@ struct dugks_handle {
   bool borrowed = false;
 
   bool fp64() const { return precision == DUGKS_FP64; }
+  bool upwind() const { return params.recon == DUGKS_RECON_UPWIND; }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
   size_t n() const { return (size_t)nx * ny; }
   size_t elem() const { return fp64() ? 8 : 4; }

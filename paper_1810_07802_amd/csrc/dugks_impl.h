@@ -96,7 +96,38 @@ struct StepArgs {
   int one_row;                 // every item is one row (seg_rows == 1): row kernel
 };
 
+// Upwind reconstruction: scratch planes of the three-kernel step, in values
+// of the working type. Cell planes (n values each): bar-plus f0..f8 and
+// (coupled) g0..g8, then grad phi x, y, mu_phi, D x, y and p. Face planes of
+// the populations that cross a face, f then (coupled) g: x-faces (n values
+// each, the face east of each cell) for e_x != 0, y-faces (n + nx values
+// each, face row jj = 0 .. ny between cell rows jj-1 and jj) for e_y != 0.
+__host__ __device__ constexpr int up_bar_planes(bool coupled) { return coupled ? 18 : 9; }
+__host__ __device__ constexpr int up_cell_planes(bool coupled) { return up_bar_planes(coupled) + 6; }
+__host__ __device__ constexpr int up_face_planes(bool coupled) { return coupled ? 12 : 6; }
+__host__ __device__ constexpr long long up_scratch_values(long long n, long long nx, bool coupled) {
+  return (long long)(up_cell_planes(coupled) + up_face_planes(coupled)) * n +
+         (long long)up_face_planes(coupled) * (n + nx);
+}
+// slot of population q among the six crossing an x-face / a y-face (-1: none)
+__host__ __device__ constexpr int up_xslot(int q) {
+  return q == 1 ? 0 : q == 2 ? 1 : q == 8 ? 2 : q == 4 ? 3 : q == 5 ? 4 : q == 6 ? 5 : -1;
+}
+__host__ __device__ constexpr int up_yslot(int q) {
+  return q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 2 : q == 6 ? 3 : q == 7 ? 4 : q == 8 ? 5 : -1;
+}
+
+// Launch arguments of the upwind step kernels (one case, one step).
+struct UpArgs {
+  const CaseDev* cases;
+  const long long* step_base;
+  int kofs;
+  void* scratch;
+};
+
 // host-side launchers (dugks_kernels.hip)
+hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, int nx, int ny,
+                              const UpArgs& a, hipStream_t s);
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
 int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);

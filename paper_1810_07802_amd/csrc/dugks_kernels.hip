@@ -1209,6 +1209,303 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
   for (int k = 0; k < kDiagQ; ++k) out[k] = a[k];
 }
 
+// ------------------------------------------- upwind reconstruction (3 kernels)
+
+// The upwind, limited reconstruction (selected per handle) is not linear in
+// the populations: the face macros come from the nine reconstructed values
+// of each face instead of reconstructed cell moments, and a face reads the
+// limited slopes of both adjacent cells, a radius-two stencil. The step then
+// runs as three kernels over one thread per cell, through scratch planes
+// (layout in dugks_impl.h):
+//   k_up_stage  cell stage of every cell: bar-plus and the face inputs to
+//               scratch, tilde-plus and the history into the output state;
+//   k_up_faces  the x-face east and the y-face north of every cell (and the
+//               wall faces): reconstruction, face macros and face
+//               distributions, once per face, to the face planes;
+//   k_up_update the update (Eq. 24) of every cell from its four faces.
+// The cell stage, face distribution and wall face are the central path's.
+
+constexpr int kUpCols = 64, kUpRows = 4;  // cells of one 256-thread block
+
+// Cell of this thread, with the block order remapped so that each XCD gets a
+// contiguous share of the grid (the grid is a multiple of 8 blocks). False
+// for threads outside the grid.
+__device__ __forceinline__ bool up_cell(int nx, int ny, int& i, int& j) {
+  const int nbx = (nx + kUpCols - 1) / kUpCols;
+  const int per = gridDim.x >> 3;
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  const int bx = idx % nbx, by = idx / nbx;
+  i = bx * kUpCols + (threadIdx.x & (kUpCols - 1));
+  j = by * kUpRows + (threadIdx.x >> 6);
+  return i < nx && j < ny;
+}
+
+// Step index of this launch in the case's window, or -1 when outside it.
+__device__ __forceinline__ long long up_step(const CaseDev& C, const UpArgs& A) {
+  const long long n = *A.step_base + A.kofs - C.step0;
+  return (n < 0 || n >= C.nsteps) ? -1 : n;
+}
+
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
+  const CaseDev C = *A.cases;
+  const long long n = up_step(C, A);
+  int i, j;
+  if (n < 0 || !up_cell(C.nx, C.ny, i, j)) return;
+  const int nx = C.nx, ny = C.ny;
+  constexpr int walls = WALLS ? 1 : 0;
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  const long long N = C.plane, PB = N * (long long)sizeof(T);
+  constexpr int NV = num_grouped(CPL);
+  const T* phiP = reinterpret_cast<const T*>(in + NV * PB);
+  const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;
+  T ph[3][3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const long long rb = (long long)row_idx(j + r - 1, ny, walls) * nx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ph[r][c] = phiP[rb + wrap(i + c - 1, nx)];
+  }
+  T v[NV];
+  load_groups<T, NV>(in, PB, cell, v);
+  T ft[9], gt[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    ft[q] = v[val_f(q)];
+    gt[q] = CPL ? v[val_g(q)] : T(0);
+  }
+  Cell<T> o;
+  T tp[18];
+  const double tn = C.t0 + (double)n * C.dt;
+  cell_stage<T, CPL>(C, ph, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], (double)i + 0.5,
+                     (double)j + 0.5, tn, o, tp);
+  T nv[NV];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    nv[val_f(q)] = tp[q];
+    if (CPL) nv[val_g(q)] = tp[9 + q];
+  }
+  nv[val_hist(CPL, 0)] = o.hx;
+  nv[val_hist(CPL, 1)] = o.hy;
+  store_groups<T, NV>(out, PB, cell, nv);
+  T* S = static_cast<T*>(A.scratch);
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    S[q * N + cell] = o.fb[q];
+    if (CPL) S[(9 + q) * N + cell] = o.gb[q];
+  }
+  T* in6 = S + up_bar_planes(CPL) * N;
+  in6[cell] = o.gx;
+  in6[N + cell] = o.gy;
+  in6[2 * N + cell] = o.mu;
+  in6[3 * N + cell] = o.Dx;
+  in6[4 * N + cell] = o.Dy;
+  in6[5 * N + cell] = o.p;
+}
+
+// van Leer's limited slope of two one-sided differences.
+template <typename T>
+__device__ __forceinline__ T van_leer(T a, T b) {
+  return a * b > T(0) ? T(2) * a * b / (a + b) : T(0);
+}
+
+// Bar-plus plane access and limited slopes for the face kernel.
+template <typename T, bool WALLS>
+struct UpBars {
+  const T* S;
+  long long N;
+  int nx, ny;
+  __device__ __forceinline__ T at(int p, int i, int j) const {
+    return S[p * N + (long long)j * nx + i];
+  }
+  __device__ __forceinline__ T lim_x(int p, int i, int j) const {
+    const T c = at(p, i, j);
+    return van_leer(c - at(p, wrap(i - 1, nx), j), at(p, wrap(i + 1, nx), j) - c);
+  }
+  __device__ __forceinline__ T lim_y(int p, int i, int j) const {
+    if (WALLS) {  // one-sided, unlimited, next to a wall
+      if (j == 0) return at(p, i, 1) - at(p, i, 0);
+      if (j == ny - 1) return at(p, i, ny - 1) - at(p, i, ny - 2);
+    }
+    const T c = at(p, i, j);
+    return van_leer(c - at(p, i, wrap(j - 1, ny)), at(p, i, wrap(j + 1, ny)) - c);
+  }
+  // value of plane p's population (velocity ex, ey) at the face of normal
+  // DIR between cells A (below / left) and B: traced back by h xi into the
+  // upwind cell, or the mean of both cells along the face
+  template <int DIR>
+  __device__ __forceinline__ T face(int p, int ex, int ey, T h, int ia, int ja, int ib,
+                                    int jb) const {
+    const int en = DIR == 0 ? ex : ey, et = DIR == 0 ? ey : ex;
+    auto ln = [&](int i, int j) { return DIR == 0 ? lim_x(p, i, j) : lim_y(p, i, j); };
+    auto lt = [&](int i, int j) { return DIR == 0 ? lim_y(p, i, j) : lim_x(p, i, j); };
+    const T hal = T(0.5) - h;
+    if (en > 0) {
+      T v = at(p, ia, ja) + hal * ln(ia, ja);
+      if (et != 0) v -= h * T(et) * lt(ia, ja);
+      return v;
+    }
+    if (en < 0) {
+      T v = at(p, ib, jb) - hal * ln(ib, jb);
+      if (et != 0) v -= h * T(et) * lt(ib, jb);
+      return v;
+    }
+    T v = T(0.5) * (at(p, ia, ja) + at(p, ib, jb));
+    if (et != 0) v -= h * T(et) * (T(0.5) * (lt(ia, ja) + lt(ib, jb)));
+    return v;
+  }
+};
+
+// Face of normal DIR between cells A and B: reconstruction, face macros and
+// the face distributions of the crossing populations, written to the face
+// planes F (f) and G (g) at index fi with stride FS.
+template <typename T, bool CPL, bool WALLS, int DIR>
+__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS>& B,
+                                        const T* in6, int ia, int ja, int ib, int jb,
+                                        double xf, double yf, double tf, T* F, long long FS,
+                                        long long fi) {
+  const T h = T(C.h);
+  T fbar[9], gbar[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    fbar[q] = B.template face<DIR>(q, EX[q], EY[q], h, ia, ja, ib, jb);
+    gbar[q] = (CPL && q > 0) ? B.template face<DIR>(9 + q, EX[q], EY[q], h, ia, ja, ib, jb) : T(0);
+  }
+  const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
+                 ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
+  T N0f = T(0), Jxf = T(0), Jyf = T(0);
+  if (CPL) {
+    N0f = ((gbar[1] + gbar[2]) + (gbar[3] + gbar[4])) + ((gbar[5] + gbar[6]) + (gbar[7] + gbar[8]));
+    Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
+    Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
+  }
+  const long long N = B.N;
+  const long long a = (long long)ja * B.nx + ia, b = (long long)jb * B.nx + ib;
+  auto mean = [&](int k) { return T(0.5) * (in6[k * N + a] + in6[k * N + b]); };
+  T fo[9], go[9];
+  face_df<T, CPL, DIR>(C, phif, N0f, Jxf, Jyf, mean(0), mean(1), mean(2), mean(3), mean(4), fbar,
+                       gbar, xf, yf, tf, fo, go);
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const int s = DIR == 0 ? up_xslot(q) : up_yslot(q);
+    if (s < 0) continue;
+    F[s * FS + fi] = fo[q];
+    if (CPL) F[(6 + s) * FS + fi] = go[q];
+  }
+}
+
+// Wall face below row 0 (BOTTOM) or above row ny-1 of column i, into face
+// row 0 or ny: the central path's face bounce-back, fed from the planes.
+template <typename T, bool BOTTOM>
+__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true>& B,
+                                        const T* in6, const T* phiP, int i, T* F, long long FS) {
+  const int nx = B.nx, ny = B.ny;
+  const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
+  const long long N = B.N, cw = (long long)jw * nx + i;
+  Cell<T> c, cn;
+  T txf[9], txg[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    c.fb[q] = B.at(q, i, jw);
+    c.gb[q] = B.at(9 + q, i, jw);
+    cn.fb[q] = B.at(q, i, jn);
+    cn.gb[q] = B.at(9 + q, i, jn);
+    const bool diag = EX[q] != 0 && EY[q] != 0;
+    txf[q] = diag ? B.at(q, wrap(i + 1, nx), jw) - B.at(q, wrap(i - 1, nx), jw) : T(0);
+    txg[q] = diag ? B.at(9 + q, wrap(i + 1, nx), jw) - B.at(9 + q, wrap(i - 1, nx), jw) : T(0);
+  }
+  c.phi = phiP[cw];
+  c.gx = in6[cw];
+  c.mu = in6[2 * N + cw];
+  c.Dx = in6[3 * N + cw];
+  c.p = in6[5 * N + cw];
+  T fo[9], go[9];
+  wall_face<T, BOTTOM>(C, c, cn, txf, txg, fo, go);
+  const long long fi = (BOTTOM ? 0LL : (long long)ny * nx) + i;
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const int s = up_yslot(q);
+    if (s < 0) continue;
+    F[s * FS + fi] = fo[q];
+    F[(6 + s) * FS + fi] = go[q];
+  }
+}
+
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
+  const CaseDev C = *A.cases;
+  const long long n = up_step(C, A);
+  int i, j;
+  if (n < 0 || !up_cell(C.nx, C.ny, i, j)) return;
+  const int nx = C.nx, ny = C.ny;
+  const long long N = C.plane, N1 = N + nx;
+  T* S = static_cast<T*>(A.scratch);
+  const UpBars<T, WALLS> B{S, N, nx, ny};
+  const T* in6 = S + up_bar_planes(CPL) * N;
+  T* XF = S + up_cell_planes(CPL) * N;
+  T* YF = XF + up_face_planes(CPL) * N;
+  const double tf = C.t0 + (double)n * C.dt + C.h;
+  const long long cell = (long long)j * nx + i;
+  up_face<T, CPL, WALLS, 0>(C, B, in6, i, j, wrap(i + 1, nx), j, (double)i + 1.0, (double)j + 0.5,
+                            tf, XF, N, cell);
+  if (!(WALLS && j == ny - 1))
+    up_face<T, CPL, WALLS, 1>(C, B, in6, i, j, i, wrap(j + 1, ny), (double)i + 0.5,
+                              (double)j + 1.0, tf, YF, N1, cell + nx);
+  if constexpr (WALLS) {
+    const int cur = (C.cur0 + (int)(n & 1)) & 1;
+    const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+    const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * N * (long long)sizeof(T));
+    if (j == 0) up_wall<T, true>(C, B, in6, phiP, i, YF, N1);
+    if (j == ny - 1) up_wall<T, false>(C, B, in6, phiP, i, YF, N1);
+  }
+}
+
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(256) void k_up_update(UpArgs A) {
+  const CaseDev C = *A.cases;
+  const long long n = up_step(C, A);
+  int i, j;
+  if (n < 0 || !up_cell(C.nx, C.ny, i, j)) return;
+  const int nx = C.nx, ny = C.ny;
+  const long long N = C.plane, N1 = N + nx, PB = N * (long long)sizeof(T);
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  constexpr int NV = num_grouped(CPL);
+  const T* S = static_cast<const T*>(A.scratch);
+  const T* XF = S + up_cell_planes(CPL) * N;
+  const T* YF = XF + up_face_planes(CPL) * N;
+  const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;
+  const long long ce = cell, cw = (long long)j * nx + wrap(i - 1, nx);
+  // face rows above and below: periodic y takes the face below row 0 from
+  // the top (face row ny)
+  const long long fn = (long long)(j + 1) * nx + i;
+  const long long fs = (long long)((!WALLS && j == 0) ? ny : j) * nx + i;
+  T v[NV];
+  load_groups<T, NV>(out, PB, cell, v);
+  const T dt = T(C.dt);
+  T phin = T(0);
+  auto upd = [&](int q, int off) {
+    T J = T(0);
+    const int sx = up_xslot(q), sy = up_yslot(q);
+    if (EX[q] != 0) J += T(EX[q]) * (XF[(off + sx) * N + ce] - XF[(off + sx) * N + cw]);
+    if (EY[q] != 0) J += T(EY[q]) * (YF[(off + sy) * N1 + fn] - YF[(off + sy) * N1 + fs]);
+    return J;
+  };
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    v[val_f(q)] = v[val_f(q)] - dt * upd(q, 0);
+    phin += v[val_f(q)];
+  }
+  if (CPL) {
+#pragma unroll
+    for (int q = 0; q < 9; ++q) v[val_g(q)] = v[val_g(q)] - dt * upd(q, 6);
+  }
+  store_groups<T, NV>(out, PB, cell, v);
+  gstore<T>(out + NV * PB, cell * (unsigned)sizeof(T), phin);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
@@ -1240,6 +1537,30 @@ hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, h
     else if (walls) hipLaunchKernelGGL((k_step<float, true, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_step<float, true, false>), grid, block, 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, int nx, int ny,
+                              const UpArgs& a, hipStream_t s) {
+  if (walls && !coupled) return hipErrorInvalidValue;
+  const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + kUpRows - 1) / kUpRows);
+  dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * kUpRows);
+#define UP_LAUNCH(T, CPL, W)                                            \
+  do {                                                                  \
+    hipLaunchKernelGGL((k_up_stage<T, CPL, W>), grid, block, 0, s, a);  \
+    hipLaunchKernelGGL((k_up_faces<T, CPL, W>), grid, block, 0, s, a);  \
+    hipLaunchKernelGGL((k_up_update<T, CPL, W>), grid, block, 0, s, a); \
+  } while (0)
+  if (fp64) {
+    if (!coupled) UP_LAUNCH(double, false, false);
+    else if (walls) UP_LAUNCH(double, true, true);
+    else UP_LAUNCH(double, true, false);
+  } else {
+    if (!coupled) UP_LAUNCH(float, false, false);
+    else if (walls) UP_LAUNCH(float, true, true);
+    else UP_LAUNCH(float, true, false);
+  }
+#undef UP_LAUNCH
   return hipGetLastError();
 }
 

@@ -1,0 +1,191 @@
+"""The upwind, limited reconstruction on the GPU (through the C ABI) against
+the FP64 oracle's upwind mode, and its invariants.
+
+The reconstruction is the one Sec. III names as the remedy for the central
+scheme's Peclet-number error growth (the oracle's upwind mode fixes its
+reading: trace back by h xi into the upwind cell, van Leer limited slopes).
+Tolerances are those of the central path: FP64 relative L2 <= 1e-12 after
+hundreds of steps (the same double formulas in another order; van Leer's
+limiter is Lipschitz, so rounding does not grow through its branches), FP32
+relative L2 <= 1e-5 on phi. Sizes span several 64 x 4 thread blocks with a
+ragged last block in x and y, and periodic and wall-bounded y.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1810_07802_amd as D
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def upwind(c):
+    c = dict(c)
+    c["params"] = dict(c["params"], recon="upwind")
+    return c
+
+
+def gpu(c, steps, precision="fp64"):
+    s = D.Solver(c["nx"], c["ny"], c["params"], c["model"], precision)
+    s.init(c["phi"], c["u"], c["v"], c["p"])
+    s.step(steps)
+    return s
+
+
+def orc(c, steps):
+    o = oracle.Sim(c["nx"], c["ny"], c["params"], c["model"])
+    o.init(c["phi"], c["u"], c["v"], c["p"])
+    o.step(steps)
+    return o.macros()
+
+
+def compare(tag, c, steps, precision="fp64"):
+    print(f"[upwind parity] {tag} {c['nx']}x{c['ny']} {precision} {steps} steps", flush=True)
+    g = gpu(c, steps, precision).macros()
+    r = orc(c, steps)
+    e = {k: rel(g[k], r[k]) for k in ("phi", "u", "v", "p")}
+    print(tag, " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    return e, g, r
+
+
+def test_fp64_coupled_periodic():
+    c = upwind(W.random_coupled(100, 42, seed=3, rho_ratio=100.0))
+    e, _, _ = compare("periodic", c, 300)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+def test_fp64_coupled_walls():
+    c = upwind(W.random_coupled(70, 38, seed=4, rho_ratio=10.0, walls_y=True))
+    e, _, _ = compare("walls", c, 300)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+@pytest.mark.parametrize("vel", ["uniform", "rotation", "shear", "deform"])
+def test_fp64_interface_only(vel):
+    c = W.smoothed_deformation(L0=96, Pe=96, M=0.02)
+    c["params"] = dict(c["params"], vel=vel, T_period=400.0, U0=0.02)
+    e, _, _ = compare(f"ac {vel}", upwind(c), 400)
+    assert e["phi"] < 1e-12
+
+
+def test_fp64_density_ratio_1000_driven_flow():
+    c = upwind(W.random_coupled(100, 40, seed=5, rho_ratio=1000.0, U=0.01))
+    e, _, _ = compare("ratio1000", c, 100)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12, (k, e[k])
+
+
+def test_fp32_coupled_periodic():
+    c = upwind(W.random_coupled(100, 42, seed=6, rho_ratio=10.0))
+    e, _, _ = compare("fp32 periodic", c, 200, "fp32")
+    assert e["phi"] < 1e-5
+    for k in ("u", "v"):
+        assert e[k] < 1e-4, (k, e[k])
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (5, 4), (65, 5), (129, 9)])
+def test_tiny_and_ragged_grids(shape):
+    """Grids smaller than one block and one cell past a block edge."""
+    nx, ny = shape
+    walls = ny >= 4 and nx % 2 == 1
+    c = upwind(W.random_coupled(nx, ny, seed=nx + ny, rho_ratio=10.0, walls_y=walls))
+    e, g, r = compare(f"tiny walls={walls}", c, 50)
+    for k in ("phi", "u", "v", "p"):
+        assert e[k] < 1e-12 or np.abs(g[k] - r[k]).max() < 1e-15, (k, e[k])
+
+
+def test_phi_is_conserved_and_differs_from_central():
+    c = W.random_coupled(100, 42, seed=9, rho_ratio=100.0)
+    cu = upwind(c)
+    s = gpu(cu, 0)
+    phi0 = s.macros()["phi"].sum()
+    s.step(500)
+    m_up = s.macros()
+    assert abs(m_up["phi"].sum() - phi0) < 1e-12 * np.abs(c["phi"]).sum()
+    m_c = gpu(c, 500).macros()
+    assert rel(m_up["phi"], m_c["phi"]) > 1e-8  # a different scheme
+
+
+def test_uniform_state_is_preserved():
+    nx, ny = 70, 9
+    phi = np.full((ny, nx), 0.37)
+    params = dict(phi_H=1.0, phi_L=0.0, rho_H=50.0, rho_L=1.0, sigma=1e-3, visc="reciprocal",
+                  mu_H=0.2, mu_L=0.02, M=0.05, recon="upwind")
+    s = D.Solver(nx, ny, params, "coupled", "fp64")
+    s.init(phi, np.full_like(phi, 0.013), np.full_like(phi, -0.007), np.full_like(phi, 2e-3))
+    m0 = s.macros()
+    s.step(50)
+    m1 = s.macros()
+    for k in ("phi", "u", "v"):
+        np.testing.assert_allclose(m1[k], m0[k], rtol=0, atol=1e-14)
+    np.testing.assert_allclose(m1["p"], m0["p"], rtol=0, atol=2e-13)
+
+
+def test_checkpoint_resume_is_bitwise():
+    c = upwind(W.random_coupled(70, 36, seed=8, rho_ratio=10.0, walls_y=True))
+    a = gpu(c, 31)
+    buf, st = a.get_state()
+    a.step(30)
+    b = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp64")
+    b.set_state(buf, st)
+    b.step(30)
+    assert np.array_equal(a.get_state()[0], b.get_state()[0])
+
+
+def test_switching_the_reconstruction_between_steps():
+    """The reconstruction is a parameter: a run that switches to upwind after
+    20 central steps equals the oracle doing the same."""
+    c = W.random_coupled(70, 20, seed=10, rho_ratio=10.0)
+    s = gpu(c, 20)
+    s.set_params(dict(c["params"], recon="upwind"))
+    s.step(20)
+    o = oracle.Sim(c["nx"], c["ny"], c["params"], c["model"])
+    o.init(c["phi"], c["u"], c["v"], c["p"])
+    o.step(20)
+    o.set_params(dict(c["params"], recon="upwind"))
+    o.step(20)
+    g, r = s.macros(), o.macros()
+    for k in ("phi", "u", "v", "p"):
+        assert rel(g[k], r[k]) < 1e-12, k
+
+
+def test_batches_pools_and_autotune_reject_upwind():
+    c = upwind(W.random_coupled(40, 20, seed=2, rho_ratio=10.0))
+    s = gpu(c, 1)
+    with pytest.raises(D.DugksError):
+        D.Batch([s])
+    with pytest.raises(D.DugksError):
+        s.autotune(2)
+    pool = D.Pool(1 << 26, max_cases=2, max_cells=40 * 20)
+    with pytest.raises(D.DugksError):
+        pool.admit(c, 10)
+
+
+@pytest.mark.parametrize("Pe", [512, 1024])
+def test_paper_claim_at_the_paper_size(Pe):
+    """Sec. III: upwind reduces the central scheme's error growth with Pe.
+    Diagonal translation at the paper's size (L0 = 256, Table I set-up), one
+    full period in FP64 on the GPU: the upwind error is below the central
+    one, and both conserve phi."""
+    L0, M = 256, 0.02
+    err = {}
+    for mode in ("central", "upwind"):
+        c = W.diag_translation(L0=L0, W=4.0, U0=Pe * M / L0, M=M, phi_H=1.0, phi_L=0.0)
+        c["params"] = dict(c["params"], recon=mode)
+        s = D.Solver(L0, L0, c["params"], "ac", "fp64")
+        s.init(c["phi"])
+        s.step(c["steps"])
+        phi = s.macros()["phi"]
+        assert abs(phi.sum() - c["phi"].sum()) < 1e-9 * c["phi"].sum()
+        err[mode] = np.sqrt(((phi - c["phi"]) ** 2).sum() / (c["phi"] ** 2).sum())
+    print(f"Pe={Pe} sqrt(E_phi): central {err['central']:.3e} upwind {err['upwind']:.3e}",
+          flush=True)
+    assert err["upwind"] < err["central"]
