@@ -17,6 +17,9 @@ The same JSON line carries:
   served        the served request stream through the continuous-batching
                 pool: p50 / p99 time to solution at 80 % load, aggregate
                 MLUPS, vs the plain sequential per-case loop
+  upwind        the same bubble with the upwind, limited face reconstruction
+                (three kernels per step, 708 algorithmic bytes per cell in
+                FP32), 128^2 and 4096^2, launched step by step
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -33,6 +36,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 B_PER_CELL = {"fp32": 160.0, "fp64": 320.0}  # read + write of 18 populations + 2 history values
+# upwind reconstruction, coupled, FP32: stage 260 (state in, tilde-plus and
+# history out, 18 bar-plus + 6 face inputs out), faces 188 (18 bar-plus + 5
+# inputs in, 24 face values out), update 260 (20 state + 24 face values in,
+# 21 values out) bytes per cell
+B_UPWIND = {"fp32": 708.0, "fp64": 1416.0}
 
 
 def parse():
@@ -52,6 +60,9 @@ def parse():
                     help="run only the timed default workload (for profilers)")
     ap.add_argument("--profile-large", action="store_true",
                     help="run only the timed 4096x4096 workload (for profilers)")
+    ap.add_argument("--profile-upwind", action="store_true",
+                    help="only the upwind leg on 4096^2 (for rocprofv3)")
+    ap.add_argument("--upwind-steps", type=int, default=50)
     ap.add_argument("--profile-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (calibrates the "
                          "HBM byte counters)")
@@ -134,6 +145,31 @@ def roofline(cells, steps, seconds, prec, workload=None):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": counter_traffic(workload),
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
+
+
+def timed_upwind(torch, D, c, steps, warmup):
+    """Upwind-reconstruction steps of case `c` (coupled FP32), launched one
+    step (three kernels) at a time on torch's current stream; seconds by HIP
+    events on that stream."""
+    stream = torch.cuda.current_stream()
+    s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon="upwind"), "coupled", "fp32")
+    s.set_stream(stream.cuda_stream)
+    s.init(c["phi"])
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    d = s.diagnostics()
+    cells = c["nx"] * c["ny"]
+    ach = B_UPWIND["fp32"] * cells * steps / t / 1e9
+    return {"mlups": round(cells * steps / t / 1e6, 1), "steps": steps,
+            "us_per_step": round(t / steps * 1e6, 3), "bytes_per_cell": B_UPWIND["fp32"],
+            "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "nonfinite": d["nonfinite"]}
 
 
 def served_stream(torch, D, W, n_req):
@@ -262,6 +298,11 @@ def main():
                           "seg_rows": seg, "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
                           "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}), flush=True)
         return
+    if args.profile_upwind:
+        cl = W.bubble(L=4096, R=1024, steps=0)
+        print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, upwind reconstruction",
+                          **timed_upwind(torch, D, cl, args.upwind_steps, 3)}), flush=True)
+        return
     c = W.bubble(L=128, R=32)
     cells = c["nx"] * c["ny"]
     s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
@@ -333,6 +374,13 @@ def main():
                           "per_case_loop_mlups": round(bc * args.batch_steps / tp / 1e6, 1),
                           "roofline": roofline(bc, args.batch_steps, tb, "fp32")}
         del solvers
+        # upwind, limited reconstruction on the same physics
+        rec["upwind"] = {
+            "workload": "stationary bubble, coupled FP32, upwind reconstruction, "
+                        "one step (three kernels) per host call",
+            "bubble128": timed_upwind(torch, D, c, min(args.steps, 5000), 100),
+            "bubble4096": timed_upwind(torch, D, W.bubble(L=4096, R=1024, steps=0),
+                                       args.upwind_steps, 5)}
         if args.serve_requests > 0:
             rec["served"] = served_stream(torch, D, W, args.serve_requests)
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
