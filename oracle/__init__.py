@@ -95,8 +95,10 @@ def lib():
         L.orc_sg.argtypes = [C.c_double] * 6 + [dp]
         L.orc_bar_plus.argtypes = [C.c_double, C.c_double, dp, dp, dp, dp, dp]
         L.orc_face_df.argtypes = [C.c_double, C.c_double, dp, dp, dp, dp]
-        L.orc_stencils.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp]
-        L.orc_recon.argtypes = [C.c_int] * 4 + [C.c_double, C.c_int, dp, dp, dp]
+        L.orc_stencils.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
+        L.orc_recon.argtypes = [C.c_int] * 3 + [dp, dp, C.c_int, C.c_double, C.c_int, dp, dp, dp]
+        L.orc_set_mesh.restype = C.c_int
+        L.orc_set_mesh.argtypes = [C.c_void_p, dp, dp]
         _lib = L
     return _lib
 
@@ -160,6 +162,13 @@ class Sim:
                 raise ValueError(f"field shape {a.shape} != {shape}")
         self._keep = arrs
         lib().orc_init(self._h, *[_ptr(a) for a in arrs])
+
+    def set_mesh(self, dx=None, dy=None):
+        """Stretched mesh of cell widths dx[nx], dy[ny] (None: unit widths on
+        that axis; both None: the unit mesh)."""
+        self._mesh = (_f64(dx), _f64(dy))
+        if lib().orc_set_mesh(self._h, _ptr(self._mesh[0]), _ptr(self._mesh[1])) != 0:
+            raise ValueError("mesh widths must be > 0")
 
     def set_params(self, params: dict):
         """New parameters from the next step on (the state is kept)."""
@@ -247,21 +256,26 @@ def face_df(tau, h, bar, eq, S):
     return out
 
 
-def recon(a, q, h, mode="central", walls_y=False):
+def recon(a, q, h, mode="central", walls_y=False, dx=None, dy=None):
     """Bar values of population q of the cell field ``a`` ([ny][nx]) at the
-    x-faces (east of each cell) and y-faces (north of each cell)."""
+    x-faces (east of each cell) and y-faces (north of each cell); ``dx``,
+    ``dy``: cell widths of a stretched mesh (None: unit widths)."""
     a = np.ascontiguousarray(a, dtype=np.float64)
     ny, nx = a.shape
+    dx, dy = _f64(dx), _f64(dy)
     xf, yf = np.empty_like(a), np.empty_like(a)
-    lib().orc_recon(nx, ny, int(walls_y), RECON[mode], float(h), int(q), _ptr(a), _ptr(xf), _ptr(yf))
+    lib().orc_recon(nx, ny, int(walls_y), _ptr(dx), _ptr(dy), RECON[mode], float(h), int(q),
+                    _ptr(a), _ptr(xf), _ptr(yf))
     return xf, yf
 
 
-def stencils(phi, walls_y=False):
+def stencils(phi, walls_y=False, dx=None, dy=None):
     phi = _f64(phi)
     ny, nx = phi.shape
+    dx, dy = _f64(dx), _f64(dy)
     gx, gy, lap = np.empty_like(phi), np.empty_like(phi), np.empty_like(phi)
-    lib().orc_stencils(nx, ny, int(walls_y), _ptr(phi), _ptr(gx), _ptr(gy), _ptr(lap))
+    lib().orc_stencils(nx, ny, int(walls_y), _ptr(dx), _ptr(dy), _ptr(phi), _ptr(gx), _ptr(gy),
+                       _ptr(lap))
     return gx, gy, lap
 
 

@@ -102,6 +102,9 @@ struct orc_sim {
        east of cell (i,j); y-face arrays have ny+1 rows, row jj is the face at
        y = jj (between cell rows jj-1 and jj). */
     double *fxf, *gxf, *fyf, *gyf;
+    /* stretched mesh (R27): cell widths and centres, NULL on the unit mesh;
+       dl is the smallest width */
+    double *mdx, *mdy, *mxc, *myc, dl;
 };
 
 /* ---------------------------------------------------------------- helpers */
@@ -110,7 +113,8 @@ static int wrapi(int i, int n) { return ((i % n) + n) % n; }
 
 static void derive(orc_sim *s) {
     const orc_params *P = &s->P;
-    s->dt = P->cfl;              /* Eq. 37 with delta_l = 1, sqrt(3RT) = 1 */
+    /* Eq. 37 with sqrt(3RT) = 1 and delta_l the smallest cell width */
+    s->dt = s->mdx ? P->cfl * s->dl : P->cfl;
     s->h = 0.5 * s->dt;
     s->Dphi = P->phi_H - P->phi_L;
     s->phibar = 0.5 * (P->phi_H + P->phi_L);
@@ -279,6 +283,63 @@ static double phi_at(const orc_sim *s, const double *phi, int i, int j) {
     return phi[(size_t)j * nx + i];
 }
 
+/* Stretched mesh (R27): widths of cells i and j (x periodic; with walls a
+   mirrored ghost row has the width of the row it mirrors), distances between
+   neighbouring centres (m: to the previous cell, p: to the next), and the
+   first and second derivatives at 0 of the parabola through (-hm, am),
+   (0, ac), (hp, ap). */
+static double wx(const orc_sim *s, int i) { return s->mdx[wrapi(i, s->nx)]; }
+static double wy(const orc_sim *s, int j) {
+    int ny = s->ny;
+    if (s->P.walls_y) {
+        if (j < 0) j = -1 - j;
+        if (j >= ny) j = 2 * ny - 1 - j;
+    } else {
+        j = wrapi(j, ny);
+    }
+    return s->mdy[j];
+}
+static double hxm(const orc_sim *s, int i) { return 0.5 * (wx(s, i - 1) + wx(s, i)); }
+static double hxp(const orc_sim *s, int i) { return 0.5 * (wx(s, i) + wx(s, i + 1)); }
+static double hym(const orc_sim *s, int j) { return 0.5 * (wy(s, j - 1) + wy(s, j)); }
+static double hyp(const orc_sim *s, int j) { return 0.5 * (wy(s, j) + wy(s, j + 1)); }
+static double d1(double am, double ac, double ap, double hm, double hp) {
+    return (hm * hm * (ap - ac) + hp * hp * (ac - am)) / (hm * hp * (hm + hp));
+}
+static double d2(double am, double ac, double ap, double hm, double hp) {
+    return 2.0 * ((ap - ac) / hp - (ac - am) / hm) / (hm + hp);
+}
+/* cell centres and face positions */
+static double xcen(const orc_sim *s, int i) { return s->mdx ? s->mxc[i] : i + 0.5; }
+static double ycen(const orc_sim *s, int j) { return s->mdx ? s->myc[j] : j + 0.5; }
+
+/* R27: the stencils of R8 and R9 on a stretched mesh. Each is a weighted sum
+   of one-dimensional derivatives on the rows (columns) j-1, j, j+1 (i-1, i,
+   i+1), the neighbouring rows weighted by the opposite distance so that the
+   sum is centred on the cell: exact on quadratics, and R8, R9 on the unit
+   mesh. */
+static void stencils_mesh(const orc_sim *s, const double *phi, int i, int j,
+                          double *gx, double *gy, double *lap) {
+    double xm = hxm(s, i), xp = hxp(s, i), ym = hym(s, j), yp = hyp(s, j);
+    double dxr[3], dxxr[3], dyc[3], dyyc[3];
+    for (int k = -1; k <= 1; ++k) {
+        double m = phi_at(s, phi, i - 1, j + k), c = phi_at(s, phi, i, j + k),
+               pp = phi_at(s, phi, i + 1, j + k);
+        dxr[k + 1] = d1(m, c, pp, xm, xp);
+        dxxr[k + 1] = d2(m, c, pp, xm, xp);
+        m = phi_at(s, phi, i + k, j - 1);
+        c = phi_at(s, phi, i + k, j);
+        pp = phi_at(s, phi, i + k, j + 1);
+        dyc[k + 1] = d1(m, c, pp, ym, yp);
+        dyyc[k + 1] = d2(m, c, pp, ym, yp);
+    }
+    *gx = (2.0 / 3.0) * dxr[1] + (1.0 / 3.0) * (ym * dxr[2] + yp * dxr[0]) / (ym + yp);
+    *gy = (2.0 / 3.0) * dyc[1] + (1.0 / 3.0) * (xm * dyc[2] + xp * dyc[0]) / (xm + xp);
+    *lap = (5.0 / 6.0) * (dxxr[1] + dyyc[1]) +
+           (1.0 / 6.0) * (ym * dxxr[2] + yp * dxxr[0]) / (ym + yp) +
+           (1.0 / 6.0) * (xm * dyyc[2] + xp * dyyc[0]) / (xm + xp);
+}
+
 /* R8: isotropic gradient, d/dx = (1/RT) sum_q w_q e_qx phi(x + e_q), written
    as differences of opposite neighbours so that a uniform field gives an
    exactly zero gradient (and n = 0 by R7):
@@ -286,6 +347,10 @@ static double phi_at(const orc_sim *s, const double *phi, int i, int j) {
    R9: isotropic Laplacian, (2/RT) sum_q w_q [phi(x + e_q) - phi(x)]. */
 static void stencils(const orc_sim *s, const double *phi, int i, int j,
                      double *gx, double *gy, double *lap) {
+    if (s->mdx) {
+        stencils_mesh(s, phi, i, j, gx, gy, lap);
+        return;
+    }
     double c = phi_at(s, phi, i, j);
     double E = phi_at(s, phi, i + 1, j), Wv = phi_at(s, phi, i - 1, j);
     double N = phi_at(s, phi, i, j + 1), S = phi_at(s, phi, i, j - 1);
@@ -299,23 +364,26 @@ static void stencils(const orc_sim *s, const double *phi, int i, int j,
     *lap = 2.0 * sl / RT;
 }
 
-void orc_stencils(int nx, int ny, int walls_y, const double *phi, double *gx,
-                  double *gy, double *lap) {
+void orc_stencils(int nx, int ny, int walls_y, const double *dx, const double *dy,
+                  const double *phi, double *gx, double *gy, double *lap) {
     orc_sim tmp;
     memset(&tmp, 0, sizeof tmp);
     tmp.nx = nx;
     tmp.ny = ny;
     tmp.P.walls_y = walls_y;
+    if ((dx || dy) && orc_set_mesh(&tmp, dx, dy) != 0) return;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
             stencils(&tmp, phi, i, j, &gx[c], &gy[c], &lap[c]);
         }
+    orc_set_mesh(&tmp, NULL, NULL);
 }
 
-/* R7: regularised unit normal. */
+/* R7: regularised unit normal (eps in gradient units: over the smallest
+   cell width on a stretched mesh, R27). */
 static void unit(const orc_sim *s, double gx, double gy, double *nx, double *ny) {
-    double eps = 1e-6 * s->Dphi;
+    double eps = s->mdx ? 1e-6 * s->Dphi / s->dl : 1e-6 * s->Dphi;
     double m = sqrt(gx * gx + gy * gy + eps * eps);
     *nx = gx / m;
     *ny = gy / m;
@@ -356,7 +424,41 @@ void orc_destroy(orc_sim *s) {
                      s->theta, s->taug, s->fbp, s->gbp, s->ftp, s->gtp,
                      s->fxf, s->gxf, s->fyf, s->gyf};
     for (size_t k = 0; k < sizeof arr / sizeof arr[0]; ++k) free(arr[k]);
+    orc_set_mesh(s, NULL, NULL);
     free(s);
+}
+
+/* R27: widths dx[nx], dy[ny] of a stretched tensor-product mesh (either may
+   be NULL: unit widths on that axis). Both NULL: back to the unit mesh and
+   its own code. The time step becomes cfl times the smallest width. */
+int orc_set_mesh(orc_sim *s, const double *dx, const double *dy) {
+    free(s->mdx); free(s->mdy); free(s->mxc); free(s->myc);
+    s->mdx = s->mdy = s->mxc = s->myc = NULL;
+    s->dl = 1.0;
+    if (dx || dy) {
+        int nx = s->nx, ny = s->ny;
+        s->mdx = alloc(nx); s->mdy = alloc(ny); s->mxc = alloc(nx); s->myc = alloc(ny);
+        double x = 0.0, y = 0.0, lo = HUGE_VAL;
+        for (int i = 0; i < nx; ++i) {
+            double w = dx ? dx[i] : 1.0;
+            if (!(w > 0.0)) return orc_set_mesh(s, NULL, NULL), -1;
+            s->mdx[i] = w;
+            s->mxc[i] = x + 0.5 * w;
+            x += w;
+            if (w < lo) lo = w;
+        }
+        for (int j = 0; j < ny; ++j) {
+            double w = dy ? dy[j] : 1.0;
+            if (!(w > 0.0)) return orc_set_mesh(s, NULL, NULL), -1;
+            s->mdy[j] = w;
+            s->myc[j] = y + 0.5 * w;
+            y += w;
+            if (w < lo) lo = w;
+        }
+        s->dl = lo;
+    }
+    derive(s);
+    return 0;
 }
 
 int orc_set_params(orc_sim *s, const orc_params *P) {
@@ -421,7 +523,7 @@ static void pass_a(orc_sim *s) {
                     (m0 + 0.5 * s->dt * (ux * drx + uy * dry) + rho * G0); /* Eq. 33 */
                 s->taug[c] = taug_of(s, phi, rho);
             } else {
-                presc_vel(&s->P, i + 0.5, j + 0.5, t, &ux, &uy);
+                presc_vel(&s->P, xcen(s, i), ycen(s, j), t, &ux, &uy);
                 s->taug[c] = 0.0;
             }
             s->ux[c] = ux;
@@ -476,8 +578,28 @@ static void pass_b(orc_sim *s) {
 
 /* ------------------------------------------------------- Pass C: faces */
 
+/* R27 on a stretched mesh: slopes are derivatives (differences over the
+   centre distances), and the face value and tangential slope interpolate
+   linearly to the face position instead of taking the plain mean. */
+static double slope_y_mesh(const orc_sim *s, const double *a, int i, int j) {
+    int nx = s->nx, ny = s->ny;
+    if (s->P.walls_y) {
+        if (j == 0) return (a[(size_t)1 * nx + i] - a[i]) / hyp(s, 0);
+        if (j == ny - 1)
+            return (a[(size_t)(ny - 1) * nx + i] - a[(size_t)(ny - 2) * nx + i]) / hym(s, ny - 1);
+    }
+    return d1(a[(size_t)wrapi(j - 1, ny) * nx + i], a[(size_t)j * nx + i],
+              a[(size_t)wrapi(j + 1, ny) * nx + i], hym(s, j), hyp(s, j));
+}
+static double slope_x_mesh(const orc_sim *s, const double *a, int i, int j) {
+    int nx = s->nx;
+    return d1(a[(size_t)j * nx + wrapi(i - 1, nx)], a[(size_t)j * nx + i],
+              a[(size_t)j * nx + wrapi(i + 1, nx)], hxm(s, i), hxp(s, i));
+}
+
 /* Central slope of a cell field in y (R4); one-sided next to a wall. */
 static double slope_y(const orc_sim *s, const double *a, int i, int j) {
+    if (s->mdx) return slope_y_mesh(s, a, i, j);
     int nx = s->nx, ny = s->ny;
     if (s->P.walls_y) {
         if (j == 0) return a[(size_t)1 * nx + i] - a[i];
@@ -490,6 +612,7 @@ static double slope_y(const orc_sim *s, const double *a, int i, int j) {
 
 /* Central slope of a cell field in x (x is always periodic). */
 static double slope_x(const orc_sim *s, const double *a, int i, int j) {
+    if (s->mdx) return slope_x_mesh(s, a, i, j);
     int nx = s->nx;
     return 0.5 * (a[(size_t)j * nx + wrapi(i + 1, nx)] -
                   a[(size_t)j * nx + wrapi(i - 1, nx)]);
@@ -500,15 +623,37 @@ static double van_leer(double a, double b) {
     return a * b > 0.0 ? 2.0 * a * b / (a + b) : 0.0;
 }
 
+/* R27: on a stretched mesh the limited slope is van Leer's of the two
+   one-sided slopes (differences over the centre distances), capped at twice
+   the smaller one-sided difference over the cell's own width, so that the
+   one-dimensional reconstruction anywhere in the cell stays between the
+   neighbours. The cap never binds on linear data, nor on the unit mesh. */
+static double lim_mesh(double b, double f, double hm, double hp, double w) {
+    double s = van_leer(b / hm, f / hp);
+    double cap = 2.0 * fmin(fabs(b), fabs(f)) / w;
+    return s > cap ? cap : (s < -cap ? -cap : s);
+}
+
 /* Limited x and y slopes of a cell field (one-sided next to a wall in y). */
 static double lim_x(const orc_sim *s, const double *a, int i, int j) {
     int nx = s->nx;
     size_t c = (size_t)j * nx + i;
+    if (s->mdx)
+        return lim_mesh(a[c] - a[(size_t)j * nx + wrapi(i - 1, nx)],
+                        a[(size_t)j * nx + wrapi(i + 1, nx)] - a[c], hxm(s, i), hxp(s, i),
+                        wx(s, i));
     return van_leer(a[c] - a[(size_t)j * nx + wrapi(i - 1, nx)],
                     a[(size_t)j * nx + wrapi(i + 1, nx)] - a[c]);
 }
 static double lim_y(const orc_sim *s, const double *a, int i, int j) {
     int nx = s->nx, ny = s->ny;
+    if (s->mdx) {
+        if (s->P.walls_y && (j == 0 || j == ny - 1)) return slope_y_mesh(s, a, i, j);
+        size_t c = (size_t)j * nx + i;
+        return lim_mesh(a[c] - a[(size_t)wrapi(j - 1, ny) * nx + i],
+                        a[(size_t)wrapi(j + 1, ny) * nx + i] - a[c], hym(s, j), hyp(s, j),
+                        wy(s, j));
+    }
     if (s->P.walls_y) {
         if (j == 0) return a[(size_t)1 * nx + i] - a[i];
         if (j == ny - 1) return a[(size_t)(ny - 1) * nx + i] - a[(size_t)(ny - 2) * nx + i];
@@ -525,6 +670,15 @@ static double upwind_x(const orc_sim *s, const double *a, int q, int i, int ir, 
     int nx = s->nx;
     size_t L = (size_t)j * nx + i, R = (size_t)j * nx + ir;
     double h = s->h;
+    if (s->mdx) { /* offsets from the upwind centre: (dL - h, -h e_y) or (h - dR, -h e_y) */
+        double dL = 0.5 * wx(s, i), dR = 0.5 * wx(s, ir);
+        if (EX[q] > 0)
+            return a[L] + (dL - h) * lim_x(s, a, i, j) - h * EY[q] * lim_y(s, a, i, j);
+        if (EX[q] < 0)
+            return a[R] + (h - dR) * lim_x(s, a, ir, j) - h * EY[q] * lim_y(s, a, ir, j);
+        return (dR * (a[L] - h * EY[q] * lim_y(s, a, i, j)) +
+                dL * (a[R] - h * EY[q] * lim_y(s, a, ir, j))) / (dL + dR);
+    }
     if (EX[q] > 0)
         return a[L] + (0.5 - h) * lim_x(s, a, i, j) - h * EY[q] * lim_y(s, a, i, j);
     if (EX[q] < 0)
@@ -537,6 +691,15 @@ static double upwind_y(const orc_sim *s, const double *a, int q, int i, int jd, 
     int nx = s->nx;
     size_t Dn = (size_t)jd * nx + i, Up = (size_t)ju * nx + i;
     double h = s->h;
+    if (s->mdx) {
+        double dD = 0.5 * wy(s, jd), dU = 0.5 * wy(s, ju);
+        if (EY[q] > 0)
+            return a[Dn] + (dD - h) * lim_y(s, a, i, jd) - h * EX[q] * lim_x(s, a, i, jd);
+        if (EY[q] < 0)
+            return a[Up] + (h - dU) * lim_y(s, a, i, ju) - h * EX[q] * lim_x(s, a, i, ju);
+        return (dU * (a[Dn] - h * EX[q] * lim_x(s, a, i, jd)) +
+                dD * (a[Up] - h * EX[q] * lim_x(s, a, i, ju))) / (dD + dU);
+    }
     if (EY[q] > 0)
         return a[Dn] + (0.5 - h) * lim_y(s, a, i, jd) - h * EX[q] * lim_x(s, a, i, jd);
     if (EY[q] < 0)
@@ -548,6 +711,12 @@ static double upwind_y(const orc_sim *s, const double *a, int q, int i, int jd, 
    with the central reconstruction of R4: a - h (e_qx d_n + e_qy d_t). */
 static double central_x(const orc_sim *s, const double *a, int q, int i, int ir, int j) {
     size_t L = (size_t)j * s->nx + i, R = (size_t)j * s->nx + ir;
+    if (s->mdx) {
+        double dL = 0.5 * wx(s, i), dR = 0.5 * wx(s, ir), H = dL + dR;
+        double af = (dR * a[L] + dL * a[R]) / H, dn = (a[R] - a[L]) / H;
+        double dtg = (dR * slope_y(s, a, i, j) + dL * slope_y(s, a, ir, j)) / H;
+        return af - s->h * (EX[q] * dn + EY[q] * dtg);
+    }
     double avg = 0.5 * (a[L] + a[R]), dn = a[R] - a[L];
     double dtg = 0.5 * (slope_y(s, a, i, j) + slope_y(s, a, ir, j));
     return avg - s->h * (EX[q] * dn + EY[q] * dtg);
@@ -556,6 +725,12 @@ static double central_x(const orc_sim *s, const double *a, int q, int i, int ir,
 /* Same at the y-face between D = (i,jd) and U = (i,ju). */
 static double central_y(const orc_sim *s, const double *a, int q, int i, int jd, int ju) {
     size_t Dn = (size_t)jd * s->nx + i, Up = (size_t)ju * s->nx + i;
+    if (s->mdx) {
+        double dD = 0.5 * wy(s, jd), dU = 0.5 * wy(s, ju), H = dD + dU;
+        double af = (dU * a[Dn] + dD * a[Up]) / H, dn = (a[Up] - a[Dn]) / H;
+        double dtg = (dU * slope_x(s, a, i, jd) + dD * slope_x(s, a, i, ju)) / H;
+        return af - s->h * (EY[q] * dn + EX[q] * dtg);
+    }
     double avg = 0.5 * (a[Dn] + a[Up]), dn = a[Up] - a[Dn];
     double dtg = 0.5 * (slope_x(s, a, i, jd) + slope_x(s, a, i, ju));
     return avg - s->h * (EY[q] * dn + EX[q] * dtg);
@@ -574,21 +749,23 @@ static double recon_y(const orc_sim *s, const double *a, int q, int i, int jd, i
 /* Bar values of population q on every x-face (east of each cell) and every
    y-face (north of each cell; rows 0 .. ny-2 with walls) for a cell field a,
    in the reconstruction recon selects, with the functions Pass C uses. */
-void orc_recon(int nx, int ny, int walls_y, int recon, double h, int q, const double *a,
-               double *xface, double *yface) {
+void orc_recon(int nx, int ny, int walls_y, const double *dx, const double *dy, int recon,
+               double h, int q, const double *a, double *xface, double *yface) {
     orc_sim tmp;
     memset(&tmp, 0, sizeof tmp);
     tmp.nx = nx;
     tmp.ny = ny;
-    tmp.h = h;
     tmp.P.walls_y = walls_y;
     tmp.P.recon = recon;
+    if ((dx || dy) && orc_set_mesh(&tmp, dx, dy) != 0) return;
+    tmp.h = h;
     for (int j = 0; j < ny; ++j)
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
             xface[c] = recon_x(&tmp, a, q, i, wrapi(i + 1, nx), j);
             yface[c] = (walls_y && j == ny - 1) ? 0.0 : recon_y(&tmp, a, q, i, j, wrapi(j + 1, ny));
         }
+    orc_set_mesh(&tmp, NULL, NULL);
 }
 
 /* Face macros and the face original distributions (Eq. 28) from the bar
@@ -650,6 +827,11 @@ static void wall_face(orc_sim *s, int i, int bottom) {
     size_t row = bottom ? 0 : (size_t)ny;
     double dyw = bottom ? -0.5 : 0.5; /* wall y minus cell-centre y */
     double sgn = bottom ? 1.0 : -1.0; /* sign of the one-sided difference */
+    double idy = 1.0;                 /* 1 / distance to the next centre */
+    if (s->mdx) {                     /* R27 */
+        dyw = bottom ? -0.5 * wy(s, 0) : 0.5 * wy(s, ny - 1);
+        idy = 1.0 / (bottom ? hyp(s, 0) : hym(s, ny - 1));
+    }
 
     double phiw = s->phi[c];
     double rhow = rho_of(s, phiw), thw = theta_of(s, phiw);
@@ -672,9 +854,11 @@ static void wall_face(orc_sim *s, int i, int bottom) {
         double dx = -s->h * EX[q], dy = dyw - s->h * EY[q];
         double sxf = slope_x(s, s->fbp + q * n, i, j);
         double syf = sgn * (s->fbp[q * n + cn] - s->fbp[q * n + c]);
+        if (s->mdx) syf *= idy;
         fb[q] = s->fbp[q * n + c] + dx * sxf + dy * syf;
         double sxg = slope_x(s, s->gbp + q * n, i, j);
         double syg = sgn * (s->gbp[q * n + cn] - s->gbp[q * n + c]);
+        if (s->mdx) syg *= idy;
         gb[q] = s->gbp[q * n + c] + dx * sxg + dy * syg;
     }
     orc_face_df(s->tau_f, s->h, fb, feq, sf, fo);
@@ -712,13 +896,24 @@ static void pass_c(orc_sim *s) {
                 if (s->coupled) gb[q] = recon_x(s, s->gbp + q * n, q, i, ir, j);
             }
             face_in in;
-            in.gx = 0.5 * (s->gpx[L] + s->gpx[R]);
-            in.gy = 0.5 * (s->gpy[L] + s->gpy[R]);
-            in.mu = 0.5 * (s->mu[L] + s->mu[R]);
-            in.Dx = 0.5 * (s->Dx[L] + s->Dx[R]);
-            in.Dy = 0.5 * (s->Dy[L] + s->Dy[R]);
-            in.xf = i + 1.0;
-            in.yf = j + 0.5;
+            if (s->mdx) { /* R27: linear interpolation to the face */
+                double dL = 0.5 * wx(s, i), dR = 0.5 * wx(s, ir), H = dL + dR;
+                in.gx = (dR * s->gpx[L] + dL * s->gpx[R]) / H;
+                in.gy = (dR * s->gpy[L] + dL * s->gpy[R]) / H;
+                in.mu = (dR * s->mu[L] + dL * s->mu[R]) / H;
+                in.Dx = (dR * s->Dx[L] + dL * s->Dx[R]) / H;
+                in.Dy = (dR * s->Dy[L] + dL * s->Dy[R]) / H;
+                in.xf = xcen(s, i) + dL;
+                in.yf = ycen(s, j);
+            } else {
+                in.gx = 0.5 * (s->gpx[L] + s->gpx[R]);
+                in.gy = 0.5 * (s->gpy[L] + s->gpy[R]);
+                in.mu = 0.5 * (s->mu[L] + s->mu[R]);
+                in.Dx = 0.5 * (s->Dx[L] + s->Dx[R]);
+                in.Dy = 0.5 * (s->Dy[L] + s->Dy[R]);
+                in.xf = i + 1.0;
+                in.yf = j + 0.5;
+            }
             face_df(s, &in, fb, gb, fo, go);
             for (int q = 0; q < 9; ++q) {
                 s->fxf[q * n + L] = fo[q];
@@ -740,13 +935,24 @@ static void pass_c(orc_sim *s) {
                 if (s->coupled) gb[q] = recon_y(s, s->gbp + q * n, q, i, jd, ju);
             }
             face_in in;
-            in.gx = 0.5 * (s->gpx[Dn] + s->gpx[Up]);
-            in.gy = 0.5 * (s->gpy[Dn] + s->gpy[Up]);
-            in.mu = 0.5 * (s->mu[Dn] + s->mu[Up]);
-            in.Dx = 0.5 * (s->Dx[Dn] + s->Dx[Up]);
-            in.Dy = 0.5 * (s->Dy[Dn] + s->Dy[Up]);
-            in.xf = i + 0.5;
-            in.yf = (double)jj;
+            if (s->mdx) {
+                double dD = 0.5 * wy(s, jd), dU = 0.5 * wy(s, ju), H = dD + dU;
+                in.gx = (dU * s->gpx[Dn] + dD * s->gpx[Up]) / H;
+                in.gy = (dU * s->gpy[Dn] + dD * s->gpy[Up]) / H;
+                in.mu = (dU * s->mu[Dn] + dD * s->mu[Up]) / H;
+                in.Dx = (dU * s->Dx[Dn] + dD * s->Dx[Up]) / H;
+                in.Dy = (dU * s->Dy[Dn] + dD * s->Dy[Up]) / H;
+                in.xf = xcen(s, i);
+                in.yf = ycen(s, jd) + dD;
+            } else {
+                in.gx = 0.5 * (s->gpx[Dn] + s->gpx[Up]);
+                in.gy = 0.5 * (s->gpy[Dn] + s->gpy[Up]);
+                in.mu = 0.5 * (s->mu[Dn] + s->mu[Up]);
+                in.Dx = 0.5 * (s->Dx[Dn] + s->Dx[Up]);
+                in.Dy = 0.5 * (s->Dy[Dn] + s->Dy[Up]);
+                in.xf = i + 0.5;
+                in.yf = (double)jj;
+            }
             face_df(s, &in, fb, gb, fo, go);
             for (int q = 0; q < 9; ++q) {
                 s->fyf[q * n1 + (size_t)jj * nx + i] = fo[q];
@@ -770,8 +976,9 @@ static void pass_c(orc_sim *s) {
 
 /* ------------------------------------------------------ Pass D: update */
 
-/* Eq. 24 with the microflux of Eq. 22 on unit square cells: the outward
-   normals are +-x and +-y and each face has unit length. */
+/* Eq. 24 with the microflux of Eq. 22 on rectangular cells: the outward
+   normals are +-x and +-y; a face's length over the cell's area is 1/dx or
+   1/dy (1 on the unit mesh). */
 static void pass_d(orc_sim *s) {
     int nx = s->nx, ny = s->ny;
     size_t n = (size_t)nx * ny, n1 = (size_t)nx * (ny + 1);
@@ -780,13 +987,17 @@ static void pass_d(orc_sim *s) {
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i, w = (size_t)j * nx + wrapi(i - 1, nx);
             size_t fn = (size_t)(j + 1) * nx + i, fs = (size_t)j * nx + i;
+            /* R27: face lengths over the cell area, 1/dx and 1/dy */
+            double ax = s->mdx ? 1.0 / wx(s, i) : 1.0, ay = s->mdx ? 1.0 / wy(s, j) : 1.0;
             for (int q = 0; q < 9; ++q) {
-                double J = EX[q] * (s->fxf[q * n + c] - s->fxf[q * n + w]) +
-                           EY[q] * (s->fyf[q * n1 + fn] - s->fyf[q * n1 + fs]);
+                double Jx = EX[q] * (s->fxf[q * n + c] - s->fxf[q * n + w]);
+                double Jy = EY[q] * (s->fyf[q * n1 + fn] - s->fyf[q * n1 + fs]);
+                double J = s->mdx ? ax * Jx + ay * Jy : Jx + Jy;
                 s->f[q * n + c] = s->ftp[q * n + c] - s->dt * J;
                 if (s->coupled) {
-                    double Jg = EX[q] * (s->gxf[q * n + c] - s->gxf[q * n + w]) +
-                                EY[q] * (s->gyf[q * n1 + fn] - s->gyf[q * n1 + fs]);
+                    double Jgx = EX[q] * (s->gxf[q * n + c] - s->gxf[q * n + w]);
+                    double Jgy = EY[q] * (s->gyf[q * n1 + fn] - s->gyf[q * n1 + fs]);
+                    double Jg = s->mdx ? ax * Jgx + ay * Jgy : Jgx + Jgy;
                     s->g[q * n + c] = s->gtp[q * n + c] - s->dt * Jg;
                 }
             }
@@ -833,7 +1044,7 @@ int orc_init(orc_sim *s, const double *phi0, const double *u0, const double *v0,
                 uy = v0 ? v0[c] : 0.0;
                 p = p0 ? p0[c] : 0.0;
             } else {
-                presc_vel(&s->P, i + 0.5, j + 0.5, 0.0, &ux, &uy);
+                presc_vel(&s->P, xcen(s, i), ycen(s, j), 0.0, &ux, &uy);
             }
             s->ux[c] = ux;
             s->uy[c] = uy;

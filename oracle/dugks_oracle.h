@@ -40,6 +40,10 @@ typedef struct orc_sim orc_sim;
 orc_sim *orc_create(int nx, int ny, int coupled, const orc_params *P);
 void orc_destroy(orc_sim *s);
 int orc_set_params(orc_sim *s, const orc_params *P);
+/* Stretched tensor-product mesh: cell widths dx[nx], dy[ny] (> 0; either may
+   be NULL for unit widths on that axis; both NULL: the unit mesh). Returns -1
+   on a width <= 0. dt becomes cfl times the smallest width. */
+int orc_set_mesh(orc_sim *s, const double *dx, const double *dy);
 int orc_init(orc_sim *s, const double *phi0, const double *u0,
              const double *v0, const double *p0);
 void orc_step(orc_sim *s, int nsteps);
@@ -68,10 +72,11 @@ void orc_face_df(double tau, double h, const double *bar, const double *eq,
                  const double *S, double *out);
 /* Bar values of population q at the faces (Eq. 27, both reconstructions):
    xface[j nx + i] east of cell (i,j), yface[j nx + i] north of it. */
-void orc_recon(int nx, int ny, int walls_y, int recon, double h, int q, const double *a,
-               double *xface, double *yface);
-void orc_stencils(int nx, int ny, int walls_y, const double *phi, double *gx,
-                  double *gy, double *lap);
+void orc_recon(int nx, int ny, int walls_y, const double *dx, const double *dy, int recon,
+               double h, int q, const double *a, double *xface, double *yface);
+/* Gradient and Laplacian of phi (R8, R9; R27 when dx or dy is given). */
+void orc_stencils(int nx, int ny, int walls_y, const double *dx, const double *dy,
+                  const double *phi, double *gx, double *gy, double *lap);
 
 #ifdef __cplusplus
 }

@@ -260,3 +260,40 @@ def random_coupled(nx, ny, seed=0, rho_ratio=10.0, sigma=1e-3, U=0.01,
                   gy=-1e-6 if walls_y else 0.0, gravity="buoyancy")
     return _case(f"random_coupled_{nx}x{ny}_s{seed}", nx, ny, "coupled", params,
                  phi, u=u, v=v)
+
+
+# ------------------------------------------------------- stretched meshes
+
+def stretched_widths(n, amp=0.3, length=None, phase=0.0, periods=1):
+    """Cell widths of a smoothly stretched axis: w_i proportional to
+    1 + amp sin(2 pi periods (i + 1/2) / n + phase), scaled to sum to
+    ``length`` (default n)."""
+    i = np.arange(n) + 0.5
+    w = 1.0 + amp * np.sin(2 * np.pi * periods * i / n + phase)
+    return w * ((n if length is None else length) / w.sum())
+
+
+def random_widths(n, seed, lo=0.5, hi=1.5):
+    """Cell widths drawn uniformly from [lo, hi] (a rough mesh)."""
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+def clustered_widths(n, length, centres, fine=0.5, spread=None):
+    """Widths that shrink to ``fine`` times the mean near each of ``centres``
+    (positions along the axis) and grow away from them: w proportional to
+    1 - (1 - fine) exp(-((x - c) / spread)^2) summed over the centres,
+    iterated so that the widths follow their own centres."""
+    spread = length / 8.0 if spread is None else spread
+    w = np.full(n, length / n)
+    for _ in range(20):
+        x = np.cumsum(w) - 0.5 * w
+        g = np.ones(n)
+        for c in centres:
+            g -= (1.0 - fine) * np.exp(-((x - c) / spread) ** 2)
+        w = g * (length / g.sum())
+    return w
+
+
+def mesh_centres(w):
+    """Centres of cells of widths ``w`` starting at 0."""
+    return np.cumsum(w) - 0.5 * w
