@@ -25,7 +25,8 @@
  *     independent. All device work of a handle is ordered on its stream
  *     (default: the null stream; see dugks_set_stream()).
  *   - Time is implicit: t = steps * dt with dt = CFL (grid spacing 1,
- *     sqrt(3RT) = 1; Eq. 37).
+ *     sqrt(3RT) = 1; Eq. 37), or CFL times the smallest width on a
+ *     stretched mesh (dugks_set_mesh).
  */
 #ifndef DUGKS_H
 #define DUGKS_H
@@ -138,6 +139,30 @@ int dugks_set_stream(dugks_handle *h, void *stream);
  * outside [0, 4096]. dugks_get_tile returns the value in use (-1 for NULL). */
 int dugks_set_tile(dugks_handle *h, int seg_rows);
 int dugks_get_tile(const dugks_handle *h);
+
+/* Stretched tensor-product mesh (DUGKS is a finite-volume scheme: Eq. 21
+ * integrates the microflux over the cell surface and divides by the cell
+ * volume; the introduction names this as its advantage over the uniform
+ * lattice of the lattice Boltzmann method). dx[nx] and dy[ny] are the cell
+ * widths (host arrays of double, copied; finite and > 0; either may be NULL
+ * for unit widths on that axis). Both NULL returns to the unit mesh.
+ * On a stretched mesh:
+ *   - dt = cfl * (smallest width), and the time of dugks_time follows it;
+ *   - the update divides the x and y microfluxes by the cell's widths;
+ *   - the gradient and Laplacian are weighted sums of the derivatives of the
+ *     parabola through three neighbouring centres (exact on quadratics, the
+ *     unit-mesh stencils on unit widths);
+ *   - the face reconstruction interpolates linearly to the face, with slopes
+ *     over the centre distances (both reconstructions; the upwind slopes are
+ *     van Leer's of the one-sided slopes, capped at twice the smaller
+ *     one-sided difference over the cell width);
+ *   - the regularisation of the unit normal is 1e-6 |phi_H - phi_L| over
+ *     the smallest width.
+ * The step then runs as three kernels with the scratch of the upwind mode
+ * (see recon). Cell centres start at x = 0, y = 0. Takes effect at the next
+ * dugks_init_fields (the state is invalidated: ESTATE until then). Not for
+ * batches or pool cases (EINVAL). Errors: EINVAL (widths), ENOMEM. */
+int dugks_set_mesh(dugks_handle *h, const double *dx, const double *dy);
 
 /* Build the initial state from cell macros: host arrays [ny][nx] of double,
  * copied during the call. u, v, p may be NULL (zero); the interface-only

@@ -109,6 +109,7 @@ def lib():
             "dugks_set_stream": (i, [vp, vp]),
             "dugks_set_tile": (i, [vp, i]),
             "dugks_get_tile": (i, [vp]),
+            "dugks_set_mesh": (i, [vp, dp, dp]),
             "dugks_autotune": (i, [vp, i, C.POINTER(i), dp]),
             "dugks_init_fields": (i, [vp, dp, dp, dp, dp]),
             "dugks_init_fields_device": (i, [vp, vp, vp, vp, vp]),
@@ -271,6 +272,16 @@ class Solver:
     def set_params(self, params):
         """New parameters from the next step on (the state is kept)."""
         set_params(self.h, params)
+
+    def set_mesh(self, dx=None, dy=None):
+        """Stretched mesh of cell widths dx[nx], dy[ny] (None: unit widths on
+        that axis; both None: the unit mesh). Call before init."""
+        ax = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (dx, dy)]
+        for a, n in zip(ax, (self.nx, self.ny)):
+            if a is not None and a.shape != (n,):
+                raise ValueError(f"widths must have shape ({n},)")
+        _check(lib().dugks_set_mesh(self.h, *[_dptr(a) for a in ax]), self.h)
+        self._mesh = ax
 
     def init(self, phi, u=None, v=None, p=None):
         init_fields(self.h, self.shape, phi, u, v, p)

@@ -102,8 +102,17 @@ void fill_case(dugks_handle* h) {
   C.plane = (long long)h->n();
   C.set[0] = h->buf[0];
   C.set[1] = h->buf[1];
-  C.dt = P.cfl;  // Eq. 37 with unit grid spacing and sqrt(3RT) = 1
+  // Eq. 37 with sqrt(3RT) = 1 and delta_l the smallest cell width (1 on
+  // the unit mesh)
+  double dl = 1.0;
+  if (h->mesh) {
+    dl = HUGE_VAL;
+    for (double w : h->mdx) dl = std::min(dl, w);
+    for (double w : h->mdy) dl = std::min(dl, w);
+  }
+  C.dt = P.cfl * dl;
   C.h = 0.5 * C.dt;
+  C.mesh = h->mesh ? h->dmesh : nullptr;
   C.t0 = 0.0;
   const double D = P.phi_H - P.phi_L;
   C.phi_H = P.phi_H;
@@ -130,7 +139,9 @@ void fill_case(dugks_handle* h) {
   C.U0 = P.U0;
   C.L0 = P.L0;
   C.T_period = P.T_period;
-  C.eps_n2 = (1e-6 * D) * (1e-6 * D);
+  // regularisation of the unit normal, in gradient units (over the smallest
+  // width on a stretched mesh)
+  C.eps_n2 = (1e-6 * D / dl) * (1e-6 * D / dl);
   C.fb = 3.0 * C.h / (2.0 * C.tau_f + C.dt);
   C.ffb = C.h / (2.0 * C.tau_f + C.h);
   C.gb = 3.0 * C.h / (2.0 * C.tau_g_uniform + C.dt);
@@ -139,9 +150,46 @@ void fill_case(dugks_handle* h) {
   C.nsteps = LLONG_MAX;
 }
 
+// Metric arrays of a stretched mesh (layout of CaseDev::mesh): per axis the
+// widths, the distances to the previous and next centres (x periodic; y
+// periodic, or with walls mirrored so that the ghost row has the width of
+// its row), and the centres.
+static std::vector<double> mesh_metrics(const dugks_handle* h, bool walls) {
+  std::vector<double> m;
+  auto axis = [&](const std::vector<double>& w, bool mirror) {
+    const int n = (int)w.size();
+    auto at = [&](int k) {
+      if (k < 0) return mirror ? w[0] : w[n - 1];
+      if (k >= n) return mirror ? w[n - 1] : w[0];
+      return w[k];
+    };
+    std::vector<double> hm(n), hp(n), c(n);
+    double x = 0.0;
+    for (int k = 0; k < n; ++k) {
+      hm[k] = 0.5 * (at(k - 1) + w[k]);
+      hp[k] = 0.5 * (w[k] + at(k + 1));
+      c[k] = x + 0.5 * w[k];
+      x += w[k];
+    }
+    m.insert(m.end(), w.begin(), w.end());
+    m.insert(m.end(), hm.begin(), hm.end());
+    m.insert(m.end(), hp.begin(), hp.end());
+    m.insert(m.end(), c.begin(), c.end());
+  };
+  axis(h->mdx, false);
+  axis(h->mdy, walls);
+  return m;
+}
+
 int upload_case(dugks_handle* h) {
   if (!h->dirty_case) return DUGKS_OK;
   fill_case(h);
+  if (h->mesh) {  // the metrics depend on the y boundary
+    const std::vector<double> m = mesh_metrics(h, h->hc.walls != 0);
+    HIPCHK(h, hipMemcpyAsync(h->dmesh, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // m is a local
+  }
   HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
   if (h->borrowed) {  // a pool case: the pool launches it with its own items, and
     h->dirty_case = false;  // h->hc, the source of the copy, lives as long as the case
@@ -210,13 +258,26 @@ int ensure_scratch(dugks_handle* h) {
   return DUGKS_OK;
 }
 
+int ensure_up_scratch(dugks_handle* h) {
+  if (h->up) return DUGKS_OK;
+  const size_t b = (size_t)dugks::up_scratch_values((long long)h->n(), h->nx, h->coupled()) * h->elem();
+  hipError_t e = hipMalloc(&h->up, b);
+  if (e != hipSuccess) {
+    h->up = nullptr;
+    (void)hipGetLastError();
+    return fail(h, e == hipErrorOutOfMemory ? DUGKS_ENOMEM : DUGKS_EDEVICE,
+                std::string("scratch allocation failed: ") + hipGetErrorString(e));
+  }
+  return DUGKS_OK;
+}
+
 int launch_steps(dugks_handle* h, int nsteps) {
-  if (h->upwind()) {
+  if (h->general()) {
     UpArgs u{h->dc, h->step_base, 0, h->up};
     for (int k = 0; k < nsteps; ++k) {
       u.kofs = k;
-      HIPCHK(h, dugks::launch_step_upwind(h->fp64(), h->coupled(), h->hc.walls != 0, h->nx, h->ny,
-                                          u, h->stream));
+      HIPCHK(h, dugks::launch_step_upwind(h->fp64(), h->coupled(), h->hc.walls != 0, h->upwind(),
+                                          h->mesh, h->nx, h->ny, u, h->stream));
     }
     HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
     return DUGKS_OK;
@@ -280,15 +341,9 @@ int dugks_set_params(dugks_handle* h, const dugks_params* p) {
   if (!h || !p) return fail(h, DUGKS_EINVAL, "NULL argument");
   std::string why;
   if (validate(h, p, why) != DUGKS_OK) return fail(h, DUGKS_EINVAL, why);
-  if (p->recon == DUGKS_RECON_UPWIND && !h->up) {
-    const size_t b = (size_t)dugks::up_scratch_values((long long)h->n(), h->nx, h->coupled()) * h->elem();
-    hipError_t e = hipMalloc(&h->up, b);
-    if (e != hipSuccess) {
-      h->up = nullptr;
-      (void)hipGetLastError();
-      return fail(h, e == hipErrorOutOfMemory ? DUGKS_ENOMEM : DUGKS_EDEVICE,
-                  std::string("upwind scratch allocation failed: ") + hipGetErrorString(e));
-    }
+  if (p->recon == DUGKS_RECON_UPWIND || h->mesh) {
+    int rc = ensure_up_scratch(h);
+    if (rc) return rc;
   }
   h->params = *p;
   h->has_params = true;
@@ -312,6 +367,46 @@ int dugks_set_tile(dugks_handle* h, int seg_rows) {
 }
 
 int dugks_get_tile(const dugks_handle* h) { return h ? h->hc.seg_rows : -1; }
+
+int dugks_set_mesh(dugks_handle* h, const double* dx, const double* dy) {
+  if (!h) return fail(h, DUGKS_EINVAL, "NULL handle");
+  if (h->borrowed) return fail(h, DUGKS_EINVAL, "pool cases run on the unit mesh");
+  if (!dx && !dy) {  // back to the unit mesh and the fused march
+    h->mesh = false;
+    h->mdx.clear();
+    h->mdy.clear();
+    h->dirty_case = true;
+    h->has_state = false;
+    return h->has_params ? upload_case(h) : DUGKS_OK;
+  }
+  std::vector<double> wx(h->nx, 1.0), wy(h->ny, 1.0);
+  for (int i = 0; i < h->nx; ++i)
+    if (dx) wx[i] = dx[i];
+  for (int j = 0; j < h->ny; ++j)
+    if (dy) wy[j] = dy[j];
+  for (double w : wx)
+    if (!(w > 0.0 && std::isfinite(w))) return fail(h, DUGKS_EINVAL, "cell widths must be finite and > 0");
+  for (double w : wy)
+    if (!(w > 0.0 && std::isfinite(w))) return fail(h, DUGKS_EINVAL, "cell widths must be finite and > 0");
+  if (!h->dmesh) {
+    hipError_t e = hipMalloc(&h->dmesh, 4 * (size_t)(h->nx + h->ny) * sizeof(double));
+    if (e != hipSuccess) {
+      h->dmesh = nullptr;
+      (void)hipGetLastError();
+      return fail(h, DUGKS_ENOMEM, std::string("mesh allocation failed: ") + hipGetErrorString(e));
+    }
+  }
+  if (h->has_params) {
+    int rc = ensure_up_scratch(h);
+    if (rc) return rc;
+  }
+  h->mesh = true;
+  h->mdx.swap(wx);
+  h->mdy.swap(wy);
+  h->dirty_case = true;
+  h->has_state = false;  // the time step and stencils changed: init again
+  return h->has_params ? upload_case(h) : DUGKS_OK;
+}
 
 int dugks_init_fields_device(dugks_handle* h, const double* phi, const double* u, const double* v,
                              const double* p) {
@@ -414,7 +509,7 @@ int dugks_get_diagnostics(dugks_handle* h, double out[8]) {
 }
 
 long long dugks_steps_done(const dugks_handle* h) { return h ? h->steps : -1; }
-double dugks_time(const dugks_handle* h) { return h ? h->steps * h->params.cfl : 0.0; }
+double dugks_time(const dugks_handle* h) { return h ? h->steps * h->hc.dt : 0.0; }
 
 size_t dugks_state_bytes(const dugks_handle* h) { return h ? h->buf_bytes : 0; }
 
@@ -449,7 +544,8 @@ int dugks_set_state(dugks_handle* h, const void* host_buf, size_t bytes, long lo
 int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* out_us) {
   if (!h || probe_steps < 1 || probe_steps > 1000) return fail(h, DUGKS_EINVAL, "bad arguments");
   if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
-  if (h->upwind()) return fail(h, DUGKS_EINVAL, "the upwind reconstruction has no tiles to tune");
+  if (h->general())
+    return fail(h, DUGKS_EINVAL, "the upwind reconstruction and stretched meshes have no tiles to tune");
   // candidates: the shortest segments (lowest latency per step), and for
   // k = 1..8, 12, 16 the shortest segment whose tiles fit k rounds of resident waves
   // (more rounds: finer load balance, more repeated halo work)
@@ -543,6 +639,7 @@ int dugks_destroy(dugks_handle* h) {
   if (h->step_base) (void)hipFree(h->step_base);
   if (h->scratch) (void)hipFree(h->scratch);
   if (h->up) (void)hipFree(h->up);
+  if (h->dmesh) (void)hipFree(h->dmesh);
   delete h;
   return DUGKS_OK;
 }
@@ -588,8 +685,9 @@ int bfail(dugks_batch* b, int code, const std::string& m) {
 int sync_descriptors(dugks_batch* b) {
   for (size_t k = 0; k < b->cases.size(); ++k) {
     dugks_handle* h = b->cases[k];
-    if (h->upwind())  // parameters changed after the batch was made
-      return bfail(b, DUGKS_EINVAL, "the upwind reconstruction runs on single handles only");
+    if (h->general())  // parameters or mesh changed after the batch was made
+      return bfail(b, DUGKS_EINVAL,
+                   "the upwind reconstruction and stretched meshes run on single handles only");
     CaseDev c = h->hc;
     c.seg_rows = b->seg[k];
     c.nsegs = (c.ny + c.seg_rows - 1) / c.seg_rows;
@@ -661,8 +759,9 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
     if (!cases[k]->has_params) return bfail(nullptr, DUGKS_ESTATE, "case without params");
     if (cases[k]->precision != cases[0]->precision || cases[k]->model != cases[0]->model)
       return bfail(nullptr, DUGKS_EINVAL, "cases must share precision and model");
-    if (cases[k]->upwind())
-      return bfail(nullptr, DUGKS_EINVAL, "the upwind reconstruction runs on single handles only");
+    if (cases[k]->general())
+      return bfail(nullptr, DUGKS_EINVAL,
+                   "the upwind reconstruction and stretched meshes run on single handles only");
   }
   dugks_batch* b = new (std::nothrow) dugks_batch;
   if (!b) return bfail(nullptr, DUGKS_ENOMEM, "host allocation failed");

@@ -26,7 +26,11 @@ struct dugks_handle {
   long long* step_base = nullptr;  // device: steps done
   long long steps = 0;             // host mirror
   double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
-  void* up = nullptr;              // scratch planes of the upwind reconstruction
+  void* up = nullptr;              // scratch planes of the three-kernel step
+  // stretched mesh: host widths, and the device metric arrays (CaseDev::mesh)
+  bool mesh = false;
+  std::vector<double> mdx, mdy;
+  double* dmesh = nullptr;
   std::string err = "no error";
   bool dirty_case = true;
   // a case of a serving pool: its buffers, descriptor, counter and scratch
@@ -35,6 +39,9 @@ struct dugks_handle {
 
   bool fp64() const { return precision == DUGKS_FP64; }
   bool upwind() const { return params.recon == DUGKS_RECON_UPWIND; }
+  // steps run as three kernels (upwind reconstruction or stretched mesh)
+  // instead of the fused march
+  bool general() const { return upwind() || mesh; }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
   size_t n() const { return (size_t)nx * ny; }
   size_t elem() const { return fp64() ? 8 : 4; }
@@ -76,6 +83,7 @@ int upload_case(dugks_handle* h);
 int validate(const dugks_handle* h, const dugks_params* p, std::string& why);
 size_t state_set_bytes(int nx, int ny, int precision, int model);
 int ensure_scratch(dugks_handle* h);
+int ensure_up_scratch(dugks_handle* h);
 int launch_steps(dugks_handle* h, int nsteps);
 
 }  // namespace host

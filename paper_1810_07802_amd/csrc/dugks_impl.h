@@ -75,7 +75,21 @@ struct CaseDev {
   // equilibrium weights of the relaxation: cell (Eq. 29) 3h/(2tau+dt), face
   // (Eq. 28) h/(2tau+h); for f, and for g when tau_g is uniform
   double fb, ffb, gb, gfb;
+  // stretched mesh (nullptr: unit cells): per axis, x then y, four arrays
+  // of the axis length: width, distance to the previous centre, distance to
+  // the next centre, centre position (layout in mesh_axis())
+  const double* mesh;
 };
+
+// Metric arrays of one axis of a stretched mesh.
+struct MeshAxis {
+  const double *w, *hm, *hp, *c;
+};
+__host__ __device__ inline MeshAxis mesh_axis(const double* mesh, int nx, int ny, int axis) {
+  const double* b = mesh + (axis == 0 ? 0 : 4 * (long long)nx);
+  const long long n = axis == 0 ? nx : ny;
+  return MeshAxis{b, b + n, b + 2 * n, b + 3 * n};
+}
 
 enum VelKind { kVelUniform = 0, kVelRotation = 1, kVelShear = 2, kVelDeform = 3 };
 enum ViscMode { kViscUniformNu = 0, kViscReciprocal = 1, kViscLinear = 2 };
@@ -117,7 +131,8 @@ __host__ __device__ constexpr int up_yslot(int q) {
   return q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 2 : q == 6 ? 3 : q == 7 ? 4 : q == 8 ? 5 : -1;
 }
 
-// Launch arguments of the upwind step kernels (one case, one step).
+// Launch arguments of the three-kernel step (upwind reconstruction, or a
+// stretched mesh; one case, one step).
 struct UpArgs {
   const CaseDev* cases;
   const long long* step_base;
@@ -126,8 +141,8 @@ struct UpArgs {
 };
 
 // host-side launchers (dugks_kernels.hip)
-hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, int nx, int ny,
-                              const UpArgs& a, hipStream_t s);
+hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
+                              int nx, int ny, const UpArgs& a, hipStream_t s);
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
 int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);

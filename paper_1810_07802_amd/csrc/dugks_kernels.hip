@@ -235,26 +235,14 @@ struct Cell {
 };
 
 // Cell macros at t_n (Eqs. 31-33, 4, 6, 10), equilibria and sources
-// (Eqs. 15-19), bar-plus (Eq. 29) and tilde-plus (Eq. 30). ph[r][c] is phi on
-// rows (r-1, r, r+1) and columns (left, own, right). The tilde-plus values go
-// to `tp` (18 values, f then g).
+// (Eqs. 15-19), bar-plus (Eq. 29) and tilde-plus (Eq. 30) of a cell with
+// order parameter phi, gradient (gx, gy) and Laplacian lap. The tilde-plus
+// values go to `tp` (18 values, f then g).
 template <typename T, bool CPL>
-__device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3],
-                                           const T (&ft)[9], const T (&gt)[9],
-                                           T hist_x, T hist_y, double xc, double yc,
-                                           double tn, Cell<T>& o, T (&tp)[18]) {
-  const T c = ph[1][1];
-  const T E = ph[1][2], Wv = ph[1][0], N = ph[2][1], S = ph[0][1];
-  const T NE = ph[2][2], NW = ph[2][0], SE = ph[0][2], SW = ph[0][0];
-  // isotropic D2Q9-weighted gradient (six non-zero points per component) and
-  // nine-point Laplacian, the stencils named before Eq. 37
-  const T gx = (T(4) * (E - Wv) + (NE - NW) + (SE - SW)) * T(1.0 / 12.0);
-  const T gy = (T(4) * (N - S) + (NE - SE) + (NW - SW)) * T(1.0 / 12.0);
-  // differences first: near equilibrium mu_phi is a small residual of two
-  // O(beta) terms, so the Laplacian must not lose the ulps of phi
-  const T lap = T(2.0 / 3.0) * (((E - c) + (Wv - c)) + ((N - c) + (S - c))) +
-                T(1.0 / 6.0) * (((NE - c) + (NW - c)) + ((SE - c) + (SW - c)));
-  const T phi = c;
+__device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T lap,
+                                          const T (&ft)[9], const T (&gt)[9],
+                                          T hist_x, T hist_y, double xc, double yc,
+                                          double tn, Cell<T>& o, T (&tp)[18]) {
   const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
   const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;  // Eq. 4
   const T theta = T(C.theta_c) * dA * dB;                                            // Eq. 6
@@ -342,6 +330,27 @@ __device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3]
   }
 }
 
+// The same with the unit-mesh stencils. ph[r][c] is phi on rows (r-1, r,
+// r+1) and columns (left, own, right).
+template <typename T, bool CPL>
+__device__ __forceinline__ void cell_stage(const CaseDev& C, const T (&ph)[3][3],
+                                           const T (&ft)[9], const T (&gt)[9],
+                                           T hist_x, T hist_y, double xc, double yc,
+                                           double tn, Cell<T>& o, T (&tp)[18]) {
+  const T c = ph[1][1];
+  const T E = ph[1][2], Wv = ph[1][0], N = ph[2][1], S = ph[0][1];
+  const T NE = ph[2][2], NW = ph[2][0], SE = ph[0][2], SW = ph[0][0];
+  // isotropic D2Q9-weighted gradient (six non-zero points per component) and
+  // nine-point Laplacian, the stencils named before Eq. 37
+  const T gx = (T(4) * (E - Wv) + (NE - NW) + (SE - SW)) * T(1.0 / 12.0);
+  const T gy = (T(4) * (N - S) + (NE - SE) + (NW - SW)) * T(1.0 / 12.0);
+  // differences first: near equilibrium mu_phi is a small residual of two
+  // O(beta) terms, so the Laplacian must not lose the ulps of phi
+  const T lap = T(2.0 / 3.0) * (((E - c) + (Wv - c)) + ((N - c) + (S - c))) +
+                T(1.0 / 6.0) * (((NE - c) + (NW - c)) + ((SE - c) + (SW - c)));
+  cell_core<T, CPL>(C, c, gx, gy, lap, ft, gt, hist_x, hist_y, xc, yc, tn, o, tp);
+}
+
 // ------------------------------------------------------- face distribution
 
 // Face macros (Eqs. 31-33 with dt/2 -> h/2; gradient-type inputs are the mean
@@ -404,12 +413,17 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
 // p and phi are the wall cell's, and the normal parts of grad phi and D vanish.
 // `c` is the adjacent cell, `cn` the next cell inward, txf/txg the x central
 // differences of the adjacent cell's bar-plus values (diagonal populations).
-template <typename T, bool BOTTOM>
-__device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
-                                          const Cell<T>& cn, const T (&txf)[9],
-                                          const T (&txg)[9], T (&fo)[9], T (&go)[9]) {
+//
+// MESH: on a stretched mesh the wall lies dyw_m from the centre, the
+// one-sided y difference is divided by the centre distance (times idy), and
+// txf/txg hold the x slopes themselves.
+template <typename T, bool BOTTOM, bool MESH>
+__device__ __forceinline__ void wall_face_g(const CaseDev& C, const Cell<T>& c,
+                                            const Cell<T>& cn, const T (&txf)[9],
+                                            const T (&txg)[9], T dyw_m, T idy, T (&fo)[9],
+                                            T (&go)[9]) {
   const T h = T(C.h);
-  const T dyw = BOTTOM ? T(-0.5) : T(0.5);
+  const T dyw = MESH ? dyw_m : (BOTTOM ? T(-0.5) : T(0.5));
   const T phiw = c.phi;
   const double rhoD = rho_of(C, (double)phiw);
   const T theta = T(C.theta_c) * (phiw - T(C.phi_H)) * (phiw - T(C.phi_L));
@@ -430,13 +444,22 @@ __device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
     if (!out) continue;
     const T dx = -h * T(EX[q]), dy = dyw - h * T(EY[q]);
     const T sgn = BOTTOM ? T(1) : T(-1);
-    const T syf = sgn * (cn.fb[q] - c.fb[q]);
-    const T syg = sgn * (cn.gb[q] - c.gb[q]);
+    T syf = sgn * (cn.fb[q] - c.fb[q]);
+    T syg = sgn * (cn.gb[q] - c.gb[q]);
+    if (MESH) {
+      syf *= idy;
+      syg *= idy;
+    }
     T fbar = c.fb[q] + dy * syf;
     T gbar = c.gb[q] + dy * syg;
     if (EX[q] != 0) {
-      fbar += dx * T(0.5) * txf[q];
-      gbar += dx * T(0.5) * txg[q];
+      if (MESH) {
+        fbar += dx * txf[q];
+        gbar += dx * txg[q];
+      } else {
+        fbar += dx * T(0.5) * txf[q];
+        gbar += dx * T(0.5) * txg[q];
+      }
     }
     // u = 0: f^eq = w phi, S^f = w e_x (theta n_x + 3 D_x); g^eq = 3 w p,
     // S^g = 3 w (e . F)
@@ -447,6 +470,12 @@ __device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
     fo[q] = fval; go[q] = gval;
     fo[qo] = fval; go[qo] = gval;
   }
+}
+template <typename T, bool BOTTOM>
+__device__ __forceinline__ void wall_face(const CaseDev& C, const Cell<T>& c,
+                                          const Cell<T>& cn, const T (&txf)[9],
+                                          const T (&txg)[9], T (&fo)[9], T (&go)[9]) {
+  wall_face_g<T, BOTTOM, false>(C, c, cn, txf, txg, T(0), T(1), fo, go);
 }
 
 // ----------------------------------------------------------- step kernel
@@ -1027,6 +1056,69 @@ __global__ void k_advance(long long* step_base, long long by) {
 // ------------------------------------------------------------ init / macros
 
 // phi on the 3x3 neighbourhood of cell (i, j) from a row-major field.
+// ------------------------------------------------------- stretched meshes
+
+// On a stretched tensor-product mesh the gradient and Laplacian stencils are
+// weighted sums of the first and second derivatives of the parabola through
+// three neighbouring centres, on the rows j-1, j, j+1 (columns i-1, i, i+1),
+// the neighbouring rows weighted by the opposite distance so that the sum is
+// centred on the cell: exact on quadratics, and the unit-mesh stencils on
+// unit widths.
+template <typename T>
+__device__ __forceinline__ T par_d1(T am, T ac, T ap, T hm, T hp) {
+  return (hm * hm * (ap - ac) + hp * hp * (ac - am)) / (hm * hp * (hm + hp));
+}
+template <typename T>
+__device__ __forceinline__ T par_d2(T am, T ac, T ap, T hm, T hp) {
+  return T(2) * ((ap - ac) / hp - (ac - am) / hm) / (hm + hp);
+}
+template <typename T>
+__device__ __forceinline__ void mesh_stencils(const CaseDev& C, const T (&ph)[3][3], int i, int j,
+                                              T& gx, T& gy, T& lap) {
+  const MeshAxis X = mesh_axis(C.mesh, C.nx, C.ny, 0), Y = mesh_axis(C.mesh, C.nx, C.ny, 1);
+  const T xm = T(X.hm[i]), xp = T(X.hp[i]), ym = T(Y.hm[j]), yp = T(Y.hp[j]);
+  T dxr[3], dxxr[3], dyc[3], dyyc[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dxr[k] = par_d1(ph[k][0], ph[k][1], ph[k][2], xm, xp);
+    dxxr[k] = par_d2(ph[k][0], ph[k][1], ph[k][2], xm, xp);
+    dyc[k] = par_d1(ph[0][k], ph[1][k], ph[2][k], ym, yp);
+    dyyc[k] = par_d2(ph[0][k], ph[1][k], ph[2][k], ym, yp);
+  }
+  gx = T(2.0 / 3.0) * dxr[1] + T(1.0 / 3.0) * (ym * dxr[2] + yp * dxr[0]) / (ym + yp);
+  gy = T(2.0 / 3.0) * dyc[1] + T(1.0 / 3.0) * (xm * dyc[2] + xp * dyc[0]) / (xm + xp);
+  lap = T(5.0 / 6.0) * (dxxr[1] + dyyc[1]) +
+        T(1.0 / 6.0) * (ym * dxxr[2] + yp * dxxr[0]) / (ym + yp) +
+        T(1.0 / 6.0) * (xm * dyyc[2] + xp * dyyc[0]) / (xm + xp);
+}
+
+// Gradient and Laplacian of the init and readout kernels: the unit-mesh
+// stencils (as in cell_stage), or the stretched-mesh ones.
+template <typename T>
+__device__ __forceinline__ void cell_stencils(const CaseDev& C, const T (&ph)[3][3], int i, int j,
+                                              T& gx, T& gy, T& lap) {
+  if (C.mesh) {
+    mesh_stencils<T>(C, ph, i, j, gx, gy, lap);
+    return;
+  }
+  gx = (T(4) * (ph[1][2] - ph[1][0]) + (ph[2][2] - ph[2][0]) + (ph[0][2] - ph[0][0])) * T(1.0 / 12.0);
+  gy = (T(4) * (ph[2][1] - ph[0][1]) + (ph[2][2] - ph[0][2]) + (ph[2][0] - ph[0][0])) * T(1.0 / 12.0);
+  const T cc = ph[1][1];
+  lap = T(2.0 / 3.0) * (((ph[1][2] - cc) + (ph[1][0] - cc)) + ((ph[2][1] - cc) + (ph[0][1] - cc))) +
+        T(1.0 / 6.0) * (((ph[2][2] - cc) + (ph[2][0] - cc)) + ((ph[0][2] - cc) + (ph[0][0] - cc)));
+}
+
+// Cell centre (for a prescribed velocity).
+__device__ __forceinline__ void cell_centre(const CaseDev& C, int i, int j, double& x, double& y) {
+  if (C.mesh) {
+    x = mesh_axis(C.mesh, C.nx, C.ny, 0).c[i];
+    y = mesh_axis(C.mesh, C.nx, C.ny, 1).c[j];
+  } else {
+    x = i + 0.5;
+    y = j + 0.5;
+  }
+}
+
 template <typename S, typename T>
 __device__ __forceinline__ void gather3x3(const S* __restrict__ f, int i, int j, int nx,
                                           int ny, int walls, T (&ph)[3][3]) {
@@ -1052,12 +1144,9 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
   T* __restrict__ st = static_cast<T*>(C.set[buf]);
   T ph[3][3];
   gather3x3<double, T>(phi0, i, j, C.nx, C.ny, C.walls, ph);
-  const T gx = (T(4) * (ph[1][2] - ph[1][0]) + (ph[2][2] - ph[2][0]) + (ph[0][2] - ph[0][0])) * T(1.0 / 12.0);
-  const T gy = (T(4) * (ph[2][1] - ph[0][1]) + (ph[2][2] - ph[0][2]) + (ph[2][0] - ph[0][0])) * T(1.0 / 12.0);
-  const T cc = ph[1][1];
-  const T lap = T(2.0 / 3.0) * (((ph[1][2] - cc) + (ph[1][0] - cc)) + ((ph[2][1] - cc) + (ph[0][1] - cc))) +
-                T(1.0 / 6.0) * (((ph[2][2] - cc) + (ph[2][0] - cc)) + ((ph[0][2] - cc) + (ph[0][0] - cc)));
-  const T phi = cc;
+  T gx, gy, lap;
+  cell_stencils<T>(C, ph, i, j, gx, gy, lap);
+  const T phi = ph[1][1];
   const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
   const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
   const T theta = T(C.theta_c) * dA * dB;
@@ -1089,7 +1178,9 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
       st[value_index(val_g(q), c, P, CPL)] = geq - hdt * Sg;
     }
   } else {
-    presc_vel<T>(C, i + 0.5, j + 0.5, 0.0, u, v);
+    double xc, yc;
+    cell_centre(C, i, j, xc, yc);
+    presc_vel<T>(C, xc, yc, 0.0, u, v);
   }
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1125,11 +1216,8 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
   const double rhoD = rho_of(C, (double)phi);
   T u, v, p = T(0);
   if (CPL) {
-    const T gx = (T(4) * (ph[1][2] - ph[1][0]) + (ph[2][2] - ph[2][0]) + (ph[0][2] - ph[0][0])) * T(1.0 / 12.0);
-    const T gy = (T(4) * (ph[2][1] - ph[0][1]) + (ph[2][2] - ph[0][2]) + (ph[2][0] - ph[0][0])) * T(1.0 / 12.0);
-    const T cc = ph[1][1];
-    const T lap = T(2.0 / 3.0) * (((ph[1][2] - cc) + (ph[1][0] - cc)) + ((ph[2][1] - cc) + (ph[0][1] - cc))) +
-                  T(1.0 / 6.0) * (((ph[2][2] - cc) + (ph[2][0] - cc)) + ((ph[0][2] - cc) + (ph[0][0] - cc)));
+    T gx, gy, lap;
+    cell_stencils<T>(C, ph, i, j, gx, gy, lap);
     const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
     const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
     const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
@@ -1148,7 +1236,9 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
     const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
     p = T(0.6) * m0 + T(0.3) * dt * (u * drx + v * dry) - T(0.4) * rho * (u * u + v * v);
   } else {
-    presc_vel<T>(C, i + 0.5, j + 0.5, t, u, v);
+    double xc, yc;
+    cell_centre(C, i, j, xc, yc);
+    presc_vel<T>(C, xc, yc, t, u, v);
   }
   if (ophi) ophi[c] = (double)phi;
   if (ou) ou[c] = (double)u;
@@ -1209,21 +1299,29 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
   for (int k = 0; k < kDiagQ; ++k) out[k] = a[k];
 }
 
-// ------------------------------------------- upwind reconstruction (3 kernels)
+// --------------------------- three-kernel step: upwind or stretched mesh
 
-// The upwind, limited reconstruction (selected per handle) is not linear in
-// the populations: the face macros come from the nine reconstructed values
-// of each face instead of reconstructed cell moments, and a face reads the
-// limited slopes of both adjacent cells, a radius-two stencil. The step then
-// runs as three kernels over one thread per cell, through scratch planes
-// (layout in dugks_impl.h):
+// The upwind, limited reconstruction and the stretched mesh (both selected
+// per handle) do not fit the fused march. The upwind face value of each
+// population is a non-linear function of the cells. The face macros must
+// then be summed from the nine reconstructed values instead of
+// reconstructed cell moments. A face also reads the limited slopes of both
+// its cells, a radius-two stencil. On a stretched mesh every stencil
+// carries the local widths. The step then runs as three kernels over one
+// thread per cell, through scratch planes (layout in dugks_impl.h):
 //   k_up_stage  cell stage of every cell: bar-plus and the face inputs to
 //               scratch, tilde-plus and the history into the output state;
 //   k_up_faces  the x-face east and the y-face north of every cell (and the
 //               wall faces): reconstruction, face macros and face
 //               distributions, once per face, to the face planes;
 //   k_up_update the update (Eq. 24) of every cell from its four faces.
-// The cell stage, face distribution and wall face are the central path's.
+// The cell stage, face distribution and wall face are the march's.
+//
+// Stretched mesh: the reconstruction interpolates linearly to the face (the
+// value, the tangential slope and the face inputs), slopes are derivatives
+// over the centre distances, the upwind trace starts from the actual half
+// width, and the update divides the fluxes by the cell's widths. On unit
+// widths every formula reduces to the unit-mesh one.
 
 constexpr int kUpCols = 64, kUpRows = 4;  // cells of one 256-thread block
 
@@ -1246,7 +1344,7 @@ __device__ __forceinline__ long long up_step(const CaseDev& C, const UpArgs& A) 
   return (n < 0 || n >= C.nsteps) ? -1 : n;
 }
 
-template <typename T, bool CPL, bool WALLS>
+template <typename T, bool CPL, bool WALLS, bool MESH>
 __global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
   const CaseDev C = *A.cases;
   const long long n = up_step(C, A);
@@ -1279,8 +1377,17 @@ __global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
   Cell<T> o;
   T tp[18];
   const double tn = C.t0 + (double)n * C.dt;
-  cell_stage<T, CPL>(C, ph, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], (double)i + 0.5,
-                     (double)j + 0.5, tn, o, tp);
+  if constexpr (MESH) {
+    T gx, gy, lap;
+    mesh_stencils<T>(C, ph, i, j, gx, gy, lap);
+    double xc, yc;
+    cell_centre(C, i, j, xc, yc);
+    cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)],
+                      xc, yc, tn, o, tp);
+  } else {
+    cell_stage<T, CPL>(C, ph, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], (double)i + 0.5,
+                       (double)j + 0.5, tn, o, tp);
+  }
   T nv[NV];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1305,64 +1412,136 @@ __global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
   in6[5 * N + cell] = o.p;
 }
 
-// van Leer's limited slope of two one-sided differences.
+// van Leer's limited slope of two one-sided differences (or slopes).
 template <typename T>
 __device__ __forceinline__ T van_leer(T a, T b) {
   return a * b > T(0) ? T(2) * a * b / (a + b) : T(0);
 }
 
-// Bar-plus plane access and limited slopes for the face kernel.
-template <typename T, bool WALLS>
+// Stretched mesh: van Leer of the one-sided slopes, capped at twice the
+// smaller one-sided difference over the cell's width, so that the
+// one-dimensional reconstruction anywhere in the cell stays between the
+// neighbours (the cap never binds on linear data, nor on unit widths).
+template <typename T>
+__device__ __forceinline__ T lim_mesh(T b, T f, T hm, T hp, T w) {
+  const T s = van_leer(b / hm, f / hp);
+  const T ab = b < T(0) ? -b : b, af = f < T(0) ? -f : f;
+  const T cap = T(2) * (ab < af ? ab : af) / w;
+  return s > cap ? cap : (s < -cap ? -cap : s);
+}
+
+// Bar-plus plane access, slopes and face values for the face kernel.
+template <typename T, bool WALLS, bool MESH>
 struct UpBars {
   const T* S;
   long long N;
   int nx, ny;
+  MeshAxis X, Y;  // stretched mesh only
   __device__ __forceinline__ T at(int p, int i, int j) const {
     return S[p * N + (long long)j * nx + i];
   }
+  // one-sided y difference (derivative on a stretched mesh) next to a wall,
+  // unlimited
+  __device__ __forceinline__ T wall_dy(int p, int i, int j) const {
+    const T d = j == 0 ? at(p, i, 1) - at(p, i, 0) : at(p, i, ny - 1) - at(p, i, ny - 2);
+    if (MESH) return d / T(j == 0 ? Y.hp[0] : Y.hm[ny - 1]);
+    return d;
+  }
   __device__ __forceinline__ T lim_x(int p, int i, int j) const {
     const T c = at(p, i, j);
-    return van_leer(c - at(p, wrap(i - 1, nx), j), at(p, wrap(i + 1, nx), j) - c);
+    const T b = c - at(p, wrap(i - 1, nx), j), f = at(p, wrap(i + 1, nx), j) - c;
+    if (MESH) return lim_mesh(b, f, T(X.hm[i]), T(X.hp[i]), T(X.w[i]));
+    return van_leer(b, f);
   }
   __device__ __forceinline__ T lim_y(int p, int i, int j) const {
-    if (WALLS) {  // one-sided, unlimited, next to a wall
-      if (j == 0) return at(p, i, 1) - at(p, i, 0);
-      if (j == ny - 1) return at(p, i, ny - 1) - at(p, i, ny - 2);
-    }
+    if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
     const T c = at(p, i, j);
-    return van_leer(c - at(p, i, wrap(j - 1, ny)), at(p, i, wrap(j + 1, ny)) - c);
+    const T b = c - at(p, i, wrap(j - 1, ny)), f = at(p, i, wrap(j + 1, ny)) - c;
+    if (MESH) return lim_mesh(b, f, T(Y.hm[j]), T(Y.hp[j]), T(Y.w[j]));
+    return van_leer(b, f);
+  }
+  // central slopes of the stretched mesh (parabola through three centres)
+  __device__ __forceinline__ T slope_x(int p, int i, int j) const {
+    return par_d1(at(p, wrap(i - 1, nx), j), at(p, i, j), at(p, wrap(i + 1, nx), j), T(X.hm[i]),
+                  T(X.hp[i]));
+  }
+  __device__ __forceinline__ T slope_y(int p, int i, int j) const {
+    if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
+    return par_d1(at(p, i, wrap(j - 1, ny)), at(p, i, j), at(p, i, wrap(j + 1, ny)), T(Y.hm[j]),
+                  T(Y.hp[j]));
+  }
+  // half widths of cells A and B across a face of normal DIR
+  template <int DIR>
+  __device__ __forceinline__ void halves(int ia, int ja, int ib, int jb, T& dA, T& dB) const {
+    if (MESH) {
+      dA = T(0.5 * (DIR == 0 ? X.w[ia] : Y.w[ja]));
+      dB = T(0.5 * (DIR == 0 ? X.w[ib] : Y.w[jb]));
+    } else {
+      dA = dB = T(0.5);
+    }
   }
   // value of plane p's population (velocity ex, ey) at the face of normal
-  // DIR between cells A (below / left) and B: traced back by h xi into the
-  // upwind cell, or the mean of both cells along the face
-  template <int DIR>
+  // DIR between cells A (below / left) and B. Upwind: traced back by h xi
+  // into the upwind cell, or (along the face) the interpolation of both
+  // cells. Central (stretched mesh): interpolated value minus h xi times the
+  // normal and tangential slopes at the face.
+  template <int DIR, bool CENTRAL>
   __device__ __forceinline__ T face(int p, int ex, int ey, T h, int ia, int ja, int ib,
                                     int jb) const {
     const int en = DIR == 0 ? ex : ey, et = DIR == 0 ? ey : ex;
     auto ln = [&](int i, int j) { return DIR == 0 ? lim_x(p, i, j) : lim_y(p, i, j); };
     auto lt = [&](int i, int j) { return DIR == 0 ? lim_y(p, i, j) : lim_x(p, i, j); };
-    const T hal = T(0.5) - h;
-    if (en > 0) {
-      T v = at(p, ia, ja) + hal * ln(ia, ja);
-      if (et != 0) v -= h * T(et) * lt(ia, ja);
+    if constexpr (!MESH) {
+      const T hal = T(0.5) - h;
+      if (en > 0) {
+        T v = at(p, ia, ja) + hal * ln(ia, ja);
+        if (et != 0) v -= h * T(et) * lt(ia, ja);
+        return v;
+      }
+      if (en < 0) {
+        T v = at(p, ib, jb) - hal * ln(ib, jb);
+        if (et != 0) v -= h * T(et) * lt(ib, jb);
+        return v;
+      }
+      T v = T(0.5) * (at(p, ia, ja) + at(p, ib, jb));
+      if (et != 0) v -= h * T(et) * (T(0.5) * (lt(ia, ja) + lt(ib, jb)));
       return v;
+    } else {
+      T dA, dB;
+      halves<DIR>(ia, ja, ib, jb, dA, dB);
+      const T H = dA + dB, aA = at(p, ia, ja), aB = at(p, ib, jb);
+      if constexpr (CENTRAL) {
+        auto st = [&](int i, int j) { return DIR == 0 ? slope_y(p, i, j) : slope_x(p, i, j); };
+        const T af = (dB * aA + dA * aB) / H, dn = (aB - aA) / H;
+        const T dtg = (dB * st(ia, ja) + dA * st(ib, jb)) / H;
+        return af - h * (T(en) * dn + T(et) * dtg);
+      } else {
+        if (en > 0) {
+          T v = aA + (dA - h) * ln(ia, ja);
+          if (et != 0) v -= h * T(et) * lt(ia, ja);
+          return v;
+        }
+        if (en < 0) {
+          T v = aB + (h - dB) * ln(ib, jb);
+          if (et != 0) v -= h * T(et) * lt(ib, jb);
+          return v;
+        }
+        T vA = aA, vB = aB;
+        if (et != 0) {
+          vA -= h * T(et) * lt(ia, ja);
+          vB -= h * T(et) * lt(ib, jb);
+        }
+        return (dB * vA + dA * vB) / H;
+      }
     }
-    if (en < 0) {
-      T v = at(p, ib, jb) - hal * ln(ib, jb);
-      if (et != 0) v -= h * T(et) * lt(ib, jb);
-      return v;
-    }
-    T v = T(0.5) * (at(p, ia, ja) + at(p, ib, jb));
-    if (et != 0) v -= h * T(et) * (T(0.5) * (lt(ia, ja) + lt(ib, jb)));
-    return v;
   }
 };
 
 // Face of normal DIR between cells A and B: reconstruction, face macros and
 // the face distributions of the crossing populations, written to the face
-// planes F (f) and G (g) at index fi with stride FS.
-template <typename T, bool CPL, bool WALLS, int DIR>
-__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS>& B,
+// planes F (f, then g) at index fi with stride FS.
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR>
+__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH>& B,
                                         const T* in6, int ia, int ja, int ib, int jb,
                                         double xf, double yf, double tf, T* F, long long FS,
                                         long long fi) {
@@ -1370,8 +1549,9 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS>
   T fbar[9], gbar[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    fbar[q] = B.template face<DIR>(q, EX[q], EY[q], h, ia, ja, ib, jb);
-    gbar[q] = (CPL && q > 0) ? B.template face<DIR>(9 + q, EX[q], EY[q], h, ia, ja, ib, jb) : T(0);
+    fbar[q] = B.template face<DIR, CENTRAL>(q, EX[q], EY[q], h, ia, ja, ib, jb);
+    gbar[q] = (CPL && q > 0) ? B.template face<DIR, CENTRAL>(9 + q, EX[q], EY[q], h, ia, ja, ib, jb)
+                             : T(0);
   }
   const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
                  ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
@@ -1383,7 +1563,14 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS>
   }
   const long long N = B.N;
   const long long a = (long long)ja * B.nx + ia, b = (long long)jb * B.nx + ib;
-  auto mean = [&](int k) { return T(0.5) * (in6[k * N + a] + in6[k * N + b]); };
+  T dA, dB;
+  B.template halves<DIR>(ia, ja, ib, jb, dA, dB);
+  // gradient-type face inputs: the mean of the two cells (linear
+  // interpolation to the face on a stretched mesh)
+  auto mean = [&](int k) {
+    if (MESH) return (dB * in6[k * N + a] + dA * in6[k * N + b]) / (dA + dB);
+    return T(0.5) * (in6[k * N + a] + in6[k * N + b]);
+  };
   T fo[9], go[9];
   face_df<T, CPL, DIR>(C, phif, N0f, Jxf, Jyf, mean(0), mean(1), mean(2), mean(3), mean(4), fbar,
                        gbar, xf, yf, tf, fo, go);
@@ -1397,9 +1584,9 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS>
 }
 
 // Wall face below row 0 (BOTTOM) or above row ny-1 of column i, into face
-// row 0 or ny: the central path's face bounce-back, fed from the planes.
-template <typename T, bool BOTTOM>
-__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true>& B,
+// row 0 or ny: the march's face bounce-back, fed from the planes.
+template <typename T, bool BOTTOM, bool MESH>
+__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH>& B,
                                         const T* in6, const T* phiP, int i, T* F, long long FS) {
   const int nx = B.nx, ny = B.ny;
   const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
@@ -1413,8 +1600,13 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true>&
     cn.fb[q] = B.at(q, i, jn);
     cn.gb[q] = B.at(9 + q, i, jn);
     const bool diag = EX[q] != 0 && EY[q] != 0;
-    txf[q] = diag ? B.at(q, wrap(i + 1, nx), jw) - B.at(q, wrap(i - 1, nx), jw) : T(0);
-    txg[q] = diag ? B.at(9 + q, wrap(i + 1, nx), jw) - B.at(9 + q, wrap(i - 1, nx), jw) : T(0);
+    if (MESH) {  // x slopes
+      txf[q] = diag ? B.slope_x(q, i, jw) : T(0);
+      txg[q] = diag ? B.slope_x(9 + q, i, jw) : T(0);
+    } else {  // x central differences (halved in wall_face)
+      txf[q] = diag ? B.at(q, wrap(i + 1, nx), jw) - B.at(q, wrap(i - 1, nx), jw) : T(0);
+      txg[q] = diag ? B.at(9 + q, wrap(i + 1, nx), jw) - B.at(9 + q, wrap(i - 1, nx), jw) : T(0);
+    }
   }
   c.phi = phiP[cw];
   c.gx = in6[cw];
@@ -1422,7 +1614,12 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true>&
   c.Dx = in6[3 * N + cw];
   c.p = in6[5 * N + cw];
   T fo[9], go[9];
-  wall_face<T, BOTTOM>(C, c, cn, txf, txg, fo, go);
+  T dyw = T(0), idy = T(1);
+  if (MESH) {
+    dyw = T(BOTTOM ? -0.5 * B.Y.w[0] : 0.5 * B.Y.w[ny - 1]);
+    idy = T(1.0 / (BOTTOM ? B.Y.hp[0] : B.Y.hm[ny - 1]));
+  }
+  wall_face_g<T, BOTTOM, MESH>(C, c, cn, txf, txg, dyw, idy, fo, go);
   const long long fi = (BOTTOM ? 0LL : (long long)ny * nx) + i;
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
@@ -1433,7 +1630,7 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true>&
   }
 }
 
-template <typename T, bool CPL, bool WALLS>
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL>
 __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
   const CaseDev C = *A.cases;
   const long long n = up_step(C, A);
@@ -1442,27 +1639,38 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
   const int nx = C.nx, ny = C.ny;
   const long long N = C.plane, N1 = N + nx;
   T* S = static_cast<T*>(A.scratch);
-  const UpBars<T, WALLS> B{S, N, nx, ny};
+  UpBars<T, WALLS, MESH> B{S, N, nx, ny, MeshAxis{}, MeshAxis{}};
+  if (MESH) {
+    B.X = mesh_axis(C.mesh, nx, ny, 0);
+    B.Y = mesh_axis(C.mesh, nx, ny, 1);
+  }
   const T* in6 = S + up_bar_planes(CPL) * N;
   T* XF = S + up_cell_planes(CPL) * N;
   T* YF = XF + up_face_planes(CPL) * N;
   const double tf = C.t0 + (double)n * C.dt + C.h;
   const long long cell = (long long)j * nx + i;
-  up_face<T, CPL, WALLS, 0>(C, B, in6, i, j, wrap(i + 1, nx), j, (double)i + 1.0, (double)j + 0.5,
-                            tf, XF, N, cell);
+  double xe = (double)i + 1.0, ye = (double)j + 0.5, xn = (double)i + 0.5, yn = (double)j + 1.0;
+  if (MESH) {  // face positions from the centres and half widths
+    xn = B.X.c[i];
+    xe = xn + 0.5 * B.X.w[i];
+    ye = B.Y.c[j];
+    yn = ye + 0.5 * B.Y.w[j];
+  }
+  up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, i, j, wrap(i + 1, nx), j, xe, ye, tf, XF, N,
+                                           cell);
   if (!(WALLS && j == ny - 1))
-    up_face<T, CPL, WALLS, 1>(C, B, in6, i, j, i, wrap(j + 1, ny), (double)i + 0.5,
-                              (double)j + 1.0, tf, YF, N1, cell + nx);
+    up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, i, j, i, wrap(j + 1, ny), xn, yn, tf, YF,
+                                             N1, cell + nx);
   if constexpr (WALLS) {
     const int cur = (C.cur0 + (int)(n & 1)) & 1;
     const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
     const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * N * (long long)sizeof(T));
-    if (j == 0) up_wall<T, true>(C, B, in6, phiP, i, YF, N1);
-    if (j == ny - 1) up_wall<T, false>(C, B, in6, phiP, i, YF, N1);
+    if (j == 0) up_wall<T, true, MESH>(C, B, in6, phiP, i, YF, N1);
+    if (j == ny - 1) up_wall<T, false, MESH>(C, B, in6, phiP, i, YF, N1);
   }
 }
 
-template <typename T, bool CPL, bool WALLS>
+template <typename T, bool CPL, bool WALLS, bool MESH>
 __global__ __launch_bounds__(256) void k_up_update(UpArgs A) {
   const CaseDev C = *A.cases;
   const long long n = up_step(C, A);
@@ -1482,13 +1690,25 @@ __global__ __launch_bounds__(256) void k_up_update(UpArgs A) {
   // the top (face row ny)
   const long long fn = (long long)(j + 1) * nx + i;
   const long long fs = (long long)((!WALLS && j == 0) ? ny : j) * nx + i;
+  // face length over cell area: 1/dx and 1/dy (1 on unit cells)
+  T ax = T(1), ay = T(1);
+  if (MESH) {
+    ax = T(1.0 / mesh_axis(C.mesh, nx, ny, 0).w[i]);
+    ay = T(1.0 / mesh_axis(C.mesh, nx, ny, 1).w[j]);
+  }
   T v[NV];
   load_groups<T, NV>(out, PB, cell, v);
   const T dt = T(C.dt);
   T phin = T(0);
   auto upd = [&](int q, int off) {
-    T J = T(0);
     const int sx = up_xslot(q), sy = up_yslot(q);
+    if (MESH) {
+      T Jx = T(0), Jy = T(0);
+      if (EX[q] != 0) Jx = T(EX[q]) * (XF[(off + sx) * N + ce] - XF[(off + sx) * N + cw]);
+      if (EY[q] != 0) Jy = T(EY[q]) * (YF[(off + sy) * N1 + fn] - YF[(off + sy) * N1 + fs]);
+      return ax * Jx + ay * Jy;
+    }
+    T J = T(0);
     if (EX[q] != 0) J += T(EX[q]) * (XF[(off + sx) * N + ce] - XF[(off + sx) * N + cw]);
     if (EY[q] != 0) J += T(EY[q]) * (YF[(off + sy) * N1 + fn] - YF[(off + sy) * N1 + fs]);
     return J;
@@ -1540,26 +1760,34 @@ hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, h
   return hipGetLastError();
 }
 
-hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, int nx, int ny,
-                              const UpArgs& a, hipStream_t s) {
+hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
+                              int nx, int ny, const UpArgs& a, hipStream_t s) {
   if (walls && !coupled) return hipErrorInvalidValue;
+  if (!upwind && !mesh) return hipErrorInvalidValue;  // the march covers that case
   const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + kUpRows - 1) / kUpRows);
   dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * kUpRows);
-#define UP_LAUNCH(T, CPL, W)                                            \
-  do {                                                                  \
-    hipLaunchKernelGGL((k_up_stage<T, CPL, W>), grid, block, 0, s, a);  \
-    hipLaunchKernelGGL((k_up_faces<T, CPL, W>), grid, block, 0, s, a);  \
-    hipLaunchKernelGGL((k_up_update<T, CPL, W>), grid, block, 0, s, a); \
+#define UP_LAUNCH(T, CPL, W, M, CEN)                                        \
+  do {                                                                      \
+    hipLaunchKernelGGL((k_up_stage<T, CPL, W, M>), grid, block, 0, s, a);   \
+    hipLaunchKernelGGL((k_up_faces<T, CPL, W, M, CEN>), grid, block, 0, s, a); \
+    hipLaunchKernelGGL((k_up_update<T, CPL, W, M>), grid, block, 0, s, a);  \
+  } while (0)
+#define UP_MODES(T, CPL, W)                                  \
+  do {                                                       \
+    if (!mesh) UP_LAUNCH(T, CPL, W, false, false);           \
+    else if (upwind) UP_LAUNCH(T, CPL, W, true, false);      \
+    else UP_LAUNCH(T, CPL, W, true, true);                   \
   } while (0)
   if (fp64) {
-    if (!coupled) UP_LAUNCH(double, false, false);
-    else if (walls) UP_LAUNCH(double, true, true);
-    else UP_LAUNCH(double, true, false);
+    if (!coupled) UP_MODES(double, false, false);
+    else if (walls) UP_MODES(double, true, true);
+    else UP_MODES(double, true, false);
   } else {
-    if (!coupled) UP_LAUNCH(float, false, false);
-    else if (walls) UP_LAUNCH(float, true, true);
-    else UP_LAUNCH(float, true, false);
+    if (!coupled) UP_MODES(float, false, false);
+    else if (walls) UP_MODES(float, true, true);
+    else UP_MODES(float, true, false);
   }
+#undef UP_MODES
 #undef UP_LAUNCH
   return hipGetLastError();
 }
