@@ -20,6 +20,8 @@ The same JSON line carries:
   upwind        the same bubble with the upwind, limited face reconstruction
                 (three kernels per step, 708 algorithmic bytes per cell in
                 FP32), 128^2 and 4096^2, launched step by step
+  mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
+                central and upwind, through the same three kernels
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -62,6 +64,8 @@ def parse():
                     help="run only the timed 4096x4096 workload (for profilers)")
     ap.add_argument("--profile-upwind", action="store_true",
                     help="only the upwind leg on 4096^2 (for rocprofv3)")
+    ap.add_argument("--profile-mesh", action="store_true",
+                    help="only the stretched-mesh central leg on 4096^2 (for rocprofv3)")
     ap.add_argument("--upwind-steps", type=int, default=50)
     ap.add_argument("--profile-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (calibrates the "
@@ -147,13 +151,16 @@ def roofline(cells, steps, seconds, prec, workload=None):
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
 
 
-def timed_upwind(torch, D, c, steps, warmup):
-    """Upwind-reconstruction steps of case `c` (coupled FP32), launched one
-    step (three kernels) at a time on torch's current stream; seconds by HIP
-    events on that stream."""
+def timed_upwind(torch, D, c, steps, warmup, recon="upwind", mesh=None):
+    """Three-kernel steps of case `c` (coupled FP32): the upwind
+    reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
+    reconstruction, launched one step (three kernels) at a time on torch's
+    current stream; seconds by HIP events on that stream."""
     stream = torch.cuda.current_stream()
-    s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon="upwind"), "coupled", "fp32")
+    s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
     s.set_stream(stream.cuda_stream)
+    if mesh is not None:
+        s.set_mesh(*mesh)
     s.init(c["phi"])
     s.step(warmup)
     torch.cuda.synchronize()
@@ -298,6 +305,13 @@ def main():
                           "seg_rows": seg, "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
                           "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}), flush=True)
         return
+    if args.profile_mesh:
+        cl = W.bubble(L=4096, R=1024, steps=0)
+        mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
+        print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, stretched mesh, central",
+                          **timed_upwind(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
+              flush=True)
+        return
     if args.profile_upwind:
         cl = W.bubble(L=4096, R=1024, steps=0)
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, upwind reconstruction",
@@ -381,6 +395,14 @@ def main():
             "bubble128": timed_upwind(torch, D, c, min(args.steps, 5000), 100),
             "bubble4096": timed_upwind(torch, D, W.bubble(L=4096, R=1024, steps=0),
                                        args.upwind_steps, 5)}
+        # stretched tensor-product mesh, both reconstructions
+        cm = W.bubble(L=4096, R=1024, steps=0)
+        mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
+        rec["mesh"] = {
+            "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
+                        "both axes), coupled FP32, one step (three kernels) per host call",
+            "central": timed_upwind(torch, D, cm, args.upwind_steps, 5, "central", mesh),
+            "upwind": timed_upwind(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
         if args.serve_requests > 0:
             rec["served"] = served_stream(torch, D, W, args.serve_requests)
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -1430,18 +1430,26 @@ __device__ __forceinline__ T lim_mesh(T b, T f, T hm, T hp, T w) {
   return s > cap ? cap : (s < -cap ? -cap : s);
 }
 
-// Bar-plus plane access, slopes and face values for the face kernel.
-template <typename T, bool WALLS, bool MESH>
+// The face kernel stages the bar-plus values of its block's cells and their
+// halo (one column/row before, two after) in LDS: a block's faces read each
+// value several times (the limited slopes of both cells of every face).
+constexpr int kTileR = kUpRows + 3, kTileC = kUpCols + 3;
+
+// Bar-plus values, slopes and face values for the face kernel. Cells are
+// addressed by unwrapped grid indices within the block's tile (the halo
+// holds the wrapped or clamped neighbours); metric arrays and the
+// wall checks use the wrapped indices.
+template <typename T, bool WALLS, bool MESH, int NB>
 struct UpBars {
-  const T* S;
-  long long N;
+  const T (*L)[kTileR][kTileC];  // LDS tile [NB][kTileR][kTileC]
+  int i0, j0;                    // grid cell of tile position (1, 1)
   int nx, ny;
   MeshAxis X, Y;  // stretched mesh only
-  __device__ __forceinline__ T at(int p, int i, int j) const {
-    return S[p * N + (long long)j * nx + i];
-  }
+  __device__ __forceinline__ T at(int p, int i, int j) const { return L[p][j - j0 + 1][i - i0 + 1]; }
+  __device__ __forceinline__ int xi(int i) const { return wrap(i, nx); }
+  __device__ __forceinline__ int yj(int j) const { return wrap(j, ny); }
   // one-sided y difference (derivative on a stretched mesh) next to a wall,
-  // unlimited
+  // unlimited (j is row 0 or ny-1)
   __device__ __forceinline__ T wall_dy(int p, int i, int j) const {
     const T d = j == 0 ? at(p, i, 1) - at(p, i, 0) : at(p, i, ny - 1) - at(p, i, ny - 2);
     if (MESH) return d / T(j == 0 ? Y.hp[0] : Y.hm[ny - 1]);
@@ -1449,33 +1457,39 @@ struct UpBars {
   }
   __device__ __forceinline__ T lim_x(int p, int i, int j) const {
     const T c = at(p, i, j);
-    const T b = c - at(p, wrap(i - 1, nx), j), f = at(p, wrap(i + 1, nx), j) - c;
-    if (MESH) return lim_mesh(b, f, T(X.hm[i]), T(X.hp[i]), T(X.w[i]));
+    const T b = c - at(p, i - 1, j), f = at(p, i + 1, j) - c;
+    if (MESH) {
+      const int k = xi(i);
+      return lim_mesh(b, f, T(X.hm[k]), T(X.hp[k]), T(X.w[k]));
+    }
     return van_leer(b, f);
   }
   __device__ __forceinline__ T lim_y(int p, int i, int j) const {
     if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
     const T c = at(p, i, j);
-    const T b = c - at(p, i, wrap(j - 1, ny)), f = at(p, i, wrap(j + 1, ny)) - c;
-    if (MESH) return lim_mesh(b, f, T(Y.hm[j]), T(Y.hp[j]), T(Y.w[j]));
+    const T b = c - at(p, i, j - 1), f = at(p, i, j + 1) - c;
+    if (MESH) {
+      const int k = yj(j);
+      return lim_mesh(b, f, T(Y.hm[k]), T(Y.hp[k]), T(Y.w[k]));
+    }
     return van_leer(b, f);
   }
   // central slopes of the stretched mesh (parabola through three centres)
   __device__ __forceinline__ T slope_x(int p, int i, int j) const {
-    return par_d1(at(p, wrap(i - 1, nx), j), at(p, i, j), at(p, wrap(i + 1, nx), j), T(X.hm[i]),
-                  T(X.hp[i]));
+    const int k = xi(i);
+    return par_d1(at(p, i - 1, j), at(p, i, j), at(p, i + 1, j), T(X.hm[k]), T(X.hp[k]));
   }
   __device__ __forceinline__ T slope_y(int p, int i, int j) const {
     if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
-    return par_d1(at(p, i, wrap(j - 1, ny)), at(p, i, j), at(p, i, wrap(j + 1, ny)), T(Y.hm[j]),
-                  T(Y.hp[j]));
+    const int k = yj(j);
+    return par_d1(at(p, i, j - 1), at(p, i, j), at(p, i, j + 1), T(Y.hm[k]), T(Y.hp[k]));
   }
   // half widths of cells A and B across a face of normal DIR
   template <int DIR>
   __device__ __forceinline__ void halves(int ia, int ja, int ib, int jb, T& dA, T& dB) const {
     if (MESH) {
-      dA = T(0.5 * (DIR == 0 ? X.w[ia] : Y.w[ja]));
-      dB = T(0.5 * (DIR == 0 ? X.w[ib] : Y.w[jb]));
+      dA = T(0.5 * (DIR == 0 ? X.w[xi(ia)] : Y.w[yj(ja)]));
+      dB = T(0.5 * (DIR == 0 ? X.w[xi(ib)] : Y.w[yj(jb)]));
     } else {
       dA = dB = T(0.5);
     }
@@ -1537,12 +1551,13 @@ struct UpBars {
   }
 };
 
-// Face of normal DIR between cells A and B: reconstruction, face macros and
-// the face distributions of the crossing populations, written to the face
-// planes F (f, then g) at index fi with stride FS.
-template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR>
-__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH>& B,
-                                        const T* in6, int ia, int ja, int ib, int jb,
+// Face of normal DIR between cells A and B (unwrapped indices):
+// reconstruction, face macros and the face distributions of the crossing
+// populations, written to the face planes F (f, then g) at index fi with
+// stride FS.
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR, int NB>
+__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH, NB>& B,
+                                        const T* in6, long long N, int ia, int ja, int ib, int jb,
                                         double xf, double yf, double tf, T* F, long long FS,
                                         long long fi) {
   const T h = T(C.h);
@@ -1561,8 +1576,8 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS,
     Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
     Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
   }
-  const long long N = B.N;
-  const long long a = (long long)ja * B.nx + ia, b = (long long)jb * B.nx + ib;
+  const long long a = (long long)B.yj(ja) * B.nx + B.xi(ia);
+  const long long b = (long long)B.yj(jb) * B.nx + B.xi(ib);
   T dA, dB;
   B.template halves<DIR>(ia, ja, ib, jb, dA, dB);
   // gradient-type face inputs: the mean of the two cells (linear
@@ -1584,13 +1599,14 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS,
 }
 
 // Wall face below row 0 (BOTTOM) or above row ny-1 of column i, into face
-// row 0 or ny: the march's face bounce-back, fed from the planes.
-template <typename T, bool BOTTOM, bool MESH>
-__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH>& B,
-                                        const T* in6, const T* phiP, int i, T* F, long long FS) {
+// row 0 or ny: the march's face bounce-back, fed from the tile.
+template <typename T, bool BOTTOM, bool MESH, int NB>
+__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH, NB>& B,
+                                        const T* in6, long long N, const T* phiP, int i, T* F,
+                                        long long FS) {
   const int nx = B.nx, ny = B.ny;
   const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
-  const long long N = B.N, cw = (long long)jw * nx + i;
+  const long long cw = (long long)jw * nx + i;
   Cell<T> c, cn;
   T txf[9], txg[9];
 #pragma unroll
@@ -1604,8 +1620,8 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
       txf[q] = diag ? B.slope_x(q, i, jw) : T(0);
       txg[q] = diag ? B.slope_x(9 + q, i, jw) : T(0);
     } else {  // x central differences (halved in wall_face)
-      txf[q] = diag ? B.at(q, wrap(i + 1, nx), jw) - B.at(q, wrap(i - 1, nx), jw) : T(0);
-      txg[q] = diag ? B.at(9 + q, wrap(i + 1, nx), jw) - B.at(9 + q, wrap(i - 1, nx), jw) : T(0);
+      txf[q] = diag ? B.at(q, i + 1, jw) - B.at(q, i - 1, jw) : T(0);
+      txg[q] = diag ? B.at(9 + q, i + 1, jw) - B.at(9 + q, i - 1, jw) : T(0);
     }
   }
   c.phi = phiP[cw];
@@ -1634,12 +1650,52 @@ template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL>
 __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
   const CaseDev C = *A.cases;
   const long long n = up_step(C, A);
-  int i, j;
-  if (n < 0 || !up_cell(C.nx, C.ny, i, j)) return;
+  if (n < 0) return;
   const int nx = C.nx, ny = C.ny;
+  // block origin (the same map as up_cell); blocks past the grid leave
+  // before the barrier, all of their threads together
+  const int nbx = (nx + kUpCols - 1) / kUpCols;
+  const int idx = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int i0 = (idx % nbx) * kUpCols, j0 = (idx / nbx) * kUpRows;
+  if (j0 >= ny) return;
+  const int lane = threadIdx.x & (kUpCols - 1), wv = threadIdx.x >> 6;
   const long long N = C.plane, N1 = N + nx;
   T* S = static_cast<T*>(A.scratch);
-  UpBars<T, WALLS, MESH> B{S, N, nx, ny, MeshAxis{}, MeshAxis{}};
+  constexpr int NB = up_bar_planes(CPL);
+  __shared__ T tile[NB][kTileR][kTileC];
+  // rows j0-1 .. j0+kUpRows+1, columns i0-1 .. i0+kUpCols+1: periodic wrap,
+  // clamped at walls (rows past a wall are never read). Wave wv loads rows
+  // wv, wv + 4, ... of the [plane][row] list; all its loads are issued before
+  // the first LDS write, so their latencies overlap.
+  constexpr int kLoads = (NB * kTileR + kUpRows - 1) / kUpRows;
+  const int c0 = wrap(i0 - 1 + lane, nx);
+  const int c1 = wrap(i0 - 1 + kUpCols + (lane < kTileC - kUpCols ? lane : 0), nx);
+  T v0[kLoads], v1[kLoads];
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int pr = wv + k * kUpRows;
+    if (pr < NB * kTileR) {
+      const int p = pr / kTileR, r = pr - p * kTileR;
+      int gj = j0 - 1 + r;
+      gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap(gj, ny);
+      const T* src = S + p * N + (long long)gj * nx;
+      v0[k] = src[c0];
+      if (lane < kTileC - kUpCols) v1[k] = src[c1];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kLoads; ++k) {
+    const int pr = wv + k * kUpRows;
+    if (pr < NB * kTileR) {
+      const int p = pr / kTileR, r = pr - p * kTileR;
+      tile[p][r][lane] = v0[k];
+      if (lane < kTileC - kUpCols) tile[p][r][kUpCols + lane] = v1[k];
+    }
+  }
+  __syncthreads();
+  const int i = i0 + lane, j = j0 + wv;
+  if (i >= nx || j >= ny) return;
+  UpBars<T, WALLS, MESH, NB> B{tile, i0, j0, nx, ny, MeshAxis{}, MeshAxis{}};
   if (MESH) {
     B.X = mesh_axis(C.mesh, nx, ny, 0);
     B.Y = mesh_axis(C.mesh, nx, ny, 1);
@@ -1656,17 +1712,16 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
     ye = B.Y.c[j];
     yn = ye + 0.5 * B.Y.w[j];
   }
-  up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, i, j, wrap(i + 1, nx), j, xe, ye, tf, XF, N,
-                                           cell);
+  up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i, j, i + 1, j, xe, ye, tf, XF, N, cell);
   if (!(WALLS && j == ny - 1))
-    up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, i, j, i, wrap(j + 1, ny), xn, yn, tf, YF,
-                                             N1, cell + nx);
+    up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j, i, j + 1, xn, yn, tf, YF, N1,
+                                             cell + nx);
   if constexpr (WALLS) {
     const int cur = (C.cur0 + (int)(n & 1)) & 1;
     const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
     const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * N * (long long)sizeof(T));
-    if (j == 0) up_wall<T, true, MESH>(C, B, in6, phiP, i, YF, N1);
-    if (j == ny - 1) up_wall<T, false, MESH>(C, B, in6, phiP, i, YF, N1);
+    if (j == 0) up_wall<T, true, MESH, NB>(C, B, in6, N, phiP, i, YF, N1);
+    if (j == ny - 1) up_wall<T, false, MESH, NB>(C, B, in6, N, phiP, i, YF, N1);
   }
 }
 
