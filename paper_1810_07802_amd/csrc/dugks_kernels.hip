@@ -1325,6 +1325,15 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
 
 constexpr int kUpCols = 64, kUpRows = 4;  // cells of one 256-thread block
 
+// Periodic index for an index at most one period outside [0, n): a
+// conditional add or subtract (an integer remainder costs tens of
+// instructions), with the remainder kept for grids smaller than a halo.
+__device__ __forceinline__ int wrap_near(int a, int n) {
+  if (a < 0) a += n;
+  else if (a >= n) a -= n;
+  return (a >= 0 && a < n) ? a : wrap(a, n);
+}
+
 // Cell of this thread, with the block order remapped so that each XCD gets a
 // contiguous share of the grid (the grid is a multiple of 8 blocks). False
 // for threads outside the grid.
@@ -1364,7 +1373,7 @@ __global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
   for (int r = 0; r < 3; ++r) {
     const long long rb = (long long)row_idx(j + r - 1, ny, walls) * nx;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ph[r][c] = phiP[rb + wrap(i + c - 1, nx)];
+    for (int c = 0; c < 3; ++c) ph[r][c] = phiP[rb + wrap_near(i + c - 1, nx)];
   }
   T v[NV];
   load_groups<T, NV>(in, PB, cell, v);
@@ -1435,32 +1444,43 @@ __device__ __forceinline__ T lim_mesh(T b, T f, T hm, T hp, T w) {
 // value several times (the limited slopes of both cells of every face).
 constexpr int kTileR = kUpRows + 3, kTileC = kUpCols + 3;
 
-// Bar-plus values, slopes and face values for the face kernel. Cells are
-// addressed by unwrapped grid indices within the block's tile (the halo
-// holds the wrapped or clamped neighbours); metric arrays and the
-// wall checks use the wrapped indices.
+// Metrics of one cell along one axis of a stretched mesh.
+template <typename T>
+struct Met {
+  T w, hm, hp;
+};
+
+// Bar-plus values, slopes and face values for the face kernel of the cell
+// (ic, jc): its faces read the cells (ic, jc), (ic + 1, jc) and (ic, jc + 1)
+// and their neighbours. Cells are addressed by unwrapped grid indices within
+// the block's tile (the halo holds the wrapped or clamped neighbours). The
+// metrics of columns ic, ic + 1 and rows jc, jc + 1 are held in registers,
+// and ic1, jc1 are the wrapped indices of ic + 1, jc + 1.
 template <typename T, bool WALLS, bool MESH, int NB>
 struct UpBars {
   const T (*L)[kTileR][kTileC];  // LDS tile [NB][kTileR][kTileC]
   int i0, j0;                    // grid cell of tile position (1, 1)
   int nx, ny;
-  MeshAxis X, Y;  // stretched mesh only
+  int ic, jc, ic1, jc1;
+  Met<T> mx[2], my[2];  // stretched mesh only
   __device__ __forceinline__ T at(int p, int i, int j) const { return L[p][j - j0 + 1][i - i0 + 1]; }
-  __device__ __forceinline__ int xi(int i) const { return wrap(i, nx); }
-  __device__ __forceinline__ int yj(int j) const { return wrap(j, ny); }
+  __device__ __forceinline__ int xi(int i) const { return i == ic ? ic : ic1; }
+  __device__ __forceinline__ int yj(int j) const { return j == jc ? jc : jc1; }
+  __device__ __forceinline__ const Met<T>& MX(int i) const { return i == ic ? mx[0] : mx[1]; }
+  __device__ __forceinline__ const Met<T>& MY(int j) const { return j == jc ? my[0] : my[1]; }
   // one-sided y difference (derivative on a stretched mesh) next to a wall,
   // unlimited (j is row 0 or ny-1)
   __device__ __forceinline__ T wall_dy(int p, int i, int j) const {
     const T d = j == 0 ? at(p, i, 1) - at(p, i, 0) : at(p, i, ny - 1) - at(p, i, ny - 2);
-    if (MESH) return d / T(j == 0 ? Y.hp[0] : Y.hm[ny - 1]);
+    if (MESH) return d / (j == 0 ? MY(j).hp : MY(j).hm);
     return d;
   }
   __device__ __forceinline__ T lim_x(int p, int i, int j) const {
     const T c = at(p, i, j);
     const T b = c - at(p, i - 1, j), f = at(p, i + 1, j) - c;
     if (MESH) {
-      const int k = xi(i);
-      return lim_mesh(b, f, T(X.hm[k]), T(X.hp[k]), T(X.w[k]));
+      const Met<T>& m = MX(i);
+      return lim_mesh(b, f, m.hm, m.hp, m.w);
     }
     return van_leer(b, f);
   }
@@ -1469,27 +1489,27 @@ struct UpBars {
     const T c = at(p, i, j);
     const T b = c - at(p, i, j - 1), f = at(p, i, j + 1) - c;
     if (MESH) {
-      const int k = yj(j);
-      return lim_mesh(b, f, T(Y.hm[k]), T(Y.hp[k]), T(Y.w[k]));
+      const Met<T>& m = MY(j);
+      return lim_mesh(b, f, m.hm, m.hp, m.w);
     }
     return van_leer(b, f);
   }
   // central slopes of the stretched mesh (parabola through three centres)
   __device__ __forceinline__ T slope_x(int p, int i, int j) const {
-    const int k = xi(i);
-    return par_d1(at(p, i - 1, j), at(p, i, j), at(p, i + 1, j), T(X.hm[k]), T(X.hp[k]));
+    const Met<T>& m = MX(i);
+    return par_d1(at(p, i - 1, j), at(p, i, j), at(p, i + 1, j), m.hm, m.hp);
   }
   __device__ __forceinline__ T slope_y(int p, int i, int j) const {
     if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
-    const int k = yj(j);
-    return par_d1(at(p, i, j - 1), at(p, i, j), at(p, i, j + 1), T(Y.hm[k]), T(Y.hp[k]));
+    const Met<T>& m = MY(j);
+    return par_d1(at(p, i, j - 1), at(p, i, j), at(p, i, j + 1), m.hm, m.hp);
   }
   // half widths of cells A and B across a face of normal DIR
   template <int DIR>
   __device__ __forceinline__ void halves(int ia, int ja, int ib, int jb, T& dA, T& dB) const {
     if (MESH) {
-      dA = T(0.5 * (DIR == 0 ? X.w[xi(ia)] : Y.w[yj(ja)]));
-      dB = T(0.5 * (DIR == 0 ? X.w[xi(ib)] : Y.w[yj(jb)]));
+      dA = T(0.5) * (DIR == 0 ? MX(ia).w : MY(ja).w);
+      dB = T(0.5) * (DIR == 0 ? MX(ib).w : MY(jb).w);
     } else {
       dA = dB = T(0.5);
     }
@@ -1632,8 +1652,9 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
   T fo[9], go[9];
   T dyw = T(0), idy = T(1);
   if (MESH) {
-    dyw = T(BOTTOM ? -0.5 * B.Y.w[0] : 0.5 * B.Y.w[ny - 1]);
-    idy = T(1.0 / (BOTTOM ? B.Y.hp[0] : B.Y.hm[ny - 1]));
+    const Met<T>& m = B.MY(jw);
+    dyw = BOTTOM ? T(-0.5) * m.w : T(0.5) * m.w;
+    idy = T(1) / (BOTTOM ? m.hp : m.hm);
   }
   wall_face_g<T, BOTTOM, MESH>(C, c, cn, txf, txg, dyw, idy, fo, go);
   const long long fi = (BOTTOM ? 0LL : (long long)ny * nx) + i;
@@ -1668,8 +1689,8 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
   // wv, wv + 4, ... of the [plane][row] list; all its loads are issued before
   // the first LDS write, so their latencies overlap.
   constexpr int kLoads = (NB * kTileR + kUpRows - 1) / kUpRows;
-  const int c0 = wrap(i0 - 1 + lane, nx);
-  const int c1 = wrap(i0 - 1 + kUpCols + (lane < kTileC - kUpCols ? lane : 0), nx);
+  const int c0 = wrap_near(i0 - 1 + lane, nx);
+  const int c1 = wrap_near(i0 - 1 + kUpCols + (lane < kTileC - kUpCols ? lane : 0), nx);
   T v0[kLoads], v1[kLoads];
 #pragma unroll
   for (int k = 0; k < kLoads; ++k) {
@@ -1677,7 +1698,7 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
     if (pr < NB * kTileR) {
       const int p = pr / kTileR, r = pr - p * kTileR;
       int gj = j0 - 1 + r;
-      gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap(gj, ny);
+      gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap_near(gj, ny);
       const T* src = S + p * N + (long long)gj * nx;
       v0[k] = src[c0];
       if (lane < kTileC - kUpCols) v1[k] = src[c1];
@@ -1695,10 +1716,18 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
   __syncthreads();
   const int i = i0 + lane, j = j0 + wv;
   if (i >= nx || j >= ny) return;
-  UpBars<T, WALLS, MESH, NB> B{tile, i0, j0, nx, ny, MeshAxis{}, MeshAxis{}};
+  UpBars<T, WALLS, MESH, NB> B{tile, i0, j0, nx, ny, i, j, wrap_near(i + 1, nx), wrap_near(j + 1, ny),
+                               {}, {}};
+  MeshAxis X{}, Y{};
   if (MESH) {
-    B.X = mesh_axis(C.mesh, nx, ny, 0);
-    B.Y = mesh_axis(C.mesh, nx, ny, 1);
+    X = mesh_axis(C.mesh, nx, ny, 0);
+    Y = mesh_axis(C.mesh, nx, ny, 1);
+    const int cx[2] = {i, B.ic1}, cy[2] = {j, B.jc1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      B.mx[k] = Met<T>{T(X.w[cx[k]]), T(X.hm[cx[k]]), T(X.hp[cx[k]])};
+      B.my[k] = Met<T>{T(Y.w[cy[k]]), T(Y.hm[cy[k]]), T(Y.hp[cy[k]])};
+    }
   }
   const T* in6 = S + up_bar_planes(CPL) * N;
   T* XF = S + up_cell_planes(CPL) * N;
@@ -1707,10 +1736,10 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
   const long long cell = (long long)j * nx + i;
   double xe = (double)i + 1.0, ye = (double)j + 0.5, xn = (double)i + 0.5, yn = (double)j + 1.0;
   if (MESH) {  // face positions from the centres and half widths
-    xn = B.X.c[i];
-    xe = xn + 0.5 * B.X.w[i];
-    ye = B.Y.c[j];
-    yn = ye + 0.5 * B.Y.w[j];
+    xn = X.c[i];
+    xe = xn + 0.5 * X.w[i];
+    ye = Y.c[j];
+    yn = ye + 0.5 * Y.w[j];
   }
   up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i, j, i + 1, j, xe, ye, tf, XF, N, cell);
   if (!(WALLS && j == ny - 1))
@@ -1740,7 +1769,7 @@ __global__ __launch_bounds__(256) void k_up_update(UpArgs A) {
   const T* XF = S + up_cell_planes(CPL) * N;
   const T* YF = XF + up_face_planes(CPL) * N;
   const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;
-  const long long ce = cell, cw = (long long)j * nx + wrap(i - 1, nx);
+  const long long ce = cell, cw = (long long)j * nx + wrap_near(i - 1, nx);
   // face rows above and below: periodic y takes the face below row 0 from
   // the top (face row ny)
   const long long fn = (long long)(j + 1) * nx + i;
