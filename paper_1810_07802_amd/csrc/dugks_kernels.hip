@@ -1444,10 +1444,17 @@ __device__ __forceinline__ T lim_mesh(T b, T f, T hm, T hp, T w) {
 // value several times (the limited slopes of both cells of every face).
 constexpr int kTileR = kUpRows + 3, kTileC = kUpCols + 3;
 
-// Metrics of one cell along one axis of a stretched mesh.
+// Metrics of one cell along one axis of a stretched mesh: width, centre
+// distances to the previous and next cells, their reciprocals, and the
+// weights of the parabola derivative d1 = cp (a+ - a) + cm (a - a-) (the
+// divisions of the stencils done once per cell).
 template <typename T>
 struct Met {
-  T w, hm, hp;
+  T w, hm, hp, ihm, ihp, cp, cm;
+  __device__ static Met make(double w, double hm, double hp) {
+    return Met{T(w), T(hm), T(hp), T(1.0 / hm), T(1.0 / hp), T(hm / (hp * (hm + hp))),
+               T(hp / (hm * (hm + hp)))};
+  }
 };
 
 // Bar-plus values, slopes and face values for the face kernel of the cell
@@ -1472,37 +1479,41 @@ struct UpBars {
   // unlimited (j is row 0 or ny-1)
   __device__ __forceinline__ T wall_dy(int p, int i, int j) const {
     const T d = j == 0 ? at(p, i, 1) - at(p, i, 0) : at(p, i, ny - 1) - at(p, i, ny - 2);
-    if (MESH) return d / (j == 0 ? MY(j).hp : MY(j).hm);
+    if (MESH) return d * (j == 0 ? MY(j).ihp : MY(j).ihm);
     return d;
   }
   __device__ __forceinline__ T lim_x(int p, int i, int j) const {
     const T c = at(p, i, j);
     const T b = c - at(p, i - 1, j), f = at(p, i + 1, j) - c;
-    if (MESH) {
-      const Met<T>& m = MX(i);
-      return lim_mesh(b, f, m.hm, m.hp, m.w);
-    }
+    if (MESH) return lim_met(b, f, MX(i));
     return van_leer(b, f);
   }
   __device__ __forceinline__ T lim_y(int p, int i, int j) const {
     if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
     const T c = at(p, i, j);
     const T b = c - at(p, i, j - 1), f = at(p, i, j + 1) - c;
-    if (MESH) {
-      const Met<T>& m = MY(j);
-      return lim_mesh(b, f, m.hm, m.hp, m.w);
-    }
+    if (MESH) return lim_met(b, f, MY(j));
     return van_leer(b, f);
+  }
+  // stretched mesh: capped van Leer slope (lim_mesh) with the cell's
+  // precomputed reciprocals
+  __device__ __forceinline__ static T lim_met(T b, T f, const Met<T>& m) {
+    const T s = van_leer(b * m.ihm, f * m.ihp);
+    const T ab = b < T(0) ? -b : b, af = f < T(0) ? -f : f;
+    const T cap = T(2) * (ab < af ? ab : af) / m.w;
+    return s > cap ? cap : (s < -cap ? -cap : s);
   }
   // central slopes of the stretched mesh (parabola through three centres)
   __device__ __forceinline__ T slope_x(int p, int i, int j) const {
     const Met<T>& m = MX(i);
-    return par_d1(at(p, i - 1, j), at(p, i, j), at(p, i + 1, j), m.hm, m.hp);
+    const T c = at(p, i, j);
+    return m.cp * (at(p, i + 1, j) - c) + m.cm * (c - at(p, i - 1, j));
   }
   __device__ __forceinline__ T slope_y(int p, int i, int j) const {
     if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
     const Met<T>& m = MY(j);
-    return par_d1(at(p, i, j - 1), at(p, i, j), at(p, i, j + 1), m.hm, m.hp);
+    const T c = at(p, i, j);
+    return m.cp * (at(p, i, j + 1) - c) + m.cm * (c - at(p, i, j - 1));
   }
   // half widths of cells A and B across a face of normal DIR
   template <int DIR>
@@ -1543,11 +1554,13 @@ struct UpBars {
     } else {
       T dA, dB;
       halves<DIR>(ia, ja, ib, jb, dA, dB);
-      const T H = dA + dB, aA = at(p, ia, ja), aB = at(p, ib, jb);
+      // one reciprocal of the centre distance per face (shared by the
+      // populations once inlined)
+      const T iH = T(1) / (dA + dB), aA = at(p, ia, ja), aB = at(p, ib, jb);
       if constexpr (CENTRAL) {
         auto st = [&](int i, int j) { return DIR == 0 ? slope_y(p, i, j) : slope_x(p, i, j); };
-        const T af = (dB * aA + dA * aB) / H, dn = (aB - aA) / H;
-        const T dtg = (dB * st(ia, ja) + dA * st(ib, jb)) / H;
+        const T af = (dB * aA + dA * aB) * iH, dn = (aB - aA) * iH;
+        const T dtg = (dB * st(ia, ja) + dA * st(ib, jb)) * iH;
         return af - h * (T(en) * dn + T(et) * dtg);
       } else {
         if (en > 0) {
@@ -1565,7 +1578,7 @@ struct UpBars {
           vA -= h * T(et) * lt(ia, ja);
           vB -= h * T(et) * lt(ib, jb);
         }
-        return (dB * vA + dA * vB) / H;
+        return (dB * vA + dA * vB) * iH;
       }
     }
   }
@@ -1602,8 +1615,9 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS,
   B.template halves<DIR>(ia, ja, ib, jb, dA, dB);
   // gradient-type face inputs: the mean of the two cells (linear
   // interpolation to the face on a stretched mesh)
+  const T iH = T(1) / (dA + dB);
   auto mean = [&](int k) {
-    if (MESH) return (dB * in6[k * N + a] + dA * in6[k * N + b]) / (dA + dB);
+    if (MESH) return (dB * in6[k * N + a] + dA * in6[k * N + b]) * iH;
     return T(0.5) * (in6[k * N + a] + in6[k * N + b]);
   };
   T fo[9], go[9];
@@ -1654,7 +1668,7 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
   if (MESH) {
     const Met<T>& m = B.MY(jw);
     dyw = BOTTOM ? T(-0.5) * m.w : T(0.5) * m.w;
-    idy = T(1) / (BOTTOM ? m.hp : m.hm);
+    idy = BOTTOM ? m.ihp : m.ihm;
   }
   wall_face_g<T, BOTTOM, MESH>(C, c, cn, txf, txg, dyw, idy, fo, go);
   const long long fi = (BOTTOM ? 0LL : (long long)ny * nx) + i;
@@ -1725,8 +1739,8 @@ __global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
     const int cx[2] = {i, B.ic1}, cy[2] = {j, B.jc1};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      B.mx[k] = Met<T>{T(X.w[cx[k]]), T(X.hm[cx[k]]), T(X.hp[cx[k]])};
-      B.my[k] = Met<T>{T(Y.w[cy[k]]), T(Y.hm[cy[k]]), T(Y.hp[cy[k]])};
+      B.mx[k] = Met<T>::make(X.w[cx[k]], X.hm[cx[k]], X.hp[cx[k]]);
+      B.my[k] = Met<T>::make(Y.w[cy[k]], Y.hm[cy[k]], Y.hp[cy[k]]);
     }
   }
   const T* in6 = S + up_bar_planes(CPL) * N;
