@@ -1445,15 +1445,15 @@ __device__ __forceinline__ T lim_mesh(T b, T f, T hm, T hp, T w) {
 constexpr int kTileR = kUpRows + 3, kTileC = kUpCols + 3;
 
 // Metrics of one cell along one axis of a stretched mesh: width, centre
-// distances to the previous and next cells, their reciprocals, and the
-// weights of the parabola derivative d1 = cp (a+ - a) + cm (a - a-) (the
-// divisions of the stencils done once per cell).
+// distances to the previous and next cells, their reciprocals, the weights
+// of the parabola derivative d1 = cp (a+ - a) + cm (a - a-), and twice the
+// reciprocal width (the divisions of the stencils done once per cell).
 template <typename T>
 struct Met {
-  T w, hm, hp, ihm, ihp, cp, cm;
+  T w, hm, hp, ihm, ihp, cp, cm, iw2;  // iw2 = 2 / w
   __device__ static Met make(double w, double hm, double hp) {
     return Met{T(w), T(hm), T(hp), T(1.0 / hm), T(1.0 / hp), T(hm / (hp * (hm + hp))),
-               T(hp / (hm * (hm + hp)))};
+               T(hp / (hm * (hm + hp))), T(2.0 / w)};
   }
 };
 
@@ -1500,7 +1500,7 @@ struct UpBars {
   __device__ __forceinline__ static T lim_met(T b, T f, const Met<T>& m) {
     const T s = van_leer(b * m.ihm, f * m.ihp);
     const T ab = b < T(0) ? -b : b, af = f < T(0) ? -f : f;
-    const T cap = T(2) * (ab < af ? ab : af) / m.w;
+    const T cap = (ab < af ? ab : af) * m.iw2;
     return s > cap ? cap : (s < -cap ? -cap : s);
   }
   // central slopes of the stretched mesh (parabola through three centres)
