@@ -64,3 +64,31 @@ def test_params_marshalling_rejects_unknown_keys():
         D.make_params(dict(bogus=1.0))
     p = D.make_params(dict(visc="reciprocal", walls_y=True, vel="deform", M=0.3))
     assert p.visc_mode == 1 and p.bc_y == 1 and p.vel_kind == 3 and p.M_phi == 0.3
+
+
+def test_params_struct_matches_the_header(tmp_path):
+    """The ctypes mirror of dugks_params has the C layout: size and every
+    field offset, from a program compiled against include/dugks.h."""
+    fields = [f for f, _ in D.Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dugks.h"\n'
+                   "int main(void) {\n"
+                   '  printf("%zu\\n", sizeof(dugks_params));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(dugks_params, {f}));\n' for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    import ctypes
+    assert got[0] == ctypes.sizeof(D.Params)
+    assert got[1:] == [getattr(D.Params, f).offset for f in fields]
+
+
+def test_reconstruction_and_mesh_arguments():
+    assert D.make_params(dict(recon="upwind")).recon == 1
+    assert D.make_params({}).recon == 0
+    with pytest.raises(KeyError):
+        D.make_params(dict(recon="weno"))
+    L = D.lib()
+    assert L.dugks_set_mesh(None, None, None) == D.EINVAL
