@@ -200,8 +200,10 @@ int dugks_get_macros_device(dugks_handle *h, double *phi, double *u,
 /* Diagnostics of the current state, accumulated in double on the device in
  * a fixed order: out[0] = sum phi, out[1] = sum rho u, out[2] = sum rho v,
  * out[3] = sum rho |u|^2 / 2, out[4] = max |u|, out[5] = sum rho,
- * out[6] = number of non-finite cells, out[7] = time. Synchronises. Returns
- * ENUMERIC (with out filled) when out[6] > 0. */
+ * out[6] = number of non-finite cells, out[7] = time. Sums are over cells,
+ * not weighted by cell area (on a stretched mesh the conserved quantity is
+ * the area integral of phi). Synchronises. Returns ENUMERIC (with out
+ * filled) when out[6] > 0. */
 int dugks_get_diagnostics(dugks_handle *h, double out[8]);
 
 /* Steps taken since init and the current time. */
@@ -233,7 +235,9 @@ int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
 int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
                    double *us_per_step);
 
-/* Device bytes a handle of this shape holds (both state buffers). */
+/* Device bytes a handle of this shape holds (both state buffers). The
+ * upwind reconstruction and stretched meshes add the three-kernel scratch
+ * (see recon) and, for a mesh, 32 (nx + ny) bytes of metrics. */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
 
 /* Message of the last error on h (or of the last failed create when h is

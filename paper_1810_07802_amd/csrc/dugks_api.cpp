@@ -503,7 +503,7 @@ int dugks_get_diagnostics(dugks_handle* h, double out[8]) {
   HIPCHK(h, hipMemcpyAsync(tmp, dout, sizeof(tmp), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int k = 0; k < 7; ++k) out[k] = tmp[k];
-  out[7] = h->steps * h->params.cfl;
+  out[7] = h->steps * h->hc.dt;
   if (tmp[6] > 0) return fail(h, DUGKS_ENUMERIC, "non-finite values in the state");
   return DUGKS_OK;
 }
