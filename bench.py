@@ -18,10 +18,10 @@ The same JSON line carries:
                 pool: p50 / p99 time to solution at 80 % load, aggregate
                 MLUPS, vs the plain sequential per-case loop
   upwind        the same bubble with the upwind, limited face reconstruction
-                (three kernels per step, 708 algorithmic bytes per cell in
+                (two kernels per step, 516 algorithmic bytes per cell in
                 FP32), 128^2 and 4096^2, launched step by step
   mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
-                central and upwind, through the same three kernels
+                central and upwind, through the same two kernels
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -38,11 +38,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 B_PER_CELL = {"fp32": 160.0, "fp64": 320.0}  # read + write of 18 populations + 2 history values
-# upwind reconstruction, coupled, FP32: stage 260 (state in, tilde-plus and
-# history out, 18 bar-plus + 6 face inputs out), faces 188 (18 bar-plus + 5
-# inputs in, 24 face values out), update 260 (20 state + 24 face values in,
-# 21 values out) bytes per cell
-B_UPWIND = {"fp32": 708.0, "fp64": 1416.0}
+# upwind reconstruction / stretched mesh, coupled, FP32: stage 260 (21 state
+# values in; tilde-plus and history, 20 values, out; 18 bar-plus + 6 face
+# inputs out), faces and update 256 (18 bar-plus + 5 face inputs + 20 state
+# values in, 21 values out) bytes per cell
+B_UPWIND = {"fp32": 516.0, "fp64": 1032.0}
 
 
 def parse():
@@ -154,7 +154,7 @@ def roofline(cells, steps, seconds, prec, workload=None):
 def timed_upwind(torch, D, c, steps, warmup, recon="upwind", mesh=None):
     """Three-kernel steps of case `c` (coupled FP32): the upwind
     reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
-    reconstruction, launched one step (three kernels) at a time on torch's
+    reconstruction, launched one step (two kernels) at a time on torch's
     current stream; seconds by HIP events on that stream."""
     stream = torch.cuda.current_stream()
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
@@ -391,7 +391,7 @@ def main():
         # upwind, limited reconstruction on the same physics
         rec["upwind"] = {
             "workload": "stationary bubble, coupled FP32, upwind reconstruction, "
-                        "one step (three kernels) per host call",
+                        "one step (two kernels) per host call",
             "bubble128": timed_upwind(torch, D, c, min(args.steps, 5000), 100),
             "bubble4096": timed_upwind(torch, D, W.bubble(L=4096, R=1024, steps=0),
                                        args.upwind_steps, 5)}
@@ -400,7 +400,7 @@ def main():
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         rec["mesh"] = {
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
-                        "both axes), coupled FP32, one step (three kernels) per host call",
+                        "both axes), coupled FP32, one step (two kernels) per host call",
             "central": timed_upwind(torch, D, cm, args.upwind_steps, 5, "central", mesh),
             "upwind": timed_upwind(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
         if args.serve_requests > 0:

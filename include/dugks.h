@@ -89,8 +89,8 @@ enum { DUGKS_RECON_CENTRAL = 0, DUGKS_RECON_UPWIND = 1 };
  *                  ab > 0, else 0; one-sided and unlimited next to a wall);
  *                  populations along the face take the mean of both cells.
  *                  Upwind runs on single handles only (EINVAL in batches and
- *                  pools), and takes (18 + 6 + 2 * 12) * n values of device
- *                  scratch (coupled; 9 + 6 + 2 * 6 for interface-only),
+ *                  pools), and takes (18 + 6) * n values of device
+ *                  scratch (coupled; 9 + 6 for interface-only),
  *                  allocated by dugks_set_params.
  */
 typedef struct dugks_params {
@@ -158,7 +158,7 @@ int dugks_get_tile(const dugks_handle *h);
  *     one-sided difference over the cell width);
  *   - the regularisation of the unit normal is 1e-6 |phi_H - phi_L| over
  *     the smallest width.
- * The step then runs as three kernels with the scratch of the upwind mode
+ * The step then runs as two kernels with the scratch of the upwind mode
  * (see recon). Cell centres start at x = 0, y = 0. Takes effect at the next
  * dugks_init_fields (the state is invalidated: ESTATE until then). Not for
  * batches or pool cases (EINVAL). Errors: EINVAL (widths), ENOMEM. */
@@ -236,7 +236,7 @@ int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
                    double *us_per_step);
 
 /* Device bytes a handle of this shape holds (both state buffers). The
- * upwind reconstruction and stretched meshes add the three-kernel scratch
+ * upwind reconstruction and stretched meshes add the two-kernel scratch
  * (see recon) and, for a mesh, 32 (nx + ny) bytes of metrics. */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
 

@@ -260,7 +260,7 @@ int ensure_scratch(dugks_handle* h) {
 
 int ensure_up_scratch(dugks_handle* h) {
   if (h->up) return DUGKS_OK;
-  const size_t b = (size_t)dugks::up_scratch_values((long long)h->n(), h->nx, h->coupled()) * h->elem();
+  const size_t b = (size_t)dugks::up_scratch_values((long long)h->n(), h->coupled()) * h->elem();
   hipError_t e = hipMalloc(&h->up, b);
   if (e != hipSuccess) {
     h->up = nullptr;

@@ -26,7 +26,7 @@ struct dugks_handle {
   long long* step_base = nullptr;  // device: steps done
   long long steps = 0;             // host mirror
   double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
-  void* up = nullptr;              // scratch planes of the three-kernel step
+  void* up = nullptr;              // scratch planes of the two-kernel step
   // stretched mesh: host widths, and the device metric arrays (CaseDev::mesh)
   bool mesh = false;
   std::vector<double> mdx, mdy;
@@ -39,7 +39,7 @@ struct dugks_handle {
 
   bool fp64() const { return precision == DUGKS_FP64; }
   bool upwind() const { return params.recon == DUGKS_RECON_UPWIND; }
-  // steps run as three kernels (upwind reconstruction or stretched mesh)
+  // steps run as two kernels (upwind reconstruction or stretched mesh)
   // instead of the fused march
   bool general() const { return upwind() || mesh; }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }

@@ -110,18 +110,13 @@ struct StepArgs {
   int one_row;                 // every item is one row (seg_rows == 1): row kernel
 };
 
-// Upwind reconstruction: scratch planes of the three-kernel step, in values
-// of the working type. Cell planes (n values each): bar-plus f0..f8 and
-// (coupled) g0..g8, then grad phi x, y, mu_phi, D x, y and p. Face planes of
-// the populations that cross a face, f then (coupled) g: x-faces (n values
-// each, the face east of each cell) for e_x != 0, y-faces (n + nx values
-// each, face row jj = 0 .. ny between cell rows jj-1 and jj) for e_y != 0.
+// Scratch planes of the two-kernel step (upwind reconstruction, stretched
+// mesh), in values of the working type, n values each: bar-plus f0..f8 and
+// (coupled) g0..g8, then grad phi x, y, mu_phi, D x, y and p.
 __host__ __device__ constexpr int up_bar_planes(bool coupled) { return coupled ? 18 : 9; }
 __host__ __device__ constexpr int up_cell_planes(bool coupled) { return up_bar_planes(coupled) + 6; }
-__host__ __device__ constexpr int up_face_planes(bool coupled) { return coupled ? 12 : 6; }
-__host__ __device__ constexpr long long up_scratch_values(long long n, long long nx, bool coupled) {
-  return (long long)(up_cell_planes(coupled) + up_face_planes(coupled)) * n +
-         (long long)up_face_planes(coupled) * (n + nx);
+__host__ __device__ constexpr long long up_scratch_values(long long n, bool coupled) {
+  return (long long)up_cell_planes(coupled) * n;
 }
 // slot of population q among the six crossing an x-face / a y-face (-1: none)
 __host__ __device__ constexpr int up_xslot(int q) {
@@ -131,7 +126,7 @@ __host__ __device__ constexpr int up_yslot(int q) {
   return q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 2 : q == 6 ? 3 : q == 7 ? 4 : q == 8 ? 5 : -1;
 }
 
-// Launch arguments of the three-kernel step (upwind reconstruction, or a
+// Launch arguments of the two-kernel step (upwind reconstruction, or a
 // stretched mesh; one case, one step).
 struct UpArgs {
   const CaseDev* cases;

@@ -1299,7 +1299,7 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
   for (int k = 0; k < kDiagQ; ++k) out[k] = a[k];
 }
 
-// --------------------------- three-kernel step: upwind or stretched mesh
+// ------------------------------ two-kernel step: upwind or stretched mesh
 
 // The upwind, limited reconstruction and the stretched mesh (both selected
 // per handle) do not fit the fused march. The upwind face value of each
@@ -1307,14 +1307,15 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
 // then be summed from the nine reconstructed values instead of
 // reconstructed cell moments. A face also reads the limited slopes of both
 // its cells, a radius-two stencil. On a stretched mesh every stencil
-// carries the local widths. The step then runs as three kernels over one
+// carries the local widths. The step then runs as two kernels over one
 // thread per cell, through scratch planes (layout in dugks_impl.h):
-//   k_up_stage  cell stage of every cell: bar-plus and the face inputs to
-//               scratch, tilde-plus and the history into the output state;
-//   k_up_faces  the x-face east and the y-face north of every cell (and the
-//               wall faces): reconstruction, face macros and face
-//               distributions, once per face, to the face planes;
-//   k_up_update the update (Eq. 24) of every cell from its four faces.
+//   k_up_stage        cell stage of every cell: bar-plus and the face inputs
+//                     to scratch, tilde-plus and the history into the output
+//                     state;
+//   k_up_faces_update per 64 x 4 block: the block's bar-plus tile in LDS,
+//                     every face of its cells once (reconstruction, face
+//                     macros, face distributions; wall faces), the face
+//                     distributions in LDS, and the update (Eq. 24).
 // The cell stage, face distribution and wall face are the march's.
 //
 // Stretched mesh: the reconstruction interpolates linearly to the face (the
@@ -1439,10 +1440,11 @@ __device__ __forceinline__ T lim_mesh(T b, T f, T hm, T hp, T w) {
   return s > cap ? cap : (s < -cap ? -cap : s);
 }
 
-// The face kernel stages the bar-plus values of its block's cells and their
-// halo (one column/row before, two after) in LDS: a block's faces read each
-// value several times (the limited slopes of both cells of every face).
-constexpr int kTileR = kUpRows + 3, kTileC = kUpCols + 3;
+// The face-and-update kernel stages the bar-plus values of its block's cells
+// and their halo (two columns/rows before, two after) in LDS: a block's faces
+// read each value several times (the limited slopes of both cells of every
+// face).
+constexpr int kTileR = kUpRows + 4, kTileC = kUpCols + 4;
 
 // Metrics of one cell along one axis of a stretched mesh: width, centre
 // distances to the previous and next cells, their reciprocals, the weights
@@ -1457,22 +1459,23 @@ struct Met {
   }
 };
 
-// Bar-plus values, slopes and face values for the face kernel of the cell
-// (ic, jc): its faces read the cells (ic, jc), (ic + 1, jc) and (ic, jc + 1)
-// and their neighbours. Cells are addressed by unwrapped grid indices within
-// the block's tile (the halo holds the wrapped or clamped neighbours). The
-// metrics of columns ic, ic + 1 and rows jc, jc + 1 are held in registers,
-// and ic1, jc1 are the wrapped indices of ic + 1, jc + 1.
+// Bar-plus values, slopes and face values of the faces of one cell (ic, jc):
+// they read the cells (ic, jc), (ic + 1, jc) and (ic, jc + 1) and their
+// neighbours. Cells are addressed by unwrapped grid indices within the
+// block's tile (the halo holds the wrapped or clamped neighbours); icw, jcw,
+// ic1, jc1 are the wrapped indices of ic, jc, ic + 1, jc + 1. On a stretched
+// mesh the metrics of columns ic, ic + 1 and rows jc, jc + 1 are held in
+// registers.
 template <typename T, bool WALLS, bool MESH, int NB>
 struct UpBars {
   const T (*L)[kTileR][kTileC];  // LDS tile [NB][kTileR][kTileC]
-  int i0, j0;                    // grid cell of tile position (1, 1)
+  int i0, j0;                    // grid cell of tile position (2, 2)
   int nx, ny;
-  int ic, jc, ic1, jc1;
+  int ic, jc, icw, jcw, ic1, jc1;
   Met<T> mx[2], my[2];  // stretched mesh only
-  __device__ __forceinline__ T at(int p, int i, int j) const { return L[p][j - j0 + 1][i - i0 + 1]; }
-  __device__ __forceinline__ int xi(int i) const { return i == ic ? ic : ic1; }
-  __device__ __forceinline__ int yj(int j) const { return j == jc ? jc : jc1; }
+  __device__ __forceinline__ T at(int p, int i, int j) const { return L[p][j - j0 + 2][i - i0 + 2]; }
+  __device__ __forceinline__ int xi(int i) const { return i == ic ? icw : ic1; }
+  __device__ __forceinline__ int yj(int j) const { return j == jc ? jcw : jc1; }
   __device__ __forceinline__ const Met<T>& MX(int i) const { return i == ic ? mx[0] : mx[1]; }
   __device__ __forceinline__ const Met<T>& MY(int j) const { return j == jc ? my[0] : my[1]; }
   // one-sided y difference (derivative on a stretched mesh) next to a wall,
@@ -1584,15 +1587,34 @@ struct UpBars {
   }
 };
 
+// The view of the tile for the faces of cell (ic, jc) (unwrapped), with its
+// wrapped indices and, on a stretched mesh, its metrics.
+template <typename T, bool WALLS, bool MESH, int NB>
+__device__ __forceinline__ UpBars<T, WALLS, MESH, NB> up_bars(const CaseDev& C,
+                                                             const T (*L)[kTileR][kTileC], int i0,
+                                                             int j0, int ic, int jc) {
+  const int nx = C.nx, ny = C.ny;
+  UpBars<T, WALLS, MESH, NB> B{L, i0, j0, nx, ny, ic, jc, wrap_near(ic, nx), wrap_near(jc, ny),
+                               wrap_near(ic + 1, nx), wrap_near(jc + 1, ny), {}, {}};
+  if (MESH) {
+    const MeshAxis X = mesh_axis(C.mesh, nx, ny, 0), Y = mesh_axis(C.mesh, nx, ny, 1);
+    const int cx[2] = {B.icw, B.ic1}, cy[2] = {B.jcw, B.jc1};
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      B.mx[k] = Met<T>::make(X.w[cx[k]], X.hm[cx[k]], X.hp[cx[k]]);
+      B.my[k] = Met<T>::make(Y.w[cy[k]], Y.hm[cy[k]], Y.hp[cy[k]]);
+    }
+  }
+  return B;
+}
+
 // Face of normal DIR between cells A and B (unwrapped indices):
-// reconstruction, face macros and the face distributions of the crossing
-// populations, written to the face planes F (f, then g) at index fi with
-// stride FS.
+// reconstruction, face macros and the face distributions fo, go (the
+// populations that cross the face).
 template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR, int NB>
 __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH, NB>& B,
                                         const T* in6, long long N, int ia, int ja, int ib, int jb,
-                                        double xf, double yf, double tf, T* F, long long FS,
-                                        long long fi) {
+                                        double xf, double yf, double tf, T (&fo)[9], T (&go)[9]) {
   const T h = T(C.h);
   T fbar[9], gbar[9];
 #pragma unroll
@@ -1620,27 +1642,19 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS,
     if (MESH) return (dB * in6[k * N + a] + dA * in6[k * N + b]) * iH;
     return T(0.5) * (in6[k * N + a] + in6[k * N + b]);
   };
-  T fo[9], go[9];
   face_df<T, CPL, DIR>(C, phif, N0f, Jxf, Jyf, mean(0), mean(1), mean(2), mean(3), mean(4), fbar,
                        gbar, xf, yf, tf, fo, go);
-#pragma unroll
-  for (int q = 1; q < 9; ++q) {
-    const int s = DIR == 0 ? up_xslot(q) : up_yslot(q);
-    if (s < 0) continue;
-    F[s * FS + fi] = fo[q];
-    if (CPL) F[(6 + s) * FS + fi] = go[q];
-  }
 }
 
-// Wall face below row 0 (BOTTOM) or above row ny-1 of column i, into face
-// row 0 or ny: the march's face bounce-back, fed from the tile.
+// Wall face below row 0 (BOTTOM) or above row ny-1 of column i: the march's
+// face bounce-back, fed from the tile. B is the view of the wall cell.
 template <typename T, bool BOTTOM, bool MESH, int NB>
 __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH, NB>& B,
-                                        const T* in6, long long N, const T* phiP, int i, T* F,
-                                        long long FS) {
+                                        const T* in6, long long N, const T* phiP, int i,
+                                        T (&fo)[9], T (&go)[9]) {
   const int nx = B.nx, ny = B.ny;
   const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
-  const long long cw = (long long)jw * nx + i;
+  const long long cw = (long long)jw * nx + B.xi(i);
   Cell<T> c, cn;
   T txf[9], txg[9];
 #pragma unroll
@@ -1663,7 +1677,6 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
   c.mu = in6[2 * N + cw];
   c.Dx = in6[3 * N + cw];
   c.p = in6[5 * N + cw];
-  T fo[9], go[9];
   T dyw = T(0), idy = T(1);
   if (MESH) {
     const Met<T>& m = B.MY(jw);
@@ -1671,128 +1684,153 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
     idy = BOTTOM ? m.ihp : m.ihm;
   }
   wall_face_g<T, BOTTOM, MESH>(C, c, cn, txf, txg, dyw, idy, fo, go);
-  const long long fi = (BOTTOM ? 0LL : (long long)ny * nx) + i;
-#pragma unroll
-  for (int q = 1; q < 9; ++q) {
-    const int s = up_yslot(q);
-    if (s < 0) continue;
-    F[s * FS + fi] = fo[q];
-    F[(6 + s) * FS + fi] = go[q];
-  }
 }
 
+// Faces and update of one 64 x 4 block of cells. Every thread forms the
+// x-face east and the y-face north of its cell; wave 0 also forms the y-face
+// south of the block's first row, and four lanes of wave 1 the x-face west
+// of its first column. The face distributions go to LDS (over the tile,
+// whose reads are finished by then), and every cell is updated from its
+// four faces (Eq. 24).
 template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL>
-__global__ __launch_bounds__(256) void k_up_faces(UpArgs A) {
+__global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   const CaseDev C = *A.cases;
   const long long n = up_step(C, A);
   if (n < 0) return;
   const int nx = C.nx, ny = C.ny;
   // block origin (the same map as up_cell); blocks past the grid leave
-  // before the barrier, all of their threads together
+  // before the barriers, all of their threads together
   const int nbx = (nx + kUpCols - 1) / kUpCols;
   const int idx = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int i0 = (idx % nbx) * kUpCols, j0 = (idx / nbx) * kUpRows;
   if (j0 >= ny) return;
   const int lane = threadIdx.x & (kUpCols - 1), wv = threadIdx.x >> 6;
-  const long long N = C.plane, N1 = N + nx;
-  T* S = static_cast<T*>(A.scratch);
+  const long long N = C.plane, PB = N * (long long)sizeof(T);
+  const T* S = static_cast<const T*>(A.scratch);
   constexpr int NB = up_bar_planes(CPL);
+  constexpr int NF = CPL ? 12 : 6;  // crossing populations of a face, f then g
   __shared__ T tile[NB][kTileR][kTileC];
-  // rows j0-1 .. j0+kUpRows+1, columns i0-1 .. i0+kUpCols+1: periodic wrap,
+  // rows j0-2 .. j0+kUpRows+1, columns i0-2 .. i0+kUpCols+1: periodic wrap,
   // clamped at walls (rows past a wall are never read). Wave wv loads rows
   // wv, wv + 4, ... of the [plane][row] list; all its loads are issued before
   // the first LDS write, so their latencies overlap.
-  constexpr int kLoads = (NB * kTileR + kUpRows - 1) / kUpRows;
-  const int c0 = wrap_near(i0 - 1 + lane, nx);
-  const int c1 = wrap_near(i0 - 1 + kUpCols + (lane < kTileC - kUpCols ? lane : 0), nx);
-  T v0[kLoads], v1[kLoads];
+  {
+    constexpr int kLoads = (NB * kTileR + kUpRows - 1) / kUpRows;
+    const int c0 = wrap_near(i0 - 2 + lane, nx);
+    const int c1 = wrap_near(i0 - 2 + kUpCols + (lane < kTileC - kUpCols ? lane : 0), nx);
+    T v0[kLoads], v1[kLoads];
 #pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int pr = wv + k * kUpRows;
-    if (pr < NB * kTileR) {
-      const int p = pr / kTileR, r = pr - p * kTileR;
-      int gj = j0 - 1 + r;
-      gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap_near(gj, ny);
-      const T* src = S + p * N + (long long)gj * nx;
-      v0[k] = src[c0];
-      if (lane < kTileC - kUpCols) v1[k] = src[c1];
+    for (int k = 0; k < kLoads; ++k) {
+      const int pr = wv + k * kUpRows;
+      if (pr < NB * kTileR) {
+        const int p = pr / kTileR, r = pr - p * kTileR;
+        int gj = j0 - 2 + r;
+        gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap_near(gj, ny);
+        const T* src = S + p * N + (long long)gj * nx;
+        v0[k] = src[c0];
+        if (lane < kTileC - kUpCols) v1[k] = src[c1];
+      }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < kLoads; ++k) {
-    const int pr = wv + k * kUpRows;
-    if (pr < NB * kTileR) {
-      const int p = pr / kTileR, r = pr - p * kTileR;
-      tile[p][r][lane] = v0[k];
-      if (lane < kTileC - kUpCols) tile[p][r][kUpCols + lane] = v1[k];
+    for (int k = 0; k < kLoads; ++k) {
+      const int pr = wv + k * kUpRows;
+      if (pr < NB * kTileR) {
+        const int p = pr / kTileR, r = pr - p * kTileR;
+        tile[p][r][lane] = v0[k];
+        if (lane < kTileC - kUpCols) tile[p][r][kUpCols + lane] = v1[k];
+      }
     }
   }
   __syncthreads();
   const int i = i0 + lane, j = j0 + wv;
-  if (i >= nx || j >= ny) return;
-  UpBars<T, WALLS, MESH, NB> B{tile, i0, j0, nx, ny, i, j, wrap_near(i + 1, nx), wrap_near(j + 1, ny),
-                               {}, {}};
+  const bool act = i < nx && j < ny;
+  const T* in6 = S + up_bar_planes(CPL) * N;
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * PB);
+  const double tf = C.t0 + (double)n * C.dt + C.h;
   MeshAxis X{}, Y{};
   if (MESH) {
     X = mesh_axis(C.mesh, nx, ny, 0);
     Y = mesh_axis(C.mesh, nx, ny, 1);
-    const int cx[2] = {i, B.ic1}, cy[2] = {j, B.jc1};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      B.mx[k] = Met<T>::make(X.w[cx[k]], X.hm[cx[k]], X.hp[cx[k]]);
-      B.my[k] = Met<T>::make(Y.w[cy[k]], Y.hm[cy[k]], Y.hp[cy[k]]);
+  }
+  // face positions: the east face of column c, the north face of row r
+  // (wrapped indices)
+  auto xeast = [&](int c) { return MESH ? X.c[c] + 0.5 * X.w[c] : (double)c + 1.0; };
+  auto xmid = [&](int c) { return MESH ? X.c[c] : (double)c + 0.5; };
+  auto ynorth = [&](int r) { return MESH ? Y.c[r] + 0.5 * Y.w[r] : (double)r + 1.0; };
+  auto ymid = [&](int r) { return MESH ? Y.c[r] : (double)r + 0.5; };
+  T fx[9], gx[9], fy[9], gy[9], fe[9], ge[9];
+  if (act) {
+    const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, j);
+    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i, j, i + 1, j, xeast(i), ymid(j), tf,
+                                             fx, gx);
+    if (WALLS && j == ny - 1) {
+      if constexpr (WALLS) up_wall<T, false, MESH, NB>(C, B, in6, N, phiP, i, fy, gy);
+    } else {
+      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j, i, j + 1, xmid(i), ynorth(j),
+                                               tf, fy, gy);
     }
   }
-  const T* in6 = S + up_bar_planes(CPL) * N;
-  T* XF = S + up_cell_planes(CPL) * N;
-  T* YF = XF + up_face_planes(CPL) * N;
-  const double tf = C.t0 + (double)n * C.dt + C.h;
-  const long long cell = (long long)j * nx + i;
-  double xe = (double)i + 1.0, ye = (double)j + 0.5, xn = (double)i + 0.5, yn = (double)j + 1.0;
-  if (MESH) {  // face positions from the centres and half widths
-    xn = X.c[i];
-    xe = xn + 0.5 * X.w[i];
-    ye = Y.c[j];
-    yn = ye + 0.5 * Y.w[j];
+  // the block's extra faces
+  const bool south = wv == 0 && i < nx;
+  const bool west = wv == 1 && lane < kUpRows && j0 + lane < ny;
+  if (south) {  // y-face between rows j0 - 1 and j0, or the bottom wall
+    if (WALLS && j0 == 0) {
+      if constexpr (WALLS) {
+        const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, 0);
+        up_wall<T, true, MESH, NB>(C, B, in6, N, phiP, i, fe, ge);
+      }
+    } else {
+      const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, j0 - 1);
+      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j0 - 1, i, j0, xmid(i),
+                                               ynorth(B.jcw), tf, fe, ge);
+    }
   }
-  up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i, j, i + 1, j, xe, ye, tf, XF, N, cell);
-  if (!(WALLS && j == ny - 1))
-    up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j, i, j + 1, xn, yn, tf, YF, N1,
-                                             cell + nx);
-  if constexpr (WALLS) {
-    const int cur = (C.cur0 + (int)(n & 1)) & 1;
-    const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
-    const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * N * (long long)sizeof(T));
-    if (j == 0) up_wall<T, true, MESH, NB>(C, B, in6, N, phiP, i, YF, N1);
-    if (j == ny - 1) up_wall<T, false, MESH, NB>(C, B, in6, N, phiP, i, YF, N1);
+  if (west) {  // x-face between columns i0 - 1 and i0 of row j0 + lane
+    const int jr = j0 + lane;
+    const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i0 - 1, jr);
+    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i0 - 1, jr, i0, jr, xeast(B.icw),
+                                             ymid(jr), tf, fe, ge);
   }
-}
-
-template <typename T, bool CPL, bool WALLS, bool MESH>
-__global__ __launch_bounds__(256) void k_up_update(UpArgs A) {
-  const CaseDev C = *A.cases;
-  const long long n = up_step(C, A);
-  int i, j;
-  if (n < 0 || !up_cell(C.nx, C.ny, i, j)) return;
-  const int nx = C.nx, ny = C.ny;
-  const long long N = C.plane, N1 = N + nx, PB = N * (long long)sizeof(T);
-  const int cur = (C.cur0 + (int)(n & 1)) & 1;
-  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  __syncthreads();  // every read of the tile is done: it now holds the faces
+  // x-faces [NF][kUpRows][kUpCols + 1] (column c: the face east of i0 - 1 + c),
+  // y-faces [NF][kUpRows + 1][kUpCols] (row r: the face north of j0 - 1 + r)
+  T* FX = &tile[0][0][0];
+  T* FY = FX + NF * kUpRows * (kUpCols + 1);
+  auto fxi = [&](int s, int r, int c) { return (s * kUpRows + r) * (kUpCols + 1) + c; };
+  auto fyi = [&](int s, int r, int c) { return (s * (kUpRows + 1) + r) * kUpCols + c; };
+#pragma unroll
+  for (int q = 1; q < 9; ++q) {
+    const int sx = up_xslot(q), sy = up_yslot(q);
+    if (act && sx >= 0) {
+      FX[fxi(sx, wv, lane + 1)] = fx[q];
+      if (CPL) FX[fxi(6 + sx, wv, lane + 1)] = gx[q];
+    }
+    if (act && sy >= 0) {
+      FY[fyi(sy, wv + 1, lane)] = fy[q];
+      if (CPL) FY[fyi(6 + sy, wv + 1, lane)] = gy[q];
+    }
+    if (south && sy >= 0) {
+      FY[fyi(sy, 0, lane)] = fe[q];
+      if (CPL) FY[fyi(6 + sy, 0, lane)] = ge[q];
+    }
+    if (west && sx >= 0) {
+      FX[fxi(sx, lane, 0)] = fe[q];
+      if (CPL) FX[fxi(6 + sx, lane, 0)] = ge[q];
+    }
+  }
+  __syncthreads();
+  if (!act) return;
+  // update (Eq. 24): face length over cell area is 1/dx and 1/dy (1 on unit
+  // cells)
   constexpr int NV = num_grouped(CPL);
-  const T* S = static_cast<const T*>(A.scratch);
-  const T* XF = S + up_cell_planes(CPL) * N;
-  const T* YF = XF + up_face_planes(CPL) * N;
   const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;
-  const long long ce = cell, cw = (long long)j * nx + wrap_near(i - 1, nx);
-  // face rows above and below: periodic y takes the face below row 0 from
-  // the top (face row ny)
-  const long long fn = (long long)(j + 1) * nx + i;
-  const long long fs = (long long)((!WALLS && j == 0) ? ny : j) * nx + i;
-  // face length over cell area: 1/dx and 1/dy (1 on unit cells)
   T ax = T(1), ay = T(1);
   if (MESH) {
-    ax = T(1.0 / mesh_axis(C.mesh, nx, ny, 0).w[i]);
-    ay = T(1.0 / mesh_axis(C.mesh, nx, ny, 1).w[j]);
+    ax = T(1.0 / X.w[i]);
+    ay = T(1.0 / Y.w[j]);
   }
   T v[NV];
   load_groups<T, NV>(out, PB, cell, v);
@@ -1802,13 +1840,13 @@ __global__ __launch_bounds__(256) void k_up_update(UpArgs A) {
     const int sx = up_xslot(q), sy = up_yslot(q);
     if (MESH) {
       T Jx = T(0), Jy = T(0);
-      if (EX[q] != 0) Jx = T(EX[q]) * (XF[(off + sx) * N + ce] - XF[(off + sx) * N + cw]);
-      if (EY[q] != 0) Jy = T(EY[q]) * (YF[(off + sy) * N1 + fn] - YF[(off + sy) * N1 + fs]);
+      if (EX[q] != 0) Jx = T(EX[q]) * (FX[fxi(off + sx, wv, lane + 1)] - FX[fxi(off + sx, wv, lane)]);
+      if (EY[q] != 0) Jy = T(EY[q]) * (FY[fyi(off + sy, wv + 1, lane)] - FY[fyi(off + sy, wv, lane)]);
       return ax * Jx + ay * Jy;
     }
     T J = T(0);
-    if (EX[q] != 0) J += T(EX[q]) * (XF[(off + sx) * N + ce] - XF[(off + sx) * N + cw]);
-    if (EY[q] != 0) J += T(EY[q]) * (YF[(off + sy) * N1 + fn] - YF[(off + sy) * N1 + fs]);
+    if (EX[q] != 0) J += T(EX[q]) * (FX[fxi(off + sx, wv, lane + 1)] - FX[fxi(off + sx, wv, lane)]);
+    if (EY[q] != 0) J += T(EY[q]) * (FY[fyi(off + sy, wv + 1, lane)] - FY[fyi(off + sy, wv, lane)]);
     return J;
   };
 #pragma unroll
@@ -1864,11 +1902,10 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
   if (!upwind && !mesh) return hipErrorInvalidValue;  // the march covers that case
   const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + kUpRows - 1) / kUpRows);
   dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * kUpRows);
-#define UP_LAUNCH(T, CPL, W, M, CEN)                                        \
-  do {                                                                      \
-    hipLaunchKernelGGL((k_up_stage<T, CPL, W, M>), grid, block, 0, s, a);   \
-    hipLaunchKernelGGL((k_up_faces<T, CPL, W, M, CEN>), grid, block, 0, s, a); \
-    hipLaunchKernelGGL((k_up_update<T, CPL, W, M>), grid, block, 0, s, a);  \
+#define UP_LAUNCH(T, CPL, W, M, CEN)                                                \
+  do {                                                                              \
+    hipLaunchKernelGGL((k_up_stage<T, CPL, W, M>), grid, block, 0, s, a);           \
+    hipLaunchKernelGGL((k_up_faces_update<T, CPL, W, M, CEN>), grid, block, 0, s, a); \
   } while (0)
 #define UP_MODES(T, CPL, W)                                  \
   do {                                                       \
