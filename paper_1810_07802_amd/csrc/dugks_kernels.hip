@@ -1247,16 +1247,32 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
   if (orho) orho[c] = rhoD;
 }
 
-// Diagnostics in double, in a fixed order: per-block partial sums over rows,
-// then one block folds the partials. out: sum phi, sum rho u, sum rho v,
-// sum rho |u|^2 / 2, max |u|, sum rho, #non-finite.
+// Diagnostics in double, in a fixed order: per-block partial sums (wavefront
+// butterflies, then the block's waves), then one block folds the partials.
+// out: sum phi, sum rho u, sum rho v, sum rho |u|^2 / 2, max |u|, sum rho,
+// #non-finite.
 constexpr int kDiagThreads = 256;
 constexpr int kDiagQ = 7;
+
+// Sum and maximum over the 64 lanes of a wave by a fixed butterfly of lane
+// exchanges (every lane ends with the result; the order, and so the rounding,
+// is the same on every run).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int m = kWave / 2; m > 0; m >>= 1) x += __shfl_xor(x, m, kWave);
+  return x;
+}
+__device__ __forceinline__ double wave_max(double x) {
+#pragma unroll
+  for (int m = kWave / 2; m > 0; m >>= 1) x = fmax(x, __shfl_xor(x, m, kWave));
+  return x;
+}
 
 __global__ void k_diag_partial(int nx, int ny, const double* __restrict__ phi,
                                const double* __restrict__ u, const double* __restrict__ v,
                                const double* __restrict__ rho, double* __restrict__ part) {
-  __shared__ double sh[kDiagQ][kDiagThreads];
+  constexpr int kWaves = kDiagThreads / kWave;
+  __shared__ double sh[kDiagQ][kWaves];
   double a[kDiagQ] = {0, 0, 0, 0, 0, 0, 0};
   const long long n = (long long)nx * ny;
   for (long long c = (long long)blockIdx.x * kDiagThreads + threadIdx.x; c < n;
@@ -1271,20 +1287,20 @@ __global__ void k_diag_partial(int nx, int ny, const double* __restrict__ phi,
     const bool bad = !isfinite(ph) || !isfinite(uu) || !isfinite(vv) || !isfinite(r);
     a[6] += bad ? 1.0 : 0.0;
   }
+  // wavefront reductions, then the waves' results through LDS
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
 #pragma unroll
-  for (int k = 0; k < kDiagQ; ++k) sh[k][threadIdx.x] = a[k];
-  __syncthreads();
-  for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-#pragma unroll
-      for (int k = 0; k < kDiagQ; ++k) {
-        if (k == 4) sh[k][threadIdx.x] = fmax(sh[k][threadIdx.x], sh[k][threadIdx.x + s]);
-        else sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
-      }
-    }
-    __syncthreads();
+  for (int k = 0; k < kDiagQ; ++k) {
+    const double r = k == 4 ? wave_max(a[k]) : wave_sum(a[k]);
+    if (lane == 0) sh[k][w] = r;
   }
-  if (threadIdx.x < kDiagQ) part[(long long)blockIdx.x * kDiagQ + threadIdx.x] = sh[threadIdx.x][0];
+  __syncthreads();
+  if (threadIdx.x < kDiagQ) {
+    const int k = threadIdx.x;
+    double r = sh[k][0];
+    for (int x = 1; x < kWaves; ++x) r = k == 4 ? fmax(r, sh[k][x]) : r + sh[k][x];
+    part[(long long)blockIdx.x * kDiagQ + k] = r;
+  }
 }
 
 __global__ void k_diag_final(int nblocks, const double* __restrict__ part, double* __restrict__ out) {

@@ -221,4 +221,8 @@ def test_diagnostics_match_oracle_sums():
     assert abs(d["sum_rho_u"] - (r["rho"] * r["u"]).sum()) < 1e-12 * scale_u
     assert d["sum_rho"] == pytest.approx(r["rho"].sum(), rel=1e-12)
     assert d["max_u"] == pytest.approx(np.hypot(r["u"], r["v"]).max(), rel=1e-10)
+    ke = (0.5 * r["rho"] * (r["u"] ** 2 + r["v"] ** 2)).sum()
+    assert d["kinetic"] == pytest.approx(ke, rel=1e-12)
     assert d["time"] == pytest.approx(100 * c["params"]["cfl"])
+    # the wavefront and block reductions have a fixed order: same bits again
+    assert s.diagnostics() == d
