@@ -21,6 +21,11 @@
 // Working precision T is float or double. In the float path the density,
 // its reciprocal and the relaxation time of g (interpolated across the
 // interface) are evaluated in double and narrowed.
+//
+// The upwind, limited reconstruction and stretched tensor-product meshes run
+// as a second, two-kernel step (k_up_stage, k_up_faces_update; see the
+// section "two-kernel step" below), which shares the cell-stage, face and
+// wall-face arithmetic with the march.
 
 #include <hip/hip_runtime.h>
 
