@@ -11,7 +11,9 @@ The same JSON line carries:
   roofline      HBM roofline of the step kernel at this workload (algorithmic
                 bytes: 160 B per cell and step in FP32)
   large_grid    the same physics on 4096 x 4096 (R = 1024), where the working
-                set (2.8 GB) is far larger than the 256 MB Infinity Cache
+                set (2.8 GB) is far larger than the 256 MB Infinity Cache, with
+                the bandwidth a plain 16-byte copy of the same bytes reaches
+                (copy_ceiling) and the step's fraction of it
   batched       the spinodal batch (64 cases of 64^2..512^2): one graph of
                 batched launches vs one launch per case per step
   served        the served request stream through the continuous-batching
@@ -71,6 +73,30 @@ def parse():
                     help="run only a plain 1 GiB device-to-device copy (calibrates the "
                          "HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_ceiling(torch, D, nbytes, reps=10):
+    """HBM bandwidth of the library's plain copy (one 16-byte load and store per
+    work item) over `nbytes` read and `nbytes` written, timed with HIP events on
+    the stream it runs on: what a streaming kernel reaches on this device."""
+    n = max(4, nbytes // 16 * 4)  # float32 elements, a multiple of 16 bytes
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    nb = 4 * n
+    for _ in range(3):
+        D.copy_probe(dst.data_ptr(), src.data_ptr(), nb, stream.cuda_stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        D.copy_probe(dst.data_ptr(), src.data_ptr(), nb, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    return {"GBps": round(2 * nb / t / 1e9, 1), "bytes_read": nb, "bytes_written": nb,
+            "us": round(t * 1e6, 1)}
 
 
 def timed_graph(torch, D, solvers, steps, warmup, chunk=1000, autotune=False):
@@ -368,6 +394,11 @@ def main():
                              "auto_seg_rows": auto_seg,
                              "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}
         del sl
+        # the same bytes per launch through a plain copy: the practical ceiling
+        cc_ = copy_ceiling(torch, D, int(B_PER_CELL["fp32"] / 2 * ncl))
+        lg = rec["large_grid"]
+        lg["copy_ceiling"] = cc_
+        lg["frac_of_copy"] = round(lg["roofline"]["achieved"] / cc_["GBps"], 4)
         # batched spinodal workload vs the per-case loop
         cases = W.spinodal_batch(steps=0)
         solvers = []

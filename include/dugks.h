@@ -116,8 +116,7 @@ typedef struct dugks_handle dugks_handle;
  * (DUGKS_MODEL_*) in `precision` (DUGKS_FP32: distributions and arithmetic in
  * float, density and relaxation-time interpolation in double; DUGKS_FP64: all
  * double). Allocates the two state buffers on the current HIP device.
- * nx * ny may not exceed 2^32 / (4 * value bytes): 2^28 cells in FP32, 2^27
- * in FP64 (the step kernel uses 32-bit byte offsets within a group plane).
+ * nx * ny may not exceed 2^28 cells in FP32, 2^27 in FP64.
  * Errors: EINVAL (sizes, enums), ENOMEM, EDEVICE. *out is NULL on error. */
 int dugks_create(int nx, int ny, int precision, int model, dugks_handle **out);
 
@@ -213,10 +212,11 @@ double dugks_time(const dugks_handle *h);
 /* Checkpoint/resume: the state is the tilde distributions, the history
  * (phi u)^(n-1), the phi plane and the step counter. dugks_state_bytes()
  * gives the size of the host buffer; get/set copy it (synchronous). Layout
- * (values of the handle's precision, n = nx * ny cells, cell c = y nx + x):
- * the values f0..f8, [g0..g8], hist_x, hist_y in groups of four consecutive
- * values, each group cell-interleaved ([n][4]; a last partial group of w
- * values is [n][w]), then phi [n]. */
+ * (values of the handle's precision): ny rows, row y first; each row holds
+ * the values f0..f8, [g0..g8], hist_x, hist_y of its nx cells in groups of
+ * four consecutive values, each group cell-interleaved ([nx][4]; a last
+ * partial group of w values is [nx][w]), then phi [nx], and is padded to a
+ * multiple of 128 bytes. */
 size_t dugks_state_bytes(const dugks_handle *h);
 int dugks_get_state(dugks_handle *h, void *host_buf, size_t bytes,
                     long long *steps);
@@ -239,6 +239,16 @@ int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
  * upwind reconstruction and stretched meshes add the two-kernel scratch
  * (see recon) and, for a mesh, 32 (nx + ny) bytes of metrics. */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
+
+/* Bandwidth probe, a measurement aid beside the method (the step's HBM
+ * roofline is quoted against what a plain streaming copy reaches on the
+ * device): copies `bytes` from device buffer src to device buffer dst, one
+ * 16-byte load and store per work item, asynchronously on `stream` (a
+ * hipStream_t; NULL is the default stream). Both pointers must be 16-byte
+ * aligned, non-overlapping and hold `bytes` (> 0, a multiple of 16); the
+ * caller owns both. DUGKS_EINVAL otherwise, DUGKS_EDEVICE if the launch
+ * fails; the message is dugks_last_error(NULL). */
+int dugks_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
 
 /* Message of the last error on h (or of the last failed create when h is
  * NULL). Never NULL. */

@@ -124,6 +124,7 @@ def lib():
             "dugks_get_state": (i, [vp, vp, sz, C.POINTER(ll)]),
             "dugks_set_state": (i, [vp, vp, sz, ll]),
             "dugks_footprint_bytes": (sz, [i, i, i, i]),
+            "dugks_copy_probe": (i, [vp, vp, sz, vp]),
             "dugks_last_error": (C.c_char_p, [vp]),
             "dugks_destroy": (i, [vp]),
             "dugks_batch_create": (i, [i, C.POINTER(vp), C.POINTER(vp)]),
@@ -229,6 +230,14 @@ def get_diagnostics(h):
 
 def footprint_bytes(nx, ny, precision=FP32, model=MODEL_COUPLED):
     return int(lib().dugks_footprint_bytes(int(nx), int(ny), int(precision), int(model)))
+
+
+def copy_probe(dst_ptr, src_ptr, nbytes, stream=None):
+    """Plain 16-byte device copy of `nbytes` from src_ptr to dst_ptr (device
+    addresses) on `stream`: the bandwidth probe that the step's HBM roofline is
+    compared with."""
+    _check(lib().dugks_copy_probe(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), C.c_size_t(nbytes),
+                                  C.c_void_p(stream)))
 
 
 def destroy(h):

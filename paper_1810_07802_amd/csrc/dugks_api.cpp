@@ -100,6 +100,7 @@ void fill_case(dugks_handle* h) {
   C.visc_mode = P.visc_mode;
   C.grav_form = P.gravity_form == DUGKS_GRAV_BUOYANCY ? 1 : 0;
   C.plane = (long long)h->n();
+  C.row_vals = dugks::state_row_values(h->nx, h->coupled(), (int)h->elem());
   C.set[0] = h->buf[0];
   C.set[1] = h->buf[1];
   // Eq. 37 with sqrt(3RT) = 1 and delta_l the smallest cell width (1 on
@@ -247,8 +248,8 @@ int validate(const dugks_handle* h, const dugks_params* p, std::string& why) {
 }
 
 size_t state_set_bytes(int nx, int ny, int precision, int model) {
-  const size_t e = precision == DUGKS_FP64 ? 8 : 4;
-  return (size_t)dugks::num_values(model == DUGKS_MODEL_COUPLED) * (size_t)nx * ny * e;
+  const int e = precision == DUGKS_FP64 ? 8 : 4;
+  return (size_t)dugks::state_row_values(nx, model == DUGKS_MODEL_COUPLED, e) * (size_t)ny * e;
 }
 
 int ensure_scratch(dugks_handle* h) {
@@ -309,10 +310,9 @@ int dugks_create(int nx, int ny, int precision, int model, dugks_handle** out) {
   if (nx < 3 || ny < 3) return fail(nullptr, DUGKS_EINVAL, "nx and ny must be >= 3");
   if (precision != DUGKS_FP32 && precision != DUGKS_FP64)
     return fail(nullptr, DUGKS_EINVAL, "bad precision");
-  // the step kernel addresses a group of four values of a cell with a 32-bit
-  // byte offset: 4 * sizeof(value) * cells must stay within 2^32
+  // size limit of the C ABI: 2^28 cells in FP32, 2^27 in FP64
   if ((long long)nx * ny > (1LL << 32) / (4 * (precision == DUGKS_FP64 ? 8 : 4)))
-    return fail(nullptr, DUGKS_EINVAL, "grid too large (cells > 2^32 / (4 * value bytes))");
+    return fail(nullptr, DUGKS_EINVAL, "grid too large (cells > 2^28 in FP32, 2^27 in FP64)");
   if (model != DUGKS_MODEL_AC && model != DUGKS_MODEL_COUPLED)
     return fail(nullptr, DUGKS_EINVAL, "bad model");
   dugks_handle* h = new (std::nothrow) dugks_handle;
@@ -324,6 +324,10 @@ int dugks_create(int nx, int ny, int precision, int model, dugks_handle** out) {
   h->buf_bytes = state_set_bytes(nx, ny, precision, model);
   hipError_t e = hipSuccess;
   for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMalloc(&h->buf[k], h->buf_bytes);
+  // zero both buffers once, so that the row padding (never written by the
+  // kernels) reads the same in either buffer and the saved state is a pure
+  // function of the step
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipMemset(h->buf[k], 0, h->buf_bytes);
   if (e == hipSuccess) e = hipMalloc(&h->dc, sizeof(CaseDev));
   if (e == hipSuccess) e = hipMalloc(&h->step_base, sizeof(long long));
   if (e == hipSuccess) e = hipMemset(h->step_base, 0, sizeof(long long));
@@ -621,6 +625,20 @@ int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* 
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model) {
   if (nx < 1 || ny < 1) return 0;
   return 2 * state_set_bytes(nx, ny, precision, model) + sizeof(CaseDev) + 64;
+}
+
+int dugks_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes == 0 || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) & 15) ||
+      (reinterpret_cast<uintptr_t>(src) & 15))
+    return fail(nullptr, DUGKS_EINVAL, "copy probe: NULL, unaligned or not a multiple of 16 bytes");
+  const char* a = static_cast<const char*>(src);
+  const char* b = static_cast<const char*>(dst);
+  if (a < b + bytes && b < a + bytes) return fail(nullptr, DUGKS_EINVAL, "copy probe: buffers overlap");
+  const hipError_t e = dugks::launch_copy16(dst, src, (long long)(bytes / 16),
+                                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess)
+    return fail(nullptr, DUGKS_EDEVICE, std::string("copy probe: ") + hipGetErrorString(e));
+  return DUGKS_OK;
 }
 
 const char* dugks_last_error(const dugks_handle* h) {

@@ -23,19 +23,29 @@ __host__ __device__ constexpr int num_values(bool coupled) { return coupled ? 21
 // Values stored in groups (all but phi).
 __host__ __device__ constexpr int num_grouped(bool coupled) { return num_values(coupled) - 1; }
 
-// Layout of one state buffer of n cells. The grouped values are split into
-// groups of four consecutive values; each group is stored cell-interleaved
-// ([n][4], so that one 16-byte access per cell moves a group; a last partial
-// group of w values is [n][w]). The phi plane [n] follows. A group occupies
-// 4 n values, so group g starts at 4 g n and the phi plane at num_grouped n.
-__host__ __device__ constexpr long long value_index(int v, long long c, long long n,
+// Layout of one state buffer, row-blocked: grid row j holds, one after the
+// other, the grouped values of its nx cells and then their phi. The grouped
+// values are split into groups of four consecutive values, each stored
+// cell-interleaved ([nx][4], so that one 16-byte access per cell moves a
+// group; a last partial group of w values is [nx][w]): group g starts 4 g nx
+// values into the row and phi num_grouped nx values into it. Rows are padded
+// to a multiple of 128 bytes. A wave that reads or writes one row of a strip
+// touches one contiguous block of the buffer rather than one block per value
+// plane, which streams faster from HBM.
+__host__ __device__ constexpr long long state_row_values(int nx, bool coupled, int elem_bytes) {
+  return ((long long)num_values(coupled) * nx * elem_bytes + 127) / 128 * 128 / elem_bytes;
+}
+// Index (in values) of value v of cell (i, j); rv = state_row_values().
+__host__ __device__ constexpr long long state_index(int v, int i, int j, int nx, long long rv,
                                                     bool coupled) {
-  return v == num_grouped(coupled)
-             ? (long long)num_grouped(coupled) * n + c
-             : 4LL * (v >> 2) * n +
-                   c * (num_grouped(coupled) - 4 * (v >> 2) < 4 ? num_grouped(coupled) - 4 * (v >> 2)
-                                                                 : 4) +
-                   (v & 3);
+  return (long long)j * rv +
+         (v == num_grouped(coupled)
+              ? (long long)num_grouped(coupled) * nx + i
+              : 4LL * (v >> 2) * nx +
+                    (long long)i * (num_grouped(coupled) - 4 * (v >> 2) < 4
+                                        ? num_grouped(coupled) - 4 * (v >> 2)
+                                        : 4) +
+                    (v & 3));
 }
 
 // Everything a kernel needs about one case. Lives in device memory (an array
@@ -53,7 +63,8 @@ struct CaseDev {
   int cur0;              // state buffer holding local step 0
   long long step0;       // global step index of local step 0
   long long nsteps;      // local steps allowed (active window)
-  long long plane;       // cells (values per plane)
+  long long plane;       // cells (nx ny): values per plane of the scratch buffers
+  long long row_vals;    // values per row of a state buffer (state_row_values())
   void* set[2];          // the two state buffers
   // time
   double dt, h, t0;
@@ -141,6 +152,8 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
 int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);
+// plain copy of n16 16-byte words (bandwidth probe)
+hipError_t launch_copy16(void* dst, const void* src, long long n16, hipStream_t s);
 hipError_t launch_init(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
                        const double* phi, const double* u, const double* v,
                        const double* p, hipStream_t s);

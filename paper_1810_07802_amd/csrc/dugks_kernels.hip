@@ -497,22 +497,36 @@ template <typename T>
 __device__ __forceinline__ T gload(const char* base, unsigned off) {
   return *(const typename GMem<T>::type*)((const gchar*)base + off);
 }
+// A per-lane byte offset re-defined where it is used (an empty asm statement):
+// see load_groups() for why loop-invariant offsets need it.
+__device__ __forceinline__ unsigned lane_off(unsigned off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
 template <typename T>
 __device__ __forceinline__ void gstore(char* base, unsigned off, T v) {
   *(typename GMem<T>::type*)((gchar*)base + off) = v;
 }
 
-// The grouped values of one cell (all but phi; layout in value_index()):
+// The grouped values of one cell (all but phi; layout in state_index()):
 // one 4-wide vector access per full group, scalar accesses for a last
-// partial group. `c` is the cell, PB the bytes of one plane (n values).
+// partial group. `base` is the start of the cell's row (uniform over the
+// wave), `c` its column and PB the bytes of one value across the row (nx
+// values). In a march (OPQ) the per-lane byte offset goes through lane_off():
+// the column offset is the same for every row, and hoisted out of the loop as
+// a 64-bit value it would no longer match the saddr form (scalar base plus
+// 32-bit vector offset); each access would then build a 64-bit address in
+// vector registers. Elsewhere the plain offset keeps the scheduler free (the
+// asm statement bounds its regions).
 template <typename T>
 using Vec4 = T __attribute__((ext_vector_type(4)));
-template <typename T, int NV>
+template <typename T, int NV, bool OPQ = false>
 __device__ __forceinline__ void load_groups(const char* base, long long PB, unsigned c,
                                             T (&v)[NV]) {
+  const unsigned co = OPQ ? lane_off(c * (4u * sizeof(T))) : c * (4u * sizeof(T));
 #pragma unroll
   for (int g = 0; g < NV / 4; ++g) {
-    const Vec4<T> x = gload<Vec4<T>>(base + 4 * g * PB, c * (4u * sizeof(T)));
+    const Vec4<T> x = gload<Vec4<T>>(base + 4 * g * PB, co);
     v[4 * g] = x.x; v[4 * g + 1] = x.y; v[4 * g + 2] = x.z; v[4 * g + 3] = x.w;
   }
   constexpr int w = NV % 4;
@@ -520,14 +534,15 @@ __device__ __forceinline__ void load_groups(const char* base, long long PB, unsi
   for (int k = 0; k < w; ++k)
     v[NV - w + k] = gload<T>(base + (NV - w) * PB, (c * w + k) * (unsigned)sizeof(T));
 }
-template <typename T, int NV>
+template <typename T, int NV, bool OPQ = false>
 __device__ __forceinline__ void store_groups(char* base, long long PB, unsigned c,
                                              const T (&v)[NV]) {
+  const unsigned co = OPQ ? lane_off(c * (4u * sizeof(T))) : c * (4u * sizeof(T));
 #pragma unroll
   for (int g = 0; g < NV / 4; ++g) {
     Vec4<T> x;
     x.x = v[4 * g]; x.y = v[4 * g + 1]; x.z = v[4 * g + 2]; x.w = v[4 * g + 3];
-    gstore<Vec4<T>>(base + 4 * g * PB, c * (4u * sizeof(T)), x);
+    gstore<Vec4<T>>(base + 4 * g * PB, co, x);
   }
   constexpr int w = NV % 4;
 #pragma unroll
@@ -541,6 +556,20 @@ __device__ __forceinline__ int row_idx(int r, int ny, int walls) {
   if (r < 0) return walls ? -1 - r : r + ny;
   if (r >= ny) return walls ? 2 * ny - 1 - r : r - ny;
   return r;
+}
+
+// Start of grid row `row` of a state buffer (RB bytes per row). The row must
+// be the same on every lane of the wave: taking it from the first active lane
+// tells the compiler so, which keeps the row address in scalar registers and
+// the per-lane column offset in one 32-bit register (the saddr form of the
+// global accesses).
+template <typename P>
+__device__ __forceinline__ P* row_ptr(P* base, int row, long long RB) {
+  const unsigned long long a =
+      reinterpret_cast<uintptr_t>(base) + (unsigned long long)((long long)row * RB);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
 }
 
 template <typename T, bool CPL>
@@ -696,9 +725,10 @@ __device__ __forceinline__ void row_xface(const CaseDev& C, int k, int ny, int c
 // Update of output row k (Eq. 24) and its stores. cur.fnf/fng hold the face
 // above the row, prv.fnf/fng the face below, fx the x-faces east of each
 // cell (the west face is the left lane's), tp(q) the tilde-plus values.
-template <typename T, bool CPL, typename TP>
+template <typename T, bool CPL, bool OPQ, typename TP>
 __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int nx, int walls,
-                                           int ci, bool store, char* out, long long PB,
+                                           int ci, bool store, char* out, long long RB,
+                                           long long PB,
                                            const RowData<T, CPL>& prv, const RowData<T, CPL>& cur_r,
                                            const T (&fx_f)[9], const T (&fx_g)[9], TP tp) {
   constexpr int NV = num_grouped(CPL);
@@ -707,8 +737,7 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
   const T(&fn_g)[9] = cur_r.fng;
   const T(&fs_f)[9] = prv.fnf;
   const T(&fs_g)[9] = prv.fng;
-  const int kr = row_idx(k, ny, walls);
-  const unsigned cell = (unsigned)kr * (unsigned)nx + ci;
+  char* orow = row_ptr(out, row_idx(k, ny, walls), RB);
   const T dt = T(C.dt);
   T nv[NV];  // new tilde f, tilde g, history
   T phin = T(0);
@@ -733,8 +762,8 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
   nv[val_hist(CPL, 1)] = cur_r.cell.hy;
   // one masked region for all stores of the row
   if (store) {
-    store_groups<T, NV>(out, PB, cell, nv);
-    gstore<T>(out + NV * PB, cell * es, phin);
+    store_groups<T, NV, OPQ>(orow, PB, (unsigned)ci, nv);
+    gstore<T>(orow + NV * PB, OPQ ? lane_off((unsigned)ci * es) : (unsigned)ci * es, phin);
   }
 }
 
@@ -764,9 +793,9 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const long long PB = C.plane * (long long)sizeof(T);  // bytes per plane
+  const long long RB = C.row_vals * (long long)sizeof(T);  // bytes per grid row
+  const long long PB = (long long)nx * sizeof(T);            // bytes of one value across a row
   constexpr int NV = num_grouped(CPL);
-  const char* phiP = in + NV * PB;
   const unsigned es = sizeof(T);
   const double tn = C.t0 + (double)n * C.dt;
   const double xc = (double)ci + 0.5;  // wrapped: halo lanes see their true cell
@@ -785,7 +814,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   };
   auto fetch = [&](int r, Raw& R) {
     T v[NV];
-    load_groups<T, NV>(in, PB, (unsigned)row_idx(r, ny, walls) * (unsigned)nx + ci, v);
+    load_groups<T, NV, true>(row_ptr(in, row_idx(r, ny, walls), RB), PB, (unsigned)ci, v);
 #pragma unroll
     for (int q = 0; q < 9; ++q) R.f[q] = v[val_f(q)];
     if (CPL) {
@@ -794,9 +823,9 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     }
     R.hx = v[val_hist(CPL, 0)];
     R.hy = v[val_hist(CPL, 1)];
-    const unsigned rb = (unsigned)row_idx(r + 1, ny, walls) * (unsigned)nx;
-    R.po = gload<T>(phiP, (rb + ci) * es);
-    R.pe = gload<T>(phiP, (rb + cx) * es);
+    const char* prow = row_ptr(in, row_idx(r + 1, ny, walls), RB) + NV * PB;
+    R.po = gload<T>(prow, lane_off((unsigned)ci * es));
+    R.pe = gload<T>(prow, lane_off((unsigned)cx * es));
   };
   // phi of one row for (left, own, right) columns from own and extra values
   auto phi_lr = [&](T own, T ext, T (&o)[3]) {
@@ -806,8 +835,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     o[0] = left; o[1] = own; o[2] = right;
   };
   auto phi_row = [&](int r, T (&o)[3]) {
-    const unsigned rb = (unsigned)row_idx(r, ny, walls) * (unsigned)nx;
-    phi_lr(gload<T>(phiP, (rb + ci) * es), gload<T>(phiP, (rb + cx) * es), o);
+    const char* prow = row_ptr(in, row_idx(r, ny, walls), RB) + NV * PB;
+    phi_lr(gload<T>(prow, lane_off((unsigned)ci * es)), gload<T>(prow, lane_off((unsigned)cx * es)), o);
   };
   auto stage = [&](int r, const Raw& R, const T (&pm)[3], const T (&p0)[3], const T (&pp)[3],
                    RowData<T, CPL>& rd) {
@@ -847,7 +876,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     T fx_f[9], fx_g[9];
     row_xface<T, CPL, WALLS>(C, k, ny, ci, tn, prv, cur_r, nxt, fx_f, fx_g);
     const int slot = k & 1;
-    row_update<T, CPL>(C, k, ny, nx, walls, ci, store, out, PB, prv, cur_r, fx_f, fx_g,
+    row_update<T, CPL, true>(C, k, ny, nx, walls, ci, store, out, RB, PB, prv, cur_r, fx_f, fx_g,
                        [&](int q) { return stash[slot][q][lane]; });
   };
 
@@ -934,7 +963,7 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;  // uniform over the work group
 
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform over the wave
   const int lane = threadIdx.x & 63;
   const int nx = C.nx, ny = C.ny;
   constexpr int walls = WALLS ? 1 : 0;
@@ -946,9 +975,9 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const long long PB = C.plane * (long long)sizeof(T);
+  const long long RB = C.row_vals * (long long)sizeof(T);  // bytes per grid row
+  const long long PB = (long long)nx * sizeof(T);            // bytes of one value across a row
   constexpr int NV = num_grouped(CPL);
-  const char* phiP = in + NV * PB;
   const unsigned es = sizeof(T);
   const double tn = C.t0 + (double)n * C.dt;
   const double xc = (double)ci + 0.5;
@@ -964,7 +993,7 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
   RowData<T, CPL> rd;
   if (exists) {
     T v[NV];
-    load_groups<T, NV>(in, PB, (unsigned)row_idx(r, ny, walls) * (unsigned)nx + ci, v);
+    load_groups<T, NV>(row_ptr(in, row_idx(r, ny, walls), RB), PB, (unsigned)ci, v);
     T f[9], g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -974,8 +1003,8 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
     T ph[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const unsigned rb = (unsigned)row_idx(r - 1 + a, ny, walls) * (unsigned)nx;
-      const T own = gload<T>(phiP, (rb + ci) * es), ext = gload<T>(phiP, (rb + cx) * es);
+      const char* prow = row_ptr(in, row_idx(r - 1 + a, ny, walls), RB) + NV * PB;
+      const T own = gload<T>(prow, (unsigned)ci * es), ext = gload<T>(prow, (unsigned)cx * es);
       T left = nbr_l(own), right = nbr_r(own);
       if (lane == 0) left = ext;
       if (lane == 63) right = ext;
@@ -1049,9 +1078,17 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
         if (CPL) prv.fng[q] = below[9 + q][lane];
       }
     }
-    row_update<T, CPL>(C, j, ny, nx, walls, ci, store, out, PB, prv, rd, fx_f, fx_g,
+    row_update<T, CPL, false>(C, j, ny, nx, walls, ci, store, out, RB, PB, prv, rd, fx_f, fx_g,
                        [&](int q) { return tplus[q][lane]; });
   }
+}
+
+// Plain device copy, one work item per 16 bytes: the bandwidth a streaming
+// kernel reaches on the device, the practical ceiling of the step's traffic.
+__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
+                                                uint4* __restrict__ dst, long long n16) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n16) dst[i] = src[i];
 }
 
 __global__ void k_advance(long long* step_base, long long by) {
@@ -1125,13 +1162,13 @@ __device__ __forceinline__ void cell_centre(const CaseDev& C, int i, int j, doub
 }
 
 template <typename S, typename T>
-__device__ __forceinline__ void gather3x3(const S* __restrict__ f, int i, int j, int nx,
-                                          int ny, int walls, T (&ph)[3][3]) {
+__device__ __forceinline__ void gather3x3(const S* __restrict__ f, long long rs, int i, int j,
+                                          int nx, int ny, int walls, T (&ph)[3][3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const int r = row_of(j + a - 1, ny, walls);
 #pragma unroll
-    for (int b = 0; b < 3; ++b) ph[a][b] = T(f[(long long)r * nx + wrap(i + b - 1, nx)]);
+    for (int b = 0; b < 3; ++b) ph[a][b] = T(f[(long long)r * rs + wrap(i + b - 1, nx)]);
   }
 }
 
@@ -1145,10 +1182,11 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= C.nx || j >= C.ny) return;
-  const long long c = (long long)j * C.nx + i, P = C.plane;
+  const long long c = (long long)j * C.nx + i, rv = C.row_vals;
   T* __restrict__ st = static_cast<T*>(C.set[buf]);
+  auto at = [&](int v) -> T& { return st[state_index(v, i, j, C.nx, rv, CPL)]; };
   T ph[3][3];
-  gather3x3<double, T>(phi0, i, j, C.nx, C.ny, C.walls, ph);
+  gather3x3<double, T>(phi0, C.nx, i, j, C.nx, C.ny, C.walls, ph);
   T gx, gy, lap;
   cell_stencils<T>(C, ph, i, j, gx, gy, lap);
   const T phi = ph[1][1];
@@ -1180,7 +1218,7 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
       const T Sg = wq<T>(q) * ((aq - a0) * Gh + T(3) * (bq - b0) * (T(1) + Gh));
       T geq = wq<T>(q) * (T(3) * p + rho * Gh);
       if (q == 0) geq -= T(3) * p;
-      st[value_index(val_g(q), c, P, CPL)] = geq - hdt * Sg;
+      at(val_g(q)) = geq - hdt * Sg;
     }
   } else {
     double xc, yc;
@@ -1192,15 +1230,15 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
     const T en = T(EX[q]) * nxv + T(EY[q]) * nyv;
     const T feq = wq<T>(q) * phi * (T(1) + T(3) * (T(EX[q]) * u + T(EY[q]) * v));
     const T Sf = wq<T>(q) * theta * en;
-    st[value_index(val_f(q), c, P, CPL)] = feq - hdt * Sf;
+    at(val_f(q)) = feq - hdt * Sf;
   }
-  st[value_index(val_hist(CPL, 0), c, P, CPL)] = phi * u;
-  st[value_index(val_hist(CPL, 1), c, P, CPL)] = phi * v;
+  at(val_hist(CPL, 0)) = phi * u;
+  at(val_hist(CPL, 1)) = phi * v;
   // phi plane = sum of the stored f (the same sum the step kernel forms)
   T s = T(0);
 #pragma unroll
-  for (int q = 0; q < 9; ++q) s += st[value_index(val_f(q), c, P, CPL)];
-  st[value_index(val_phi(CPL), c, P, CPL)] = s;
+  for (int q = 0; q < 9; ++q) s += at(val_f(q));
+  at(val_phi(CPL)) = s;
 }
 
 // Cell macros of a state (Eqs. 31-33, 10) into double arrays.
@@ -1213,10 +1251,11 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (i >= C.nx || j >= C.ny) return;
-  const long long c = (long long)j * C.nx + i, P = C.plane;
+  const long long c = (long long)j * C.nx + i, rv = C.row_vals;
   const T* __restrict__ st = static_cast<const T*>(C.set[buf]);
   T ph[3][3];
-  gather3x3<T, T>(st + value_index(val_phi(CPL), 0, P, CPL), i, j, C.nx, C.ny, C.walls, ph);
+  gather3x3<T, T>(st + state_index(val_phi(CPL), 0, 0, C.nx, rv, CPL), rv, i, j, C.nx, C.ny,
+                  C.walls, ph);
   const T phi = ph[1][1];
   const double rhoD = rho_of(C, (double)phi);
   T u, v, p = T(0);
@@ -1231,7 +1270,7 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
     const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
     T g[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) g[q] = st[value_index(val_g(q), c, P, CPL)];
+    for (int q = 0; q < 9; ++q) g[q] = st[state_index(val_g(q), i, j, C.nx, rv, CPL)];
     const T mx = (g[1] + g[2] + g[8]) - (g[4] + g[5] + g[6]);
     const T my = (g[2] + g[3] + g[4]) - (g[6] + g[7] + g[8]);
     const T m0 = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
@@ -1386,19 +1425,20 @@ __global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const long long N = C.plane, PB = N * (long long)sizeof(T);
+  const long long N = C.plane, rv = C.row_vals;
+  const long long RB = rv * (long long)sizeof(T), PB = (long long)nx * sizeof(T);
   constexpr int NV = num_grouped(CPL);
-  const T* phiP = reinterpret_cast<const T*>(in + NV * PB);
-  const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;
+  const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;  // scratch index
+  // a wave is one row of the block (kUpCols == 64), so j is the same on its lanes
   T ph[3][3];
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const long long rb = (long long)row_idx(j + r - 1, ny, walls) * nx;
+    const T* prow = reinterpret_cast<const T*>(row_ptr(in, row_idx(j + r - 1, ny, walls), RB) + NV * PB);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ph[r][c] = phiP[rb + wrap_near(i + c - 1, nx)];
+    for (int c = 0; c < 3; ++c) ph[r][c] = prow[wrap_near(i + c - 1, nx)];
   }
   T v[NV];
-  load_groups<T, NV>(in, PB, cell, v);
+  load_groups<T, NV>(row_ptr(in, j, RB), PB, (unsigned)i, v);
   T ft[9], gt[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1427,7 +1467,7 @@ __global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
   }
   nv[val_hist(CPL, 0)] = o.hx;
   nv[val_hist(CPL, 1)] = o.hy;
-  store_groups<T, NV>(out, PB, cell, nv);
+  store_groups<T, NV>(row_ptr(out, j, RB), PB, (unsigned)i, nv);
   T* S = static_cast<T*>(A.scratch);
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
@@ -1671,8 +1711,8 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS,
 // face bounce-back, fed from the tile. B is the view of the wall cell.
 template <typename T, bool BOTTOM, bool MESH, int NB>
 __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH, NB>& B,
-                                        const T* in6, long long N, const T* phiP, int i,
-                                        T (&fo)[9], T (&go)[9]) {
+                                        const T* in6, long long N, const T* phiP, long long rv,
+                                        int i, T (&fo)[9], T (&go)[9]) {
   const int nx = B.nx, ny = B.ny;
   const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
   const long long cw = (long long)jw * nx + B.xi(i);
@@ -1693,7 +1733,7 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
       txg[q] = diag ? B.at(9 + q, i + 1, jw) - B.at(9 + q, i - 1, jw) : T(0);
     }
   }
-  c.phi = phiP[cw];
+  c.phi = phiP[(long long)jw * rv + B.xi(i)];
   c.gx = in6[cw];
   c.mu = in6[2 * N + cw];
   c.Dx = in6[3 * N + cw];
@@ -1726,7 +1766,8 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   const int i0 = (idx % nbx) * kUpCols, j0 = (idx / nbx) * kUpRows;
   if (j0 >= ny) return;
   const int lane = threadIdx.x & (kUpCols - 1), wv = threadIdx.x >> 6;
-  const long long N = C.plane, PB = N * (long long)sizeof(T);
+  const long long N = C.plane;
+  const long long RB = C.row_vals * (long long)sizeof(T), PB = (long long)nx * sizeof(T);
   const T* S = static_cast<const T*>(A.scratch);
   constexpr int NB = up_bar_planes(CPL);
   constexpr int NF = CPL ? 12 : 6;  // crossing populations of a face, f then g
@@ -1769,7 +1810,7 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * PB);
+  const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * PB);  // phi of row 0
   const double tf = C.t0 + (double)n * C.dt + C.h;
   MeshAxis X{}, Y{};
   if (MESH) {
@@ -1788,7 +1829,7 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
     up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i, j, i + 1, j, xeast(i), ymid(j), tf,
                                              fx, gx);
     if (WALLS && j == ny - 1) {
-      if constexpr (WALLS) up_wall<T, false, MESH, NB>(C, B, in6, N, phiP, i, fy, gy);
+      if constexpr (WALLS) up_wall<T, false, MESH, NB>(C, B, in6, N, phiP, C.row_vals, i, fy, gy);
     } else {
       up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j, i, j + 1, xmid(i), ynorth(j),
                                                tf, fy, gy);
@@ -1801,7 +1842,7 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
     if (WALLS && j0 == 0) {
       if constexpr (WALLS) {
         const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, 0);
-        up_wall<T, true, MESH, NB>(C, B, in6, N, phiP, i, fe, ge);
+        up_wall<T, true, MESH, NB>(C, B, in6, N, phiP, C.row_vals, i, fe, ge);
       }
     } else {
       const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, j0 - 1);
@@ -1847,14 +1888,14 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   // update (Eq. 24): face length over cell area is 1/dx and 1/dy (1 on unit
   // cells)
   constexpr int NV = num_grouped(CPL);
-  const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;
+  char* orow = row_ptr(out, j, RB);  // one row per wave
   T ax = T(1), ay = T(1);
   if (MESH) {
     ax = T(1.0 / X.w[i]);
     ay = T(1.0 / Y.w[j]);
   }
   T v[NV];
-  load_groups<T, NV>(out, PB, cell, v);
+  load_groups<T, NV>(orow, PB, (unsigned)i, v);
   const T dt = T(C.dt);
   T phin = T(0);
   auto upd = [&](int q, int off) {
@@ -1879,8 +1920,8 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
 #pragma unroll
     for (int q = 0; q < 9; ++q) v[val_g(q)] = v[val_g(q)] - dt * upd(q, 6);
   }
-  store_groups<T, NV>(out, PB, cell, v);
-  gstore<T>(out + NV * PB, cell * (unsigned)sizeof(T), phin);
+  store_groups<T, NV>(orow, PB, (unsigned)i, v);
+  gstore<T>(orow + NV * PB, (unsigned)i * (unsigned)sizeof(T), phin);
 }
 
 }  // namespace
@@ -1962,6 +2003,15 @@ int step_waves_per_cu(bool fp64, bool coupled, bool walls) {
     else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, true, false>, kWave, 0);
   }
   return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+hipError_t launch_copy16(void* dst, const void* src, long long n16, hipStream_t s) {
+  if (n16 <= 0) return hipSuccess;
+  const long long blocks = (n16 + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s,
+                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+  return hipGetLastError();
 }
 
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s) {

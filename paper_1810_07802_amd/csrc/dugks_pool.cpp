@@ -271,7 +271,7 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
   if (nx < 3 || ny < 3) return pfail(p, DUGKS_EINVAL, "nx and ny must be >= 3");
   if ((size_t)nx * ny > p->max_cells) return pfail(p, DUGKS_EINVAL, "case larger than max_cells");
   if ((long long)nx * ny > (1LL << 32) / (4 * (p->fp64() ? 8 : 4)))
-    return pfail(p, DUGKS_EINVAL, "grid too large (cells > 2^32 / (4 * value bytes))");
+    return pfail(p, DUGKS_EINVAL, "grid too large (cells > 2^28 in FP32, 2^27 in FP64)");
   int k = 0;
   while (k < p->max_cases && p->slot[k]) ++k;
   if (k == p->max_cases) return pfail(p, DUGKS_EBUSY, "no free slot");
@@ -293,6 +293,13 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
   h->buf_bytes = state_set_bytes(nx, ny, p->precision, p->model);
   h->buf[0] = p->arena + o;
   h->buf[1] = p->arena + o + half;
+  // the row padding of both buffers reads zero, whatever the arena held
+  if (hipMemsetAsync(p->arena + o, 0, 2 * half, p->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    free_insert(p, o, 2 * half);
+    return pfail(p, DUGKS_EDEVICE, "clearing the slot's state failed");
+  }
   h->dc = p->sdc + k;
   h->step_base = p->scount + k;
   h->scratch = p->staging;

@@ -31,12 +31,19 @@ def test_library_exports_every_declared_function():
 
 
 def test_footprint_matches_layout():
-    # coupled: 21 planes (9 f + 9 g + 2 history + phi) per state buffer, two buffers
-    n = 1000 * 700
+    # coupled: 21 values (9 f + 9 g + 2 history + phi) per cell, AC-only 12;
+    # a state buffer is ny rows of nx cells, each row padded to 128 bytes;
+    # two buffers
+    def row(nx, nv, e):
+        return -(-nx * nv * e // 128) * 128
     fp = D.footprint_bytes(1000, 700, D.FP32, D.MODEL_COUPLED)
-    assert 2 * 21 * n * 4 <= fp < 2 * 21 * n * 4 + 4096
+    assert row(1000, 21, 4) == 84096
+    assert 2 * 700 * row(1000, 21, 4) <= fp < 2 * 700 * row(1000, 21, 4) + 4096
     fp = D.footprint_bytes(1000, 700, D.FP64, D.MODEL_AC)
-    assert 2 * 12 * n * 8 <= fp < 2 * 12 * n * 8 + 4096
+    assert 2 * 700 * row(1000, 12, 8) <= fp < 2 * 700 * row(1000, 12, 8) + 4096
+    # rows of whole cache lines add nothing
+    fp = D.footprint_bytes(4096, 64, D.FP32, D.MODEL_COUPLED)
+    assert 2 * 21 * 4096 * 64 * 4 <= fp < 2 * 21 * 4096 * 64 * 4 + 4096
 
 
 def test_null_and_bad_arguments_do_not_crash():
@@ -51,7 +58,13 @@ def test_null_and_bad_arguments_do_not_crash():
         D.create(16, 16, precision=7)
     assert e.value.code == D.EINVAL
     assert L.dugks_autotune(None, 10, None, None) == D.EINVAL
-    # 32-bit group offsets: at most 2^28 cells in FP32 and 2^27 in FP64
+    # the copy probe checks its arguments before touching the device
+    for dst, src, n in ((0, 0, 16), (0x1000, 0x2000, 15), (0x1008, 0x2000, 16),
+                        (0x1000, 0x1010, 32), (0x1000, 0x2000, 0)):
+        with pytest.raises(D.DugksError) as e:
+            D.copy_probe(dst, src, n)
+        assert e.value.code == D.EINVAL and "copy probe" in str(e.value)
+    # size limit of the C ABI: at most 2^28 cells in FP32 and 2^27 in FP64
     # (rejected before any device allocation)
     for nx, ny, prec in ((1 << 15, 1 << 14, D.FP32), (1 << 14, 1 << 14, D.FP64)):
         with pytest.raises(D.DugksError) as e:

@@ -68,3 +68,18 @@ def test_uniform_state_is_preserved_bitwise(prec, walls):
     before = s.get_state()[0]
     s.step(25)
     assert np.array_equal(s.get_state()[0], before)
+
+
+@pytest.mark.parametrize("nbytes", [16, 16 * 257, 16 * 1000003])
+def test_copy_probe_copies_exactly(nbytes):
+    """The bandwidth probe that the large-grid roofline is compared with: a
+    plain copy, exact to the byte, for one word, a ragged last work group and
+    a large buffer; the bytes past the end stay untouched."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).cuda()
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    D.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes].cpu(), src.cpu())
+    assert int(dst[nbytes:].sum()) == 0
