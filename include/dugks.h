@@ -225,7 +225,7 @@ int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
 
 /* Tile autotuner: times probe_steps (1..1000) steps for each of a few
  * segment lengths (1 and 2 rows, for the lowest latency per step, and for
- * k = 1..8, 12, 16 the shortest segment whose tiles fit k rounds of the
+ * k = 1..8, 12, 16, 20, 24 the shortest segment whose tiles fit k rounds of the
  * device's resident waves) on the handle's current state, keeps the fastest as the
  * handle's tile (dugks_set_tile) and puts the state and step counter back as
  * they were. Results do not depend on the tile, bit for bit. Synchronous;

@@ -551,7 +551,7 @@ int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* 
   if (h->general())
     return fail(h, DUGKS_EINVAL, "the upwind reconstruction and stretched meshes have no tiles to tune");
   // candidates: the shortest segments (lowest latency per step), and for
-  // k = 1..8, 12, 16 the shortest segment whose tiles fit k rounds of resident waves
+  // k = 1..8, 12, 16, 20, 24 the shortest segment whose tiles fit k rounds of resident waves
   // (more rounds: finer load balance, more repeated halo work)
   const int keep = h->seg_rows;
   int rc = DUGKS_OK;
@@ -559,7 +559,7 @@ int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* 
   const std::vector<StripShape> shape = {StripShape{h->hc.nstrips, h->ny}};
   const long long cap = wave_capacity(h->fp64(), h->coupled(), h->hc.walls != 0);
   std::vector<int> use = {1, 2};
-  for (int k : {1, 2, 3, 4, 5, 6, 7, 8, 12, 16}) {
+  for (int k : {1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 20, 24}) {
     const int c = fit_seg_rows(shape, k * cap);
     if (std::find(use.begin(), use.end(), c) == use.end()) use.push_back(c);
   }
@@ -886,7 +886,7 @@ int dugks_batch_autotune(dugks_batch* b, int probe_steps, int* seg_periodic, int
     if (shapes.empty()) continue;
     const long long cap = wave_capacity(b->fp64, b->coupled, w == 1);
     std::vector<int> cand = {1, 2};
-    for (int r : {1, 2, 3, 4, 5, 6, 7, 8, 12, 16}) {
+    for (int r : {1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 20, 24}) {
       const int c = fit_seg_rows(shapes, r * cap);
       if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
     }
