@@ -178,7 +178,7 @@ def roofline(cells, steps, seconds, prec, workload=None):
 
 
 def timed_upwind(torch, D, c, steps, warmup, recon="upwind", mesh=None):
-    """Three-kernel steps of case `c` (coupled FP32): the upwind
+    """Two-kernel steps of case `c` (coupled FP32): the upwind
     reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
     reconstruction, launched one step (two kernels) at a time on torch's
     current stream; seconds by HIP events on that stream."""
