@@ -210,7 +210,7 @@ long long dugks_steps_done(const dugks_handle *h);
 double dugks_time(const dugks_handle *h);
 
 /* Checkpoint/resume: the state is the tilde distributions, the history
- * (phi u)^(n-1), the phi plane and the step counter. dugks_state_bytes()
+ * (phi u)^(n-1), phi and the step counter. dugks_state_bytes()
  * gives the size of the host buffer; get/set copy it (synchronous). Layout
  * (values of the handle's precision): ny rows, row y first; each row holds
  * the values f0..f8, [g0..g8], hist_x, hist_y of its nx cells in groups of

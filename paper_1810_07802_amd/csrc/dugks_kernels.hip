@@ -1173,7 +1173,7 @@ __device__ __forceinline__ void gather3x3(const S* __restrict__ f, long long rs,
 }
 
 // Initial state: tilde = psi^eq - (dt/2) S with d_t(phi u) = 0, from
-// the macros phi, u, v, p (double, [ny][nx]); hist = phi u; phi plane.
+// the macros phi, u, v, p (double, [ny][nx]); hist = phi u; phi.
 template <typename T, bool CPL>
 __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __restrict__ phi0,
                        const double* __restrict__ u0, const double* __restrict__ v0,
@@ -1234,7 +1234,7 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
   }
   at(val_hist(CPL, 0)) = phi * u;
   at(val_hist(CPL, 1)) = phi * v;
-  // phi plane = sum of the stored f (the same sum the step kernel forms)
+  // phi = sum of the stored f (the same sum the step kernel forms)
   T s = T(0);
 #pragma unroll
   for (int q = 0; q < 9; ++q) s += at(val_f(q));
