@@ -83,3 +83,52 @@ def test_copy_probe_copies_exactly(nbytes):
     torch.cuda.synchronize()
     assert torch.equal(dst[:nbytes].cpu(), src.cpu())
     assert int(dst[nbytes:].sum()) == 0
+
+
+def _decode_state(buf, nx, ny, coupled, dtype):
+    """Split a saved state by the layout dugks.h documents: ny rows, each the
+    value groups of its nx cells (groups of four consecutive values,
+    cell-interleaved, a last partial group of w values), then phi, padded
+    to a multiple of 128 bytes."""
+    es = np.dtype(dtype).itemsize
+    nv = 20 if coupled else 11  # grouped values: f0..f8, [g0..g8], hist_x, hist_y
+    rb = -(-(nv + 1) * nx * es // 128) * 128
+    assert buf.nbytes == rb * ny
+    rows = buf.reshape(ny, rb)
+    vals = np.empty((nv, ny, nx), dtype=dtype)
+    for v0 in range(0, nv, 4):
+        w = min(4, nv - v0)
+        blk = rows[:, v0 * nx * es:(v0 + w) * nx * es].copy().view(dtype).reshape(ny, nx, w)
+        for k in range(w):
+            vals[v0 + k] = blk[:, :, k]
+    phi = rows[:, nv * nx * es:(nv + 1) * nx * es].copy().view(dtype).reshape(ny, nx)
+    pad = rows[:, (nv + 1) * nx * es:]
+    return vals, phi, pad
+
+
+@pytest.mark.parametrize("prec,model,nx,ny", [("fp32", "coupled", 70, 9), ("fp64", "coupled", 37, 6),
+                                              ("fp32", "ac", 5, 7), ("fp64", "ac", 64, 5)])
+def test_saved_state_follows_the_documented_layout(prec, model, nx, ny):
+    """A checkpoint decoded by the documented layout: the padding reads zero,
+    the stored phi is the sum of the stored f in the order the kernels form
+    it (bit for bit), and get_macros returns that phi."""
+    dtype = np.float32 if prec == "fp32" else np.float64
+    if model == "coupled":
+        c = W.random_coupled(nx, ny, seed=nx, rho_ratio=10.0)
+    else:
+        c = W.smoothed_deformation(L0=64, Pe=64, M=0.02)
+        c["params"] = dict(c["params"], vel="rotation", T_period=400.0, U0=0.02)
+        c["phi"] = c["phi"][:ny, :nx]
+    s = D.Solver(nx, ny, c["params"], model, prec)
+    s.init(c["phi"])
+    for steps in (0, 3):  # after init, then after 3 steps (the other buffer)
+        if steps:
+            s.step(steps)
+        buf, _ = s.get_state()
+        vals, phi, pad = _decode_state(buf, nx, ny, model == "coupled", dtype)
+        assert not pad.any()
+        acc = np.zeros((ny, nx), dtype=dtype)
+        for q in range(9):
+            acc = acc + vals[q]
+        assert np.array_equal(acc, phi)
+        assert np.array_equal(s.macros()["phi"], phi.astype(np.float64))
