@@ -305,6 +305,10 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    # a created stream (default priority) as torch's current stream: the library
+    # captures its HIP graphs on the caller's stream, and the null stream that
+    # torch uses by default cannot be captured
+    torch.cuda.set_stream(torch.cuda.Stream())
     if args.profile_copy:
         n = 1 << 28  # float32 elements: 1 GiB read + 1 GiB written per copy
         src = torch.ones(n, dtype=torch.float32, device="cuda")

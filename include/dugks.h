@@ -270,8 +270,10 @@ int dugks_batch_create(int n, dugks_handle *const *cases, dugks_batch **out);
 
 /* Advance every active case by nsteps. use_graph = 1 records the sequence of
  * nsteps launches in a HIP graph on first use (per distinct nsteps) and
- * replays it. Cases with a step budget (dugks_batch_set_budget) stop when it
- * runs out. Asynchronous on the batch stream. */
+ * replays it; it needs a stream set with dugks_batch_set_stream (the null
+ * stream cannot be captured: EINVAL). Cases with a step budget
+ * (dugks_batch_set_budget) stop when it runs out. Asynchronous on the batch
+ * stream. */
 int dugks_batch_step(dugks_batch *b, int nsteps, int use_graph);
 
 /* Limit case k to `steps` more steps (negative = unlimited); takes effect
@@ -329,7 +331,9 @@ int dugks_pool_admit(dugks_pool *p, int nx, int ny, const dugks_params *prm,
                      const double *pr, long long nsteps, int *slot);
 /* Enqueue nsteps pool steps: every case with steps left advances by
  * min(nsteps, steps left). use_graph: replay a captured HIP graph while the
- * set of running cases does not change. Asynchronous. */
+ * set of running cases does not change; it needs a stream set with
+ * dugks_pool_set_stream (the null stream cannot be captured: EINVAL).
+ * Asynchronous. */
 int dugks_pool_step(dugks_pool *p, int nsteps, int use_graph);
 /* Steps done and steps left of a slot (host bookkeeping, -1 for a free slot). */
 long long dugks_pool_steps_done(const dugks_pool *p, int slot);

@@ -934,6 +934,10 @@ int dugks_batch_set_stream(dugks_batch* b, void* stream) {
 
 int dugks_batch_step(dugks_batch* b, int nsteps, int use_graph) {
   if (!b || nsteps < 0) return bfail(b, DUGKS_EINVAL, "bad arguments");
+  if (use_graph && !b->stream)
+    return bfail(b, DUGKS_EINVAL,
+                 "use_graph needs a stream set with dugks_batch_set_stream "
+                 "(the null stream cannot be captured)");
   for (auto* h : b->cases)
     if (!h->has_state) return bfail(b, DUGKS_ESTATE, "a case has no state");
   if (nsteps == 0) return DUGKS_OK;
@@ -942,7 +946,7 @@ int dugks_batch_step(dugks_batch* b, int nsteps, int use_graph) {
     if (h->stream != b->stream) BHIPCHK(b, hipStreamSynchronize(h->stream));
   int rc = sync_descriptors(b);
   if (rc) return rc;
-  if (use_graph && b->stream) {
+  if (use_graph) {
     auto itg = b->graphs.find(nsteps);
     if (itg == b->graphs.end()) {
       hipGraph_t g;

@@ -340,11 +340,15 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
 
 int dugks_pool_step(dugks_pool* p, int nsteps, int use_graph) {
   if (!p || nsteps < 0) return pfail(p, DUGKS_EINVAL, "bad arguments");
+  if (use_graph && !p->stream)
+    return pfail(p, DUGKS_EINVAL,
+                 "use_graph needs a stream set with dugks_pool_set_stream "
+                 "(the null stream cannot be captured)");
   if (nsteps == 0) return DUGKS_OK;
   int rc = rebuild(p);
   if (rc) return rc;
   if (p->nitems[0] + p->nitems[1] == 0) return DUGKS_OK;  // nothing to run
-  if (use_graph && p->stream) {
+  if (use_graph) {
     auto itg = p->graphs.find(nsteps);
     if (itg == p->graphs.end()) {
       hipGraph_t g;

@@ -226,3 +226,46 @@ def test_diagnostics_match_oracle_sums():
     assert d["time"] == pytest.approx(100 * c["params"]["cfl"])
     # the wavefront and block reductions have a fixed order: same bits again
     assert s.diagnostics() == d
+
+
+def test_graph_replays_match_direct_steps_with_eager_work_between():
+    """A captured step sequence replayed four times, with direct launches,
+    host readouts and torch work on the same stream between the replays:
+    after every replay each case equals the same case stepped alone."""
+    import torch
+    cases = [W.spinodal(L=L, seed=40 + k, steps=0) for k, L in enumerate((64, 37))]
+    solvers, refs = [], []
+    for c in cases:
+        for lst in (solvers, refs):
+            s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+            s.init(c["phi"])
+            lst.append(s)
+    stream = torch.cuda.Stream()
+    b = D.Batch(solvers)
+    b.set_stream(stream.cuda_stream)
+    done = 0
+    for rep in range(4):
+        b.step(6, use_graph=True)
+        b.step(2, use_graph=False)
+        with torch.cuda.stream(stream):
+            torch.ones(1 << 20, device="cuda").sum()  # unrelated eager work
+        b.sync()
+        done += 8
+        for k, (s, r) in enumerate(zip(solvers, refs)):
+            r.step(8)
+            assert s.steps_done == done
+            assert np.array_equal(s.get_state()[0], r.get_state()[0]), (rep, k)
+            s.macros()
+
+
+def test_graph_steps_need_a_stream():
+    c = W.spinodal(L=40, seed=50, steps=0)
+    s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    s.init(c["phi"])
+    b = D.Batch([s])
+    with pytest.raises(D.DugksError) as e:
+        b.step(3, use_graph=True)  # no stream set: the null stream
+    assert e.value.code == D.EINVAL and "stream" in str(e.value)
+    b.step(3, use_graph=False)
+    b.sync()
+    assert s.steps_done == 3
