@@ -50,7 +50,9 @@ def run(pool, requests, chunk=100, keep=None, use_graph=True, clock=time.perf_co
     """Serve ``requests`` on ``pool``; returns the list of ``Served`` in
     completion order. ``keep(request)`` decides whether a result's macros are
     copied back (default: all); ``chunk`` is the number of steps the pool
-    advances between two looks at arrivals and completions."""
+    advances between two looks at arrivals and completions. With
+    ``use_graph`` the pool replays captured HIP graphs, which needs a stream
+    set with ``pool.set_stream`` (the null stream cannot be captured)."""
     pending = deque(sorted(requests, key=lambda r: r.arrival))
     waiting = deque()
     active = {}  # slot -> (request, admission time)
