@@ -179,7 +179,12 @@ int dugks_init_fields_device(dugks_handle *h, const double *phi,
 
 /* Enqueue nsteps >= 0 time steps (Sec. II.B: cell macros, bar-plus and
  * tilde-plus auxiliaries, half-step face reconstruction, face macros and face
- * distributions, microflux, cell update). Asynchronous; ESTATE before init. */
+ * distributions, microflux, cell update). Asynchronous; ESTATE before init.
+ * On a stream set with dugks_set_stream (not the null stream, and not while
+ * the caller captures it), a sequence of 8 or more steps is recorded once in
+ * a HIP graph per step count (the last 8 counts are kept, and all are dropped
+ * when the step's variant or tiles change) and replayed: the same kernels in
+ * the same order, the same results bit for bit. */
 int dugks_step(dugks_handle *h, int nsteps);
 
 /* Wait for the handle's stream. EDEVICE on a sticky device error. */

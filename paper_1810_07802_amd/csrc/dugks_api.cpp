@@ -297,6 +297,60 @@ int launch_steps(dugks_handle* h, int nsteps) {
   return DUGKS_OK;
 }
 
+// What the kernels of a handle's step take as launch arguments (variant,
+// tiles, device pointers). A captured step sequence stays valid while this
+// is unchanged; the case constants themselves are read from device memory.
+std::vector<long long> launch_sig(const dugks_handle* h) {
+  return {h->general() ? 1 : 0, h->upwind() ? 1 : 0, h->mesh ? 1 : 0, (long long)h->hc.walls,
+          h->fp64() ? 1 : 0, h->coupled() ? 1 : 0, (long long)(uintptr_t)h->items,
+          (long long)h->nitems, (long long)h->hc.seg_rows, (long long)(uintptr_t)h->dc,
+          (long long)(uintptr_t)h->step_base, (long long)(uintptr_t)h->up, (long long)h->nx,
+          (long long)h->ny};
+}
+
+void drop_graphs(dugks_handle* h) {
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  h->graphs.clear();
+}
+
+// Sequences of at least kGraphMin steps on a created stream are recorded once
+// in a HIP graph (per step count, at most kGraphCache kept) and replayed: one
+// launch from the host instead of one (or two) per step.
+constexpr int kGraphMin = 8;
+constexpr size_t kGraphCache = 8;
+
+int launch_steps_graph(dugks_handle* h, int nsteps) {
+  const std::vector<long long> sig = launch_sig(h);
+  if (sig != h->gsig) {
+    drop_graphs(h);
+    h->gsig = sig;
+  }
+  hipGraphExec_t ex = nullptr;
+  for (auto& g : h->graphs)
+    if (g.first == nsteps) ex = g.second;
+  if (!ex) {
+    if (h->graphs.size() >= kGraphCache) {
+      (void)hipGraphExecDestroy(h->graphs.front().second);
+      h->graphs.erase(h->graphs.begin());
+    }
+    hipGraph_t g = nullptr;
+    HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    const int rc = launch_steps(h, nsteps);
+    hipError_t e = hipStreamEndCapture(h->stream, &g);  // always ends the capture
+    if (rc) {
+      if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+    h->graphs.emplace_back(nsteps, ex);
+  }
+  HIPCHK(h, hipGraphLaunch(ex, h->stream));
+  return DUGKS_OK;
+}
+
 }  // namespace host
 }  // namespace dugks
 
@@ -450,7 +504,14 @@ int dugks_step(dugks_handle* h, int nsteps) {
   if (!h || nsteps < 0) return fail(h, DUGKS_EINVAL, "bad arguments");
   if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
   if (nsteps == 0) return DUGKS_OK;
-  int rc = launch_steps(h, nsteps);
+  // graph replay on a created stream that is not being captured by the caller
+  bool graph = false;
+  if (h->stream && nsteps >= kGraphMin) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    HIPCHK(h, hipStreamIsCapturing(h->stream, &st));
+    graph = st == hipStreamCaptureStatusNone;
+  }
+  int rc = graph ? launch_steps_graph(h, nsteps) : launch_steps(h, nsteps);
   if (rc) return rc;
   h->steps += nsteps;
   return DUGKS_OK;
@@ -658,6 +719,7 @@ int dugks_destroy(dugks_handle* h) {
   if (h->scratch) (void)hipFree(h->scratch);
   if (h->up) (void)hipFree(h->up);
   if (h->dmesh) (void)hipFree(h->dmesh);
+  drop_graphs(h);
   delete h;
   return DUGKS_OK;
 }

@@ -36,6 +36,10 @@ struct dugks_handle {
   // a case of a serving pool: its buffers, descriptor, counter and scratch
   // belong to the pool, which also launches its steps
   bool borrowed = false;
+  // step sequences replayed from HIP graphs (a created stream only): nsteps
+  // and its graph, valid while the launch signature gsig is unchanged
+  std::vector<std::pair<int, hipGraphExec_t>> graphs;
+  std::vector<long long> gsig;
 
   bool fp64() const { return precision == DUGKS_FP64; }
   bool upwind() const { return params.recon == DUGKS_RECON_UPWIND; }

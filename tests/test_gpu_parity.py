@@ -269,3 +269,38 @@ def test_graph_steps_need_a_stream():
     b.step(3, use_graph=False)
     b.sync()
     assert s.steps_done == 3
+
+
+@pytest.mark.parametrize("variant", ["central", "upwind", "mesh"])
+def test_handle_graph_replays_match_direct_launches(variant):
+    """Solver.step on a created stream replays captured graphs (8 or more
+    steps); interleaved with short direct sequences, readouts and torch work,
+    and with a change of reconstruction that drops the graphs, the state
+    equals a handle stepped by direct launches on the null stream, bit for
+    bit, after every call."""
+    import torch
+    c = W.random_coupled(70, 36, seed=60, rho_ratio=10.0, walls_y=(variant == "upwind"))
+    recon = "upwind" if variant == "upwind" else "central"
+    c["params"] = dict(c["params"], recon=recon)
+    dx = W.stretched_widths(70, 0.3) if variant == "mesh" else None
+    stream = torch.cuda.Stream()
+    a = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    b = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    a.set_stream(stream.cuda_stream)
+    for s in (a, b):
+        if dx is not None:
+            s.set_mesh(dx, None)
+        s.init(c["phi"], c["u"], c["v"])
+    for rep, n in enumerate((12, 3, 12, 12, 9)):
+        if rep == 3:  # a new variant: the recorded sequences are dropped
+            other = dict(c["params"], recon="central" if recon == "upwind" else "upwind")
+            a.set_params(other)
+            b.set_params(other)
+        a.step(n)
+        b.step(n)
+        with torch.cuda.stream(stream):
+            torch.ones(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert a.steps_done == b.steps_done
+        assert np.array_equal(a.get_state()[0], b.get_state()[0]), (variant, rep)
+        a.macros()
