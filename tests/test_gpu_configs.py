@@ -54,17 +54,18 @@ def oracle_run(case, steps):
     return _ORACLE_CACHE[key]
 
 
-def gpu_run(case, steps, precision):
-    s = D.Solver(case["nx"], case["ny"], case["params"], case["model"], precision)
+def gpu_run(case, steps, precision, seg=None):
+    s = D.Solver(case["nx"], case["ny"], case["params"], case["model"], precision, seg)
     s.init(case["phi"], case["u"], case["v"], case["p"])
     s.step(steps)
     return s.macros()
 
 
 def check(case, steps, precision, residual=(), u_scale=None, p_scale=None,
-          fp32_phi=1e-5, fp32_u=1e-4):
-    """Compare after `steps`; `residual` names fields judged against scales."""
-    g = gpu_run(case, steps, precision)
+          fp32_phi=1e-5, fp32_u=1e-4, seg=None):
+    """Compare after `steps`; `residual` names fields judged against scales;
+    `seg` fixes the tile (rows per segment) instead of the automatic one."""
+    g = gpu_run(case, steps, precision, seg)
     r = oracle_run(case, steps)
     e = {k: rel(g[k], r[k]) for k in ("phi", "u", "v", "p")}
     dsum = abs(g["phi"].sum() - r["phi"].sum()) / np.abs(r["phi"]).sum()
@@ -158,3 +159,16 @@ def test_served_bubble_256_fp32():
     c = W.bubble(L=256, R=64)
     us, ps = _scales(c)
     check(c, 1000, "fp32", residual=("u", "v", "p"), u_scale=us, p_scale=ps)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_grid_bubble_4096_in_the_bench_tiling(prec):
+    """The large-grid benchmark case at its full size (4096^2, R = 1024, the
+    same physics as the 128^2 bubble) in the tiling the bench times (6-row
+    segments of the march): three steps against the oracle on every cell
+    (the oracle takes about a second per step at this size). The velocity
+    and pressure are the spurious current's residuals, judged against the
+    capillary scales."""
+    c = W.bubble(L=4096, R=1024, steps=0)
+    u_star, p_star = _scales(c)
+    check(c, 3, prec, residual=("u", "v", "p"), u_scale=u_star, p_scale=p_star, seg=6)
