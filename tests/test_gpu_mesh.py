@@ -223,3 +223,23 @@ def test_rayleigh_taylor_full_size_on_a_clustered_mesh(recon):
         d = np.abs(g[k] - r[k]).max()
         print(f"rti mesh {recon} {k}: max |gpu - oracle| {d:.2e} = {d / sc:.2e} of its scale", flush=True)
         assert d < 1e-12 * sc, (k, d)
+
+
+@pytest.mark.parametrize("recon", ["central", "upwind"])
+def test_bench_mesh_case_at_full_size(recon):
+    """The benchmark's stretched-mesh case at its full size (4096^2 bubble,
+    widths 1 + 0.3 sin in x and y, FP32 as timed): three steps against the
+    FP64 oracle on every cell; phi within the FP32 bar, the spurious current
+    and pressure (residuals) within 1e-4 of the capillary scales."""
+    c = with_params(W.bubble(L=4096, R=1024, steps=0), recon=recon)
+    dx, dy = W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0)
+    s = gpu(c, dx, dy, 3, "fp32")
+    o = orc(c, dx, dy, 3)
+    g, r = s.macros(), o.macros()
+    assert rel(g["phi"], r["phi"]) < 1e-5
+    p = c["params"]
+    u_star = p["sigma"] / (p["nu"] * p["rho_L"])
+    for k, sc in {"u": u_star, "v": u_star, "p": p["rho_H"] / 3.0 * u_star}.items():
+        d = np.abs(g[k] - r[k]).max()
+        print(f"mesh 4096 {recon} {k}: max|gpu - oracle| {d:.2e} = {d / sc:.2e} of its scale", flush=True)
+        assert d < 1e-4 * sc, (k, d)

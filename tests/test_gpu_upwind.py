@@ -212,3 +212,18 @@ def _residuals_within_scale(c, g, r):
         d = np.abs(g[k] - r[k]).max()
         print(f"{k}: max |gpu - oracle| {d:.2e} = {d / sc:.2e} of its scale", flush=True)
         assert d < 1e-12 * sc, (k, d)
+
+
+def test_bench_upwind_case_at_full_size():
+    """The benchmark's upwind case at its full size (4096^2 bubble, FP32 as
+    timed): three steps against the FP64 oracle on every cell."""
+    c = upwind(W.bubble(L=4096, R=1024, steps=0))
+    g = gpu(c, 3, "fp32").macros()
+    r = orc(c, 3)
+    assert rel(g["phi"], r["phi"]) < 1e-5
+    p = c["params"]
+    u_star = p["sigma"] / (p["nu"] * p["rho_L"])
+    for k, sc in {"u": u_star, "v": u_star, "p": p["rho_H"] / 3.0 * u_star}.items():
+        d = np.abs(g[k] - r[k]).max()
+        print(f"upwind 4096 {k}: max|gpu - oracle| {d:.2e} = {d / sc:.2e} of its scale", flush=True)
+        assert d < 1e-4 * sc, (k, d)
