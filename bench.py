@@ -60,6 +60,9 @@ def parse():
                     help="requests of the served stream (0: skip the serving leg)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--skip-extra", action="store_true", help="only the default workload")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="run only the batched spinodal leg (one graph per chunk, "
+                         "autotuned tiles): for kernel traces")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="run only the timed default workload (for profilers)")
     ap.add_argument("--profile-large", action="store_true",
@@ -350,6 +353,20 @@ def main():
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, stretched mesh, central",
                           **timed_upwind(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
               flush=True)
+        return
+    if args.profile_batch:
+        cases = W.spinodal_batch(steps=0)
+        solvers = []
+        for cc in cases:
+            t = D.Solver(cc["nx"], cc["ny"], cc["params"], "coupled", "fp32")
+            t.init(cc["phi"])
+            solvers.append(t)
+        bc = sum(cc["nx"] * cc["ny"] for cc in cases)
+        tb, bt = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100, autotune=True)
+        print(json.dumps({"workload": "spinodal batch, 64 cases of 64^2..512^2 (seed 1810), coupled FP32",
+                          "cells": bc, "steps": args.batch_steps, "tile_seg_rows": bt.tiles,
+                          "batched_graph_mlups": round(bc * args.batch_steps / tb / 1e6, 1),
+                          "roofline": roofline(bc, args.batch_steps, tb, "fp32")}), flush=True)
         return
     if args.profile_upwind:
         cl = W.bubble(L=4096, R=1024, steps=0)
