@@ -47,6 +47,17 @@ int wave_capacity(bool fp64, bool coupled, bool walls) {
   return prop.multiProcessorCount * dugks::step_waves_per_cu(fp64, coupled, walls);
 }
 
+// Compute units of the current device (256 if it cannot be queried).
+long long cu_count() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 256;
+  }
+  return prop.multiProcessorCount;
+}
+
 // Waves (tiles) of a list of cases cut into segments of `seg` rows.
 long long tile_count(const std::vector<StripShape>& cs, int seg) {
   long long w = 0;
@@ -76,9 +87,18 @@ int fit_seg_rows(const std::vector<StripShape>& cs, long long budget) {
 // than the device caches) eight rounds of shorter tiles, which keeps the
 // rows in flight closer together and measured faster on MI355X (4096^2
 // FP32 coupled: 23.4k MLUPS with 137-row segments, 26.8k with 17).
-int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity) {
+int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity, bool fp64, bool walls) {
   const int a = fit_seg_rows(cs, capacity);
-  return a > 64 ? fit_seg_rows(cs, 8 * capacity) : a;
+  if (a > 64) return fit_seg_rows(cs, 8 * capacity);
+  if (a == 1 && !fp64 && !walls) {
+    // one-row tiles that outnumber the CUs put two work groups (six waves)
+    // on some CUs, whose waves then share SIMDs; two-row tiles that fit one
+    // per CU run the four-wave two-row kernel instead (128^2: 5.0 against
+    // 5.2 us per step)
+    const long long cus = cu_count();
+    if (tile_count(cs, 1) > cus && tile_count(cs, 2) <= cus) return 2;
+  }
+  return a;
 }
 
 // Derived constants (Sec. II.B, Eqs. 3, 28-29, 34, 37) into the descriptor.
@@ -93,7 +113,8 @@ void fill_case(dugks_handle* h) {
   C.seg_rows = h->seg_rows > 0
                    ? h->seg_rows
                    : auto_seg_rows({StripShape{C.nstrips, h->ny}},
-                                   wave_capacity(h->fp64(), h->coupled(), C.walls != 0));
+                                   wave_capacity(h->fp64(), h->coupled(), C.walls != 0),
+                                   h->fp64(), C.walls != 0);
   C.nsegs = (h->ny + C.seg_rows - 1) / C.seg_rows;
   C.walls = P.bc_y == DUGKS_BC_WALLS ? 1 : 0;
   C.vel_kind = P.vel_kind;
@@ -289,6 +310,7 @@ int launch_steps(dugks_handle* h, int nsteps) {
   a.nitems = h->nitems;
   a.step_base = h->step_base;
   a.one_row = h->hc.seg_rows == 1 ? 1 : 0;
+  a.two_row = h->hc.seg_rows == 2 ? 1 : 0;
   for (int k = 0; k < nsteps; ++k) {
     a.kofs = k;
     HIPCHK(h, dugks::launch_step(h->fp64(), h->coupled(), h->hc.walls != 0, a, h->stream));
@@ -737,6 +759,7 @@ struct dugks_batch {
   Item* items[2] = {nullptr, nullptr};  // work items: periodic cases, wall cases
   int nitems[2] = {0, 0};
   int one_row[2] = {1, 1};              // every case of the group has one-row tiles
+  int two_row[2] = {1, 1};              // every case of the group has two-row tiles
   std::vector<int> seg;                 // rows per segment used for each case
   long long* step_base = nullptr;  // device: global step of the batch
   long long gstep = 0;             // host mirror
@@ -786,10 +809,12 @@ int sync_descriptors(dugks_batch* b) {
 hipError_t build_items(dugks_batch* b) {
   std::vector<Item> it[2];
   b->one_row[0] = b->one_row[1] = 1;
+  b->two_row[0] = b->two_row[1] = 1;
   for (size_t k = 0; k < b->cases.size(); ++k) {
     const CaseDev& c = b->cases[k]->hc;
     const int w = c.walls ? 1 : 0;
     if (b->seg[k] != 1) b->one_row[w] = 0;
+    if (b->seg[k] != 2) b->two_row[w] = 0;
     const int nsegs = (c.ny + b->seg[k] - 1) / b->seg[k];
     for (int s = 0; s < nsegs; ++s)
       for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{(int)k, x, s, 0});
@@ -820,6 +845,7 @@ int record_steps(dugks_batch* b, int nsteps) {
       a.items = b->items[w];
       a.nitems = b->nitems[w];
       a.one_row = b->one_row[w];
+      a.two_row = b->two_row[w];
       BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, w == 1, a, b->stream));
     }
   }
@@ -866,7 +892,8 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
   for (int w = 0; w < 2; ++w)
     segw[w] = shapes[w].empty()
                   ? 1
-                  : auto_seg_rows(shapes[w], wave_capacity(b->fp64, b->coupled, w == 1));
+                  : auto_seg_rows(shapes[w], wave_capacity(b->fp64, b->coupled, w == 1), b->fp64,
+                                  w == 1);
   for (int k = 0; k < n; ++k) {
     const int w = cases[k]->hc.walls ? 1 : 0;
     // a case's explicit tile wins over the group's automatic one

@@ -78,7 +78,11 @@ struct StripShape {
 };
 long long tile_count(const std::vector<StripShape>& cs, int seg);
 int fit_seg_rows(const std::vector<StripShape>& cs, long long budget);
-int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity);
+// Automatic segment length of a group of cases (fp64, walls: the group's
+// precision and boundary, which decide whether the two-row kernel applies).
+int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity, bool fp64, bool walls);
+// Compute units of the current device.
+long long cu_count();
 
 // Derived constants of the handle's parameters into h->hc, and the upload of
 // the descriptor (and, for a plain handle, of its work items).

@@ -119,6 +119,8 @@ struct StepArgs {
   int kofs;                    // offset of this launch inside a step sequence
   const long long* step_base;  // device counter: global step of kofs = 0
   int one_row;                 // every item is one row (seg_rows == 1): row kernel
+  int two_row;                 // every item is two rows (seg_rows == 2): the two-row kernel
+                               // for periodic FP32 cases, else the march
 };
 
 // Scratch planes of the two-kernel step (upwind reconstruction, stretched

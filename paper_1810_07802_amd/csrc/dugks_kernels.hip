@@ -1083,6 +1083,161 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
   }
 }
 
+// --------------------------------------------------- two-row step kernel
+
+// Two output rows j and j + 1 of one 62-column strip per work group of four
+// waves, for 2-row tiles of periodic cases in FP32. Wave w stages row
+// j - 1 + w; after the records meet in LDS, wave 0 forms the face below row j
+// and the face above row j + 1, wave 1 the face between the two rows, wave 2
+// the x-faces of row j + 1 and wave 3 those of row j; waves 1 and 2 then
+// update the two rows. A 128^2 grid takes 192 such groups where one-row tiles
+// take 384: one group per CU, so no two waves share a SIMD, which costs less
+// than the second face on wave 0. Every quantity goes through the same
+// functions, with the same inputs, as in the march: the same bits.
+template <typename T, bool CPL>
+__global__ __launch_bounds__(256) void k_step_row2(StepArgs A) {
+  static_assert(sizeof(T) == 4, "the LDS records of four rows fit 64 KB in FP32 only");
+  const int nb = gridDim.x;
+  const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (idx >= A.nitems) return;  // uniform over the work group
+  const Item it = A.items[idx];
+  const CaseDev C = A.cases[it.c];
+  const long long n = *A.step_base + A.kofs - C.step0;
+  if (n < 0 || n >= C.nsteps) return;  // uniform over the work group
+
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform over the wave
+  const int lane = threadIdx.x & 63;
+  const int nx = C.nx, ny = C.ny;
+  constexpr int walls = 0;
+  const int i0 = it.strip * kStripCols;
+  const int col = i0 - 1 + lane;
+  const int ci = wrap(col, nx);
+  const int cx = lane == 0 ? wrap(col - 1, nx) : (lane == 63 ? wrap(col + 1, nx) : ci);
+  const bool store = lane >= 1 && lane <= kStripCols && col < nx;
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  const long long RB = C.row_vals * (long long)sizeof(T);  // bytes per grid row
+  const long long PB = (long long)nx * sizeof(T);            // bytes of one value across a row
+  constexpr int NV = num_grouped(CPL);
+  const unsigned es = sizeof(T);
+  const double tn = C.t0 + (double)n * C.dt;
+  const double xc = (double)ci + 0.5;
+  const int j = it.seg * 2;     // tiles of two rows: segment index = row pair
+  const bool two = j + 1 < ny;  // the last tile of an odd ny has one row
+  const int r = j - 1 + w;      // staged row (periodic)
+
+  __shared__ T rec[4][kRec][64];
+  __shared__ T tplus[2][18][64];  // tilde-plus of rows j and j + 1
+  // crossing populations of four faces (f in slots 0-5, g in 6-11): below
+  // row j, between the rows, above row j + 1, and the x-faces of row j
+  __shared__ T fyb[12][64], fym[12][64], fya[12][64], fx0[12][64];
+
+  RowData<T, CPL> rd;
+  {
+    T v[NV];
+    load_groups<T, NV>(row_ptr(in, row_idx(r, ny, walls), RB), PB, (unsigned)ci, v);
+    T f[9], g[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      f[q] = v[val_f(q)];
+      g[q] = CPL ? v[val_g(q)] : T(0);
+    }
+    T ph[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const char* prow = row_ptr(in, row_idx(r - 1 + a, ny, walls), RB) + NV * PB;
+      const T own = gload<T>(prow, (unsigned)ci * es), ext = gload<T>(prow, (unsigned)cx * es);
+      T left = nbr_l(own), right = nbr_r(own);
+      if (lane == 0) left = ext;
+      if (lane == 63) right = ext;
+      ph[a][0] = left; ph[a][1] = own; ph[a][2] = right;
+    }
+    T tp[18];
+    cell_stage<T, CPL>(C, ph, f, g, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], xc,
+                       (double)row_idx(r, ny, walls) + 0.5, tn, rd.cell, tp);
+    if (w == 1 || w == 2) {
+#pragma unroll
+      for (int q = 0; q < 18; ++q) tplus[w - 1][q][lane] = tp[q];
+    }
+    x_diffs<T, CPL>(rd);
+    move_record<T, CPL, true>(rec[w], lane, rd);
+  }
+  __syncthreads();
+  // face distributions of the populations crossing a y-face / an x-face
+  auto put = [&](T(*F)[64], bool yface, const T(&fo)[9], const T(&go)[9]) {
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      const int sl = yface ? up_yslot(q) : up_xslot(q);
+      if (sl < 0) continue;
+      F[sl][lane] = fo[q];
+      if (CPL) F[6 + sl][lane] = go[q];
+    }
+  };
+  auto get = [&](const T(*F)[64], bool yface, T(&fo)[9], T(&go)[9]) {
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      const int sl = yface ? up_yslot(q) : up_xslot(q);
+      if (sl < 0) continue;
+      fo[q] = F[sl][lane];
+      if (CPL) go[q] = F[6 + sl][lane];
+    }
+  };
+  T fx_f[9], fx_g[9];
+  if (w == 0) {
+    // the face below row j (above row j - 1): this wave's row and row j
+    RowData<T, CPL> up;
+    move_record<T, CPL, false>(rec[1], lane, up);
+    y_face<T, CPL>(C, rd, up, xc, (double)row_idx(j - 1, ny, walls) + 1.0, tn + C.h, rd.fnf, rd.fng);
+    put(fyb, true, rd.fnf, rd.fng);
+    if (two) {
+      // the face above row j + 1: rows j + 1 and j + 2
+      RowData<T, CPL> a, b;
+      move_record<T, CPL, false>(rec[2], lane, a);
+      move_record<T, CPL, false>(rec[3], lane, b);
+      y_face<T, CPL>(C, a, b, xc, (double)row_idx(j + 1, ny, walls) + 1.0, tn + C.h, a.fnf, a.fng);
+      put(fya, true, a.fnf, a.fng);
+    }
+  } else if (w == 1) {
+    // the face above row j (below row j + 1); this wave updates row j
+    RowData<T, CPL> up;
+    move_record<T, CPL, false>(rec[2], lane, up);
+    y_face<T, CPL>(C, rd, up, xc, (double)row_idx(j, ny, walls) + 1.0, tn + C.h, rd.fnf, rd.fng);
+    if (two) put(fym, true, rd.fnf, rd.fng);
+  } else if (w == 2) {
+    // x-faces of row j + 1 (this wave's row, which it updates)
+    if (two) {
+      RowData<T, CPL> pj, nj;
+      move_record<T, CPL, false>(rec[1], lane, pj);
+      move_record<T, CPL, false>(rec[3], lane, nj);
+      row_xface<T, CPL, false>(C, j + 1, ny, ci, tn, pj, rd, nj, fx_f, fx_g);
+    }
+  } else {
+    // x-faces of row j: rows j - 1, j, j + 1
+    RowData<T, CPL> pj, cj, nj;
+    move_record<T, CPL, false>(rec[0], lane, pj);
+    move_record<T, CPL, false>(rec[1], lane, cj);
+    move_record<T, CPL, false>(rec[2], lane, nj);
+    row_xface<T, CPL, false>(C, j, ny, ci, tn, pj, cj, nj, fx_f, fx_g);
+    put(fx0, false, fx_f, fx_g);
+  }
+  __syncthreads();
+  if (w == 1) {
+    RowData<T, CPL> prv;
+    get(fyb, true, prv.fnf, prv.fng);
+    get(fx0, false, fx_f, fx_g);
+    row_update<T, CPL, false>(C, j, ny, nx, walls, ci, store, out, RB, PB, prv, rd, fx_f, fx_g,
+                              [&](int q) { return tplus[0][q][lane]; });
+  } else if (w == 2 && two) {
+    RowData<T, CPL> prv;
+    get(fym, true, prv.fnf, prv.fng);
+    get(fya, true, rd.fnf, rd.fng);
+    row_update<T, CPL, false>(C, j + 1, ny, nx, walls, ci, store, out, RB, PB, prv, rd, fx_f,
+                              fx_g, [&](int q) { return tplus[1][q][lane]; });
+  }
+}
+
 // Plain device copy, one work item per 16 bytes: the bandwidth a streaming
 // kernel reaches on the device, the practical ceiling of the step's traffic.
 __global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
@@ -1929,6 +2084,12 @@ hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, h
   if (a.nitems <= 0) return hipSuccess;
   const int per = (a.nitems + 7) / 8;
   if (walls && !coupled) return hipErrorInvalidValue;
+  if (a.two_row && !fp64 && !walls) {  // four waves per two-row tile
+    dim3 grid(per * 8), block(4 * kWave);
+    if (!coupled) hipLaunchKernelGGL((k_step_row2<float, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step_row2<float, true>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   if (a.one_row) {  // three waves per one-row tile
     dim3 grid(per * 8), block(3 * kWave);
     if (fp64) {

@@ -139,7 +139,10 @@ int rebuild(dugks_pool* p) {
   if (!p->dirty && run == p->running) return DUGKS_OK;
   int* seg = p->seg;
   for (int w = 0; w < 2; ++w)
-    seg[w] = shapes[w].empty() ? 1 : auto_seg_rows(shapes[w], wave_capacity(p->fp64(), p->coupled(), w == 1));
+    seg[w] = shapes[w].empty()
+                 ? 1
+                 : auto_seg_rows(shapes[w], wave_capacity(p->fp64(), p->coupled(), w == 1),
+                                 p->fp64(), w == 1);
   std::vector<Item> it[2];
   for (int k = 0; k < p->max_cases; ++k) {
     CaseDev& c = p->hcases[k];
@@ -195,6 +198,7 @@ int record(dugks_pool* p, int nsteps) {
       a.items = p->items[w];
       a.nitems = p->nitems[w];
       a.one_row = p->seg[w] == 1 ? 1 : 0;
+      a.two_row = p->seg[w] == 2 ? 1 : 0;
       PHIPCHK(p, dugks::launch_step(p->fp64(), p->coupled(), w == 1, a, p->stream));
     }
   }

@@ -304,3 +304,27 @@ def test_handle_graph_replays_match_direct_launches(variant):
         assert a.steps_done == b.steps_done
         assert np.array_equal(a.get_state()[0], b.get_state()[0]), (variant, rep)
         a.macros()
+
+
+@pytest.mark.parametrize("model,nx,ny", [("coupled", 130, 51), ("coupled", 3, 3), ("coupled", 64, 5),
+                                         ("ac", 96, 37), ("coupled", 128, 128)])
+def test_two_row_tiles_give_the_same_bits(model, nx, ny):
+    """2-row tiles of periodic FP32 cases run the four-wave two-row kernel:
+    the same state bit for bit as 1-row tiles (the row kernel) and 5-row
+    segments (the march), odd heights (a last tile of one row) and grids
+    smaller than one tile included."""
+    if model == "coupled":
+        c = W.random_coupled(nx, ny, seed=nx + ny, rho_ratio=100.0)
+    else:
+        c = W.smoothed_deformation(L0=96, Pe=96, M=0.02)
+        c["params"] = dict(c["params"], vel="shear", T_period=400.0, U0=0.02)
+        c["phi"] = np.ascontiguousarray(c["phi"][:ny, :nx])
+        c["u"] = c["v"] = None
+    states = []
+    for seg in (2, 1, 5):
+        s = D.Solver(nx, ny, c["params"], model, "fp32", seg)
+        s.init(c["phi"], c["u"], c["v"])
+        s.step(40)
+        states.append(s.get_state()[0])
+    assert np.array_equal(states[0], states[1])
+    assert np.array_equal(states[0], states[2])
