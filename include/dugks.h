@@ -132,8 +132,10 @@ int dugks_set_stream(dugks_handle *h, void *stream);
 /* Work decomposition of the step kernel: rows per segment of a 62-column
  * strip (each (strip, segment) tile is one 64-lane wave). 0 = automatic
  * (the shortest segments whose tiles are all resident on the device at
- * once; if those would exceed 64 rows, the shortest that fit eight rounds).
- * Results do not depend on it, bit for bit. A batch uses a case's
+ * once; if those would exceed 64 rows, the shortest that fit eight rounds;
+ * for periodic FP32 cases whose one-row tiles outnumber the compute units
+ * while two-row tiles do not, two rows, run by the four-wave two-row
+ * kernel). Results do not depend on it, bit for bit. A batch uses a case's
  * explicit value, and its own automatic choice for cases left at 0. EINVAL
  * outside [0, 4096]. dugks_get_tile returns the value in use (-1 for NULL). */
 int dugks_set_tile(dugks_handle *h, int seg_rows);
