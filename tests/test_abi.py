@@ -58,6 +58,10 @@ def test_null_and_bad_arguments_do_not_crash():
         D.create(16, 16, precision=7)
     assert e.value.code == D.EINVAL
     assert L.dugks_autotune(None, 10, None, None) == D.EINVAL
+    # an empty batch is rejected before any device work
+    with pytest.raises(D.DugksError) as e:
+        D.Batch([])
+    assert e.value.code == D.EINVAL
     # the copy probe checks its arguments before touching the device
     for dst, src, n in ((0, 0, 16), (0x1000, 0x2000, 15), (0x1008, 0x2000, 16),
                         (0x1000, 0x1010, 32), (0x1000, 0x2000, 0)):

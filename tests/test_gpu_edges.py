@@ -70,6 +70,30 @@ def test_uniform_state_is_preserved_bitwise(prec, walls):
     assert np.array_equal(s.get_state()[0], before)
 
 
+def test_empty_step_requests_change_nothing():
+    """Zero steps (single handle, batch with and without graphs) leave the
+    state and the step count as they were; a negative count is EINVAL."""
+    import torch
+
+    c = W.random_coupled(70, 36, seed=2, rho_ratio=10.0)
+    s = D.Solver(70, 36, c["params"], "coupled", "fp32")
+    s.init(c["phi"], c["u"], c["v"])
+    s.step(3)
+    before, n0 = s.get_state()[0], s.steps_done
+    s.step(0)
+    assert s.steps_done == n0 and np.array_equal(s.get_state()[0], before)
+    with pytest.raises(D.DugksError) as e:
+        s.step(-1)
+    assert e.value.code == D.EINVAL
+    st = torch.cuda.Stream()
+    b = D.Batch([s])
+    b.set_stream(st.cuda_stream)
+    b.step(0)
+    b.step(0, use_graph=True)
+    b.sync()
+    assert s.steps_done == n0 and np.array_equal(s.get_state()[0], before)
+
+
 @pytest.mark.parametrize("nbytes", [16, 16 * 257, 16 * 1000003])
 def test_copy_probe_copies_exactly(nbytes):
     """The bandwidth probe that the large-grid roofline is compared with: a
