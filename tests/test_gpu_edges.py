@@ -158,25 +158,33 @@ def test_saved_state_follows_the_documented_layout(prec, model, nx, ny):
         assert np.array_equal(s.macros()["phi"], phi.astype(np.float64))
 
 
-@pytest.mark.parametrize("prec,nx,ny,walls", [("fp32", 1 << 26, 4, True), ("fp32", 1 << 21, 128, False),
-                                              ("fp64", 1 << 25, 4, False)])
-def test_largest_grids_evolve_like_a_narrow_grid(prec, nx, ny, walls):
+@pytest.mark.parametrize("prec,nx,ny,walls,mode", [("fp32", 1 << 26, 4, True, "march"),
+                                                   ("fp32", 1 << 21, 128, False, "march"),
+                                                   ("fp64", 1 << 25, 4, False, "march"),
+                                                   ("fp32", 1 << 26, 4, True, "upwind"),
+                                                   ("fp32", 1 << 21, 128, False, "mesh_y")])
+def test_largest_grids_evolve_like_a_narrow_grid(prec, nx, ny, walls, mode):
     """Grids at the size limit of the C ABI (2^28 cells in FP32, 2^27 in
-    FP64), as rows of up to 5.6 GB or as 22 GB buffers of many rows. The
-    initial state varies along y only, so every cell of a row sees the same
-    inputs and must end with the bits of the same row of a 64-column grid
-    (whose kernels give the march's bits): an address wrapped at 2^31 or
-    2^32 bytes, or a tile that misses cells, shows as a column that differs."""
+    FP64), as rows of up to 5.6 GB or as 22 GB buffers of many rows; the
+    fused march, and the two-kernel step (upwind reconstruction, a mesh
+    stretched along y) with its 26 GB of scratch planes. The initial state
+    varies along y only, so every cell of a row sees the same inputs and must
+    end with the bits of the same row of a 64-column grid (whose kernels give
+    the march's bits): an address wrapped at 2^31 or 2^32 bytes, or a tile
+    that misses cells, shows as a column that differs."""
     import torch
 
     c = W.random_coupled(64, ny, seed=3, rho_ratio=1000.0, walls_y=walls)
-    p = c["params"]
+    p = dict(c["params"], recon="upwind") if mode == "upwind" else c["params"]
+    dy = W.stretched_widths(ny, 0.3) if mode == "mesh_y" else None
     y = (np.arange(ny) + 0.5) / ny
     prof = p["phi_L"] + (p["phi_H"] - p["phi_L"]) * (0.5 + 0.45 * np.cos(2 * np.pi * y))
     steps = 3
 
     def run(width):
         s = D.Solver(width, ny, p, "coupled", prec)
+        if dy is not None:
+            s.set_mesh(None, dy)
         phi0 = torch.tensor(prof, device="cuda")[:, None].expand(ny, width).contiguous()
         out = {k: torch.empty((ny, width), dtype=torch.float64, device="cuda") for k in ("phi", "u", "v")}
         torch.cuda.synchronize()  # the library works on its own stream
