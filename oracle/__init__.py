@@ -42,6 +42,7 @@ class OrcParams(C.Structure):
         ("vel_kind", C.c_int),
         ("U0", C.c_double), ("L0", C.c_double), ("T_period", C.c_double),
         ("recon", C.c_int),
+        ("eps_n", C.c_double),
     ]
 
 
@@ -49,7 +50,7 @@ PARAM_DEFAULTS = dict(
     phi_H=1.0, phi_L=0.0, rho_H=1.0, rho_L=1.0, mu_H=0.1, mu_L=0.1, nu=0.1,
     visc="uniform_nu", sigma=0.0, W=4.0, M=0.1, gx=0.0, gy=0.0,
     gravity="rho_g", Gx=0.0, Gy=0.0, cfl=0.5, walls_y=False,
-    vel="uniform", U0=0.0, L0=1.0, T_period=1.0, recon="central",
+    vel="uniform", U0=0.0, L0=1.0, T_period=1.0, recon="central", eps_n=1e-6,
 )
 
 
@@ -122,7 +123,7 @@ def make_params(d: dict) -> OrcParams:
     s = OrcParams()
     for k in ("phi_H", "phi_L", "rho_H", "rho_L", "mu_H", "mu_L", "nu",
               "sigma", "W", "M", "gx", "gy", "Gx", "Gy", "cfl", "U0", "L0",
-              "T_period"):
+              "T_period", "eps_n"):
         setattr(s, k, float(p[k]))
     s.visc_mode = VISC[p["visc"]]
     s.gravity_form = GRAV[p["gravity"]]

@@ -40,11 +40,13 @@
  *       D) are the mean of the two adjacent cells at t_n; algebraic functions
  *       of phi (rho, theta, tau_g, gravity) are re-evaluated from the face phi.
  *   R6  Face macros use the cell formulas of Eq. 32-33 with dt/2 -> h/2.
- *   R7  n = grad phi / sqrt(|grad phi|^2 + eps^2), eps = 1e-6 |phi_H - phi_L|:
- *       the unit normal where |grad phi| >> eps, zero for a uniform field, and
- *       continuous at the saddle points of phi where the plain unit vector is
- *       undefined (there theta n would otherwise follow the rounding of a
- *       vanishing gradient).
+ *   R7  n = grad phi / sqrt(|grad phi|^2 + eps^2), eps = eps_n |phi_H - phi_L|
+ *       (eps_n = 1e-6 by default): the unit normal where |grad phi| >> eps,
+ *       zero for a uniform field, and continuous where the gradient vanishes
+ *       (at saddle points of phi, and in the flat far field, where the plain
+ *       unit vector follows the rounding of a vanishing gradient). eps_n = 0
+ *       gives the plain unit normal of Sec. II.A, with n = 0 only where the
+ *       gradient is exactly zero.
  *   R8  grad phi: isotropic D2Q9-weighted difference (six non-zero points per
  *       component).
  *   R9  Laplacian: isotropic nine-point stencil.
@@ -383,10 +385,10 @@ void orc_stencils(int nx, int ny, int walls_y, const double *dx, const double *d
 /* R7: regularised unit normal (eps in gradient units: over the smallest
    cell width on a stretched mesh, R27). */
 static void unit(const orc_sim *s, double gx, double gy, double *nx, double *ny) {
-    double eps = s->mdx ? 1e-6 * s->Dphi / s->dl : 1e-6 * s->Dphi;
+    double eps = s->P.eps_n * fabs(s->Dphi) / (s->mdx ? s->dl : 1.0);
     double m = sqrt(gx * gx + gy * gy + eps * eps);
-    *nx = gx / m;
-    *ny = gy / m;
+    *nx = m > 0.0 ? gx / m : 0.0;
+    *ny = m > 0.0 ? gy / m : 0.0;
 }
 
 /* ------------------------------------------------------ allocation / API */

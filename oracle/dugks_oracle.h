@@ -33,6 +33,8 @@ typedef struct {
     int vel_kind;          /* interface-only model: prescribed velocity */
     double U0, L0, T_period;
     int recon;             /* ORC_RECON_*: face reconstruction of Eq. 27 */
+    double eps_n;          /* R7: regularisation of the unit normal, in units of
+                              |phi_H - phi_L| / delta_l; 0 = the plain unit normal */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
