@@ -1,27 +1,33 @@
 """Benchmark of the phase-field DUGKS step on one MI355X.
 
-Default workload: the coupled (Allen-Cahn + hydrodynamics) stationary bubble,
-128 x 128 periodic, R = 32, density ratio 1000, sigma = 1e-3, nu = 0.1,
-M = 0.1, FP32 step (Sec. IV.A of arXiv:1810.07802). One benchmark step is one
-DUGKS time step of the whole grid; `--steps` of them are timed after
-`--warmup` untimed ones, replayed from a HIP graph on the stream that the
-HIP events time. `value` is MLUPS = cells * steps / s / 1e6.
+Headline workload: the coupled (Allen-Cahn + hydrodynamics) stationary
+bubble of Sec. IV.A of arXiv:1810.07802 (density ratio 1000, sigma = 1e-3,
+nu = 0.1, M = 0.1, W = 5, periodic) on a 4096 x 4096 grid with R = 1024: its
+state (2.8 GB in FP32, two buffers) is far larger than the 256 MB Infinity
+Cache, so the step streams from HBM. One benchmark step is one DUGKS time
+step of the whole grid in FP32. `--warmup` untimed steps run first; then
+every step sequence length that the timed region uses is recorded in its
+HIP graph and replayed once, untimed, so that no graph is built inside the
+timed region; then `--steps` steps are timed with HIP events on the stream
+that replays them. `value` is MLUPS = cells * steps / s / 1e6.
 
 The same JSON line carries:
-  roofline      HBM roofline of the step kernel at this workload (algorithmic
-                bytes: 160 B per cell and step in FP32)
-  large_grid    the same physics on 4096 x 4096 (R = 1024), where the working
-                set (2.8 GB) is far larger than the 256 MB Infinity Cache, with
-                the bandwidth a plain 16-byte copy of the same bytes reaches
-                (copy_ceiling) and the step's fraction of it
+  roofline      HBM roofline of the step kernel on the headline workload
+                (algorithmic bytes: 160 B per cell and step in FP32), with
+                the counter bytes of the committed rocprofv3 profile
+  copy_ceiling  what a plain device copy of the same bytes reaches
+  small_grid    the 128^2 bubble (2.6 MB: cache-resident, latency-bound)
+  rayleigh_taylor  the 256 x 1024 Rayleigh-Taylor case with walls (Sec. IV.D)
   batched       the spinodal batch (64 cases of 64^2..512^2): one graph of
                 batched launches vs one launch per case per step
   served        the served request stream through the continuous-batching
-                pool: p50 / p99 time to solution at 80 % load, aggregate
-                MLUPS, vs the plain sequential per-case loop
-  upwind        the same bubble with the upwind, limited face reconstruction
-                (two kernels per step, 516 algorithmic bytes per cell in
-                FP32), 128^2 and 4096^2, launched step by step
+                pool: p50 / p99 time to solution at 80 % load over 500
+                requests, aggregate MLUPS, vs the plain sequential per-case
+                loop
+  upwind        the bubble with the upwind, limited face reconstruction
+                (two kernels per step), 128^2 and 4096^2; the HBM fraction
+                at the method's 160 B per cell, and beside it the bytes the
+                two-kernel design moves (516 B per cell)
   mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
                 central and upwind, through the same two kernels
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
@@ -40,31 +46,34 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 B_PER_CELL = {"fp32": 160.0, "fp64": 320.0}  # read + write of 18 populations + 2 history values
-# upwind reconstruction / stretched mesh, coupled, FP32: stage 260 (21 state
-# values in; tilde-plus and history, 20 values, out; 18 bar-plus + 6 face
-# inputs out), faces and update 256 (18 bar-plus + 5 face inputs + 20 state
-# values in, 21 values out) bytes per cell
-B_UPWIND = {"fp32": 516.0, "fp64": 1032.0}
+# what the two-kernel step (upwind reconstruction, stretched mesh) moves per
+# cell in FP32 by design: stage 260 (21 state values in; tilde-plus and
+# history, 20 values, out; 18 bar-plus + 6 face inputs out), faces and update
+# 256 (18 bar-plus + 5 face inputs + 20 state values in, 21 values out)
+B_TWO_KERNEL = {"fp32": 516.0, "fp64": 1032.0}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=500)
-    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=200, help="timed steps of the headline workload")
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--large-seg", type=int, default=0,
-                    help="tile (rows per segment) of the 4096x4096 leg; 0: the library's autotuner")
+                    help="tile (rows per segment) of the 4096x4096 workload; 0: the library's autotuner")
+    ap.add_argument("--small-steps", type=int, default=20000)
     ap.add_argument("--batch-steps", type=int, default=500)
-    ap.add_argument("--serve-requests", type=int, default=60,
-                    help="requests of the served stream (0: skip the serving leg)")
+    ap.add_argument("--rti-steps", type=int, default=2000)
+    ap.add_argument("--serve-requests", type=int, default=500,
+                    help="requests of the served stream at 80 %% load (0: skip the serving leg)")
+    ap.add_argument("--serve-sample", type=int, default=100,
+                    help="requests of the closed-loop and sequential passes of the serving leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--skip-extra", action="store_true", help="only the default workload")
+    ap.add_argument("--skip-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--profile-batch", action="store_true",
                     help="run only the batched spinodal leg (one graph per chunk, "
                          "autotuned tiles): for kernel traces")
     ap.add_argument("--profile-kernel", action="store_true",
-                    help="run only the timed default workload (for profilers)")
+                    help="run only the timed 128x128 workload (for profilers)")
     ap.add_argument("--profile-large", action="store_true",
                     help="run only the timed 4096x4096 workload (for profilers)")
     ap.add_argument("--profile-upwind", action="store_true",
@@ -78,60 +87,81 @@ def parse():
     return ap.parse_args()
 
 
-def copy_ceiling(torch, D, nbytes, reps=10):
-    """HBM bandwidth of the library's plain copy (one 16-byte load and store per
-    work item) over `nbytes` read and `nbytes` written, timed with HIP events on
-    the stream it runs on: what a streaming kernel reaches on this device."""
+def copy_ceiling(torch, nbytes, reps=10):
+    """HBM bandwidth of a plain device copy (the measurement library's
+    16-byte copy, one load and store per work item) of `nbytes` read and
+    `nbytes` written, timed with HIP events on the stream it runs on: what a
+    streaming kernel reaches on this device."""
+    import ctypes
+    from paper_1810_07802_amd import build as B
+    probe = ctypes.CDLL(B.PROBE_LIB)
+    probe.copy_probe.restype = ctypes.c_int
+    probe.copy_probe.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     n = max(4, nbytes // 16 * 4)  # float32 elements, a multiple of 16 bytes
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
     nb = 4 * n
+
+    def copy():
+        rc = probe.copy_probe(dst.data_ptr(), src.data_ptr(), nb, stream.cuda_stream)
+        if rc != 0:
+            raise RuntimeError(f"copy probe failed ({rc})")
+
     for _ in range(3):
-        D.copy_probe(dst.data_ptr(), src.data_ptr(), nb, stream.cuda_stream)
+        copy()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        D.copy_probe(dst.data_ptr(), src.data_ptr(), nb, stream.cuda_stream)
+        copy()
     e1.record(stream)
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) / 1e3 / reps
     del src, dst
     return {"GBps": round(2 * nb / t / 1e9, 1), "bytes_read": nb, "bytes_written": nb,
-            "us": round(t * 1e6, 1)}
+            "us": round(t * 1e6, 1), "kernel": "16-byte copy, one load and store per work item"}
 
 
-def timed_graph(torch, D, solvers, steps, warmup, chunk=1000, autotune=False):
-    """Replay `steps` steps of `solvers` (a batch) from HIP graphs of `chunk`
-    launches on torch's current stream; returns seconds measured by HIP events
-    on that stream. With `autotune`, the batch's tiles are picked by the
-    library's autotuner first (outside the timed region)."""
+def timed(torch, stepper, steps, warmup, chunk):
+    """Time `steps` steps of `stepper(n)` (n steps per call, replayed from a
+    HIP graph recorded per call length by the library) in calls of at most
+    `chunk` steps, with HIP events on torch's current stream. First `warmup`
+    steps in calls of at most `chunk`, then one untimed call of every length
+    the timed region uses, so that every graph it replays is already built
+    (and replayed once). Returns (seconds, the lengths replayed untimed)."""
     stream = torch.cuda.current_stream()
-    b = D.Batch(solvers)
-    b.set_stream(stream.cuda_stream)
-    b.tiles = b.autotune(5) if autotune else None
     chunk = max(1, min(chunk, steps))
     w = warmup
     while w > 0:
         n = min(chunk, w)
-        b.step(n, use_graph=True)
+        stepper(n)
         w -= n
-    # make sure every graph used in the timed region is already instantiated
-    rest = steps % chunk
-    if rest:
-        b.step(rest, use_graph=True)
+    lengths = sorted({chunk} | ({steps % chunk} if steps % chunk else set()))
+    for n in lengths:
+        stepper(n)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     left = steps
     while left > 0:
         n = min(chunk, left)
-        b.step(n, use_graph=True)
+        stepper(n)
         left -= n
     e1.record(stream)
     torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3, b
+    return e0.elapsed_time(e1) / 1e3, lengths
+
+
+def batch_timed(torch, D, solvers, steps, warmup, chunk=100, autotune=False):
+    """`steps` steps of a batch of `solvers` replayed from HIP graphs of
+    `chunk` launches (see timed()); with `autotune`, the batch's tiles are
+    picked by the library's autotuner first (outside the timed region)."""
+    b = D.Batch(solvers)
+    b.set_stream(torch.cuda.current_stream().cuda_stream)
+    b.tiles = b.autotune(5) if autotune else None
+    t, _ = timed(torch, lambda n: b.step(n, use_graph=True), steps, warmup, chunk)
+    return t, b
 
 
 def timed_eager(torch, D, solvers, steps):
@@ -143,7 +173,8 @@ def timed_eager(torch, D, solvers, steps):
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for s in solvers:
-        s.step(steps)  # `steps` launches of the step kernel for this case
+        for _ in range(steps):
+            s.step(1)  # one launch of the step kernel (no graph below 8 steps)
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / 1e3
@@ -180,52 +211,41 @@ def roofline(cells, steps, seconds, prec, workload=None):
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
 
 
-def timed_upwind(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
+def timed_two_kernel(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
     """Two-kernel steps of case `c` (coupled FP32): the upwind
     reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
-    reconstruction, on torch's current stream in calls of `chunk` steps (the
-    library replays each call from a HIP graph recorded on first use; the
-    warm-up records every sequence length the timed region uses); seconds by
-    HIP events on that stream."""
-    stream = torch.cuda.current_stream()
+    reconstruction, replayed from HIP graphs (see timed()). The HBM
+    fraction is quoted at the method's 160 B per cell; the bytes the
+    two-kernel design moves (516 B per cell) are reported beside it."""
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
-    s.set_stream(stream.cuda_stream)
+    s.set_stream(torch.cuda.current_stream().cuda_stream)
     if mesh is not None:
         s.set_mesh(*mesh)
     s.init(c["phi"])
-    chunk = max(1, min(chunk, steps))
-    s.step(max(warmup, chunk))
-    if steps % chunk:
-        s.step(steps % chunk)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    left = steps
-    while left > 0:
-        n = min(chunk, left)
-        s.step(n)
-        left -= n
-    e1.record(stream)
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) / 1e3
+    t, _ = timed(torch, s.step, steps, warmup, chunk)
     d = s.diagnostics()
     cells = c["nx"] * c["ny"]
-    ach = B_UPWIND["fp32"] * cells * steps / t / 1e9
+    ach = B_PER_CELL["fp32"] * cells * steps / t / 1e9
+    des = B_TWO_KERNEL["fp32"] * cells * steps / t / 1e9
     return {"mlups": round(cells * steps / t / 1e6, 1), "steps": steps,
-            "us_per_step": round(t / steps * 1e6, 3), "bytes_per_cell": B_UPWIND["fp32"],
+            "us_per_step": round(t / steps * 1e6, 3),
             "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+            "bytes_per_cell": B_PER_CELL["fp32"],
+            "design_bytes_per_cell": B_TWO_KERNEL["fp32"],
+            "design_GBps": round(des, 1), "design_frac_hbm": round(des / HBM_PEAK_GBS, 4),
             "nonfinite": d["nonfinite"]}
 
 
-def served_stream(torch, D, W, n_req):
-    """The served request stream: closed-loop capacity, then Poisson arrivals
-    at 80 % of it (p50 / p99 time to solution, aggregate MLUPS), then the
-    plain sequential per-case loop on the same requests."""
+def served_stream(torch, D, W, n_req, n_sample):
+    """The served request stream: closed-loop capacity on the first
+    `n_sample` requests, then all `n_req` requests arriving as a Poisson
+    stream at 80 % of that capacity (p50 / p99 time to solution, aggregate
+    MLUPS), then the plain sequential per-case loop on the sample."""
     import numpy as np
     from paper_1810_07802_amd import serve
     cases = W.served_stream(n=n_req)
-    lups = [c["nx"] * c["ny"] * c["steps"] for c in cases]
-    mean_lups = float(np.mean(lups))
+    sample = cases[:min(n_sample, n_req)]
+    mean_lups = float(np.mean([c["nx"] * c["ny"] * c["steps"] for c in cases]))
 
     def pool():
         p = D.Pool(8 << 30, max_cases=32, max_cells=1024 * 1024)
@@ -234,32 +254,39 @@ def served_stream(torch, D, W, n_req):
 
     warm = [serve.Request(0, W.bubble(L=64, steps=0), 200, 0.0)]
     serve.run(pool(), warm, chunk=100)
-    # closed loop: everything queued at t = 0
-    reqs = [serve.Request(k, c, c["steps"], 0.0) for k, c in enumerate(cases)]
+    # closed loop: the sample, all queued at t = 0
+    reqs = [serve.Request(k, c, c["steps"], 0.0) for k, c in enumerate(sample)]
     closed = serve.summary(serve.run(pool(), reqs, chunk=200))
+    progress(f"served closed loop: {closed['mlups']:.0f} MLUPS")
     cap = closed["mlups"] * 1e6  # LUP/s
     rate = 0.8 * cap / mean_lups  # requests per second
     arr = np.cumsum(np.random.default_rng(7802).exponential(1.0 / rate, size=len(cases)))
     reqs = [serve.Request(k, c, c["steps"], float(arr[k])) for k, c in enumerate(cases)]
     opened = serve.summary(serve.run(pool(), reqs, chunk=200))
-    # the plain sequential per-case loop: create, init, step, read out, one case at a time
+    progress(f"served at 80% load: {opened['mlups']:.0f} MLUPS")
+    # the plain sequential per-case loop on the sample: create, init, step,
+    # read out, one case at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for c in cases:
+    for c in sample:
         s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
         s.init(c["phi"], c.get("u"), c.get("v"), c.get("p"))
         s.step(c["steps"])
         s.macros()
         del s
     seq = time.perf_counter() - t0
+    lups_sample = sum(c["nx"] * c["ny"] * c["steps"] for c in sample)
     return {"workload": f"{len(cases)} requests: layered Poiseuille (mu ratio 100, nx 64, ny 64..1024) "
                         "and stationary bubbles (64^2..1024^2), 1k-20k steps each (seed 7802), FP32, "
                         "pool of 32 slots and an 8 GiB arena",
+            "requests": len(cases), "failed": opened["failed"],
+            "closed_loop_sample": len(sample),
             "closed_loop_mlups": round(closed["mlups"], 1),
             "arrival_rate_per_s": round(rate, 3), "load": 0.8,
             "served_mlups": round(opened["mlups"], 1),
             "p50_s": round(opened["p50_s"], 4), "p99_s": round(opened["p99_s"], 4),
-            "sequential_mlups": round(sum(lups) / seq / 1e6, 1)}
+            "sequential_sample": len(sample),
+            "sequential_mlups": round(lups_sample / seq / 1e6, 1)}
 
 
 def cpu_baseline(budget_s):
@@ -305,6 +332,24 @@ def cpu_baseline(budget_s):
             "cpu_model": model}
 
 
+def progress(msg):
+    """A line on stderr as each leg ends (the JSON record is the one line on
+    stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def large_solver(D, W, seg):
+    """The headline workload: the bubble on 4096 x 4096, its tile picked by
+    the library's autotuner (outside any timed region) unless `seg` is set."""
+    cl = W.bubble(L=4096, R=1024, steps=0)
+    sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32", seg or None)
+    sl.init(cl["phi"])
+    auto_seg = sl.seg_rows
+    if not seg:
+        sl.autotune(10)
+    return cl, sl, auto_seg
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -321,6 +366,7 @@ def main():
     # captures its HIP graphs on the caller's stream, and the null stream that
     # torch uses by default cannot be captured
     torch.cuda.set_stream(torch.cuda.Stream())
+    stream = torch.cuda.current_stream().cuda_stream
     if args.profile_copy:
         n = 1 << 28  # float32 elements: 1 GiB read + 1 GiB written per copy
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -337,21 +383,19 @@ def main():
                           "copy_GBps": round(8 * n / t / 1e9, 1)}), flush=True)
         return
     if args.profile_large:
-        cl = W.bubble(L=4096, R=1024, steps=0)
-        sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32", args.large_seg or None)
-        sl.init(cl["phi"])
-        seg = sl.seg_rows if args.large_seg else sl.autotune(10)[0]
-        tl, _ = timed_graph(torch, D, [sl], args.large_steps, 5, chunk=args.large_steps)
+        cl, sl, _ = large_solver(D, W, args.large_seg)
+        sl.set_stream(stream)
+        tl, _ = timed(torch, sl.step, args.steps, 5, 1000)
         ncl = cl["nx"] * cl["ny"]
-        print(json.dumps({"workload": "bubble 4096x4096 coupled FP32", "steps": args.large_steps,
-                          "seg_rows": seg, "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
-                          "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}), flush=True)
+        print(json.dumps({"workload": "bubble 4096x4096 coupled FP32", "steps": args.steps,
+                          "seg_rows": sl.seg_rows, "mlups": round(ncl * args.steps / tl / 1e6, 1),
+                          "roofline": roofline(ncl, args.steps, tl, "fp32", "bubble4096")}), flush=True)
         return
     if args.profile_mesh:
         cl = W.bubble(L=4096, R=1024, steps=0)
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, stretched mesh, central",
-                          **timed_upwind(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
+                          **timed_two_kernel(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
               flush=True)
         return
     if args.profile_batch:
@@ -362,7 +406,7 @@ def main():
             t.init(cc["phi"])
             solvers.append(t)
         bc = sum(cc["nx"] * cc["ny"] for cc in cases)
-        tb, bt = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100, autotune=True)
+        tb, bt = batch_timed(torch, D, solvers, args.batch_steps, 20, chunk=100, autotune=True)
         print(json.dumps({"workload": "spinodal batch, 64 cases of 64^2..512^2 (seed 1810), coupled FP32",
                           "cells": bc, "steps": args.batch_steps, "tile_seg_rows": bt.tiles,
                           "batched_graph_mlups": round(bc * args.batch_steps / tb / 1e6, 1),
@@ -371,64 +415,89 @@ def main():
     if args.profile_upwind:
         cl = W.bubble(L=4096, R=1024, steps=0)
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, upwind reconstruction",
-                          **timed_upwind(torch, D, cl, args.upwind_steps, 3)}), flush=True)
+                          **timed_two_kernel(torch, D, cl, args.upwind_steps, 3)}), flush=True)
         return
-    c = W.bubble(L=128, R=32)
-    cells = c["nx"] * c["ny"]
-    s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
-    s.init(c["phi"])
-    secs, batch = timed_graph(torch, D, [s], args.steps, args.warmup)
-    mlups = cells * args.steps / secs / 1e6
+    if args.profile_kernel:
+        c = W.bubble(L=128, R=32)
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        s.set_stream(stream)
+        s.init(c["phi"])
+        secs, _ = timed(torch, s.step, args.small_steps, 500, 1000)
+        cells = c["nx"] * c["ny"]
+        print(json.dumps({"workload": "bubble 128x128 coupled FP32", "steps": args.small_steps,
+                          "mlups": round(cells * args.small_steps / secs / 1e6, 1),
+                          "roofline": roofline(cells, args.small_steps, secs, "fp32", "bubble128")}),
+              flush=True)
+        return
+
+    # ---- headline: the 4096^2 bubble, FP32 coupled step
+    cl, sl, auto_seg = large_solver(D, W, args.large_seg)
+    sl.set_stream(stream)
+    chunk = min(args.steps, 1000)
+    secs, lengths = timed(torch, sl.step, args.steps, args.warmup, chunk)
+    ncl = cl["nx"] * cl["ny"]
+    diag = sl.diagnostics()
     rec = {
         "metric": "MLUPS (coupled AC+hydro step, FP32) + %HBM peak; batched vs plain; p50/p99 solve latency",
-        "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(secs / args.steps * 1e3, 6),
+        "value": round(ncl * args.steps / secs / 1e6, 2), "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(secs / args.steps * 1e3, 6),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "stationary bubble 128x128, R=32, W=5, rho 1000:1, sigma=1e-3, "
+        "config": {"workload": "stationary bubble 4096x4096, R=1024, W=5, rho 1000:1, sigma=1e-3, "
                                "nu=0.1, M=0.1, periodic, coupled FP32 step",
-                   "nx": c["nx"], "ny": c["ny"], "seg_rows": s.seg_rows,
-                   "launch": "HIP graph of 1000 step launches"},
-        "roofline": roofline(cells, args.steps, secs, "fp32", "bubble128"),
+                   "nx": cl["nx"], "ny": cl["ny"], "seg_rows": sl.seg_rows, "auto_seg_rows": auto_seg,
+                   "launch": (f"HIP graphs of {chunk} step launches (graph lengths {lengths} "
+                              "recorded and replayed once before the timed region)"
+                              if chunk >= 8 else "one launch per step")},
+        "roofline": roofline(ncl, args.steps, secs, "fp32", "bubble4096"),
+        "check": {"nonfinite": diag["nonfinite"], "max_u": diag["max_u"]},
     }
-    diag = s.diagnostics()
-    rec["check"] = {"nonfinite": diag["nonfinite"], "max_u": diag["max_u"]}
-    if args.profile_kernel:
-        print(json.dumps(rec), flush=True)
-        return
+    del sl
+    # the same bytes per launch through a plain copy: the practical ceiling
+    cc_ = copy_ceiling(torch, int(B_PER_CELL["fp32"] / 2 * ncl))
+    rec["copy_ceiling"] = cc_
+    rec["frac_of_copy"] = round(rec["roofline"]["achieved"] / cc_["GBps"], 4)
+    progress(f"headline 4096^2: {rec['value']} MLUPS, frac {rec['roofline']['frac']}")
     if not args.skip_extra:
-        # the same step launched one kernel at a time from the host
-        e_steps = min(args.steps, 2000)
+        # the 128^2 bubble: cache-resident, latency-bound
+        c = W.bubble(L=128, R=32)
+        cells = c["nx"] * c["ny"]
+        s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+        s.set_stream(stream)
+        s.init(c["phi"])
+        t_s, _ = timed(torch, s.step, args.small_steps, 500, 1000)
+        e_steps = min(args.small_steps, 2000)
         t_e = timed_eager(torch, D, [s], e_steps)
-        rec["plain_launch_mlups"] = round(cells * e_steps / t_e / 1e6, 2)
-        # FP64 on the same workload
         s64 = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp64")
+        s64.set_stream(stream)
         s64.init(c["phi"])
-        t64, _ = timed_graph(torch, D, [s64], min(args.steps, 5000), 100)
-        rec["fp64_mlups"] = round(cells * min(args.steps, 5000) / t64 / 1e6, 2)
-        del s64
-        # large grid: HBM-resident working set
-        cl = W.bubble(L=4096, R=1024, steps=0)
-        sl = D.Solver(cl["nx"], cl["ny"], cl["params"], "coupled", "fp32")
-        sl.init(cl["phi"])
-        auto_seg = sl.seg_rows
-        if args.large_seg:
-            sl.set_tile(args.large_seg)
-        else:
-            sl.autotune(10)  # tile chosen by the library's autotuner (outside the timed region)
-        tl, _ = timed_graph(torch, D, [sl], args.large_steps, 20, chunk=100)
-        ncl = cl["nx"] * cl["ny"]
-        rec["large_grid"] = {"workload": "stationary bubble 4096x4096, R=1024, coupled FP32",
-                             "mlups": round(ncl * args.large_steps / tl / 1e6, 1),
-                             "steps": args.large_steps, "seg_rows": sl.seg_rows,
-                             "auto_seg_rows": auto_seg,
-                             "roofline": roofline(ncl, args.large_steps, tl, "fp32", "bubble4096")}
-        del sl
-        # the same bytes per launch through a plain copy: the practical ceiling
-        cc_ = copy_ceiling(torch, D, int(B_PER_CELL["fp32"] / 2 * ncl))
-        lg = rec["large_grid"]
-        lg["copy_ceiling"] = cc_
-        lg["frac_of_copy"] = round(lg["roofline"]["achieved"] / cc_["GBps"], 4)
+        n64 = min(args.small_steps, 5000)
+        t64, _ = timed(torch, s64.step, n64, 100, 1000)
+        rec["small_grid"] = {
+            "workload": "stationary bubble 128x128, R=32 (2.6 MB of state: cache-resident, "
+                        "latency-bound), coupled FP32",
+            "mlups": round(cells * args.small_steps / t_s / 1e6, 1),
+            "us_per_step": round(t_s / args.small_steps * 1e6, 3), "seg_rows": s.seg_rows,
+            "launch": "HIP graphs of 1000 step launches",
+            "plain_launch_mlups": round(cells * e_steps / t_e / 1e6, 1),
+            "fp64_mlups": round(cells * n64 / t64 / 1e6, 1)}
+        del s, s64
+        progress(f"small grid: {rec['small_grid']['mlups']} MLUPS")
+        # Rayleigh-Taylor with walls
+        cr = W.rayleigh_taylor(steps=0)
+        sr = D.Solver(cr["nx"], cr["ny"], cr["params"], "coupled", "fp32")
+        sr.set_stream(stream)
+        sr.init(cr["phi"], cr.get("u"), cr.get("v"), cr.get("p"))
+        t_r, _ = timed(torch, sr.step, args.rti_steps, 100, 1000)
+        nr = cr["nx"] * cr["ny"]
+        rec["rayleigh_taylor"] = {
+            "workload": "Rayleigh-Taylor 256x1024, periodic x, no-slip walls in y, At 0.5, Re 3000, "
+                        "coupled FP32 (42 MB of state: Infinity-Cache resident)",
+            "mlups": round(nr * args.rti_steps / t_r / 1e6, 1), "steps": args.rti_steps,
+            "us_per_step": round(t_r / args.rti_steps * 1e6, 3), "seg_rows": sr.seg_rows}
+        del sr
+        progress(f"rayleigh-taylor: {rec['rayleigh_taylor']['mlups']} MLUPS")
         # batched spinodal workload vs the per-case loop
         cases = W.spinodal_batch(steps=0)
         solvers = []
@@ -437,8 +506,8 @@ def main():
             t.init(cc["phi"])
             solvers.append(t)
         bc = sum(cc["nx"] * cc["ny"] for cc in cases)
-        tb_auto, _ = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100)
-        tb, bt = timed_graph(torch, D, solvers, args.batch_steps, 20, chunk=100, autotune=True)
+        tb_auto, _ = batch_timed(torch, D, solvers, args.batch_steps, 20, chunk=100)
+        tb, bt = batch_timed(torch, D, solvers, args.batch_steps, 20, chunk=100, autotune=True)
         tp = timed_eager(torch, D, solvers, args.batch_steps)
         rec["batched"] = {"workload": "spinodal decomposition, 64 cases of 64^2..512^2 "
                                       "(seed 1810), rho 1000:1, coupled FP32",
@@ -449,13 +518,15 @@ def main():
                           "per_case_loop_mlups": round(bc * args.batch_steps / tp / 1e6, 1),
                           "roofline": roofline(bc, args.batch_steps, tb, "fp32")}
         del solvers
+        progress(f"batch: {rec['batched']['batched_graph_mlups']} MLUPS")
         # upwind, limited reconstruction on the same physics
         rec["upwind"] = {
             "workload": "stationary bubble, coupled FP32, upwind reconstruction, two "
                         "kernels per step, replayed from HIP graphs of up to 100 steps",
-            "bubble128": timed_upwind(torch, D, c, min(args.steps, 5000), 100),
-            "bubble4096": timed_upwind(torch, D, W.bubble(L=4096, R=1024, steps=0),
-                                       args.upwind_steps, 5)}
+            "bubble128": timed_two_kernel(torch, D, c, min(args.small_steps, 5000), 100),
+            "bubble4096": timed_two_kernel(torch, D, W.bubble(L=4096, R=1024, steps=0),
+                                           args.upwind_steps, 5)}
+        progress("upwind done")
         # stretched tensor-product mesh, both reconstructions
         cm = W.bubble(L=4096, R=1024, steps=0)
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
@@ -463,10 +534,12 @@ def main():
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
                         "both axes), coupled FP32, two kernels per step, replayed from HIP "
                         "graphs of up to 100 steps",
-            "central": timed_upwind(torch, D, cm, args.upwind_steps, 5, "central", mesh),
-            "upwind": timed_upwind(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
+            "central": timed_two_kernel(torch, D, cm, args.upwind_steps, 5, "central", mesh),
+            "upwind": timed_two_kernel(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
+        progress("mesh done")
         if args.serve_requests > 0:
-            rec["served"] = served_stream(torch, D, W, args.serve_requests)
+            rec["served"] = served_stream(torch, D, W, args.serve_requests, args.serve_sample)
+            progress(f"served: p50 {rec['served']['p50_s']} s, p99 {rec['served']['p99_s']} s")
         rec["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(rec), flush=True)
 

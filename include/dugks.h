@@ -42,7 +42,7 @@ extern "C" {
 #define DUGKS_EINVAL (-1)   /* bad argument or parameter */
 #define DUGKS_ENOMEM (-2)   /* device or host allocation failed */
 #define DUGKS_EDEVICE (-3)  /* HIP runtime error */
-#define DUGKS_ENUMERIC (-4) /* NaN/Inf found by the diagnostics */
+#define DUGKS_ENUMERIC (-4) /* NaN/Inf in the state (sticky; see dugks_sync) */
 #define DUGKS_ESTATE (-5)   /* call out of order (e.g. step before init) */
 #define DUGKS_EBUSY (-6)    /* pool has no room for the request */
 
@@ -92,6 +92,14 @@ enum { DUGKS_RECON_CENTRAL = 0, DUGKS_RECON_UPWIND = 1 };
  *                  pools), and takes (18 + 6) * n values of device
  *                  scratch (coupled; 9 + 6 for interface-only),
  *                  allocated by dugks_set_params.
+ *   eps_n          regularisation of the interface normal of the phase-field
+ *                  source (Eq. 16, n of Sec. II.A):
+ *                  n = grad phi / sqrt(|grad phi|^2 + eps^2) with
+ *                  eps = eps_n |phi_H - phi_L| (over the smallest width on a
+ *                  stretched mesh). eps_n = 0 is the plain unit normal (n = 0
+ *                  where grad phi = 0 exactly); a small eps_n (1e-6, the
+ *                  Python default) keeps n continuous where the gradient
+ *                  vanishes. >= 0.
  */
 typedef struct dugks_params {
     double phi_H, phi_L;
@@ -108,6 +116,7 @@ typedef struct dugks_params {
     int vel_kind;
     double U0, L0, T_period;
     int recon;
+    double eps_n;
 } dugks_params;
 
 typedef struct dugks_handle dugks_handle;
@@ -182,6 +191,11 @@ int dugks_init_fields_device(dugks_handle *h, const double *phi,
 /* Enqueue nsteps >= 0 time steps (Sec. II.B: cell macros, bar-plus and
  * tilde-plus auxiliaries, half-step face reconstruction, face macros and face
  * distributions, microflux, cell update). Asynchronous; ESTATE before init.
+ * Every step checks each updated cell: a non-finite new phi, phi u or p sets
+ * the handle's device flag. A synchronising call that finds the flag set
+ * (dugks_sync, dugks_get_macros, dugks_get_diagnostics, dugks_get_state)
+ * makes the numeric error sticky; from then on dugks_step returns ENUMERIC
+ * without enqueuing anything, until dugks_init_fields or dugks_set_state.
  * On a stream set with dugks_set_stream (not the null stream, and not while
  * the caller captures it), a sequence of 8 or more steps is recorded once in
  * a HIP graph per step count (the last 8 counts are kept, and all are dropped
@@ -189,13 +203,17 @@ int dugks_init_fields_device(dugks_handle *h, const double *phi,
  * the same order, the same results bit for bit. */
 int dugks_step(dugks_handle *h, int nsteps);
 
-/* Wait for the handle's stream. EDEVICE on a sticky device error. */
+/* Wait for the handle's stream and read its non-finite flag. EDEVICE on a
+ * device error; ENUMERIC when a step since the last init produced a
+ * non-finite value (sticky: see dugks_step). */
 int dugks_sync(dugks_handle *h);
 
 /* Cell macros of the current state (Eqs. 31-33 and Eq. 10): phi, u, v, p,
  * rho into host arrays [ny][nx] of double; NULL skips a field. Synchronises
  * the handle's stream. For the interface-only model u, v are the prescribed
- * field at the current time and p = 0. */
+ * field at the current time and p = 0. A readout: returns OK on a non-finite
+ * state too (the values are copied as they are), but makes the numeric error
+ * sticky if the flag is set. */
 int dugks_get_macros(dugks_handle *h, double *phi, double *u, double *v,
                      double *p, double *rho);
 
@@ -247,16 +265,6 @@ int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
  * (see recon) and, for a mesh, 32 (nx + ny) bytes of metrics. */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
 
-/* Bandwidth probe, a measurement aid beside the method (the step's HBM
- * roofline is quoted against what a plain streaming copy reaches on the
- * device): copies `bytes` from device buffer src to device buffer dst, one
- * 16-byte load and store per work item, asynchronously on `stream` (a
- * hipStream_t; NULL is the default stream). Both pointers must be 16-byte
- * aligned, non-overlapping and hold `bytes` (> 0, a multiple of 16); the
- * caller owns both. DUGKS_EINVAL otherwise, DUGKS_EDEVICE if the launch
- * fails; the message is dugks_last_error(NULL). */
-int dugks_copy_probe(void *dst, const void *src, size_t bytes, void *stream);
-
 /* Message of the last error on h (or of the last failed create when h is
  * NULL). Never NULL. */
 const char *dugks_last_error(const dugks_handle *h);
@@ -265,22 +273,43 @@ const char *dugks_last_error(const dugks_handle *h);
 int dugks_destroy(dugks_handle *h);
 
 /* ---------------------------------------------------------------- batches
- * A batch advances several handles of the same precision and model together:
+ * A batch advances several cases of the same precision and model together
+ * (independent grids of uneven sizes, e.g. the spinodal runs of Sec. IV.C):
  * one kernel launch per step covers all of them (work items are the (case,
  * column strip, row segment) tiles of every case), and a step sequence can be
- * recorded once in a HIP graph and replayed. The handles stay usable on their
- * own (set_params, init, get_macros) between batch calls; the batch works on
- * the batch's stream. Handles must outlive the batch. */
+ * recorded once in a HIP graph and replayed. The cases are handles and stay
+ * usable on their own (set_params, init, get_macros) between batch calls;
+ * the batch works on the batch's stream. Work items are built at the first
+ * dugks_batch_step or dugks_batch_autotune, and again when a case's boundary
+ * or explicit tile changes. Every case needs its parameters and state then
+ * (ESTATE otherwise); the upwind reconstruction and stretched meshes are
+ * refused (EINVAL). */
 typedef struct dugks_batch dugks_batch;
 
-int dugks_batch_create(int n, dugks_handle *const *cases, dugks_batch **out);
+/* n cases of nx[k] x ny[k] cells (host arrays, read during the call) in
+ * `precision` and `model`, created and owned by the batch (destroyed with
+ * it). Set up each case through dugks_batch_case. Errors as dugks_create,
+ * naming the case. */
+int dugks_batch_create(int n, const int *nx, const int *ny, int precision,
+                       int model, dugks_batch **out);
+
+/* Case k of a batch (NULL for a bad index or batch): a handle for
+ * dugks_set_params, dugks_init_fields, dugks_get_macros and the other
+ * single-case calls. Owned by the batch when it made the case. */
+dugks_handle *dugks_batch_case(dugks_batch *b, int k);
+
+/* A batch over existing handles (with parameters set, of one precision and
+ * model), which must outlive the batch; the batch does not destroy them. */
+int dugks_batch_create_from(int n, dugks_handle *const *cases,
+                            dugks_batch **out);
 
 /* Advance every active case by nsteps. use_graph = 1 records the sequence of
  * nsteps launches in a HIP graph on first use (per distinct nsteps) and
  * replays it; it needs a stream set with dugks_batch_set_stream (the null
  * stream cannot be captured: EINVAL). Cases with a step budget
  * (dugks_batch_set_budget) stop when it runs out. Asynchronous on the batch
- * stream. */
+ * stream. ENUMERIC (nothing enqueued) while a case's numeric error is sticky
+ * (see dugks_step); the message names the cases. */
 int dugks_batch_step(dugks_batch *b, int nsteps, int use_graph);
 
 /* Limit case k to `steps` more steps (negative = unlimited); takes effect
@@ -288,6 +317,9 @@ int dugks_batch_step(dugks_batch *b, int nsteps, int use_graph);
 int dugks_batch_set_budget(dugks_batch *b, int k, long long steps);
 
 int dugks_batch_set_stream(dugks_batch *b, void *stream);
+/* Wait for the batch stream and read every case's non-finite flag: ENUMERIC
+ * (naming the cases) when one is set; those cases' numeric errors become
+ * sticky. */
 int dugks_batch_sync(dugks_batch *b);
 int dugks_batch_destroy(dugks_batch *b);
 
@@ -336,24 +368,42 @@ size_t dugks_pool_case_bytes(int nx, int ny, int precision, int model);
 int dugks_pool_admit(dugks_pool *p, int nx, int ny, const dugks_params *prm,
                      const double *phi, const double *u, const double *v,
                      const double *pr, long long nsteps, int *slot);
+/* Admit an existing handle (the form of the other calls' cases): its
+ * parameters and its current state (at its current time) are copied into a
+ * new slot, which then runs nsteps steps; the handle itself is left as it
+ * is. Waits for the handle's stream. The handle needs a state (ESTATE), the
+ * pool's precision and model, and the unit mesh with the central
+ * reconstruction (EINVAL); ENUMERIC if its state is non-finite. EBUSY as
+ * dugks_pool_admit. */
+int dugks_pool_admit_handle(dugks_pool *p, dugks_handle *h, long long nsteps,
+                            int *slot);
 /* Enqueue nsteps pool steps: every case with steps left advances by
  * min(nsteps, steps left). use_graph: replay a captured HIP graph while the
  * set of running cases does not change; it needs a stream set with
  * dugks_pool_set_stream (the null stream cannot be captured: EINVAL).
- * Asynchronous. */
+ * Asynchronous. A case whose state turns non-finite is not stopped: the
+ * caller sees it in dugks_pool_status and retires it. */
 int dugks_pool_step(dugks_pool *p, int nsteps, int use_graph);
 /* Steps done and steps left of a slot (host bookkeeping, -1 for a free slot). */
 long long dugks_pool_steps_done(const dugks_pool *p, int slot);
 long long dugks_pool_remaining(const dugks_pool *p, int slot);
 /* Cell macros of a slot's current state, as dugks_get_macros (synchronous:
- * waits for the work queued on the pool's stream). */
+ * waits for the work queued on the pool's stream). ENUMERIC (outputs filled)
+ * when the slot's state is non-finite. */
 int dugks_pool_get_macros(dugks_pool *p, int slot, double *phi, double *u,
                           double *v, double *pr, double *rho);
 /* Free a slot; its arena block is reused once the stream passes this point. */
 int dugks_pool_retire(dugks_pool *p, int slot);
 /* Free arena bytes (blocks whose retirement the stream has passed). */
 size_t dugks_pool_bytes_free(dugks_pool *p);
+/* Wait for the pool's stream and read the non-finite flag of every slot
+ * (see dugks_pool_status). */
 int dugks_pool_sync(dugks_pool *p);
+/* Numeric status of a slot as of the last dugks_pool_sync or
+ * dugks_pool_get_macros: OK, or ENUMERIC when one of its steps produced a
+ * non-finite value (a failed request: only that slot is affected). EINVAL
+ * for a free slot. */
+int dugks_pool_status(const dugks_pool *p, int slot);
 const char *dugks_pool_last_error(const dugks_pool *p);
 int dugks_pool_destroy(dugks_pool *p);
 

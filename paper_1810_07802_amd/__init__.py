@@ -46,13 +46,14 @@ class Params(C.Structure):
         ("vel_kind", C.c_int),
         ("U0", C.c_double), ("L0", C.c_double), ("T_period", C.c_double),
         ("recon", C.c_int),
+        ("eps_n", C.c_double),
     ]
 
 
 _DEFAULTS = dict(phi_H=1.0, phi_L=0.0, rho_H=1.0, rho_L=1.0, mu_H=0.1, mu_L=0.1,
                  nu=0.1, visc="uniform_nu", sigma=0.0, W=4.0, M=0.1, gx=0.0, gy=0.0,
                  gravity="rho_g", Gx=0.0, Gy=0.0, cfl=0.5, walls_y=False,
-                 vel="uniform", U0=0.0, L0=1.0, T_period=1.0, recon="central")
+                 vel="uniform", U0=0.0, L0=1.0, T_period=1.0, recon="central", eps_n=1e-6)
 
 
 def make_params(d: dict) -> Params:
@@ -63,7 +64,7 @@ def make_params(d: dict) -> Params:
     p.update(d)
     s = Params()
     for k in ("phi_H", "phi_L", "rho_H", "rho_L", "mu_H", "mu_L", "nu", "sigma", "W",
-              "gx", "gy", "Gx", "Gy", "cfl", "U0", "L0", "T_period"):
+              "gx", "gy", "Gx", "Gy", "cfl", "U0", "L0", "T_period", "eps_n"):
         setattr(s, k, float(p[k]))
     s.M_phi = float(p["M"])
     s.visc_mode = _VISC[p["visc"]]
@@ -124,10 +125,11 @@ def lib():
             "dugks_get_state": (i, [vp, vp, sz, C.POINTER(ll)]),
             "dugks_set_state": (i, [vp, vp, sz, ll]),
             "dugks_footprint_bytes": (sz, [i, i, i, i]),
-            "dugks_copy_probe": (i, [vp, vp, sz, vp]),
             "dugks_last_error": (C.c_char_p, [vp]),
             "dugks_destroy": (i, [vp]),
-            "dugks_batch_create": (i, [i, C.POINTER(vp), C.POINTER(vp)]),
+            "dugks_batch_create": (i, [i, C.POINTER(i), C.POINTER(i), i, i, C.POINTER(vp)]),
+            "dugks_batch_case": (vp, [vp, i]),
+            "dugks_batch_create_from": (i, [i, C.POINTER(vp), C.POINTER(vp)]),
             "dugks_batch_step": (i, [vp, i, i]),
             "dugks_batch_set_budget": (i, [vp, i, ll]),
             "dugks_batch_set_stream": (i, [vp, vp]),
@@ -139,6 +141,8 @@ def lib():
             "dugks_pool_set_stream": (i, [vp, vp]),
             "dugks_pool_case_bytes": (sz, [i, i, i, i]),
             "dugks_pool_admit": (i, [vp, i, i, C.POINTER(Params), dp, dp, dp, dp, ll, C.POINTER(i)]),
+            "dugks_pool_admit_handle": (i, [vp, vp, ll, C.POINTER(i)]),
+            "dugks_pool_status": (i, [vp, i]),
             "dugks_pool_step": (i, [vp, i, i]),
             "dugks_pool_steps_done": (ll, [vp, i]),
             "dugks_pool_remaining": (ll, [vp, i]),
@@ -232,14 +236,6 @@ def footprint_bytes(nx, ny, precision=FP32, model=MODEL_COUPLED):
     return int(lib().dugks_footprint_bytes(int(nx), int(ny), int(precision), int(model)))
 
 
-def copy_probe(dst_ptr, src_ptr, nbytes, stream=None):
-    """Plain 16-byte device copy of `nbytes` from src_ptr to dst_ptr (device
-    addresses) on `stream`: the bandwidth probe that the step's HBM roofline is
-    compared with."""
-    _check(lib().dugks_copy_probe(C.c_void_p(dst_ptr), C.c_void_p(src_ptr), C.c_size_t(nbytes),
-                                  C.c_void_p(stream)))
-
-
 def destroy(h):
     if h:
         lib().dugks_destroy(h)
@@ -250,7 +246,16 @@ def destroy(h):
 class Solver:
     """One grid: ``Solver(nx, ny, params, model="coupled", precision="fp32")``."""
 
+    @classmethod
+    def _view(cls, h, nx, ny, model, precision):
+        """A Solver over a handle owned elsewhere (a batch's case)."""
+        s = cls.__new__(cls)
+        s.nx, s.ny, s.shape = int(nx), int(ny), (int(ny), int(nx))
+        s.model, s.precision, s.h, s._owned = model, precision, C.c_void_p(h), False
+        return s
+
     def __init__(self, nx, ny, params, model="coupled", precision="fp32", seg_rows=None):
+        self._owned = True
         self.nx, self.ny = int(nx), int(ny)
         self.shape = (self.ny, self.nx)
         self.model = model
@@ -268,12 +273,12 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h:
+        if h and getattr(self, "_owned", True):
             try:
                 destroy(h)
             except Exception:  # interpreter shutdown: module globals may be gone
                 pass
-            self.h = None
+        self.h = None
 
     def set_stream(self, stream):
         set_stream(self.h, stream)
@@ -354,14 +359,37 @@ class Solver:
 
 
 class Batch:
-    """Several solvers of one precision and model advanced together."""
+    """Several solvers of one precision and model advanced together:
+    ``Batch(solvers)`` over existing solvers (dugks_batch_create_from), or
+    ``Batch.create(shapes, model, precision)`` with cases the batch owns
+    (dugks_batch_create), reached as ``batch.case(k)``."""
 
     def __init__(self, solvers):
         self.solvers = list(solvers)
         arr = (C.c_void_p * len(self.solvers))(*[s.h.value for s in self.solvers])
         b = C.c_void_p()
-        _check(lib().dugks_batch_create(len(self.solvers), arr, C.byref(b)), None)
+        _check(lib().dugks_batch_create_from(len(self.solvers), arr, C.byref(b)), None, batch=True)
         self.b = b
+
+    @classmethod
+    def create(cls, shapes, model="coupled", precision="fp32"):
+        """A batch owning len(shapes) new cases of (nx, ny) cells each."""
+        n = len(shapes)
+        nx = (C.c_int * n)(*[int(a) for a, _ in shapes])
+        ny = (C.c_int * n)(*[int(b) for _, b in shapes])
+        b = C.c_void_p()
+        _check(lib().dugks_batch_create(n, nx, ny, FP64 if precision == "fp64" else FP32,
+                                        MODEL_COUPLED if model == "coupled" else MODEL_AC,
+                                        C.byref(b)), None, batch=True)
+        self = cls.__new__(cls)
+        self.b = b
+        self.solvers = [Solver._view(lib().dugks_batch_case(b, k), shapes[k][0], shapes[k][1],
+                                     model, precision) for k in range(n)]
+        return self
+
+    def case(self, k):
+        """Case k as a Solver (set_params via ``set_params``, ``init``, ``macros``)."""
+        return self.solvers[k]
 
     def __del__(self):
         b = getattr(self, "b", None)
@@ -442,6 +470,22 @@ class Pool:
         self._check(rc)
         self.shapes[slot.value] = shape
         return slot.value
+
+    def admit_handle(self, solver, nsteps):
+        """Admit a Solver's parameters and current state as a new case;
+        returns its slot, or None when the pool has no room (EBUSY)."""
+        slot = C.c_int(-1)
+        rc = lib().dugks_pool_admit_handle(self.p, solver.h, int(nsteps), C.byref(slot))
+        if rc == EBUSY:
+            return None
+        self._check(rc)
+        self.shapes[slot.value] = solver.shape
+        return slot.value
+
+    def status(self, slot):
+        """OK (0) or ENUMERIC as of the last ``sync``: a slot whose state
+        went non-finite."""
+        return int(lib().dugks_pool_status(self.p, int(slot)))
 
     def step(self, nsteps, use_graph=True):
         self._check(lib().dugks_pool_step(self.p, int(nsteps), 1 if use_graph else 0))

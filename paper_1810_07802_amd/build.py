@@ -13,6 +13,9 @@ SOURCES = [os.path.join(CSRC, "dugks_kernels.hip"), os.path.join(CSRC, "dugks_ap
            os.path.join(CSRC, "dugks_pool.cpp")]
 HEADERS = [os.path.join(CSRC, "dugks_impl.h"), os.path.join(CSRC, "dugks_host.h"),
            os.path.join(os.path.dirname(HERE), "include", "dugks.h")]
+# the bandwidth probe the benchmark compares the step with (not part of libdugks)
+PROBE_LIB = os.path.join(HERE, "libcopyprobe.so")
+PROBE_SOURCES = [os.path.join(CSRC, "copy_probe.hip")]
 
 
 def hipcc() -> str:
@@ -22,7 +25,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def command(out: str = LIB, extra=()) -> list[str]:
+def command(out: str = LIB, extra=(), sources=None) -> list[str]:
     return [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
             # packed FP32 instructions stay off (see the design notes)
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -31,16 +34,17 @@ def command(out: str = LIB, extra=()) -> list[str]:
             # in every kernel that inlines it (the one-row kernel and the
             # march give the same bits)
             "-ffp-contract=on",
-            "-Wno-unused-command-line-argument", *extra, "-o", out, *SOURCES]
+            "-Wno-unused-command-line-argument", *extra, "-o", out, *(sources or SOURCES)]
 
 
 def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    for lib, src in ((LIB, SOURCES), (PROBE_LIB, PROBE_SOURCES)):
+        tmp = lib + ".tmp"
+        cmd = command(tmp, sources=src)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib)
     return LIB
 
 

@@ -135,6 +135,7 @@ void fill_case(dugks_handle* h) {
   C.dt = P.cfl * dl;
   C.h = 0.5 * C.dt;
   C.mesh = h->mesh ? h->dmesh : nullptr;
+  C.flag = h->dflag;
   C.t0 = 0.0;
   const double D = P.phi_H - P.phi_L;
   C.phi_H = P.phi_H;
@@ -163,7 +164,7 @@ void fill_case(dugks_handle* h) {
   C.T_period = P.T_period;
   // regularisation of the unit normal, in gradient units (over the smallest
   // width on a stretched mesh)
-  C.eps_n2 = (1e-6 * D / dl) * (1e-6 * D / dl);
+  C.eps_n2 = (P.eps_n * D / dl) * (P.eps_n * D / dl);
   C.fb = 3.0 * C.h / (2.0 * C.tau_f + C.dt);
   C.ffb = C.h / (2.0 * C.tau_f + C.h);
   C.gb = 3.0 * C.h / (2.0 * C.tau_g_uniform + C.dt);
@@ -240,6 +241,7 @@ int validate(const dugks_handle* h, const dugks_params* p, std::string& why) {
   if (!(p->phi_H != p->phi_L)) return bad("phi_H must differ from phi_L");
   if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return bad("cfl must lie in (0, 1]");
   if (!(p->W > 0.0)) return bad("W must be > 0");
+  if (!(p->eps_n >= 0.0 && std::isfinite(p->eps_n))) return bad("eps_n must be finite and >= 0");
   if (!(p->sigma >= 0.0)) return bad("sigma must be >= 0");
   if (!(p->M_phi >= 0.0)) return bad("M_phi must be >= 0");
   if (p->bc_y != DUGKS_BC_PERIODIC && p->bc_y != DUGKS_BC_WALLS) return bad("bad bc_y");
@@ -291,6 +293,19 @@ int ensure_up_scratch(dugks_handle* h) {
                 std::string("scratch allocation failed: ") + hipGetErrorString(e));
   }
   return DUGKS_OK;
+}
+
+int poll_flag(dugks_handle* h) {
+  int v = 0;
+  HIPCHK(h, hipMemcpyAsync(&v, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (v) h->numeric_err = true;
+  return DUGKS_OK;
+}
+
+int numeric_fail(dugks_handle* h) {
+  return fail(h, DUGKS_ENUMERIC,
+              "non-finite values in the state (phi, phi u or p); sticky until init_fields or set_state");
 }
 
 int launch_steps(dugks_handle* h, int nsteps) {
@@ -407,6 +422,8 @@ int dugks_create(int nx, int ny, int precision, int model, dugks_handle** out) {
   if (e == hipSuccess) e = hipMalloc(&h->dc, sizeof(CaseDev));
   if (e == hipSuccess) e = hipMalloc(&h->step_base, sizeof(long long));
   if (e == hipSuccess) e = hipMemset(h->step_base, 0, sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&h->dflag, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(h->dflag, 0, sizeof(int));
   if (e != hipSuccess) {
     std::string msg = std::string("device allocation failed: ") + hipGetErrorString(e);
     (void)hipGetLastError();
@@ -498,10 +515,11 @@ int dugks_init_fields_device(dugks_handle* h, const double* phi, const double* u
   h->hc.cur0 = 0;
   h->hc.step0 = 0;
   HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemsetAsync(h->step_base, 0, sizeof(long long), h->stream));
+  HIPCHK(h, dugks::launch_reset(h->step_base, 0, h->dflag, h->stream));
   HIPCHK(h, dugks::launch_init(h->fp64(), h->dc, h->hc, phi, u, v, p, h->stream));
   h->steps = 0;
   h->has_state = true;
+  h->numeric_err = false;
   return DUGKS_OK;
 }
 
@@ -525,6 +543,7 @@ int dugks_init_fields(dugks_handle* h, const double* phi, const double* u, const
 int dugks_step(dugks_handle* h, int nsteps) {
   if (!h || nsteps < 0) return fail(h, DUGKS_EINVAL, "bad arguments");
   if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  if (h->numeric_err) return numeric_fail(h);
   if (nsteps == 0) return DUGKS_OK;
   // graph replay on a created stream that is not being captured by the caller
   bool graph = false;
@@ -542,7 +561,11 @@ int dugks_step(dugks_handle* h, int nsteps) {
 int dugks_sync(dugks_handle* h) {
   if (!h) return DUGKS_EINVAL;
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  return DUGKS_OK;
+  if (h->has_state) {
+    const int rc = poll_flag(h);
+    if (rc) return rc;
+  }
+  return h->numeric_err ? numeric_fail(h) : DUGKS_OK;
 }
 
 int dugks_get_macros_device(dugks_handle* h, double* phi, double* u, double* v, double* p,
@@ -568,7 +591,7 @@ int dugks_get_macros(dugks_handle* h, double* phi, double* u, double* v, double*
   for (int k = 0; k < 5; ++k)
     if (dst[k]) HIPCHK(h, hipMemcpyAsync(dst[k], d[k], b, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
-  return DUGKS_OK;
+  return poll_flag(h);  // a readout, not a failure: the flag only becomes sticky
 }
 
 int dugks_get_diagnostics(dugks_handle* h, double out[8]) {
@@ -591,8 +614,10 @@ int dugks_get_diagnostics(dugks_handle* h, double out[8]) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int k = 0; k < 7; ++k) out[k] = tmp[k];
   out[7] = h->steps * h->hc.dt;
-  if (tmp[6] > 0) return fail(h, DUGKS_ENUMERIC, "non-finite values in the state");
-  return DUGKS_OK;
+  rc = poll_flag(h);
+  if (rc) return rc;
+  if (tmp[6] > 0) h->numeric_err = true;
+  return h->numeric_err ? numeric_fail(h) : DUGKS_OK;
 }
 
 long long dugks_steps_done(const dugks_handle* h) { return h ? h->steps : -1; }
@@ -620,11 +645,11 @@ int dugks_set_state(dugks_handle* h, const void* host_buf, size_t bytes, long lo
   h->hc.step0 = 0;
   HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
   HIPCHK(h, hipMemcpyAsync(h->buf[0], host_buf, bytes, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(h, hipMemcpyAsync(h->step_base, &steps, sizeof(long long), hipMemcpyHostToDevice,
-                           h->stream));
+  HIPCHK(h, dugks::launch_reset(h->step_base, steps, h->dflag, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->steps = steps;
   h->has_state = true;
+  h->numeric_err = false;
   return DUGKS_OK;
 }
 
@@ -647,6 +672,8 @@ int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* 
     if (std::find(use.begin(), use.end(), c) == use.end()) use.push_back(c);
   }
   // the probe steps run on a copy of the state, which is put back afterwards
+  int rc0 = poll_flag(h);  // the probes step the state: clear the flag again if it was clear
+  if (rc0) return rc0;
   const int cur = (h->hc.cur0 + (int)(h->steps & 1)) & 1;
   const long long steps0 = h->steps;
   void* saved = nullptr;
@@ -686,6 +713,7 @@ int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* 
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  if (!h->numeric_err) (void)dugks::launch_reset(nullptr, 0, h->dflag, h->stream);
   (void)hipStreamSynchronize(h->stream);
   (void)hipFree(saved);
   h->steps = steps0;
@@ -710,20 +738,6 @@ size_t dugks_footprint_bytes(int nx, int ny, int precision, int model) {
   return 2 * state_set_bytes(nx, ny, precision, model) + sizeof(CaseDev) + 64;
 }
 
-int dugks_copy_probe(void* dst, const void* src, size_t bytes, void* stream) {
-  if (!dst || !src || bytes == 0 || bytes % 16 != 0 || (reinterpret_cast<uintptr_t>(dst) & 15) ||
-      (reinterpret_cast<uintptr_t>(src) & 15))
-    return fail(nullptr, DUGKS_EINVAL, "copy probe: NULL, unaligned or not a multiple of 16 bytes");
-  const char* a = static_cast<const char*>(src);
-  const char* b = static_cast<const char*>(dst);
-  if (a < b + bytes && b < a + bytes) return fail(nullptr, DUGKS_EINVAL, "copy probe: buffers overlap");
-  const hipError_t e = dugks::launch_copy16(dst, src, (long long)(bytes / 16),
-                                            static_cast<hipStream_t>(stream));
-  if (e != hipSuccess)
-    return fail(nullptr, DUGKS_EDEVICE, std::string("copy probe: ") + hipGetErrorString(e));
-  return DUGKS_OK;
-}
-
 const char* dugks_last_error(const dugks_handle* h) {
   return h ? h->err.c_str() : g_create_error.c_str();
 }
@@ -738,6 +752,7 @@ int dugks_destroy(dugks_handle* h) {
   if (h->dc) (void)hipFree(h->dc);
   if (h->items) (void)hipFree(h->items);
   if (h->step_base) (void)hipFree(h->step_base);
+  if (h->dflag) (void)hipFree(h->dflag);
   if (h->scratch) (void)hipFree(h->scratch);
   if (h->up) (void)hipFree(h->up);
   if (h->dmesh) (void)hipFree(h->dmesh);
@@ -752,6 +767,7 @@ int dugks_destroy(dugks_handle* h) {
 
 struct dugks_batch {
   std::vector<dugks_handle*> cases;
+  bool owns = false;              // cases made by dugks_batch_create: destroyed with the batch
   std::vector<long long> budget;  // remaining steps per case, < 0 = unlimited
   bool fp64 = false, coupled = true;
   hipStream_t stream = nullptr;
@@ -761,6 +777,7 @@ struct dugks_batch {
   int one_row[2] = {1, 1};              // every case of the group has one-row tiles
   int two_row[2] = {1, 1};              // every case of the group has two-row tiles
   std::vector<int> seg;                 // rows per segment used for each case
+  std::vector<long long> bsig;          // what the items were built from (case_sig)
   long long* step_base = nullptr;  // device: global step of the batch
   long long gstep = 0;             // host mirror
   std::vector<CaseDev> hcases;
@@ -834,6 +851,75 @@ hipError_t build_items(dugks_batch* b) {
   return hipSuccess;
 }
 
+// What the work items of a batch depend on: each case's boundary group and
+// explicit tile.
+std::vector<long long> case_sig(const dugks_batch* b) {
+  std::vector<long long> s;
+  for (const auto* h : b->cases) {
+    s.push_back(h->params.bc_y == DUGKS_BC_WALLS ? 1 : 0);
+    s.push_back(h->seg_rows);
+  }
+  return s;
+}
+
+// Segment lengths and work items, built on first use and again when a
+// case's boundary group or explicit tile has changed. Every case needs its
+// parameters; the upwind reconstruction and stretched meshes are refused.
+int ensure_built(dugks_batch* b) {
+  const size_t n = b->cases.size();
+  for (size_t k = 0; k < n; ++k) {
+    dugks_handle* h = b->cases[k];
+    if (!h->has_params) return bfail(b, DUGKS_ESTATE, "case " + std::to_string(k) + " has no params");
+    if (h->general())
+      return bfail(b, DUGKS_EINVAL,
+                   "the upwind reconstruction and stretched meshes run on single handles only");
+  }
+  const std::vector<long long> sig = case_sig(b);
+  if (sig == b->bsig && b->step_base) return DUGKS_OK;
+  // one segment length per boundary group, sized to the whole group
+  std::vector<StripShape> shapes[2];
+  for (size_t k = 0; k < n; ++k) {
+    if (upload_case(b->cases[k]) != DUGKS_OK)
+      return bfail(b, DUGKS_EDEVICE, b->cases[k]->err);
+    const CaseDev& c = b->cases[k]->hc;
+    if (b->cases[k]->seg_rows == 0) shapes[c.walls ? 1 : 0].push_back(StripShape{c.nstrips, c.ny});
+  }
+  int segw[2];
+  for (int w = 0; w < 2; ++w)
+    segw[w] = shapes[w].empty()
+                  ? 1
+                  : auto_seg_rows(shapes[w], wave_capacity(b->fp64, b->coupled, w == 1), b->fp64,
+                                  w == 1);
+  for (size_t k = 0; k < n; ++k) {
+    const int w = b->cases[k]->hc.walls ? 1 : 0;
+    // a case's explicit tile wins over the group's automatic one
+    b->seg[k] = b->cases[k]->seg_rows > 0 ? b->cases[k]->seg_rows : segw[w];
+  }
+  hipError_t e = hipSuccess;
+  if (!b->dcases) e = hipMalloc(&b->dcases, n * sizeof(CaseDev));
+  if (e == hipSuccess && !b->step_base) {
+    e = hipMalloc(&b->step_base, sizeof(long long));
+    if (e == hipSuccess) e = hipMemcpy(b->step_base, &b->gstep, sizeof(long long), hipMemcpyHostToDevice);
+  }
+  if (e == hipSuccess) e = build_items(b);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, e == hipErrorOutOfMemory ? DUGKS_ENOMEM : DUGKS_EDEVICE,
+                 std::string("batch set-up failed: ") + hipGetErrorString(e));
+  }
+  b->bsig = sig;
+  return DUGKS_OK;
+}
+
+// ENUMERIC when a case's numeric error is sticky (message names the cases).
+int numeric_check(dugks_batch* b) {
+  std::string bad;
+  for (size_t k = 0; k < b->cases.size(); ++k)
+    if (b->cases[k]->numeric_err) bad += (bad.empty() ? "" : ", ") + std::to_string(k);
+  if (bad.empty()) return DUGKS_OK;
+  return bfail(b, DUGKS_ENUMERIC, "non-finite values in the state of case(s) " + bad);
+}
+
 int record_steps(dugks_batch* b, int nsteps) {
   StepArgs a{};
   a.cases = b->dcases;
@@ -853,11 +939,51 @@ int record_steps(dugks_batch* b, int nsteps) {
   return DUGKS_OK;
 }
 
+dugks_batch* new_batch(int n, dugks_handle* const* cases, bool owns) {
+  dugks_batch* b = new (std::nothrow) dugks_batch;
+  if (!b) return nullptr;
+  b->cases.assign(cases, cases + n);
+  b->owns = owns;
+  b->budget.assign(n, -1);
+  b->hcases.resize(n);
+  b->seg.assign(n, 2);
+  b->fp64 = cases[0]->fp64();
+  b->coupled = cases[0]->coupled();
+  return b;
+}
+
 }  // namespace
 
 extern "C" {
 
-int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
+int dugks_batch_create(int n, const int* nx, const int* ny, int precision, int model,
+                       dugks_batch** out) {
+  if (!out || n <= 0 || !nx || !ny) return bfail(nullptr, DUGKS_EINVAL, "bad arguments");
+  *out = nullptr;
+  std::vector<dugks_handle*> hs(n, nullptr);
+  for (int k = 0; k < n; ++k) {
+    const int rc = dugks_create(nx[k], ny[k], precision, model, &hs[k]);
+    if (rc != DUGKS_OK) {
+      const std::string m = "case " + std::to_string(k) + ": " + g_create_error;
+      for (auto* h : hs) dugks_destroy(h);
+      return bfail(nullptr, rc, m);
+    }
+  }
+  dugks_batch* b = new_batch(n, hs.data(), true);
+  if (!b) {
+    for (auto* h : hs) dugks_destroy(h);
+    return bfail(nullptr, DUGKS_ENOMEM, "host allocation failed");
+  }
+  *out = b;
+  return DUGKS_OK;
+}
+
+dugks_handle* dugks_batch_case(dugks_batch* b, int k) {
+  if (!b || k < 0 || k >= (int)b->cases.size()) return nullptr;
+  return b->cases[k];
+}
+
+int dugks_batch_create_from(int n, dugks_handle* const* cases, dugks_batch** out) {
   if (!out || n <= 0 || !cases) return bfail(nullptr, DUGKS_EINVAL, "bad arguments");
   *out = nullptr;
   for (int k = 0; k < n; ++k) {
@@ -869,44 +995,13 @@ int dugks_batch_create(int n, dugks_handle* const* cases, dugks_batch** out) {
       return bfail(nullptr, DUGKS_EINVAL,
                    "the upwind reconstruction and stretched meshes run on single handles only");
   }
-  dugks_batch* b = new (std::nothrow) dugks_batch;
+  dugks_batch* b = new_batch(n, cases, false);
   if (!b) return bfail(nullptr, DUGKS_ENOMEM, "host allocation failed");
-  b->cases.assign(cases, cases + n);
-  b->budget.assign(n, -1);
-  b->hcases.resize(n);
-  b->fp64 = cases[0]->fp64();
-  b->coupled = cases[0]->coupled();
-  b->seg.assign(n, 2);
-  // one segment length per boundary group, sized to the whole group
-  std::vector<StripShape> shapes[2];
-  for (int k = 0; k < n; ++k) {
-    if (upload_case(cases[k]) != DUGKS_OK) {
-      std::string m = cases[k]->err;
-      dugks_batch_destroy(b);
-      return bfail(nullptr, DUGKS_EDEVICE, m);
-    }
-    const CaseDev& c = cases[k]->hc;
-    if (cases[k]->seg_rows == 0) shapes[c.walls ? 1 : 0].push_back(StripShape{c.nstrips, c.ny});
-  }
-  int segw[2];
-  for (int w = 0; w < 2; ++w)
-    segw[w] = shapes[w].empty()
-                  ? 1
-                  : auto_seg_rows(shapes[w], wave_capacity(b->fp64, b->coupled, w == 1), b->fp64,
-                                  w == 1);
-  for (int k = 0; k < n; ++k) {
-    const int w = cases[k]->hc.walls ? 1 : 0;
-    // a case's explicit tile wins over the group's automatic one
-    b->seg[k] = cases[k]->seg_rows > 0 ? cases[k]->seg_rows : segw[w];
-  }
-  hipError_t e = hipMalloc(&b->dcases, n * sizeof(CaseDev));
-  if (e == hipSuccess) e = build_items(b);
-  if (e == hipSuccess) e = hipMalloc(&b->step_base, sizeof(long long));
-  if (e == hipSuccess) e = hipMemset(b->step_base, 0, sizeof(long long));
-  if (e != hipSuccess) {
-    std::string m = std::string("batch allocation failed: ") + hipGetErrorString(e);
+  const int rc = ensure_built(b);
+  if (rc != DUGKS_OK) {
+    const std::string m = b->err;
     dugks_batch_destroy(b);
-    return bfail(nullptr, DUGKS_ENOMEM, m);
+    return bfail(nullptr, rc, m);
   }
   *out = b;
   return DUGKS_OK;
@@ -922,8 +1017,16 @@ int dugks_batch_autotune(dugks_batch* b, int probe_steps, int* seg_periodic, int
   if (!b || probe_steps < 1 || probe_steps > 1000) return bfail(b, DUGKS_EINVAL, "bad arguments");
   for (auto* h : b->cases)
     if (!h->has_state) return bfail(b, DUGKS_ESTATE, "a case has no state");
+  int brc = ensure_built(b);
+  if (brc) return brc;
   for (auto* h : b->cases)
     if (h->stream != b->stream) BHIPCHK(b, hipStreamSynchronize(h->stream));
+  // the probes step every case: remember which flags were clear, to clear
+  // them again with the states put back
+  for (auto* h : b->cases) {
+    const int rc = poll_flag(h);
+    if (rc) return bfail(b, rc, h->err);
+  }
   const size_t n = b->cases.size();
   // the current state of every case, put back after each probe
   std::vector<void*> saved(n, nullptr);
@@ -1004,6 +1107,8 @@ int dugks_batch_autotune(dugks_batch* b, int probe_steps, int* seg_periodic, int
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
+  for (auto* h : b->cases)
+    if (!h->numeric_err) (void)dugks::launch_reset(nullptr, 0, h->dflag, b->stream);
   (void)hipStreamSynchronize(b->stream);
   for (void* q : saved)
     if (q) (void)hipFree(q);
@@ -1029,11 +1134,15 @@ int dugks_batch_step(dugks_batch* b, int nsteps, int use_graph) {
                  "(the null stream cannot be captured)");
   for (auto* h : b->cases)
     if (!h->has_state) return bfail(b, DUGKS_ESTATE, "a case has no state");
+  int rc = numeric_check(b);
+  if (rc) return rc;
   if (nsteps == 0) return DUGKS_OK;
+  rc = ensure_built(b);
+  if (rc) return rc;
   // the handles' own work must be finished before the batch touches them
   for (auto* h : b->cases)
     if (h->stream != b->stream) BHIPCHK(b, hipStreamSynchronize(h->stream));
-  int rc = sync_descriptors(b);
+  rc = sync_descriptors(b);
   if (rc) return rc;
   if (use_graph) {
     auto itg = b->graphs.find(nsteps);
@@ -1075,7 +1184,12 @@ int dugks_batch_step(dugks_batch* b, int nsteps, int use_graph) {
 int dugks_batch_sync(dugks_batch* b) {
   if (!b) return DUGKS_EINVAL;
   BHIPCHK(b, hipStreamSynchronize(b->stream));
-  return DUGKS_OK;
+  for (auto* h : b->cases) {
+    if (!h->has_state) continue;
+    const int rc = poll_flag(h);
+    if (rc) return bfail(b, rc, h->err);
+  }
+  return numeric_check(b);
 }
 
 int dugks_batch_destroy(dugks_batch* b) {
@@ -1086,6 +1200,8 @@ int dugks_batch_destroy(dugks_batch* b) {
   for (int w = 0; w < 2; ++w)
     if (b->items[w]) (void)hipFree(b->items[w]);
   if (b->step_base) (void)hipFree(b->step_base);
+  if (b->owns)
+    for (auto* h : b->cases) dugks_destroy(h);
   delete b;
   return DUGKS_OK;
 }

@@ -25,6 +25,8 @@ struct dugks_handle {
   int seg_rows = 0;  // 0: automatic
   long long* step_base = nullptr;  // device: steps done
   long long steps = 0;             // host mirror
+  int* dflag = nullptr;            // device: non-finite flag of the state (CaseDev::flag)
+  bool numeric_err = false;        // sticky: a synchronising call found the flag set
   double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
   void* up = nullptr;              // scratch planes of the two-kernel step
   // stretched mesh: host widths, and the device metric arrays (CaseDev::mesh)
@@ -93,6 +95,9 @@ size_t state_set_bytes(int nx, int ny, int precision, int model);
 int ensure_scratch(dugks_handle* h);
 int ensure_up_scratch(dugks_handle* h);
 int launch_steps(dugks_handle* h, int nsteps);
+// After the handle's stream has been synchronised: read its non-finite flag;
+// a set flag makes the numeric error sticky (until init or set_state).
+int poll_flag(dugks_handle* h);
 
 }  // namespace host
 }  // namespace dugks

@@ -70,7 +70,7 @@ struct CaseDev {
   double dt, h, t0;
   // phase field
   double phi_H, phi_L, phibar, inv_dphi, kappa, beta, theta_c;
-  double eps_n2;  // regularisation of the unit normal: (1e-6 |phi_H - phi_L|)^2
+  double eps_n2;  // regularisation of the unit normal: (eps_n |phi_H - phi_L| / delta_l)^2
   double rho_H, rho_L, drho;
   // density subtracted in the gravity force: the mean density (buoyancy
   // form) or 0 (rho g form), so that both forms are one expression
@@ -90,6 +90,10 @@ struct CaseDev {
   // of the axis length: width, distance to the previous centre, distance to
   // the next centre, centre position (layout in mesh_axis())
   const double* mesh;
+  // non-finite flag of the case (device word): a step that produces a
+  // non-finite phi, phi u or p in one of its cells stores 1 there; the host
+  // clears it at initialisation and reads it after synchronising
+  int* flag;
 };
 
 // Metric arrays of one axis of a stretched mesh.
@@ -154,8 +158,8 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
 int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);
-// plain copy of n16 16-byte words (bandwidth probe)
-hipError_t launch_copy16(void* dst, const void* src, long long n16, hipStream_t s);
+// step_base[0] = value (if not null) and flag[0] = 0 (if not null)
+hipError_t launch_reset(long long* step_base, long long value, int* flag, hipStream_t s);
 hipError_t launch_init(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
                        const double* phi, const double* u, const double* v,
                        const double* p, hipStream_t s);

@@ -137,10 +137,12 @@ __device__ __forceinline__ void g_relax(const CaseDev& C, double phi, double rho
 }
 
 // Unit normal n = grad phi / sqrt(|grad phi|^2 + eps^2): zero for a uniform
-// field, the plain unit vector wherever |grad phi| >> eps.
+// field, the plain unit vector wherever |grad phi| >> eps (eps = 0: the plain
+// unit vector, and 0 where the gradient is exactly 0).
 template <typename T>
 __device__ __forceinline__ void normal(const CaseDev& C, T gx, T gy, T& nx, T& ny) {
-  const T inv = rsqrt_t(gx * gx + gy * gy + T(C.eps_n2));
+  const T m2 = gx * gx + gy * gy + T(C.eps_n2);
+  const T inv = m2 > T(0) ? rsqrt_t(m2) : T(0);
   nx = gx * inv;
   ny = gy * inv;
 }
@@ -572,6 +574,15 @@ __device__ __forceinline__ P* row_ptr(P* base, int row, long long RB) {
   return reinterpret_cast<P*>(((unsigned long long)hi << 32) | lo);
 }
 
+// Non-finite guard of the update: x sums the new phi with phi u and p of
+// the cell stage (a NaN or Inf in f shows in the new phi at once, one in g in
+// u and p of the next step). A lane holding a non-finite sum stores 1 in the
+// case's flag (a plain vector store; nothing is read back on the device).
+template <typename T>
+__device__ __forceinline__ void flag_nonfinite(const CaseDev& C, T x) {
+  if (!__builtin_isfinite(x) && C.flag) *(volatile int*)C.flag = 1;
+}
+
 template <typename T, bool CPL>
 struct RowData {
   Cell<T> cell;
@@ -764,6 +775,7 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
   if (store) {
     store_groups<T, NV, OPQ>(orow, PB, (unsigned)ci, nv);
     gstore<T>(orow + NV * PB, OPQ ? lane_off((unsigned)ci * es) : (unsigned)ci * es, phin);
+    flag_nonfinite(C, phin + cur_r.cell.hx + cur_r.cell.hy + cur_r.cell.p);
   }
 }
 
@@ -1238,16 +1250,17 @@ __global__ __launch_bounds__(256) void k_step_row2(StepArgs A) {
   }
 }
 
-// Plain device copy, one work item per 16 bytes: the bandwidth a streaming
-// kernel reaches on the device, the practical ceiling of the step's traffic.
-__global__ __launch_bounds__(256) void k_copy16(const uint4* __restrict__ src,
-                                                uint4* __restrict__ dst, long long n16) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i < n16) dst[i] = src[i];
-}
-
 __global__ void k_advance(long long* step_base, long long by) {
   if (threadIdx.x == 0 && blockIdx.x == 0) step_base[0] += by;
+}
+
+// Set a step counter and clear a non-finite flag (a kernel rather than
+// memsets, so that a caller may capture it in a graph).
+__global__ void k_reset(long long* step_base, long long value, int* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (step_base) step_base[0] = value;
+    if (flag) flag[0] = 0;
+  }
 }
 
 // ------------------------------------------------------------ init / macros
@@ -1396,24 +1409,19 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
   at(val_phi(CPL)) = s;
 }
 
-// Cell macros of a state (Eqs. 31-33, 10) into double arrays.
+// Cell macros of cell (i, j) of a state (Eqs. 31-33, 10): phi, u, v, p in
+// the working precision, rho in double.
 template <typename T, bool CPL>
-__global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
-                         double* __restrict__ ophi, double* __restrict__ ou,
-                         double* __restrict__ ov, double* __restrict__ op,
-                         double* __restrict__ orho) {
-  const CaseDev& C = *Cd;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i >= C.nx || j >= C.ny) return;
-  const long long c = (long long)j * C.nx + i, rv = C.row_vals;
-  const T* __restrict__ st = static_cast<const T*>(C.set[buf]);
+__device__ __forceinline__ void cell_macros(const CaseDev& C, const T* __restrict__ st, int i,
+                                            int j, double t, T& phi, T& u, T& v, T& p,
+                                            double& rhoD) {
+  const long long rv = C.row_vals;
   T ph[3][3];
   gather3x3<T, T>(st + state_index(val_phi(CPL), 0, 0, C.nx, rv, CPL), rv, i, j, C.nx, C.ny,
                   C.walls, ph);
-  const T phi = ph[1][1];
-  const double rhoD = rho_of(C, (double)phi);
-  T u, v, p = T(0);
+  phi = ph[1][1];
+  rhoD = rho_of(C, (double)phi);
+  p = T(0);
   if (CPL) {
     T gx, gy, lap;
     cell_stencils<T>(C, ph, i, j, gx, gy, lap);
@@ -1439,6 +1447,22 @@ __global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
     cell_centre(C, i, j, xc, yc);
     presc_vel<T>(C, xc, yc, t, u, v);
   }
+}
+
+// Cell macros of a state into double arrays.
+template <typename T, bool CPL>
+__global__ void k_macros(const CaseDev* __restrict__ Cd, int buf, double t,
+                         double* __restrict__ ophi, double* __restrict__ ou,
+                         double* __restrict__ ov, double* __restrict__ op,
+                         double* __restrict__ orho) {
+  const CaseDev& C = *Cd;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= C.nx || j >= C.ny) return;
+  const long long c = (long long)j * C.nx + i;
+  T phi, u, v, p;
+  double rhoD;
+  cell_macros<T, CPL>(C, static_cast<const T*>(C.set[buf]), i, j, t, phi, u, v, p, rhoD);
   if (ophi) ophi[c] = (double)phi;
   if (ou) ou[c] = (double)u;
   if (ov) ov[c] = (double)v;
@@ -2074,6 +2098,7 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   }
   store_groups<T, NV>(orow, PB, (unsigned)i, v);
   gstore<T>(orow + NV * PB, (unsigned)i * (unsigned)sizeof(T), phin);
+  flag_nonfinite(C, phin + v[val_hist(CPL, 0)] + v[val_hist(CPL, 1)]);
 }
 
 }  // namespace
@@ -2163,17 +2188,13 @@ int step_waves_per_cu(bool fp64, bool coupled, bool walls) {
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
-hipError_t launch_copy16(void* dst, const void* src, long long n16, hipStream_t s) {
-  if (n16 <= 0) return hipSuccess;
-  const long long blocks = (n16 + 255) / 256;
-  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s,
-                     static_cast<const uint4*>(src), static_cast<uint4*>(dst), n16);
+hipError_t launch_advance(long long* step_base, long long by, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, step_base, by);
   return hipGetLastError();
 }
 
-hipError_t launch_advance(long long* step_base, long long by, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, step_base, by);
+hipError_t launch_reset(long long* step_base, long long value, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, step_base, value, flag);
   return hipGetLastError();
 }
 

@@ -44,6 +44,8 @@ struct dugks_pool {
   std::vector<size_t> off, bytes;   // arena block of the slot
   CaseDev* sdc = nullptr;           // device: per-slot descriptor (init, readout)
   long long* scount = nullptr;      // device: per-slot step counter (init, readout)
+  int* sflags = nullptr;            // device: per-slot non-finite flag (CaseDev::flag)
+  std::vector<int> hflags;          // host copy of sflags as of the last dugks_pool_sync
   CaseDev* dcases = nullptr;        // device: per-slot descriptor of the pool steps
   long long* step_base = nullptr;   // device: pool step counter
   long long gstep = 0;              // host mirror
@@ -232,11 +234,14 @@ int dugks_pool_create(size_t hbm_bytes, int max_cases, long long max_cells, int 
   p->bytes.assign(max_cases, 0);
   p->hcases.assign(max_cases, CaseDev{});
   p->running.assign(max_cases, 0);
+  p->hflags.assign(max_cases, 0);
   const size_t staging = 5 * (size_t)max_cells + (size_t)kDiagBlocks * 7 + 16;
   hipError_t e = hipMalloc(&p->arena, p->arena_bytes);
   if (e == hipSuccess) e = hipMalloc(&p->sdc, max_cases * sizeof(CaseDev));
   if (e == hipSuccess) e = hipMalloc(&p->dcases, max_cases * sizeof(CaseDev));
   if (e == hipSuccess) e = hipMalloc(&p->scount, max_cases * sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc(&p->sflags, max_cases * sizeof(int));
+  if (e == hipSuccess) e = hipMemset(p->sflags, 0, max_cases * sizeof(int));
   if (e == hipSuccess) e = hipMalloc(&p->step_base, sizeof(long long));
   if (e == hipSuccess) e = hipMalloc(&p->staging, staging * sizeof(double));
   if (e == hipSuccess) e = hipMemset(p->step_base, 0, sizeof(long long));
@@ -268,10 +273,17 @@ size_t dugks_pool_case_bytes(int nx, int ny, int precision, int model) {
   return 2 * round_up(state_set_bytes(nx, ny, precision, model));
 }
 
-int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, const double* phi,
-                     const double* u, const double* v, const double* pr, long long nsteps,
-                     int* slot_out) {
-  if (!p || !prm || !phi || !slot_out || nsteps < 0) return pfail(p, DUGKS_EINVAL, "bad arguments");
+}  // extern "C"
+
+namespace {
+
+// A slot and an arena block for a case of nx x ny with parameters prm; the
+// new handle has the parameters set and both buffers cleared. `fill` then
+// builds local step 0 in buffer 0 on the pool's stream. On success the slot
+// is taken and *slot_out set.
+template <typename Fill>
+int admit_case(dugks_pool* p, int nx, int ny, const dugks_params* prm, long long nsteps,
+               int* slot_out, Fill fill) {
   if (nx < 3 || ny < 3) return pfail(p, DUGKS_EINVAL, "nx and ny must be >= 3");
   if ((size_t)nx * ny > p->max_cells) return pfail(p, DUGKS_EINVAL, "case larger than max_cells");
   if ((long long)nx * ny > (1LL << 32) / (4 * (p->fp64() ? 8 : 4)))
@@ -306,20 +318,10 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
   }
   h->dc = p->sdc + k;
   h->step_base = p->scount + k;
+  h->dflag = p->sflags + k;
   h->scratch = p->staging;
   int rc = dugks_set_params(h, prm);
-  if (rc == DUGKS_OK) {
-    // host fields into the staging area, then the initial state; all
-    // on the pool stream, so the staging area is reused in order
-    const size_t n = h->n(), b = n * sizeof(double);
-    const double* src[4] = {phi, u, v, pr};
-    double* d[4] = {p->staging, p->staging + n, p->staging + 2 * n, p->staging + 3 * n};
-    for (int i = 0; i < 4 && rc == DUGKS_OK; ++i)
-      if (src[i] && hipMemcpyAsync(d[i], src[i], b, hipMemcpyHostToDevice, p->stream) != hipSuccess)
-        rc = hip_fail(h, hipGetLastError(), "hipMemcpyAsync");
-    if (rc == DUGKS_OK)
-      rc = dugks_init_fields_device(h, d[0], u ? d[1] : nullptr, v ? d[2] : nullptr, pr ? d[3] : nullptr);
-  }
+  if (rc == DUGKS_OK) rc = fill(h);
   if (rc != DUGKS_OK) {
     std::string m = h->err;
     delete h;
@@ -333,6 +335,7 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
     return pfail(p, rc, m);
   }
   p->slot[k] = h;
+  p->hflags[k] = 0;
   p->target[k] = nsteps;
   p->start[k] = p->gstep;
   p->off[k] = o;
@@ -340,6 +343,60 @@ int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, con
   p->dirty = true;
   *slot_out = k;
   return DUGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dugks_pool_admit(dugks_pool* p, int nx, int ny, const dugks_params* prm, const double* phi,
+                     const double* u, const double* v, const double* pr, long long nsteps,
+                     int* slot_out) {
+  if (!p || !prm || !phi || !slot_out || nsteps < 0) return pfail(p, DUGKS_EINVAL, "bad arguments");
+  return admit_case(p, nx, ny, prm, nsteps, slot_out, [&](dugks_handle* h) {
+    // host fields into the staging area, then the initial state; all on the
+    // pool stream, so the staging area is reused in order
+    const size_t n = h->n(), b = n * sizeof(double);
+    const double* src[4] = {phi, u, v, pr};
+    double* d[4] = {p->staging, p->staging + n, p->staging + 2 * n, p->staging + 3 * n};
+    for (int i = 0; i < 4; ++i)
+      if (src[i] && hipMemcpyAsync(d[i], src[i], b, hipMemcpyHostToDevice, p->stream) != hipSuccess)
+        return hip_fail(h, hipGetLastError(), "hipMemcpyAsync");
+    return dugks_init_fields_device(h, d[0], u ? d[1] : nullptr, v ? d[2] : nullptr,
+                                    pr ? d[3] : nullptr);
+  });
+}
+
+int dugks_pool_admit_handle(dugks_pool* p, dugks_handle* src, long long nsteps, int* slot_out) {
+  if (!p || !src || !slot_out || nsteps < 0) return pfail(p, DUGKS_EINVAL, "bad arguments");
+  if (src->borrowed) return pfail(p, DUGKS_EINVAL, "the handle is a pool case");
+  if (src->precision != p->precision || src->model != p->model)
+    return pfail(p, DUGKS_EINVAL, "the handle's precision and model must be the pool's");
+  if (src->general())
+    return pfail(p, DUGKS_EINVAL,
+                 "the upwind reconstruction and stretched meshes run on single handles only");
+  if (!src->has_state) return pfail(p, DUGKS_ESTATE, "the handle has no state (init_fields first)");
+  // the handle's queued steps must be done before its state is copied
+  if (hipStreamSynchronize(src->stream) != hipSuccess)
+    return pfail(p, DUGKS_EDEVICE, "synchronising the handle's stream failed");
+  if (poll_flag(src) != DUGKS_OK) return pfail(p, DUGKS_EDEVICE, src->err);
+  if (src->numeric_err) return pfail(p, DUGKS_ENUMERIC, "the handle's state is non-finite");
+  const int cur = (src->hc.cur0 + (int)(src->steps & 1)) & 1;
+  return admit_case(p, src->nx, src->ny, &src->params, nsteps, slot_out, [&](dugks_handle* h) {
+    // the handle's current state becomes local step 0 (buffer 0) at its time
+    h->hc.cur0 = 0;
+    h->hc.step0 = 0;
+    h->hc.t0 = src->hc.t0 + (double)src->steps * src->hc.dt;
+    HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, p->stream));
+    HIPCHK(h, hipMemcpyAsync(h->buf[0], src->buf[cur], src->buf_bytes, hipMemcpyDeviceToDevice,
+                             p->stream));
+    HIPCHK(h, dugks::launch_reset(h->step_base, 0, h->dflag, p->stream));
+    // h->hc is a member of the new handle: the copy above may run later
+    HIPCHK(h, hipStreamSynchronize(p->stream));
+    h->steps = 0;
+    h->has_state = true;
+    return DUGKS_OK;
+  });
 }
 
 int dugks_pool_step(dugks_pool* p, int nsteps, int use_graph) {
@@ -393,7 +450,16 @@ int dugks_pool_get_macros(dugks_pool* p, int k, double* phi, double* u, double* 
   h->steps = p->done(k);  // local step the state is at once the stream has run
   const int rc = dugks_get_macros(h, phi, u, v, pr, rho);
   if (rc) return pfail(p, rc, h->err);
+  if (h->numeric_err) {
+    p->hflags[k] = 1;
+    return pfail(p, DUGKS_ENUMERIC, "non-finite values in the state of slot " + std::to_string(k));
+  }
   return DUGKS_OK;
+}
+
+int dugks_pool_status(const dugks_pool* p, int k) {
+  if (!p || k < 0 || k >= p->max_cases || !p->slot[k]) return DUGKS_EINVAL;
+  return p->hflags[k] ? DUGKS_ENUMERIC : DUGKS_OK;
 }
 
 int dugks_pool_retire(dugks_pool* p, int k) {
@@ -419,7 +485,13 @@ size_t dugks_pool_bytes_free(dugks_pool* p) {
 
 int dugks_pool_sync(dugks_pool* p) {
   if (!p) return DUGKS_EINVAL;
+  PHIPCHK(p, hipMemcpyAsync(p->hflags.data(), p->sflags, p->hflags.size() * sizeof(int),
+                            hipMemcpyDeviceToHost, p->stream));
   PHIPCHK(p, hipStreamSynchronize(p->stream));
+  for (int k = 0; k < p->max_cases; ++k) {
+    if (!p->slot[k]) p->hflags[k] = 0;
+    else if (p->hflags[k]) p->slot[k]->numeric_err = true;
+  }
   return DUGKS_OK;
 }
 
@@ -437,6 +509,7 @@ int dugks_pool_destroy(dugks_pool* p) {
   if (p->sdc) (void)hipFree(p->sdc);
   if (p->dcases) (void)hipFree(p->dcases);
   if (p->scount) (void)hipFree(p->scount);
+  if (p->sflags) (void)hipFree(p->sflags);
   if (p->step_base) (void)hipFree(p->step_base);
   if (p->staging) (void)hipFree(p->staging);
   for (int w = 0; w < 2; ++w)

@@ -9,10 +9,15 @@ out every case that has reached its step count, and retires it so that its
 slot and memory can be reused. It reports each request's time to solution
 (arrival to result on the host).
 
+A request whose state turns non-finite (NaN or Inf: the pool reports
+ENUMERIC for its slot after a sync) fails alone: it is retired at once with
+``error`` set, its slot and memory return to the pool, and every other
+request goes on unaffected.
+
 The pool can be the HIP one (``paper_1810_07802_amd.Pool``) or any object
-with the same methods (``admit``, ``step``, ``remaining``, ``macros``,
-``retire``, ``sync``), which is how the scheduling logic is tested without a
-GPU.
+with the same methods (``admit``, ``step``, ``remaining``, ``status``,
+``macros``, ``retire``, ``sync``), which is how the scheduling logic is
+tested without a GPU.
 """
 from __future__ import annotations
 
@@ -38,6 +43,7 @@ class Served:
     admitted: float
     finished: float
     macros: dict | None = field(default=None, repr=False)
+    error: str | None = None  # "ENUMERIC": the state went non-finite (no result)
 
     @property
     def tts(self) -> float:
@@ -77,15 +83,22 @@ def run(pool, requests, chunk=100, keep=None, use_graph=True, clock=time.perf_co
                 sleep(max(0.0, pending[0].arrival - (clock() - t0)))
             continue
         pool.step(chunk, use_graph)
-        done = [s for s in active if pool.remaining(s) == 0]
         # one chunk in flight: the wait keeps the host from queueing ahead of
-        # the device, so that new arrivals join at the next chunk
+        # the device, so that new arrivals join at the next chunk; it also
+        # brings every slot's numeric status up to date
+        pool.sync()
+        failed = [s for s in active if pool.status(s) != 0]
+        done = [s for s in active if s not in failed and pool.remaining(s) == 0]
         results = {}
         for s in done:
             r, _ = active[s]
             results[s] = pool.macros(s) if (keep is None or keep(r)) else None
-        pool.sync()
         fin = clock() - t0
+        for s in failed:
+            r, adm = active.pop(s)
+            pool.retire(s)
+            out.append(Served(r.rid, r.case["nx"] * r.case["ny"], r.steps, r.arrival, adm, fin,
+                              None, "ENUMERIC"))
         for s in done:
             r, adm = active.pop(s)
             pool.retire(s)
@@ -97,10 +110,11 @@ def run(pool, requests, chunk=100, keep=None, use_graph=True, clock=time.perf_co
 def summary(served, makespan=None):
     """p50 / p99 time to solution and aggregate MLUPS of a served run."""
     import numpy as np
-    tts = np.array([s.tts for s in served])
-    lups = float(sum(s.cells * s.steps for s in served))
+    ok = [s for s in served if s.error is None]
+    tts = np.array([s.tts for s in ok])
+    lups = float(sum(s.cells * s.steps for s in ok))
     if makespan is None:
         makespan = max(s.finished for s in served) - min(s.arrival for s in served)
-    return {"requests": len(served), "p50_s": float(np.percentile(tts, 50)),
+    return {"requests": len(served), "failed": len(served) - len(ok), "p50_s": float(np.percentile(tts, 50)),
             "p99_s": float(np.percentile(tts, 99)), "mlups": lups / makespan / 1e6,
             "makespan_s": makespan}

@@ -62,12 +62,18 @@ def test_null_and_bad_arguments_do_not_crash():
     with pytest.raises(D.DugksError) as e:
         D.Batch([])
     assert e.value.code == D.EINVAL
-    # the copy probe checks its arguments before touching the device
-    for dst, src, n in ((0, 0, 16), (0x1000, 0x2000, 15), (0x1008, 0x2000, 16),
-                        (0x1000, 0x1010, 32), (0x1000, 0x2000, 0)):
-        with pytest.raises(D.DugksError) as e:
-            D.copy_probe(dst, src, n)
-        assert e.value.code == D.EINVAL and "copy probe" in str(e.value)
+    # batch constructors and case access check their arguments first
+    import ctypes as C
+    b = C.c_void_p()
+    assert L.dugks_batch_create(0, None, None, D.FP32, D.MODEL_COUPLED, C.byref(b)) == D.EINVAL
+    nx = (C.c_int * 1)(2)
+    assert L.dugks_batch_create(1, nx, nx, D.FP32, D.MODEL_COUPLED, C.byref(b)) == D.EINVAL
+    assert L.dugks_batch_case(None, 0) is None
+    assert L.dugks_batch_create_from(1, None, C.byref(b)) == D.EINVAL
+    # pool calls on a NULL pool
+    slot = C.c_int(-1)
+    assert L.dugks_pool_admit_handle(None, None, 10, C.byref(slot)) == D.EINVAL
+    assert L.dugks_pool_status(None, 0) == D.EINVAL
     # size limit of the C ABI: at most 2^28 cells in FP32 and 2^27 in FP64
     # (rejected before any device allocation)
     for nx, ny, prec in ((1 << 15, 1 << 14, D.FP32), (1 << 14, 1 << 14, D.FP64)):

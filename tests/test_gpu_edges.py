@@ -94,21 +94,6 @@ def test_empty_step_requests_change_nothing():
     assert s.steps_done == n0 and np.array_equal(s.get_state()[0], before)
 
 
-@pytest.mark.parametrize("nbytes", [16, 16 * 257, 16 * 1000003])
-def test_copy_probe_copies_exactly(nbytes):
-    """The bandwidth probe that the large-grid roofline is compared with: a
-    plain copy, exact to the byte, for one word, a ragged last work group and
-    a large buffer; the bytes past the end stay untouched."""
-    import torch
-    g = torch.Generator(device="cpu").manual_seed(nbytes)
-    src = torch.randint(0, 256, (nbytes,), dtype=torch.uint8, generator=g).cuda()
-    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
-    D.copy_probe(dst.data_ptr(), src.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
-    assert torch.equal(dst[:nbytes].cpu(), src.cpu())
-    assert int(dst[nbytes:].sum()) == 0
-
-
 def _decode_state(buf, nx, ny, coupled, dtype):
     """Split a saved state by the layout dugks.h documents: ny rows, each the
     value groups of its nx cells (groups of four consecutive values,

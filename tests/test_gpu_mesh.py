@@ -216,7 +216,8 @@ def test_rayleigh_taylor_full_size_on_a_clustered_mesh(recon):
     o = orc(c, dx, dy, 50)
     g, r = s.macros(), o.macros()
     assert rel(g["phi"], r["phi"]) < 1e-12
-    # u, v, p start from rest and are small residuals after 50 steps: judged
+    # u, v start from rest (p from the hydrostatic base state); after 50 steps
+    # their differences are small residuals: judged
     # against the flow's scales U = sqrt(g L0) = 0.04 and rho_H U / 3
     U = 0.04
     for k, sc in {"u": U, "v": U, "p": c["params"]["rho_H"] / 3.0 * U}.items():

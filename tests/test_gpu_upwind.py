@@ -203,7 +203,8 @@ def test_rayleigh_taylor_full_size_fp64():
 
 
 def _residuals_within_scale(c, g, r):
-    """u, v, p start from rest and are small residuals after 50 steps: judged
+    """u, v start from rest (p from the hydrostatic base state) and after 50
+    steps differ by small residuals: judged
     against the flow's scales U = sqrt(g L0) = 0.04 and rho_H U / 3 (as the
     central path's test of this configuration)."""
     U = 0.04

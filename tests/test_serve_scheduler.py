@@ -11,8 +11,10 @@ class FakePool:
     one step of the running set costs `cost` seconds of simulated time per
     running case, advanced on `clock`."""
 
-    def __init__(self, budget, max_cases, clock, cost=1e-3):
+    def __init__(self, budget, max_cases, clock, cost=1e-3, poison=()):
         self.budget, self.max_cases, self.clock, self.cost = budget, max_cases, clock, cost
+        self.poison = set(poison)  # rids whose state goes non-finite at their first step
+        self.bad = set()           # slots whose state is non-finite
         self.used = 0
         self.slots = {}  # slot -> [remaining, bytes, done]
         self.admit_log, self.step_log = [], []
@@ -24,6 +26,8 @@ class FakePool:
             return None
         k = free[0]
         self.slots[k] = [steps, b, 0]
+        self.rid_of = getattr(self, "rid_of", {})
+        self.rid_of[k] = case["rid"]
         self.used += b
         self.admit_log.append((case["rid"], self.clock.t))
         return k
@@ -31,6 +35,9 @@ class FakePool:
     def step(self, n, use_graph=True):
         running = [s for s in self.slots.values() if s[0] > 0]
         self.step_log.append(len(running))
+        for k, s in self.slots.items():
+            if s[0] > 0 and self.rid_of[k] in self.poison:
+                self.bad.add(k)
         for s in running:
             d = min(n, s[0])
             s[0] -= d
@@ -40,11 +47,15 @@ class FakePool:
     def remaining(self, k):
         return self.slots[k][0]
 
+    def status(self, k):
+        return -4 if k in self.bad else 0
+
     def macros(self, k):
         return {"done": self.slots[k][2]}
 
     def retire(self, k):
         self.used -= self.slots.pop(k)[1]
+        self.bad.discard(k)
 
     def sync(self):
         pass
@@ -135,3 +146,23 @@ def test_summary_percentiles():
     m = serve.summary(s)
     assert m["p50_s"] == pytest.approx(50.5) and m["p99_s"] == pytest.approx(99.01)
     assert m["mlups"] == pytest.approx(100 * 100 * 10 / 100.0 / 1e6)
+
+
+def test_a_request_that_goes_non_finite_fails_alone_and_frees_its_slot():
+    """The pool reports ENUMERIC for one slot (its state went non-finite):
+    that request is retired with an error at the next look, its slot and
+    memory are reused, and every other request completes with its result."""
+    clk = Clock()
+    pool = FakePool(budget=3 * 64 * 64 * 168, max_cases=2, clock=clk, poison={1})
+    reqs = [req(k, 64, 100, 0.0) for k in range(5)]
+    out = serve.run(pool, reqs, chunk=20, clock=clk, sleep=clk.sleep)
+    by = {s.rid: s for s in out}
+    assert sorted(by) == list(range(5))
+    assert by[1].error == "ENUMERIC" and by[1].macros is None
+    # failed at the first look, long before its 100 steps
+    assert by[1].finished - by[1].admitted <= 20 * pool.cost * 2 + 1e-12
+    for k in (0, 2, 3, 4):
+        assert by[k].error is None and by[k].macros["done"] == 100
+    assert not pool.slots and pool.used == 0
+    summ = serve.summary(out)
+    assert summ["failed"] == 1 and summ["requests"] == 5

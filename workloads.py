@@ -127,12 +127,31 @@ def bubble(L=128, R=None, W=5.0, rho_H=1000.0, rho_L=1.0, sigma=1e-3,
     return _case(f"bubble_{L}", L, L, "coupled", params, phi, steps=steps)
 
 
+def hydrostatic_pressure(phi, params):
+    """Initial pressure of a fluid at rest under gravity: the hydrostatic
+    pressure of the row-averaged density profile, dp/dy = G_y with
+    G = (rho - rho_ref) g (rho_ref the mean density in the buoyancy form, 0
+    otherwise) and rho linear in phi between the phases, integrated along y
+    by the trapezoid rule and shifted to zero mean. Shape of ``phi``."""
+    p = params
+    s = np.clip((phi - p["phi_L"]) / (p["phi_H"] - p["phi_L"]), 0.0, 1.0)
+    rho = (p["rho_L"] + (p["rho_H"] - p["rho_L"]) * s).mean(axis=1)
+    ref = 0.5 * (p["rho_H"] + p["rho_L"]) if p.get("gravity") == "buoyancy" else 0.0
+    G = (rho - ref) * p.get("gy", 0.0)
+    col = np.concatenate([[0.0], np.cumsum(0.5 * (G[1:] + G[:-1]))])
+    return np.repeat((col - col.mean())[:, None], phi.shape[1], axis=1)
+
+
 def rayleigh_taylor(L0=256, At=0.5, Re=3000.0, U=0.04, W=5.0, sigma=5e-5,
                     Pe=1000.0, cfl=0.25, steps=20000, rho_L=1.0):
     """Rayleigh-Taylor instability, L0 x 4L0, periodic in x, no-slip walls in
     y (Sec. IV.D, Eqs. 48-49). Heavy fluid above y = 2L0 + 0.1 L0 cos(2 pi x/L0).
     One dynamic viscosity mu = rho_H L0 U / Re; g = U^2 / L0 (U = sqrt(g L0));
-    M = U L0 / Pe; buoyancy-form gravity."""
+    M = U L0 / Pe; buoyancy-form gravity. The fluids start at rest in the
+    hydrostatic pressure of the mean (flat-interface) density profile, so
+    that only the interface perturbation drives the flow: from p = 0 the
+    weakly compressible g model first sets the whole column in motion, which
+    moves phi off phi_H in the heavy bulk."""
     rho_H = rho_L * (1.0 + At) / (1.0 - At)
     mu = rho_H * L0 * U / Re
     g = U * U / L0
@@ -143,7 +162,8 @@ def rayleigh_taylor(L0=256, At=0.5, Re=3000.0, U=0.04, W=5.0, sigma=5e-5,
     params = dict(phi_H=1.0, phi_L=0.0, rho_H=rho_H, rho_L=rho_L, mu_H=mu,
                   mu_L=mu, visc="linear", sigma=sigma, W=W, M=U * L0 / Pe,
                   gx=0.0, gy=-g, gravity="buoyancy", cfl=cfl, walls_y=True)
-    return _case(f"rti_{nx}x{ny}", nx, ny, "coupled", params, phi, steps=steps)
+    return _case(f"rti_{nx}x{ny}", nx, ny, "coupled", params, phi,
+                 p=hydrostatic_pressure(phi, params), steps=steps)
 
 
 def spinodal(L=64, seed=1810, amp=0.01, rho_H=1000.0, rho_L=1.0, nu=0.1,
