@@ -230,6 +230,22 @@ int dugks_get_macros_device(dugks_handle *h, double *phi, double *u,
  * filled) when out[6] > 0. */
 int dugks_get_diagnostics(dugks_handle *h, double out[8]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops): the diagnostics of dugks_get_diagnostics
+ * (out_dev[0..6], same order and meaning) written asynchronously on the
+ * handle's stream to out_dev, a device array of at least 7 doubles owned by
+ * the caller; the time is dugks_time. Allocates nothing: the cell macros are
+ * formed inside the reduction, and its per-row partial sums go to a
+ * file-scope device array of the library (65536 rows x 7 doubles, one per
+ * GPU, held until the process ends). Every call on a GPU shares that array:
+ * calls that overlap on one GPU (other streams, other threads) race, and
+ * must be ordered by the caller. The sums are accumulated in double in a
+ * fixed order (rows, then row order): they agree with dugks_get_diagnostics
+ * to rounding; the maximum and the count agree exactly. EINVAL for a grid
+ * of more than 65536 rows; ESTATE before init. Does not read or report the
+ * non-finite flag (out_dev[6] counts non-finite cells). */
+int dugks_get_diagnostics_noalloc(dugks_handle *h, double *out_dev);
+
 /* Steps taken since init and the current time. */
 long long dugks_steps_done(const dugks_handle *h);
 double dugks_time(const dugks_handle *h);

@@ -119,6 +119,7 @@ def lib():
             "dugks_get_macros": (i, [vp, dp, dp, dp, dp, dp]),
             "dugks_get_macros_device": (i, [vp, vp, vp, vp, vp, vp]),
             "dugks_get_diagnostics": (i, [vp, dp]),
+            "dugks_get_diagnostics_noalloc": (i, [vp, vp]),
             "dugks_steps_done": (ll, [vp]),
             "dugks_time": (C.c_double, [vp]),
             "dugks_state_bytes": (sz, [vp]),
@@ -322,6 +323,11 @@ class Solver:
 
     def diagnostics(self):
         return get_diagnostics(self.h)
+
+    def diagnostics_noalloc(self, out_ptr):
+        """The seven diagnostics into device memory at `out_ptr` (7 doubles),
+        asynchronously, with no device allocation."""
+        _check(lib().dugks_get_diagnostics_noalloc(self.h, C.c_void_p(out_ptr)), self.h)
 
     @property
     def steps_done(self):

@@ -620,6 +620,20 @@ int dugks_get_diagnostics(dugks_handle* h, double out[8]) {
   return h->numeric_err ? numeric_fail(h) : DUGKS_OK;
 }
 
+int dugks_get_diagnostics_noalloc(dugks_handle* h, double* out_dev) {
+  if (!h || !out_dev) return fail(h, DUGKS_EINVAL, "NULL argument");
+  double* part = nullptr;
+  int max_rows = 0;
+  HIPCHK(h, dugks::noalloc_scratch(&part, &max_rows));
+  if (h->ny > max_rows)
+    return fail(h, DUGKS_EINVAL,
+                "grid too tall for the diagnostics without allocation (at most " +
+                    std::to_string(max_rows) + " rows)");
+  if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
+  HIPCHK(h, dugks::launch_diag_noalloc(h->fp64(), h->dc, h->hc, h->steps, part, out_dev, h->stream));
+  return DUGKS_OK;
+}
+
 long long dugks_steps_done(const dugks_handle* h) { return h ? h->steps : -1; }
 double dugks_time(const dugks_handle* h) { return h ? h->steps * h->hc.dt : 0.0; }
 

@@ -166,6 +166,13 @@ hipError_t launch_init(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
 hipError_t launch_macros(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
                          long long local_step, double* phi, double* u,
                          double* v, double* p, double* rho, hipStream_t s);
+// Diagnostics without device allocation: the device address of the
+// library's file-scope partial-sum array on the current device (looked up
+// once per device) and its capacity in grid rows; the fused macros and
+// reduction kernels writing the seven diagnostics to out (device).
+hipError_t noalloc_scratch(double** ptr, int* max_rows);
+hipError_t launch_diag_noalloc(bool fp64, const CaseDev* dcase, const CaseDev& hcase,
+                               long long local_step, double* part, double* out, hipStream_t s);
 hipError_t launch_diag(const CaseDev& hcase, const double* phi, const double* u,
                        const double* v, const double* rho, double* partial,
                        int npartial, double* out, hipStream_t s);

@@ -29,6 +29,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "dugks_impl.h"
 
 namespace dugks {
@@ -1538,6 +1540,57 @@ __global__ void k_diag_final(int nblocks, const double* __restrict__ part, doubl
   for (int k = 0; k < kDiagQ; ++k) out[k] = a[k];
 }
 
+// ------------------------------------------ diagnostics without allocation
+
+// The diagnostics of k_diag_partial / k_diag_final for callers that cannot
+// allocate device memory: the cell macros are formed inside the reduction
+// (no macro arrays), one work group per grid row folds its row into seven
+// partial sums, and one work group folds the rows in row order. The per-row
+// partials live in this file-scope device array: one copy per GPU, held for
+// the life of the process and shared by every call on that GPU, so calls
+// that overlap on one GPU race on it. Host code never passes the array's
+// name to a kernel: noalloc_scratch() looks up its device address.
+constexpr int kNoAllocRows = 65536;
+static __device__ __align__(256) double scratch[kNoAllocRows * kDiagQ];
+
+template <typename T, bool CPL>
+__global__ __launch_bounds__(kDiagThreads) void k_diag_rows(const CaseDev* __restrict__ Cd, int buf,
+                                                            double t, double* __restrict__ part) {
+  constexpr int kWaves = kDiagThreads / kWave;
+  __shared__ double sh[kDiagQ][kWaves];
+  const CaseDev& C = *Cd;
+  const int j = blockIdx.x;
+  const T* st = static_cast<const T*>(C.set[buf]);
+  double a[kDiagQ] = {0, 0, 0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < C.nx; i += kDiagThreads) {
+    T phi, u, v, p;
+    double r;
+    cell_macros<T, CPL>(C, st, i, j, t, phi, u, v, p, r);
+    const double ph = (double)phi, uu = (double)u, vv = (double)v;
+    a[0] += ph;
+    a[1] += r * uu;
+    a[2] += r * vv;
+    a[3] += 0.5 * r * (uu * uu + vv * vv);
+    a[4] = fmax(a[4], sqrt(uu * uu + vv * vv));
+    a[5] += r;
+    const bool bad = !isfinite(ph) || !isfinite(uu) || !isfinite(vv) || !isfinite(r);
+    a[6] += bad ? 1.0 : 0.0;
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+#pragma unroll
+  for (int k = 0; k < kDiagQ; ++k) {
+    const double r = k == 4 ? wave_max(a[k]) : wave_sum(a[k]);
+    if (lane == 0) sh[k][w] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDiagQ) {
+    const int k = threadIdx.x;
+    double r = sh[k][0];
+    for (int x = 1; x < kWaves; ++x) r = k == 4 ? fmax(r, sh[k][x]) : r + sh[k][x];
+    part[(long long)j * kDiagQ + k] = r;
+  }
+}
+
 // ------------------------------ two-kernel step: upwind or stretched mesh
 
 // The upwind, limited reconstruction and the stretched mesh (both selected
@@ -2224,6 +2277,44 @@ hipError_t launch_macros(bool fp64, const CaseDev* dcase, const CaseDev& hc, lon
     if (hc.coupled) hipLaunchKernelGGL((k_macros<float, true>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
     else hipLaunchKernelGGL((k_macros<float, false>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
   }
+  return hipGetLastError();
+}
+
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy of the array at its own address).
+hipError_t noalloc_scratch(double** ptr, int* max_rows) {
+  static std::mutex lock;
+  static double* addr[256] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(lock);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  *max_rows = kNoAllocRows;
+  return hipSuccess;
+}
+
+hipError_t launch_diag_noalloc(bool fp64, const CaseDev* dcase, const CaseDev& hc,
+                               long long local_step, double* part, double* out, hipStream_t s) {
+  if (hc.ny > kNoAllocRows) return hipErrorInvalidValue;
+  const int buf = (hc.cur0 + (int)(local_step & 1)) & 1;
+  const double t = hc.t0 + (double)local_step * hc.dt;
+  dim3 grid(hc.ny), block(kDiagThreads);
+  if (fp64) {
+    if (hc.coupled) hipLaunchKernelGGL((k_diag_rows<double, true>), grid, block, 0, s, dcase, buf, t, part);
+    else hipLaunchKernelGGL((k_diag_rows<double, false>), grid, block, 0, s, dcase, buf, t, part);
+  } else {
+    if (hc.coupled) hipLaunchKernelGGL((k_diag_rows<float, true>), grid, block, 0, s, dcase, buf, t, part);
+    else hipLaunchKernelGGL((k_diag_rows<float, false>), grid, block, 0, s, dcase, buf, t, part);
+  }
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, s, hc.ny, part, out);
   return hipGetLastError();
 }
 
