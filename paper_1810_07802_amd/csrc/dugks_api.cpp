@@ -221,7 +221,7 @@ int upload_case(dugks_handle* h) {
   std::vector<Item> it;
   it.reserve((size_t)h->hc.nstrips * h->hc.nsegs);
   for (int s = 0; s < h->hc.nsegs; ++s)
-    for (int x = 0; x < h->hc.nstrips; ++x) it.push_back(Item{0, x, s, 0});
+    for (int x = 0; x < h->hc.nstrips; ++x) it.push_back(Item{0, x, s, dugks::item_dir(s, h->hc.walls != 0)});
   if ((int)it.size() != h->nitems) {
     if (h->items) (void)hipFree(h->items);
     h->items = nullptr;
@@ -848,7 +848,7 @@ hipError_t build_items(dugks_batch* b) {
     if (b->seg[k] != 2) b->two_row[w] = 0;
     const int nsegs = (c.ny + b->seg[k] - 1) / b->seg[k];
     for (int s = 0; s < nsegs; ++s)
-      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{(int)k, x, s, 0});
+      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{(int)k, x, s, dugks::item_dir(s, w == 1)});
   }
   for (int w = 0; w < 2; ++w) {
     if (b->items[w]) (void)hipFree(b->items[w]);

@@ -110,10 +110,14 @@ enum VelKind { kVelUniform = 0, kVelRotation = 1, kVelShear = 2, kVelDeform = 3 
 enum ViscMode { kViscUniformNu = 0, kViscReciprocal = 1, kViscLinear = 2 };
 
 // Work item of the step kernel: which case, which column strip, which row
-// segment.
+// segment, and the direction the march of a multi-row segment takes (0 up,
+// 1 down; see item_dir()).
 struct Item {
-  int c, strip, seg, pad;
+  int c, strip, seg, dir;
 };
+// Alternate segments of a periodic case march in opposite directions; wall
+// cases march upwards (the step kernel with walls has no downward march).
+__host__ __device__ constexpr int item_dir(int seg, bool walls) { return walls ? 0 : (seg & 1); }
 
 // Launch arguments of the step kernel.
 struct StepArgs {

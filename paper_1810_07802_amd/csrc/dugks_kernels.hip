@@ -280,12 +280,13 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
     g_relax<false>(C, (double)phi, rhoD, gbD, tauD);
     const T gb = T(gbD);
     const GTerms<T> s = g_terms<T>(u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy);
-    // Eq. 29-30 as increments: bar+ = g + d, tilde+ = g + (4/3) d with
-    // d = b (g^eq + tau S - g)
+    // Eq. 29-30 as increments: bar+ = g + b e, tilde+ = g + (4/3) b e with
+    // e = g^eq + tau S - g (one multiply-add each)
+    const T gb43 = T(4.0 / 3.0) * gb;
     auto relax = [&](int q, T target) {
-      const T d = gb * (target - gt[q]);
-      o.gb[q] = gt[q] + d;
-      tp[9 + q] = gt[q] + T(4.0 / 3.0) * d;
+      const T e = target - gt[q];
+      o.gb[q] = gt[q] + gb * e;
+      tp[9 + q] = gt[q] + gb43 * e;
     };
     relax(0, g_rest<T>(s, p));
 #pragma unroll
@@ -304,13 +305,13 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
   const T Dx = (hx - hist_x) * T(1.0 / C.dt), Dy = (hy - hist_y) * T(1.0 / C.dt);
   {
     // f^eq + tau_f S^f = w (phi + xi . V) with V = 3 phi u + tau_f (theta n + 3 D)
-    const T fbc = T(C.fb), tauf = T(C.tau_f);
+    const T fbc = T(C.fb), fbc43 = T(4.0 / 3.0 * C.fb), tauf = T(C.tau_f);
     const T Vx = T(3) * phi * u + tauf * (theta * nxv + T(3) * Dx);
     const T Vy = T(3) * phi * v + tauf * (theta * nyv + T(3) * Dy);
     auto relax = [&](int q, T target) {
-      const T d = fbc * (target - ft[q]);
-      o.fb[q] = ft[q] + d;
-      tp[q] = ft[q] + T(4.0 / 3.0) * d;
+      const T e = target - ft[q];
+      o.fb[q] = ft[q] + fbc * e;
+      tp[q] = ft[q] + fbc43 * e;
     };
     relax(0, wq<T>(0) * phi);
 #pragma unroll
@@ -781,21 +782,17 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
   }
 }
 
-template <typename T, bool CPL, bool WALLS>
-__global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A) {
-  const int nb = gridDim.x;
-  const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
-  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (idx >= A.nitems) return;
-  const Item it = A.items[idx];
-  // The case constants are copied into registers once: read through the
-  // descriptor pointer, they would be re-read after every store of the march
-  // (the stores could alias them as far as the compiler knows).
-  const CaseDev* Cg = A.cases + it.c;
-  const CaseDev C = *Cg;
-  const long long n = *A.step_base + A.kofs - C.step0;
-  if (n < 0 || n >= C.nsteps) return;
-
+// The march of one work item: the wave owns a 62-column strip and rows
+// [j0, j1) of it, and marches through them upwards (DOWN = false) or
+// downwards. Alternate segments march in opposite directions (the item's
+// `dir`), so that the two waves on either side of a segment boundary reach it
+// at the same time, both at their start or both at their end: the halo rows
+// that both read then come from the L2 cache for the second one. Every row,
+// face and update goes through the same functions with the same inputs in
+// either direction, so the results are the same bit for bit.
+template <typename T, bool CPL, bool WALLS, bool DOWN>
+__device__ __forceinline__ void march(const CaseDev& C, const Item& it, long long n) {
+  constexpr int sgn = DOWN ? -1 : 1;  // marching direction in rows
   const int lane = threadIdx.x;
   const int nx = C.nx, ny = C.ny;
   constexpr int walls = WALLS ? 1 : 0;
@@ -819,10 +816,10 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   __shared__ T stash[2][18][64];
 
   // Raw inputs of the cell stage of row r (tilde f, g, history) and phi of
-  // row r+1 (own column and the halo lanes' extra column). Two sets are in
-  // flight: a pass consumes one set in its cell stage and then reloads it for
-  // the pass after next, so that more than a pass of arithmetic covers the
-  // memory latency.
+  // the row after it in marching order (own column and the halo lanes'
+  // extra column). Two sets are in flight: a pass consumes one set in its
+  // cell stage and then reloads it for the pass after next, so that more
+  // than a pass of arithmetic covers the memory latency.
   struct Raw {
     T f[9], g[9], hx, hy, po, pe;
   };
@@ -837,7 +834,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     }
     R.hx = v[val_hist(CPL, 0)];
     R.hy = v[val_hist(CPL, 1)];
-    const char* prow = row_ptr(in, row_idx(r + 1, ny, walls), RB) + NV * PB;
+    const char* prow = row_ptr(in, row_idx(r + sgn, ny, walls), RB) + NV * PB;
     R.po = gload<T>(prow, lane_off((unsigned)ci * es));
     R.pe = gload<T>(prow, lane_off((unsigned)cx * es));
   };
@@ -852,6 +849,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     const char* prow = row_ptr(in, row_idx(r, ny, walls), RB) + NV * PB;
     phi_lr(gload<T>(prow, lane_off((unsigned)ci * es)), gload<T>(prow, lane_off((unsigned)cx * es)), o);
   };
+  // pm, p0, pp: phi of the rows below, at and above row r
   auto stage = [&](int r, const Raw& R, const T (&pm)[3], const T (&p0)[3], const T (&pp)[3],
                    RowData<T, CPL>& rd) {
     const int rr = row_idx(r, ny, walls);
@@ -866,32 +864,45 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
     x_diffs<T, CPL>(rd);
   };
 
-  // One pass of the march for output row k. It stages row k+1 into `nxt`,
-  // forms the face above row k, and (for k >= j0) the x-face east of row k
-  // and the update of row k. Passes start at k = j0 - 2 so that every row,
-  // halo rows included, goes through the same code: results do not depend on
-  // the segmentation, bit for bit.
+  // One pass of the march for output row k. With the records of the rows
+  // before (prv), at (cur_r) and after (nxt) row k in marching order, and phi
+  // of rows k, k + sgn and (from `raw`) k + 2 sgn, it stages row k + sgn into
+  // `nxt`, forms the y-face between rows k and k + sgn (a record's fnf/fng
+  // hold the face above its row), and (for output rows) the x-face east of
+  // row k and the update of row k. The passes start two rows before the
+  // segment so that every row, halo rows included, goes through the same
+  // code: results do not depend on the segmentation, bit for bit.
   auto pass = [&](int k, Raw& raw, RowData<T, CPL>& prv, RowData<T, CPL>& cur_r,
                   RowData<T, CPL>& nxt, const T (&pa)[3], const T (&pb)[3], T (&pc)[3]) {
-    const int rs = k + 1;
+    const int rs = k + sgn;
     // the phi ring advances every pass (ghost rows mirror into the grid), the
     // cell stage runs only for rows that exist
     phi_lr(raw.po, raw.pe, pc);
-    if (!(walls && (rs < 0 || rs >= ny))) stage(rs, raw, pa, pb, pc, nxt);
-    // inputs of pass k + 2 (row k + 3); rows past j1 + 1 are never staged,
-    // so the fetch stays on the rows the segment reads anyway
-    fetch(min(k + 3, j1 + 1), raw);
-    // face above row k
-    if (k >= j0 - 1 && !(walls && (k < 0 || k >= ny - 1))) {
-      const int kr = row_idx(k, ny, walls);
-      y_face<T, CPL>(C, cur_r, nxt, xc, (double)kr + 1.0, tn + C.h, cur_r.fnf, cur_r.fng);
+    if (!(walls && (rs < 0 || rs >= ny))) {
+      if (DOWN) stage(rs, raw, pc, pb, pa, nxt);
+      else stage(rs, raw, pa, pb, pc, nxt);
     }
-    if (k < j0) return;
+    // inputs of pass k + 2 sgn (row k + 3 sgn); rows past the segment's halo
+    // are never staged, so the fetch stays on the rows the segment reads
+    fetch(DOWN ? max(k - 3, j0 - 1) : min(k + 3, j1 + 1), raw);
+    // the y-face between rows k and k + sgn, above the lower one
+    RowData<T, CPL>& lo = DOWN ? nxt : cur_r;
+    RowData<T, CPL>& hi = DOWN ? cur_r : nxt;
+    const int kl = DOWN ? k - 1 : k;  // the lower row
+    const bool face = DOWN ? k <= j1 : k >= j0 - 1;
+    if (face && !(walls && (kl < 0 || kl >= ny - 1))) {
+      const int kr = row_idx(kl, ny, walls);
+      y_face<T, CPL>(C, lo, hi, xc, (double)kr + 1.0, tn + C.h, lo.fnf, lo.fng);
+    }
+    if (DOWN ? k >= j1 : k < j0) return;
+    // the rows below and above row k
+    RowData<T, CPL>& below = DOWN ? nxt : prv;
+    RowData<T, CPL>& above = DOWN ? prv : nxt;
     T fx_f[9], fx_g[9];
-    row_xface<T, CPL, WALLS>(C, k, ny, ci, tn, prv, cur_r, nxt, fx_f, fx_g);
+    row_xface<T, CPL, WALLS>(C, k, ny, ci, tn, below, cur_r, above, fx_f, fx_g);
     const int slot = k & 1;
-    row_update<T, CPL, true>(C, k, ny, nx, walls, ci, store, out, RB, PB, prv, cur_r, fx_f, fx_g,
-                       [&](int q) { return stash[slot][q][lane]; });
+    row_update<T, CPL, true>(C, k, ny, nx, walls, ci, store, out, RB, PB, below, cur_r, fx_f,
+                             fx_g, [&](int q) { return stash[slot][q][lane]; });
   };
 
   // The three row records and the three phi rows rotate after each pass. (A
@@ -908,19 +919,43 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
       P1[m] = P2[m];
     }
   };
-  Raw ra, rb;  // inputs of the even and odd passes (counted from j0 - 2)
-  phi_row(j0 - 2, P0);
-  phi_row(j0 - 1, P1);
-  fetch(j0 - 1, ra);
-  fetch(j0, rb);
-  for (int k = j0 - 2; k < j1; k += 2) {
+  Raw ra, rb;  // inputs of the even and odd passes (counted from the first)
+  // passes k = kb, kb + sgn, ..., two halo passes and one per segment row
+  const int kb = DOWN ? j1 + 1 : j0 - 2;
+  const int npass = j1 - j0 + 2;
+  phi_row(kb, P0);
+  phi_row(kb + sgn, P1);
+  fetch(kb + sgn, ra);
+  fetch(kb + 2 * sgn, rb);
+  for (int m = 0; m < npass; m += 2) {
+    const int k = kb + m * sgn;
     pass(k, ra, R0, R1, R2, P0, P1, P2);
     rotate();
-    if (k + 1 < j1) {
-      pass(k + 1, rb, R0, R1, R2, P0, P1, P2);
+    if (m + 1 < npass) {
+      pass(k + sgn, rb, R0, R1, R2, P0, P1, P2);
       rotate();
     }
   }
+}
+
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A) {
+  const int nb = gridDim.x;
+  const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (idx >= A.nitems) return;
+  const Item it = A.items[idx];
+  // The case constants are copied into registers once: read through the
+  // descriptor pointer, they would be re-read after every store of the march
+  // (the stores could alias them as far as the compiler knows).
+  const CaseDev* Cg = A.cases + it.c;
+  const CaseDev C = *Cg;
+  const long long n = *A.step_base + A.kofs - C.step0;
+  if (n < 0 || n >= C.nsteps) return;
+  // wall cases march upwards only (see item_dir): one copy of the march
+  // keeps their register budget
+  if (!WALLS && it.dir) march<T, CPL, WALLS, !WALLS>(C, it, n);
+  else march<T, CPL, WALLS, false>(C, it, n);
 }
 
 // --------------------------------------------------- one-row step kernel

@@ -161,7 +161,7 @@ int rebuild(dugks_pool* p) {
     c.step0 = p->start[k];
     c.nsteps = p->target[k];
     for (int s = 0; s < c.nsegs; ++s)
-      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{k, x, s, 0});
+      for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{k, x, s, dugks::item_dir(s, w == 1)});
   }
   // captured graphs refer to the old items; drop them before the buffers change
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.second);
