@@ -25,11 +25,10 @@ The same JSON line carries:
                 requests, aggregate MLUPS, vs the plain sequential per-case
                 loop
   upwind        the bubble with the upwind, limited face reconstruction
-                (two kernels per step), 128^2 and 4096^2; the HBM fraction
-                at the method's 160 B per cell, and beside it the bytes the
-                two-kernel design moves (516 B per cell)
+                (the block step: one kernel per step), 128^2 and 4096^2;
+                the HBM fraction at the method's 160 B per cell
   mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
-                central and upwind, through the same two kernels
+                central and upwind, through the same block step
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -46,11 +45,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 B_PER_CELL = {"fp32": 160.0, "fp64": 320.0}  # read + write of 18 populations + 2 history values
-# what the two-kernel step (upwind reconstruction, stretched mesh) moves per
-# cell in FP32 by design: stage 260 (21 state values in; tilde-plus and
-# history, 20 values, out; 18 bar-plus + 6 face inputs out), faces and update
-# 256 (18 bar-plus + 5 face inputs + 20 state values in, 21 values out)
-B_TWO_KERNEL = {"fp32": 516.0, "fp64": 1032.0}
 
 
 def parse():
@@ -211,12 +205,11 @@ def roofline(cells, steps, seconds, prec, workload=None):
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
 
 
-def timed_two_kernel(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
-    """Two-kernel steps of case `c` (coupled FP32): the upwind
-    reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
+def timed_block_step(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
+    """Block steps (one kernel per step) of case `c` (coupled FP32): the
+    upwind reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
     reconstruction, replayed from HIP graphs (see timed()). The HBM
-    fraction is quoted at the method's 160 B per cell; the bytes the
-    two-kernel design moves (516 B per cell) are reported beside it."""
+    fraction is quoted at the method's 160 B per cell."""
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
     s.set_stream(torch.cuda.current_stream().cuda_stream)
     if mesh is not None:
@@ -226,14 +219,10 @@ def timed_two_kernel(torch, D, c, steps, warmup, recon="upwind", mesh=None, chun
     d = s.diagnostics()
     cells = c["nx"] * c["ny"]
     ach = B_PER_CELL["fp32"] * cells * steps / t / 1e9
-    des = B_TWO_KERNEL["fp32"] * cells * steps / t / 1e9
     return {"mlups": round(cells * steps / t / 1e6, 1), "steps": steps,
             "us_per_step": round(t / steps * 1e6, 3),
             "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
-            "bytes_per_cell": B_PER_CELL["fp32"],
-            "design_bytes_per_cell": B_TWO_KERNEL["fp32"],
-            "design_GBps": round(des, 1), "design_frac_hbm": round(des / HBM_PEAK_GBS, 4),
-            "nonfinite": d["nonfinite"]}
+            "bytes_per_cell": B_PER_CELL["fp32"], "nonfinite": d["nonfinite"]}
 
 
 def served_stream(torch, D, W, n_req, n_sample):
@@ -395,7 +384,7 @@ def main():
         cl = W.bubble(L=4096, R=1024, steps=0)
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, stretched mesh, central",
-                          **timed_two_kernel(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
+                          **timed_block_step(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
               flush=True)
         return
     if args.profile_batch:
@@ -415,7 +404,7 @@ def main():
     if args.profile_upwind:
         cl = W.bubble(L=4096, R=1024, steps=0)
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, upwind reconstruction",
-                          **timed_two_kernel(torch, D, cl, args.upwind_steps, 3)}), flush=True)
+                          **timed_block_step(torch, D, cl, args.upwind_steps, 3)}), flush=True)
         return
     if args.profile_kernel:
         c = W.bubble(L=128, R=32)
@@ -521,10 +510,10 @@ def main():
         progress(f"batch: {rec['batched']['batched_graph_mlups']} MLUPS")
         # upwind, limited reconstruction on the same physics
         rec["upwind"] = {
-            "workload": "stationary bubble, coupled FP32, upwind reconstruction, two "
-                        "kernels per step, replayed from HIP graphs of up to 100 steps",
-            "bubble128": timed_two_kernel(torch, D, c, min(args.small_steps, 5000), 100),
-            "bubble4096": timed_two_kernel(torch, D, W.bubble(L=4096, R=1024, steps=0),
+            "workload": "stationary bubble, coupled FP32, upwind reconstruction, one "
+                        "block-step kernel per step, replayed from HIP graphs of up to 100 steps",
+            "bubble128": timed_block_step(torch, D, c, min(args.small_steps, 5000), 100),
+            "bubble4096": timed_block_step(torch, D, W.bubble(L=4096, R=1024, steps=0),
                                            args.upwind_steps, 5)}
         progress("upwind done")
         # stretched tensor-product mesh, both reconstructions
@@ -532,10 +521,10 @@ def main():
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         rec["mesh"] = {
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
-                        "both axes), coupled FP32, two kernels per step, replayed from HIP "
-                        "graphs of up to 100 steps",
-            "central": timed_two_kernel(torch, D, cm, args.upwind_steps, 5, "central", mesh),
-            "upwind": timed_two_kernel(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
+                        "both axes), coupled FP32, one block-step kernel per step, replayed "
+                        "from HIP graphs of up to 100 steps",
+            "central": timed_block_step(torch, D, cm, args.upwind_steps, 5, "central", mesh),
+            "upwind": timed_block_step(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
         progress("mesh done")
         if args.serve_requests > 0:
             rec["served"] = served_stream(torch, D, W, args.serve_requests, args.serve_sample)

@@ -89,9 +89,7 @@ enum { DUGKS_RECON_CENTRAL = 0, DUGKS_RECON_UPWIND = 1 };
  *                  ab > 0, else 0; one-sided and unlimited next to a wall);
  *                  populations along the face take the mean of both cells.
  *                  Upwind runs on single handles only (EINVAL in batches and
- *                  pools), and takes (18 + 6) * n values of device
- *                  scratch (coupled; 9 + 6 for interface-only),
- *                  allocated by dugks_set_params.
+ *                  pools); it needs no device memory beyond the state.
  *   eps_n          regularisation of the interface normal of the phase-field
  *                  source (Eq. 16, n of Sec. II.A):
  *                  n = grad phi / sqrt(|grad phi|^2 + eps^2) with
@@ -168,8 +166,8 @@ int dugks_get_tile(const dugks_handle *h);
  *     one-sided difference over the cell width);
  *   - the regularisation of the unit normal is 1e-6 |phi_H - phi_L| over
  *     the smallest width.
- * The step then runs as two kernels with the scratch of the upwind mode
- * (see recon). Cell centres start at x = 0, y = 0. Takes effect at the next
+ * The step then runs as the upwind mode's kernel (see recon), which needs no
+ * device memory beyond the state and the metrics. Cell centres start at x = 0, y = 0. Takes effect at the next
  * dugks_init_fields (the state is invalidated: ESTATE until then). Not for
  * batches or pool cases (EINVAL). Errors: EINVAL (widths), ENOMEM. */
 int dugks_set_mesh(dugks_handle *h, const double *dx, const double *dy);
@@ -276,9 +274,8 @@ int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
 int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
                    double *us_per_step);
 
-/* Device bytes a handle of this shape holds (both state buffers). The
- * upwind reconstruction and stretched meshes add the two-kernel scratch
- * (see recon) and, for a mesh, 32 (nx + ny) bytes of metrics. */
+/* Device bytes a handle of this shape holds (both state buffers). A
+ * stretched mesh adds 104 (nx + ny) bytes of metrics. */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
 
 /* Message of the last error on h (or of the last failed create when h is

@@ -120,7 +120,6 @@ void fill_case(dugks_handle* h) {
   C.vel_kind = P.vel_kind;
   C.visc_mode = P.visc_mode;
   C.grav_form = P.gravity_form == DUGKS_GRAV_BUOYANCY ? 1 : 0;
-  C.plane = (long long)h->n();
   C.row_vals = dugks::state_row_values(h->nx, h->coupled(), (int)h->elem());
   C.set[0] = h->buf[0];
   C.set[1] = h->buf[1];
@@ -173,10 +172,11 @@ void fill_case(dugks_handle* h) {
   C.nsteps = LLONG_MAX;
 }
 
-// Metric arrays of a stretched mesh (layout of CaseDev::mesh): per axis the
-// widths, the distances to the previous and next centres (x periodic; y
-// periodic, or with walls mirrored so that the ghost row has the width of
-// its row), and the centres.
+// Metric arrays of a stretched mesh (layout of CaseDev::mesh, see
+// MeshAxis): per axis the widths, the distances to the previous and next
+// centres (x periodic; y periodic, or with walls mirrored so that the ghost
+// row has the width of its row), the centres, and the reciprocals and
+// stencil weights derived from them.
 static std::vector<double> mesh_metrics(const dugks_handle* h, bool walls) {
   std::vector<double> m;
   auto axis = [&](const std::vector<double>& w, bool mirror) {
@@ -186,18 +186,26 @@ static std::vector<double> mesh_metrics(const dugks_handle* h, bool walls) {
       if (k >= n) return mirror ? w[n - 1] : w[0];
       return w[k];
     };
-    std::vector<double> hm(n), hp(n), c(n);
+    std::vector<std::vector<double>> a(dugks::kMeshArrays, std::vector<double>(n));
     double x = 0.0;
     for (int k = 0; k < n; ++k) {
-      hm[k] = 0.5 * (at(k - 1) + w[k]);
-      hp[k] = 0.5 * (w[k] + at(k + 1));
-      c[k] = x + 0.5 * w[k];
+      const double hm = 0.5 * (at(k - 1) + w[k]), hp = 0.5 * (w[k] + at(k + 1)), s = hm + hp;
+      a[0][k] = w[k];
+      a[1][k] = hm;
+      a[2][k] = hp;
+      a[3][k] = x + 0.5 * w[k];
+      a[4][k] = 1.0 / w[k];
+      a[5][k] = 1.0 / hm;
+      a[6][k] = 1.0 / hp;
+      a[7][k] = hm / (hp * s);
+      a[8][k] = hp / (hm * s);
+      a[9][k] = 2.0 / (hp * s);
+      a[10][k] = 2.0 / (hm * s);
+      a[11][k] = hm / s;
+      a[12][k] = hp / s;
       x += w[k];
     }
-    m.insert(m.end(), w.begin(), w.end());
-    m.insert(m.end(), hm.begin(), hm.end());
-    m.insert(m.end(), hp.begin(), hp.end());
-    m.insert(m.end(), c.begin(), c.end());
+    for (const auto& v : a) m.insert(m.end(), v.begin(), v.end());
   };
   axis(h->mdx, false);
   axis(h->mdy, walls);
@@ -282,19 +290,6 @@ int ensure_scratch(dugks_handle* h) {
   return DUGKS_OK;
 }
 
-int ensure_up_scratch(dugks_handle* h) {
-  if (h->up) return DUGKS_OK;
-  const size_t b = (size_t)dugks::up_scratch_values((long long)h->n(), h->coupled()) * h->elem();
-  hipError_t e = hipMalloc(&h->up, b);
-  if (e != hipSuccess) {
-    h->up = nullptr;
-    (void)hipGetLastError();
-    return fail(h, e == hipErrorOutOfMemory ? DUGKS_ENOMEM : DUGKS_EDEVICE,
-                std::string("scratch allocation failed: ") + hipGetErrorString(e));
-  }
-  return DUGKS_OK;
-}
-
 int poll_flag(dugks_handle* h) {
   int v = 0;
   HIPCHK(h, hipMemcpyAsync(&v, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -310,7 +305,7 @@ int numeric_fail(dugks_handle* h) {
 
 int launch_steps(dugks_handle* h, int nsteps) {
   if (h->general()) {
-    UpArgs u{h->dc, h->step_base, 0, h->up};
+    UpArgs u{h->dc, h->step_base, 0};
     for (int k = 0; k < nsteps; ++k) {
       u.kofs = k;
       HIPCHK(h, dugks::launch_step_upwind(h->fp64(), h->coupled(), h->hc.walls != 0, h->upwind(),
@@ -341,7 +336,7 @@ std::vector<long long> launch_sig(const dugks_handle* h) {
   return {h->general() ? 1 : 0, h->upwind() ? 1 : 0, h->mesh ? 1 : 0, (long long)h->hc.walls,
           h->fp64() ? 1 : 0, h->coupled() ? 1 : 0, (long long)(uintptr_t)h->items,
           (long long)h->nitems, (long long)h->hc.seg_rows, (long long)(uintptr_t)h->dc,
-          (long long)(uintptr_t)h->step_base, (long long)(uintptr_t)h->up, (long long)h->nx,
+          (long long)(uintptr_t)h->step_base, (long long)h->nx,
           (long long)h->ny};
 }
 
@@ -438,10 +433,6 @@ int dugks_set_params(dugks_handle* h, const dugks_params* p) {
   if (!h || !p) return fail(h, DUGKS_EINVAL, "NULL argument");
   std::string why;
   if (validate(h, p, why) != DUGKS_OK) return fail(h, DUGKS_EINVAL, why);
-  if (p->recon == DUGKS_RECON_UPWIND || h->mesh) {
-    int rc = ensure_up_scratch(h);
-    if (rc) return rc;
-  }
   h->params = *p;
   h->has_params = true;
   h->dirty_case = true;
@@ -486,16 +477,12 @@ int dugks_set_mesh(dugks_handle* h, const double* dx, const double* dy) {
   for (double w : wy)
     if (!(w > 0.0 && std::isfinite(w))) return fail(h, DUGKS_EINVAL, "cell widths must be finite and > 0");
   if (!h->dmesh) {
-    hipError_t e = hipMalloc(&h->dmesh, 4 * (size_t)(h->nx + h->ny) * sizeof(double));
+    hipError_t e = hipMalloc(&h->dmesh, dugks::kMeshArrays * (size_t)(h->nx + h->ny) * sizeof(double));
     if (e != hipSuccess) {
       h->dmesh = nullptr;
       (void)hipGetLastError();
       return fail(h, DUGKS_ENOMEM, std::string("mesh allocation failed: ") + hipGetErrorString(e));
     }
-  }
-  if (h->has_params) {
-    int rc = ensure_up_scratch(h);
-    if (rc) return rc;
   }
   h->mesh = true;
   h->mdx.swap(wx);
@@ -768,7 +755,6 @@ int dugks_destroy(dugks_handle* h) {
   if (h->step_base) (void)hipFree(h->step_base);
   if (h->dflag) (void)hipFree(h->dflag);
   if (h->scratch) (void)hipFree(h->scratch);
-  if (h->up) (void)hipFree(h->up);
   if (h->dmesh) (void)hipFree(h->dmesh);
   drop_graphs(h);
   delete h;

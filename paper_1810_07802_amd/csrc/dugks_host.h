@@ -28,7 +28,6 @@ struct dugks_handle {
   int* dflag = nullptr;            // device: non-finite flag of the state (CaseDev::flag)
   bool numeric_err = false;        // sticky: a synchronising call found the flag set
   double* scratch = nullptr;       // 5 n doubles (macros) + diag partials + out
-  void* up = nullptr;              // scratch planes of the two-kernel step
   // stretched mesh: host widths, and the device metric arrays (CaseDev::mesh)
   bool mesh = false;
   std::vector<double> mdx, mdy;
@@ -45,8 +44,8 @@ struct dugks_handle {
 
   bool fp64() const { return precision == DUGKS_FP64; }
   bool upwind() const { return params.recon == DUGKS_RECON_UPWIND; }
-  // steps run as two kernels (upwind reconstruction or stretched mesh)
-  // instead of the fused march
+  // steps run as the block step (upwind reconstruction or stretched mesh)
+  // instead of the march
   bool general() const { return upwind() || mesh; }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
   size_t n() const { return (size_t)nx * ny; }
@@ -93,7 +92,6 @@ int upload_case(dugks_handle* h);
 int validate(const dugks_handle* h, const dugks_params* p, std::string& why);
 size_t state_set_bytes(int nx, int ny, int precision, int model);
 int ensure_scratch(dugks_handle* h);
-int ensure_up_scratch(dugks_handle* h);
 int launch_steps(dugks_handle* h, int nsteps);
 // After the handle's stream has been synchronised: read its non-finite flag;
 // a set flag makes the numeric error sticky (until init or set_state).

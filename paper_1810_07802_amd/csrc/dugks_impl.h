@@ -63,7 +63,6 @@ struct CaseDev {
   int cur0;              // state buffer holding local step 0
   long long step0;       // global step index of local step 0
   long long nsteps;      // local steps allowed (active window)
-  long long plane;       // cells (nx ny): values per plane of the scratch buffers
   long long row_vals;    // values per row of a state buffer (state_row_values())
   void* set[2];          // the two state buffers
   // time
@@ -96,14 +95,24 @@ struct CaseDev {
   int* flag;
 };
 
-// Metric arrays of one axis of a stretched mesh.
+// Metric arrays of one axis of a stretched mesh, each of the axis length,
+// in this order: the width w, the distances hm and hp to the previous and
+// next centres, the centre c, and what the stencils derive from them (once,
+// on the host, in double): 1/w, 1/hm, 1/hp; the weights of the parabola
+// derivatives through three centres, d1 = cp (a+ - a) + cm (a - a-) and
+// d2 = ep (a+ - a) - em (a - a-), with cp = hm / (hp (hm + hp)),
+// cm = hp / (hm (hm + hp)), ep = 2 / (hp (hm + hp)), em = 2 / (hm (hm + hp));
+// and the interpolation weights of the next and previous centres at the
+// cell centre's mirror point, wp = hm / (hm + hp), wm = hp / (hm + hp).
+constexpr int kMeshArrays = 13;
 struct MeshAxis {
-  const double *w, *hm, *hp, *c;
+  const double *w, *hm, *hp, *c, *iw, *ihm, *ihp, *cp, *cm, *ep, *em, *wp, *wm;
 };
 __host__ __device__ inline MeshAxis mesh_axis(const double* mesh, int nx, int ny, int axis) {
-  const double* b = mesh + (axis == 0 ? 0 : 4 * (long long)nx);
+  const double* b = mesh + (axis == 0 ? 0 : kMeshArrays * (long long)nx);
   const long long n = axis == 0 ? nx : ny;
-  return MeshAxis{b, b + n, b + 2 * n, b + 3 * n};
+  return MeshAxis{b,         b + n,     b + 2 * n, b + 3 * n,  b + 4 * n,  b + 5 * n, b + 6 * n,
+                  b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
 }
 
 enum VelKind { kVelUniform = 0, kVelRotation = 1, kVelShear = 2, kVelDeform = 3 };
@@ -131,14 +140,9 @@ struct StepArgs {
                                // for periodic FP32 cases, else the march
 };
 
-// Scratch planes of the two-kernel step (upwind reconstruction, stretched
-// mesh), in values of the working type, n values each: bar-plus f0..f8 and
-// (coupled) g0..g8, then grad phi x, y, mu_phi, D x, y and p.
+// Bar-plus planes of the block step's LDS tile (upwind reconstruction,
+// stretched mesh): f0..f8 and (coupled) g0..g8.
 __host__ __device__ constexpr int up_bar_planes(bool coupled) { return coupled ? 18 : 9; }
-__host__ __device__ constexpr int up_cell_planes(bool coupled) { return up_bar_planes(coupled) + 6; }
-__host__ __device__ constexpr long long up_scratch_values(long long n, bool coupled) {
-  return (long long)up_cell_planes(coupled) * n;
-}
 // slot of population q among the six crossing an x-face / a y-face (-1: none)
 __host__ __device__ constexpr int up_xslot(int q) {
   return q == 1 ? 0 : q == 2 ? 1 : q == 8 ? 2 : q == 4 ? 3 : q == 5 ? 4 : q == 6 ? 5 : -1;
@@ -147,13 +151,12 @@ __host__ __device__ constexpr int up_yslot(int q) {
   return q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 2 : q == 6 ? 3 : q == 7 ? 4 : q == 8 ? 5 : -1;
 }
 
-// Launch arguments of the two-kernel step (upwind reconstruction, or a
-// stretched mesh; one case, one step).
+// Launch arguments of the block step (upwind reconstruction, or a stretched
+// mesh; one case, one step).
 struct UpArgs {
   const CaseDev* cases;
   const long long* step_base;
   int kofs;
-  void* scratch;
 };
 
 // host-side launchers (dugks_kernels.hip)

@@ -23,9 +23,8 @@
 // interface) are evaluated in double and narrowed.
 //
 // The upwind, limited reconstruction and stretched tensor-product meshes run
-// as a second, two-kernel step (k_up_stage, k_up_faces_update; see the
-// section "two-kernel step" below), which shares the cell-stage, face and
-// wall-face arithmetic with the march.
+// as a block step (k_up_step; see the section "block step" below), which
+// shares the cell-stage, face and wall-face arithmetic with the march.
 
 #include <hip/hip_runtime.h>
 
@@ -1312,31 +1311,28 @@ __global__ void k_reset(long long* step_base, long long value, int* flag) {
 // centred on the cell: exact on quadratics, and the unit-mesh stencils on
 // unit widths.
 template <typename T>
-__device__ __forceinline__ T par_d1(T am, T ac, T ap, T hm, T hp) {
-  return (hm * hm * (ap - ac) + hp * hp * (ac - am)) / (hm * hp * (hm + hp));
-}
-template <typename T>
-__device__ __forceinline__ T par_d2(T am, T ac, T ap, T hm, T hp) {
-  return T(2) * ((ap - ac) / hp - (ac - am) / hm) / (hm + hp);
-}
-template <typename T>
 __device__ __forceinline__ void mesh_stencils(const CaseDev& C, const T (&ph)[3][3], int i, int j,
                                               T& gx, T& gy, T& lap) {
   const MeshAxis X = mesh_axis(C.mesh, C.nx, C.ny, 0), Y = mesh_axis(C.mesh, C.nx, C.ny, 1);
-  const T xm = T(X.hm[i]), xp = T(X.hp[i]), ym = T(Y.hm[j]), yp = T(Y.hp[j]);
+  // parabola weights of column i (x) and row j (y), and the weights of the
+  // neighbouring rows (columns) in the centred sum
+  const T cpx = T(X.cp[i]), cmx = T(X.cm[i]), epx = T(X.ep[i]), emx = T(X.em[i]);
+  const T cpy = T(Y.cp[j]), cmy = T(Y.cm[j]), epy = T(Y.ep[j]), emy = T(Y.em[j]);
+  const T wpx = T(X.wp[i]), wmx = T(X.wm[i]), wpy = T(Y.wp[j]), wmy = T(Y.wm[j]);
   T dxr[3], dxxr[3], dyc[3], dyyc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    dxr[k] = par_d1(ph[k][0], ph[k][1], ph[k][2], xm, xp);
-    dxxr[k] = par_d2(ph[k][0], ph[k][1], ph[k][2], xm, xp);
-    dyc[k] = par_d1(ph[0][k], ph[1][k], ph[2][k], ym, yp);
-    dyyc[k] = par_d2(ph[0][k], ph[1][k], ph[2][k], ym, yp);
+    const T fx = ph[k][2] - ph[k][1], bx = ph[k][1] - ph[k][0];
+    const T fy = ph[2][k] - ph[1][k], by = ph[1][k] - ph[0][k];
+    dxr[k] = cpx * fx + cmx * bx;
+    dxxr[k] = epx * fx - emx * bx;
+    dyc[k] = cpy * fy + cmy * by;
+    dyyc[k] = epy * fy - emy * by;
   }
-  gx = T(2.0 / 3.0) * dxr[1] + T(1.0 / 3.0) * (ym * dxr[2] + yp * dxr[0]) / (ym + yp);
-  gy = T(2.0 / 3.0) * dyc[1] + T(1.0 / 3.0) * (xm * dyc[2] + xp * dyc[0]) / (xm + xp);
-  lap = T(5.0 / 6.0) * (dxxr[1] + dyyc[1]) +
-        T(1.0 / 6.0) * (ym * dxxr[2] + yp * dxxr[0]) / (ym + yp) +
-        T(1.0 / 6.0) * (xm * dyyc[2] + xp * dyyc[0]) / (xm + xp);
+  gx = T(2.0 / 3.0) * dxr[1] + T(1.0 / 3.0) * (wpy * dxr[2] + wmy * dxr[0]);
+  gy = T(2.0 / 3.0) * dyc[1] + T(1.0 / 3.0) * (wpx * dyc[2] + wmx * dyc[0]);
+  lap = T(5.0 / 6.0) * (dxxr[1] + dyyc[1]) + T(1.0 / 6.0) * (wpy * dxxr[2] + wmy * dxxr[0]) +
+        T(1.0 / 6.0) * (wpx * dyyc[2] + wmx * dyyc[0]);
 }
 
 // Gradient and Laplacian of the init and readout kernels: the unit-mesh
@@ -1626,24 +1622,18 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_rows(const CaseDev* __res
   }
 }
 
-// ------------------------------ two-kernel step: upwind or stretched mesh
+// ------------------------------ block step: upwind or stretched mesh
 
 // The upwind, limited reconstruction and the stretched mesh (both selected
 // per handle) do not fit the fused march. The upwind face value of each
-// population is a non-linear function of the cells. The face macros must
-// then be summed from the nine reconstructed values instead of
-// reconstructed cell moments. A face also reads the limited slopes of both
-// its cells, a radius-two stencil. On a stretched mesh every stencil
-// carries the local widths. The step then runs as two kernels over one
-// thread per cell, through scratch planes (layout in dugks_impl.h):
-//   k_up_stage        cell stage of every cell: bar-plus and the face inputs
-//                     to scratch, tilde-plus and the history into the output
-//                     state;
-//   k_up_faces_update per 64 x 4 block: the block's bar-plus tile in LDS,
-//                     every face of its cells once (reconstruction, face
-//                     macros, face distributions; wall faces), the face
-//                     distributions in LDS, and the update (Eq. 24).
-// The cell stage, face distribution and wall face are the march's.
+// population is a non-linear function of the cells, so the face macros must
+// be summed from the nine reconstructed values instead of reconstructed cell
+// moments. A face also reads the limited slopes of both its cells, a
+// radius-two stencil. On a stretched mesh every stencil carries the local
+// widths. The step then runs as one kernel over 64 x 4 blocks of cells
+// (k_up_step): each block stages its cells and a halo of two cells into LDS,
+// forms every face of its cells once and updates them. The cell stage, face
+// distribution and wall face are the march's.
 //
 // Stretched mesh: the reconstruction interpolates linearly to the face (the
 // value, the tangential slope and the face inputs), slopes are derivatives
@@ -1651,7 +1641,25 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_rows(const CaseDev* __res
 // width, and the update divides the fluxes by the cell's widths. On unit
 // widths every formula reduces to the unit-mesh one.
 
-constexpr int kUpCols = 64, kUpRows = 4;  // cells of one 256-thread block
+// A block is 64 columns by ROWS rows of cells, one thread per cell, with a
+// register budget of WPE waves per SIMD (1: the compiler's choice). Measured
+// on the 4096^2 bubble (FP32, microseconds per step, rows/WPE):
+//   upwind           4/3: 1131  8/1: 1336  4/1: 1494  6/1: 1700  6/3: 1708
+//   mesh, upwind     4/3: 1870  8/1: 1950  4/1: 2205  6/1: 2528  6/3: 2816
+//   mesh, central    8/1: 1668  4/1: 1727  4/3: 2031  6/1: 2150  6/3: 2830
+// Four rows at three waves per SIMD fit three blocks (150 KB of LDS) per CU;
+// the central mesh kernel holds more registers (the compiler spills at that
+// budget) and runs best as one 8-row block per CU. FP64 keeps four rows at
+// one wave per SIMD.
+constexpr int kUpCols = 64;
+template <typename T, bool MESH, bool CENTRAL>
+__host__ __device__ constexpr int up_rows() {
+  return sizeof(T) == 8 ? 4 : (MESH && CENTRAL) ? 8 : 4;
+}
+template <typename T, bool MESH, bool CENTRAL>
+__host__ __device__ constexpr int up_wpe() {
+  return sizeof(T) == 8 ? 1 : (MESH && CENTRAL) ? 1 : 3;
+}
 
 // Periodic index for an index at most one period outside [0, n): a
 // conditional add or subtract (an integer remainder costs tens of
@@ -1662,92 +1670,10 @@ __device__ __forceinline__ int wrap_near(int a, int n) {
   return (a >= 0 && a < n) ? a : wrap(a, n);
 }
 
-// Cell of this thread, with the block order remapped so that each XCD gets a
-// contiguous share of the grid (the grid is a multiple of 8 blocks). False
-// for threads outside the grid.
-__device__ __forceinline__ bool up_cell(int nx, int ny, int& i, int& j) {
-  const int nbx = (nx + kUpCols - 1) / kUpCols;
-  const int per = gridDim.x >> 3;
-  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  const int bx = idx % nbx, by = idx / nbx;
-  i = bx * kUpCols + (threadIdx.x & (kUpCols - 1));
-  j = by * kUpRows + (threadIdx.x >> 6);
-  return i < nx && j < ny;
-}
-
 // Step index of this launch in the case's window, or -1 when outside it.
 __device__ __forceinline__ long long up_step(const CaseDev& C, const UpArgs& A) {
   const long long n = *A.step_base + A.kofs - C.step0;
   return (n < 0 || n >= C.nsteps) ? -1 : n;
-}
-
-template <typename T, bool CPL, bool WALLS, bool MESH>
-__global__ __launch_bounds__(256) void k_up_stage(UpArgs A) {
-  const CaseDev C = *A.cases;
-  const long long n = up_step(C, A);
-  int i, j;
-  if (n < 0 || !up_cell(C.nx, C.ny, i, j)) return;
-  const int nx = C.nx, ny = C.ny;
-  constexpr int walls = WALLS ? 1 : 0;
-  const int cur = (C.cur0 + (int)(n & 1)) & 1;
-  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
-  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const long long N = C.plane, rv = C.row_vals;
-  const long long RB = rv * (long long)sizeof(T), PB = (long long)nx * sizeof(T);
-  constexpr int NV = num_grouped(CPL);
-  const unsigned cell = (unsigned)j * (unsigned)nx + (unsigned)i;  // scratch index
-  // a wave is one row of the block (kUpCols == 64), so j is the same on its lanes
-  T ph[3][3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    const T* prow = reinterpret_cast<const T*>(row_ptr(in, row_idx(j + r - 1, ny, walls), RB) + NV * PB);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) ph[r][c] = prow[wrap_near(i + c - 1, nx)];
-  }
-  T v[NV];
-  load_groups<T, NV>(row_ptr(in, j, RB), PB, (unsigned)i, v);
-  T ft[9], gt[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    ft[q] = v[val_f(q)];
-    gt[q] = CPL ? v[val_g(q)] : T(0);
-  }
-  Cell<T> o;
-  T tp[18];
-  const double tn = C.t0 + (double)n * C.dt;
-  if constexpr (MESH) {
-    T gx, gy, lap;
-    mesh_stencils<T>(C, ph, i, j, gx, gy, lap);
-    double xc, yc;
-    cell_centre(C, i, j, xc, yc);
-    cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)],
-                      xc, yc, tn, o, tp);
-  } else {
-    cell_stage<T, CPL>(C, ph, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], (double)i + 0.5,
-                       (double)j + 0.5, tn, o, tp);
-  }
-  T nv[NV];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    nv[val_f(q)] = tp[q];
-    if (CPL) nv[val_g(q)] = tp[9 + q];
-  }
-  nv[val_hist(CPL, 0)] = o.hx;
-  nv[val_hist(CPL, 1)] = o.hy;
-  store_groups<T, NV>(row_ptr(out, j, RB), PB, (unsigned)i, nv);
-  T* S = static_cast<T*>(A.scratch);
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    S[q * N + cell] = o.fb[q];
-    if (CPL) S[(9 + q) * N + cell] = o.gb[q];
-  }
-  T* in6 = S + up_bar_planes(CPL) * N;
-  in6[cell] = o.gx;
-  in6[N + cell] = o.gy;
-  in6[2 * N + cell] = o.mu;
-  in6[3 * N + cell] = o.Dx;
-  in6[4 * N + cell] = o.Dy;
-  in6[5 * N + cell] = o.p;
 }
 
 // van Leer's limited slope of two one-sided differences (or slopes).
@@ -1762,22 +1688,21 @@ __device__ __forceinline__ T van_leer(T a, T b) {
   return a * b > T(0) ? q : T(0);
 }
 
-// The face-and-update kernel stages the bar-plus values of its block's cells
-// and their halo (two columns/rows before, two after) in LDS: a block's faces
-// read each value several times (the limited slopes of both cells of every
-// face).
-constexpr int kTileR = kUpRows + 4, kTileC = kUpCols + 4;
+// The block step holds the bar-plus values of its block's cells and their
+// halo (two columns/rows before, two after) in LDS: a block's faces read each
+// value several times (the limited slopes of both cells of every face). The
+// tile has kTileC columns and ROWS + 4 rows.
+constexpr int kTileC = kUpCols + 4;
 
-// Metrics of one cell along one axis of a stretched mesh: width, centre
-// distances to the previous and next cells, their reciprocals, the weights
-// of the parabola derivative d1 = cp (a+ - a) + cm (a - a-), and twice the
-// reciprocal width (the divisions of the stencils done once per cell).
+// Metrics of one cell along one axis of a stretched mesh: width, the
+// reciprocal centre distances to the previous and next cells, the weights of
+// the parabola derivative d1 = cp (a+ - a) + cm (a - a-), and twice the
+// reciprocal width (read from the metric arrays, which the host derives once).
 template <typename T>
 struct Met {
-  T w, hm, hp, ihm, ihp, cp, cm, iw2;  // iw2 = 2 / w
-  __device__ static Met make(double w, double hm, double hp) {
-    return Met{T(w), T(hm), T(hp), T(1.0 / hm), T(1.0 / hp), T(hm / (hp * (hm + hp))),
-               T(hp / (hm * (hm + hp))), T(2.0 / w)};
+  T w, ihm, ihp, cp, cm, iw2;  // iw2 = 2 / w
+  __device__ static Met load(const MeshAxis& A, int k) {
+    return Met{T(A.w[k]), T(A.ihm[k]), T(A.ihp[k]), T(A.cp[k]), T(A.cm[k]), T(2.0 * A.iw[k])};
   }
 };
 
@@ -1788,9 +1713,9 @@ struct Met {
 // ic1, jc1 are the wrapped indices of ic, jc, ic + 1, jc + 1. On a stretched
 // mesh the metrics of columns ic, ic + 1 and rows jc, jc + 1 are held in
 // registers.
-template <typename T, bool WALLS, bool MESH, int NB>
+template <typename T, bool WALLS, bool MESH, int NB, int TR>
 struct UpBars {
-  const T (*L)[kTileR][kTileC];  // LDS tile [NB][kTileR][kTileC]
+  const T (*L)[TR][kTileC];  // LDS tile [planes][TR][kTileC]
   int i0, j0;                    // grid cell of tile position (2, 2)
   int nx, ny;
   int ic, jc, icw, jcw, ic1, jc1;
@@ -1914,20 +1839,20 @@ struct UpBars {
 
 // The view of the tile for the faces of cell (ic, jc) (unwrapped), with its
 // wrapped indices and, on a stretched mesh, its metrics.
-template <typename T, bool WALLS, bool MESH, int NB>
-__device__ __forceinline__ UpBars<T, WALLS, MESH, NB> up_bars(const CaseDev& C,
-                                                             const T (*L)[kTileR][kTileC], int i0,
-                                                             int j0, int ic, int jc) {
+template <typename T, bool WALLS, bool MESH, int NB, int TR>
+__device__ __forceinline__ UpBars<T, WALLS, MESH, NB, TR> up_bars(const CaseDev& C,
+                                                                 const T (*L)[TR][kTileC], int i0,
+                                                                 int j0, int ic, int jc) {
   const int nx = C.nx, ny = C.ny;
-  UpBars<T, WALLS, MESH, NB> B{L, i0, j0, nx, ny, ic, jc, wrap_near(ic, nx), wrap_near(jc, ny),
+  UpBars<T, WALLS, MESH, NB, TR> B{L, i0, j0, nx, ny, ic, jc, wrap_near(ic, nx), wrap_near(jc, ny),
                                wrap_near(ic + 1, nx), wrap_near(jc + 1, ny), {}, {}};
   if (MESH) {
     const MeshAxis X = mesh_axis(C.mesh, nx, ny, 0), Y = mesh_axis(C.mesh, nx, ny, 1);
     const int cx[2] = {B.icw, B.ic1}, cy[2] = {B.jcw, B.jc1};
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      B.mx[k] = Met<T>::make(X.w[cx[k]], X.hm[cx[k]], X.hp[cx[k]]);
-      B.my[k] = Met<T>::make(Y.w[cy[k]], Y.hm[cy[k]], Y.hp[cy[k]]);
+      B.mx[k] = Met<T>::load(X, cx[k]);
+      B.my[k] = Met<T>::load(Y, cy[k]);
     }
   }
   return B;
@@ -1936,10 +1861,10 @@ __device__ __forceinline__ UpBars<T, WALLS, MESH, NB> up_bars(const CaseDev& C,
 // Face of normal DIR between cells A and B (unwrapped indices):
 // reconstruction, face macros and the face distributions fo, go (the
 // populations that cross the face).
-template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR, int NB>
-__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH, NB>& B,
-                                        const T* in6, long long N, int ia, int ja, int ib, int jb,
-                                        double xf, double yf, double tf, T (&fo)[9], T (&go)[9]) {
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR, int NB, int TR>
+__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH, NB, TR>& B,
+                                        int ia, int ja, int ib, int jb, double xf, double yf,
+                                        double tf, T (&fo)[9], T (&go)[9]) {
   const T h = T(C.h);
   T fbar[9], gbar[9];
 #pragma unroll
@@ -1956,30 +1881,27 @@ __device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS,
     Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
     Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
   }
-  const long long a = (long long)B.yj(ja) * B.nx + B.xi(ia);
-  const long long b = (long long)B.yj(jb) * B.nx + B.xi(ib);
   T dA, dB;
   B.template halves<DIR>(ia, ja, ib, jb, dA, dB);
-  // gradient-type face inputs: the mean of the two cells (linear
-  // interpolation to the face on a stretched mesh)
+  // gradient-type face inputs (tile planes NB ..): the mean of the two
+  // cells (linear interpolation to the face on a stretched mesh)
   const T iH = T(1) / (dA + dB);
   auto mean = [&](int k) {
-    if (MESH) return (dB * in6[k * N + a] + dA * in6[k * N + b]) * iH;
-    return T(0.5) * (in6[k * N + a] + in6[k * N + b]);
+    if (MESH) return (dB * B.at(NB + k, ia, ja) + dA * B.at(NB + k, ib, jb)) * iH;
+    return T(0.5) * (B.at(NB + k, ia, ja) + B.at(NB + k, ib, jb));
   };
   face_df<T, CPL, DIR>(C, phif, N0f, Jxf, Jyf, mean(0), mean(1), mean(2), mean(3), mean(4), fbar,
                        gbar, xf, yf, tf, fo, go);
 }
 
 // Wall face below row 0 (BOTTOM) or above row ny-1 of column i: the march's
-// face bounce-back, fed from the tile. B is the view of the wall cell.
-template <typename T, bool BOTTOM, bool MESH, int NB>
-__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH, NB>& B,
-                                        const T* in6, long long N, const T* phiP, long long rv,
-                                        int i, T (&fo)[9], T (&go)[9]) {
-  const int nx = B.nx, ny = B.ny;
+// face bounce-back, fed from the tile. B is the view of the wall cell; its
+// phi and p come from the registers of the thread that owns it.
+template <typename T, bool BOTTOM, bool MESH, int NB, int TR>
+__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH, NB, TR>& B,
+                                        int i, T phiw, T pw, T (&fo)[9], T (&go)[9]) {
+  const int ny = B.ny;
   const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
-  const long long cw = (long long)jw * nx + B.xi(i);
   Cell<T> c, cn;
   T txf[9], txg[9];
 #pragma unroll
@@ -1997,11 +1919,11 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
       txg[q] = diag ? B.at(9 + q, i + 1, jw) - B.at(9 + q, i - 1, jw) : T(0);
     }
   }
-  c.phi = phiP[(long long)jw * rv + B.xi(i)];
-  c.gx = in6[cw];
-  c.mu = in6[2 * N + cw];
-  c.Dx = in6[3 * N + cw];
-  c.p = in6[5 * N + cw];
+  c.phi = phiw;
+  c.gx = B.at(NB + 0, i, jw);
+  c.mu = B.at(NB + 2, i, jw);
+  c.Dx = B.at(NB + 3, i, jw);
+  c.p = pw;
   T dyw = T(0), idy = T(1);
   if (MESH) {
     const Met<T>& m = B.MY(jw);
@@ -2011,71 +1933,145 @@ __device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, 
   wall_face_g<T, BOTTOM, MESH>(C, c, cn, txf, txg, dyw, idy, fo, go);
 }
 
-// Faces and update of one 64 x 4 block of cells. Every thread forms the
-// x-face east and the y-face north of its cell; wave 0 also forms the y-face
-// south of the block's first row, and four lanes of wave 1 the x-face west
-// of its first column. The face distributions go to LDS (over the tile,
-// whose reads are finished by then), and every cell is updated from its
-// four faces (Eq. 24).
-template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL>
-__global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
+// The whole step of one 64 x ROWS block of cells. Three phases, with
+// barriers:
+//   1. stage: the cell stage (macros, equilibria, sources, bar-plus and
+//      tilde-plus; the central march's cell_stage / cell_core) of the block's
+//      cells and of a halo of two cells on each side, 68 x (ROWS + 4) cells:
+//      bar-plus and the face inputs (grad phi, mu_phi, D) go to the LDS tile,
+//      tilde-plus, the history, phi and p of the block's own cells stay in
+//      the registers of the thread that updates the cell (the halo cells skip
+//      tilde-plus);
+//   2. faces: every thread forms the x-face east and the y-face north of its
+//      cell, wave 0 also the y-face south of the block's first row, ROWS
+//      lanes of wave 1 the x-face west of its first column (reconstruction
+//      from the tile, face macros, face distributions; wall faces, by the
+//      thread that owns the wall cell);
+//   3. update (Eq. 24): the face distributions go to LDS over the tile, and
+//      every cell is updated from its four faces.
+// The two halo cells on each side are what the block's faces read: a face
+// reads the limited slopes of both its cells, and a slope reads the cell's
+// neighbours.
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int ROWS, int WPE>
+__global__ __launch_bounds__(kUpCols * ROWS) __attribute__((amdgpu_waves_per_eu(WPE)))
+void k_up_step(UpArgs A) {
+  constexpr int NT = kUpCols * ROWS, TR = ROWS + 4;
   const CaseDev C = *A.cases;
   const long long n = up_step(C, A);
   if (n < 0) return;
   const int nx = C.nx, ny = C.ny;
-  // block origin (the same map as up_cell); blocks past the grid leave
-  // before the barriers, all of their threads together
+  // block origin (blocks in XCD-contiguous order); blocks past the grid
+  // leave before the barriers, all of their threads together
   const int nbx = (nx + kUpCols - 1) / kUpCols;
   const int idx = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-  const int i0 = (idx % nbx) * kUpCols, j0 = (idx / nbx) * kUpRows;
+  const int i0 = (idx % nbx) * kUpCols, j0 = (idx / nbx) * ROWS;
   if (j0 >= ny) return;
   const int lane = threadIdx.x & (kUpCols - 1), wv = threadIdx.x >> 6;
-  const long long N = C.plane;
   const long long RB = C.row_vals * (long long)sizeof(T), PB = (long long)nx * sizeof(T);
-  const T* S = static_cast<const T*>(A.scratch);
   constexpr int NB = up_bar_planes(CPL);
   constexpr int NF = CPL ? 12 : 6;  // crossing populations of a face, f then g
-  __shared__ T tile[NB][kTileR][kTileC];
-  // rows j0-2 .. j0+kUpRows+1, columns i0-2 .. i0+kUpCols+1: periodic wrap,
-  // clamped at walls (rows past a wall are never read). Wave wv loads rows
-  // wv, wv + 4, ... of the [plane][row] list; all its loads are issued before
-  // the first LDS write, so their latencies overlap.
-  {
-    constexpr int kLoads = (NB * kTileR + kUpRows - 1) / kUpRows;
-    const int c0 = wrap_near(i0 - 2 + lane, nx);
-    const int c1 = wrap_near(i0 - 2 + kUpCols + (lane < kTileC - kUpCols ? lane : 0), nx);
-    T v0[kLoads], v1[kLoads];
-#pragma unroll
-    for (int k = 0; k < kLoads; ++k) {
-      const int pr = wv + k * kUpRows;
-      if (pr < NB * kTileR) {
-        const int p = pr / kTileR, r = pr - p * kTileR;
-        int gj = j0 - 2 + r;
-        gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap_near(gj, ny);
-        const T* src = S + p * N + (long long)gj * nx;
-        v0[k] = src[c0];
-        if (lane < kTileC - kUpCols) v1[k] = src[c1];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kLoads; ++k) {
-      const int pr = wv + k * kUpRows;
-      if (pr < NB * kTileR) {
-        const int p = pr / kTileR, r = pr - p * kTileR;
-        tile[p][r][lane] = v0[k];
-        if (lane < kTileC - kUpCols) tile[p][r][kUpCols + lane] = v1[k];
-      }
-    }
-  }
-  __syncthreads();
-  const int i = i0 + lane, j = j0 + wv;
-  const bool act = i < nx && j < ny;
-  const T* in6 = S + up_bar_planes(CPL) * N;
+  constexpr int NV = num_grouped(CPL);
+  constexpr int walls = WALLS ? 1 : 0;
+  // bar-plus planes, then grad phi x, y, mu_phi, D x, y
+  __shared__ T tile[NB + 5][TR][kTileC];
+  static_assert(NF * (ROWS * (kUpCols + 1) + (ROWS + 1) * kUpCols) <= (NB + 5) * TR * kTileC,
+                "the face planes of phase 3 fit in the tile");
   const int cur = (C.cur0 + (int)(n & 1)) & 1;
   const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
   char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const T* phiP = reinterpret_cast<const T*>(in + num_grouped(CPL) * PB);  // phi of row 0
-  const double tf = C.t0 + (double)n * C.dt + C.h;
+  const double tn = C.t0 + (double)n * C.dt;
+
+  // ---- 1. stage. Tile cell (tc, tr) is grid cell (i0 - 2 + tc, j0 - 2 + tr),
+  // wrapped in x and y (periodic) or clamped to the wall rows (the clamped
+  // copies stand for rows past a wall, which no face reads).
+  auto stage = [&](int tc, int tr, Cell<T>& o, T (&tp)[18]) {
+    const int gi = wrap_near(i0 - 2 + tc, nx);
+    int gj = j0 - 2 + tr;
+    gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap_near(gj, ny);
+    T ph[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const T* prow = reinterpret_cast<const T*>(in + (long long)row_idx(gj + r - 1, ny, walls) * RB +
+                                                 NV * PB);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ph[r][c] = prow[wrap_near(gi + c - 1, nx)];
+    }
+    T v[NV];
+    load_groups<T, NV>(in + (long long)gj * RB, PB, (unsigned)gi, v);
+    T ft[9], gt[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      ft[q] = v[val_f(q)];
+      gt[q] = CPL ? v[val_g(q)] : T(0);
+    }
+    if constexpr (MESH) {
+      T gx, gy, lap;
+      mesh_stencils<T>(C, ph, gi, gj, gx, gy, lap);
+      double xc, yc;
+      cell_centre(C, gi, gj, xc, yc);
+      cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)],
+                        xc, yc, tn, o, tp);
+    } else {
+      cell_stage<T, CPL>(C, ph, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], (double)gi + 0.5,
+                         (double)gj + 0.5, tn, o, tp);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      tile[q][tr][tc] = o.fb[q];
+      if (CPL) tile[9 + q][tr][tc] = o.gb[q];
+    }
+    tile[NB + 0][tr][tc] = o.gx;
+    tile[NB + 1][tr][tc] = o.gy;
+    tile[NB + 2][tr][tc] = o.mu;
+    tile[NB + 3][tr][tc] = o.Dx;
+    tile[NB + 4][tr][tc] = o.Dy;
+  };
+  // the thread's own cell: tilde-plus and history kept for the update, phi
+  // and p for a wall face
+  T keep[NV];
+  T own_phi, own_p;
+  {
+    Cell<T> o;
+    T tp[18];
+    stage(2 + lane, 2 + wv, o, tp);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      keep[val_f(q)] = tp[q];
+      if (CPL) keep[val_g(q)] = tp[9 + q];
+    }
+    keep[val_hist(CPL, 0)] = o.hx;
+    keep[val_hist(CPL, 1)] = o.hy;
+    own_phi = o.phi;
+    own_p = o.p;
+  }
+  // the halo: rows 0, 1 and TR - 2, TR - 1 of the tile, then columns 0, 1,
+  // kTileC - 2, kTileC - 1 of the block's rows
+  constexpr int kHalo = kTileC * TR - NT;
+  for (int hc = (int)threadIdx.x; hc < kHalo; hc += NT) {
+    int tc, tr;
+    if (hc < 2 * kTileC) {
+      tr = hc / kTileC;
+      tc = hc - tr * kTileC;
+    } else if (hc < 4 * kTileC) {
+      const int k = hc - 2 * kTileC;
+      tr = TR - 2 + k / kTileC;
+      tc = k % kTileC;
+    } else {
+      const int k = hc - 4 * kTileC;
+      tr = 2 + (k >> 2);
+      const int m = k & 3;
+      tc = m < 2 ? m : kTileC - 4 + m;
+    }
+    Cell<T> o;
+    T tp[18];
+    stage(tc, tr, o, tp);
+  }
+  __syncthreads();
+
+  // ---- 2. faces
+  const int i = i0 + lane, j = j0 + wv;
+  const bool act = i < nx && j < ny;
+  const double tf = tn + C.h;
   MeshAxis X{}, Y{};
   if (MESH) {
     X = mesh_axis(C.mesh, nx, ny, 0);
@@ -2089,44 +2085,44 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   auto ymid = [&](int r) { return MESH ? Y.c[r] : (double)r + 0.5; };
   T fx[9], gx[9], fy[9], gy[9], fe[9], ge[9];
   if (act) {
-    const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, j);
-    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i, j, i + 1, j, xeast(i), ymid(j), tf,
-                                             fx, gx);
+    const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i, j);
+    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, i, j, i + 1, j, xeast(i), ymid(j), tf, fx, gx);
     if (WALLS && j == ny - 1) {
-      if constexpr (WALLS) up_wall<T, false, MESH, NB>(C, B, in6, N, phiP, C.row_vals, i, fy, gy);
+      if constexpr (WALLS) up_wall<T, false, MESH, NB, TR>(C, B, i, own_phi, own_p, fy, gy);
     } else {
-      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j, i, j + 1, xmid(i), ynorth(j),
-                                               tf, fy, gy);
+      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, i, j, i, j + 1, xmid(i), ynorth(j), tf, fy, gy);
     }
   }
   // the block's extra faces
   const bool south = wv == 0 && i < nx;
-  const bool west = wv == 1 && lane < kUpRows && j0 + lane < ny;
-  if (south) {  // y-face between rows j0 - 1 and j0, or the bottom wall
+  const bool west = wv == 1 && lane < ROWS && j0 + lane < ny;
+  if (south) {  // y-face between rows j0 - 1 and j0, or the bottom wall (of this thread's cell)
     if (WALLS && j0 == 0) {
       if constexpr (WALLS) {
-        const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, 0);
-        up_wall<T, true, MESH, NB>(C, B, in6, N, phiP, C.row_vals, i, fe, ge);
+        const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i, 0);
+        up_wall<T, true, MESH, NB, TR>(C, B, i, own_phi, own_p, fe, ge);
       }
     } else {
-      const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i, j0 - 1);
-      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, in6, N, i, j0 - 1, i, j0, xmid(i),
-                                               ynorth(B.jcw), tf, fe, ge);
+      const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i, j0 - 1);
+      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, i, j0 - 1, i, j0, xmid(i), ynorth(B.jcw), tf,
+                                               fe, ge);
     }
   }
   if (west) {  // x-face between columns i0 - 1 and i0 of row j0 + lane
     const int jr = j0 + lane;
-    const auto B = up_bars<T, WALLS, MESH, NB>(C, tile, i0, j0, i0 - 1, jr);
-    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, in6, N, i0 - 1, jr, i0, jr, xeast(B.icw),
-                                             ymid(jr), tf, fe, ge);
+    const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i0 - 1, jr);
+    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, i0 - 1, jr, i0, jr, xeast(B.icw), ymid(jr), tf,
+                                             fe, ge);
   }
   __syncthreads();  // every read of the tile is done: it now holds the faces
-  // x-faces [NF][kUpRows][kUpCols + 1] (column c: the face east of i0 - 1 + c),
-  // y-faces [NF][kUpRows + 1][kUpCols] (row r: the face north of j0 - 1 + r)
+
+  // ---- 3. update
+  // x-faces [NF][ROWS][kUpCols + 1] (column c: the face east of i0 - 1 + c),
+  // y-faces [NF][ROWS + 1][kUpCols] (row r: the face north of j0 - 1 + r)
   T* FX = &tile[0][0][0];
-  T* FY = FX + NF * kUpRows * (kUpCols + 1);
-  auto fxi = [&](int s, int r, int c) { return (s * kUpRows + r) * (kUpCols + 1) + c; };
-  auto fyi = [&](int s, int r, int c) { return (s * (kUpRows + 1) + r) * kUpCols + c; };
+  T* FY = FX + NF * ROWS * (kUpCols + 1);
+  auto fxi = [&](int s, int r, int c) { return (s * ROWS + r) * (kUpCols + 1) + c; };
+  auto fyi = [&](int s, int r, int c) { return (s * (ROWS + 1) + r) * kUpCols + c; };
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
     const int sx = up_xslot(q), sy = up_yslot(q);
@@ -2149,17 +2145,13 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
   }
   __syncthreads();
   if (!act) return;
-  // update (Eq. 24): face length over cell area is 1/dx and 1/dy (1 on unit
-  // cells)
-  constexpr int NV = num_grouped(CPL);
+  // face length over cell area is 1/dx and 1/dy (1 on unit cells)
   char* orow = row_ptr(out, j, RB);  // one row per wave
   T ax = T(1), ay = T(1);
   if (MESH) {
-    ax = T(1.0 / X.w[i]);
-    ay = T(1.0 / Y.w[j]);
+    ax = T(X.iw[i]);
+    ay = T(Y.iw[j]);
   }
-  T v[NV];
-  load_groups<T, NV>(orow, PB, (unsigned)i, v);
   const T dt = T(C.dt);
   T phin = T(0);
   auto upd = [&](int q, int off) {
@@ -2175,15 +2167,18 @@ __global__ __launch_bounds__(256) void k_up_faces_update(UpArgs A) {
     if (EY[q] != 0) J += T(EY[q]) * (FY[fyi(off + sy, wv + 1, lane)] - FY[fyi(off + sy, wv, lane)]);
     return J;
   };
+  T v[NV];
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
-    v[val_f(q)] = v[val_f(q)] - dt * upd(q, 0);
+    v[val_f(q)] = keep[val_f(q)] - dt * upd(q, 0);
     phin += v[val_f(q)];
   }
   if (CPL) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) v[val_g(q)] = v[val_g(q)] - dt * upd(q, 6);
+    for (int q = 0; q < 9; ++q) v[val_g(q)] = keep[val_g(q)] - dt * upd(q, 6);
   }
+  v[val_hist(CPL, 0)] = keep[val_hist(CPL, 0)];
+  v[val_hist(CPL, 1)] = keep[val_hist(CPL, 1)];
   store_groups<T, NV>(orow, PB, (unsigned)i, v);
   gstore<T>(orow + NV * PB, (unsigned)i * (unsigned)sizeof(T), phin);
   flag_nonfinite(C, phin + v[val_hist(CPL, 0)] + v[val_hist(CPL, 1)]);
@@ -2233,13 +2228,15 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
                               int nx, int ny, const UpArgs& a, hipStream_t s) {
   if (walls && !coupled) return hipErrorInvalidValue;
   if (!upwind && !mesh) return hipErrorInvalidValue;  // the march covers that case
-  const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + kUpRows - 1) / kUpRows);
-  dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * kUpRows);
-#define UP_LAUNCH(T, CPL, W, M, CEN)                                                \
-  do {                                                                              \
-    hipLaunchKernelGGL((k_up_stage<T, CPL, W, M>), grid, block, 0, s, a);           \
-    hipLaunchKernelGGL((k_up_faces_update<T, CPL, W, M, CEN>), grid, block, 0, s, a); \
-  } while (0)
+  const int rows = fp64                 ? up_rows<double, false, false>()
+                   : !mesh              ? up_rows<float, false, false>()
+                   : upwind             ? up_rows<float, true, false>()
+                                        : up_rows<float, true, true>();
+  const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + rows - 1) / rows);
+  dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * rows);
+#define UP_LAUNCH(T, CPL, W, M, CEN)                                                              \
+  hipLaunchKernelGGL((k_up_step<T, CPL, W, M, CEN, up_rows<T, M, CEN>(), up_wpe<T, M, CEN>()>), \
+                     grid, block, 0, s, a)
 #define UP_MODES(T, CPL, W)                                  \
   do {                                                       \
     if (!mesh) UP_LAUNCH(T, CPL, W, false, false);           \
