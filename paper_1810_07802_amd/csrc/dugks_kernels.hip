@@ -1630,7 +1630,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_rows(const CaseDev* __res
 // be summed from the nine reconstructed values instead of reconstructed cell
 // moments. A face also reads the limited slopes of both its cells, a
 // radius-two stencil. On a stretched mesh every stencil carries the local
-// widths. The step then runs as one kernel over 64 x 4 blocks of cells
+// widths. The step then runs as one kernel over blocks of 64 x ROWS cells
 // (k_up_step): each block stages its cells and a halo of two cells into LDS,
 // forms every face of its cells once and updates them. The cell stage, face
 // distribution and wall face are the march's.
@@ -2224,36 +2224,35 @@ hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, h
   return hipGetLastError();
 }
 
+// One block-step launch: blocks of 64 x ROWS cells, the grid rounded up to
+// a multiple of eight (one share per XCD; surplus blocks leave at once).
+template <typename T, bool CPL, bool W, bool M, bool CEN>
+static void launch_up(int nx, int ny, const UpArgs& a, hipStream_t s) {
+  constexpr int rows = up_rows<T, M, CEN>();
+  const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + rows - 1) / rows);
+  const dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * rows);
+  hipLaunchKernelGGL((k_up_step<T, CPL, W, M, CEN, rows, up_wpe<T, M, CEN>()>), grid, block, 0, s, a);
+}
+template <typename T, bool CPL, bool W>
+static void launch_up_modes(bool upwind, bool mesh, int nx, int ny, const UpArgs& a, hipStream_t s) {
+  if (!mesh) launch_up<T, CPL, W, false, false>(nx, ny, a, s);
+  else if (upwind) launch_up<T, CPL, W, true, false>(nx, ny, a, s);
+  else launch_up<T, CPL, W, true, true>(nx, ny, a, s);
+}
+
 hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
                               int nx, int ny, const UpArgs& a, hipStream_t s) {
   if (walls && !coupled) return hipErrorInvalidValue;
   if (!upwind && !mesh) return hipErrorInvalidValue;  // the march covers that case
-  const int rows = fp64                 ? up_rows<double, false, false>()
-                   : !mesh              ? up_rows<float, false, false>()
-                   : upwind             ? up_rows<float, true, false>()
-                                        : up_rows<float, true, true>();
-  const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + rows - 1) / rows);
-  dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * rows);
-#define UP_LAUNCH(T, CPL, W, M, CEN)                                                              \
-  hipLaunchKernelGGL((k_up_step<T, CPL, W, M, CEN, up_rows<T, M, CEN>(), up_wpe<T, M, CEN>()>), \
-                     grid, block, 0, s, a)
-#define UP_MODES(T, CPL, W)                                  \
-  do {                                                       \
-    if (!mesh) UP_LAUNCH(T, CPL, W, false, false);           \
-    else if (upwind) UP_LAUNCH(T, CPL, W, true, false);      \
-    else UP_LAUNCH(T, CPL, W, true, true);                   \
-  } while (0)
   if (fp64) {
-    if (!coupled) UP_MODES(double, false, false);
-    else if (walls) UP_MODES(double, true, true);
-    else UP_MODES(double, true, false);
+    if (!coupled) launch_up_modes<double, false, false>(upwind, mesh, nx, ny, a, s);
+    else if (walls) launch_up_modes<double, true, true>(upwind, mesh, nx, ny, a, s);
+    else launch_up_modes<double, true, false>(upwind, mesh, nx, ny, a, s);
   } else {
-    if (!coupled) UP_MODES(float, false, false);
-    else if (walls) UP_MODES(float, true, true);
-    else UP_MODES(float, true, false);
+    if (!coupled) launch_up_modes<float, false, false>(upwind, mesh, nx, ny, a, s);
+    else if (walls) launch_up_modes<float, true, true>(upwind, mesh, nx, ny, a, s);
+    else launch_up_modes<float, true, false>(upwind, mesh, nx, ny, a, s);
   }
-#undef UP_MODES
-#undef UP_LAUNCH
   return hipGetLastError();
 }
 
