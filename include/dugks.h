@@ -164,12 +164,13 @@ int dugks_get_tile(const dugks_handle *h);
  *     over the centre distances (both reconstructions; the upwind slopes are
  *     van Leer's of the one-sided slopes, capped at twice the smaller
  *     one-sided difference over the cell width);
- *   - the regularisation of the unit normal is 1e-6 |phi_H - phi_L| over
+ *   - the regularisation of the unit normal is eps_n |phi_H - phi_L| over
  *     the smallest width.
  * The step then runs as the upwind mode's kernel (see recon), which needs no
- * device memory beyond the state and the metrics. Cell centres start at x = 0, y = 0. Takes effect at the next
- * dugks_init_fields (the state is invalidated: ESTATE until then). Not for
- * batches or pool cases (EINVAL). Errors: EINVAL (widths), ENOMEM. */
+ * device memory beyond the state and the metrics. Cell centres start at
+ * x = 0, y = 0. Takes effect at the next dugks_init_fields (the state is
+ * invalidated: ESTATE until then). Not for batches or pool cases (EINVAL).
+ * Errors: EINVAL (widths), ENOMEM. */
 int dugks_set_mesh(dugks_handle *h, const double *dx, const double *dy);
 
 /* Build the initial state from cell macros: host arrays [ny][nx] of double,
