@@ -25,10 +25,11 @@ The same JSON line carries:
                 requests, aggregate MLUPS, vs the plain sequential per-case
                 loop
   upwind        the bubble with the upwind, limited face reconstruction
-                (the block step: one kernel per step), 128^2 and 4096^2;
+                (the upwind march: one kernel per step), 128^2 and 4096^2;
                 the HBM fraction at the method's 160 B per cell
   mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
-                central and upwind, through the same block step
+                central and upwind, through the block step (one kernel per
+                step)
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -205,11 +206,11 @@ def roofline(cells, steps, seconds, prec, workload=None):
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
 
 
-def timed_block_step(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
-    """Block steps (one kernel per step) of case `c` (coupled FP32): the
-    upwind reconstruction, or a stretched mesh `mesh` = (dx, dy) in either
-    reconstruction, replayed from HIP graphs (see timed()). The HBM
-    fraction is quoted at the method's 160 B per cell."""
+def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
+    """Steps of case `c` (coupled FP32) with the upwind reconstruction (the
+    upwind march on the unit mesh), or on a stretched mesh `mesh` = (dx, dy)
+    in either reconstruction (the block step), replayed from HIP graphs (see
+    timed()). The HBM fraction is quoted at the method's 160 B per cell."""
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
     s.set_stream(torch.cuda.current_stream().cuda_stream)
     if mesh is not None:
@@ -219,10 +220,13 @@ def timed_block_step(torch, D, c, steps, warmup, recon="upwind", mesh=None, chun
     d = s.diagnostics()
     cells = c["nx"] * c["ny"]
     ach = B_PER_CELL["fp32"] * cells * steps / t / 1e9
-    return {"mlups": round(cells * steps / t / 1e6, 1), "steps": steps,
-            "us_per_step": round(t / steps * 1e6, 3),
-            "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
-            "bytes_per_cell": B_PER_CELL["fp32"], "nonfinite": d["nonfinite"]}
+    r = {"mlups": round(cells * steps / t / 1e6, 1), "steps": steps,
+         "us_per_step": round(t / steps * 1e6, 3),
+         "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
+         "bytes_per_cell": B_PER_CELL["fp32"], "nonfinite": d["nonfinite"]}
+    if mesh is None and recon == "upwind":
+        r["seg_rows"] = s.seg_rows  # segment of the upwind march
+    return r
 
 
 def served_stream(torch, D, W, n_req, n_sample):
@@ -396,7 +400,7 @@ def main():
         cl = W.bubble(L=4096, R=1024, steps=0)
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, stretched mesh, central",
-                          **timed_block_step(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
+                          **timed_recon(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
               flush=True)
         return
     if args.profile_batch:
@@ -416,7 +420,7 @@ def main():
     if args.profile_upwind:
         cl = W.bubble(L=4096, R=1024, steps=0)
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, upwind reconstruction",
-                          **timed_block_step(torch, D, cl, args.upwind_steps, 3)}), flush=True)
+                          **timed_recon(torch, D, cl, args.upwind_steps, 3)}), flush=True)
         return
     if args.profile_kernel:
         c = W.bubble(L=128, R=32)
@@ -523,9 +527,9 @@ def main():
         # upwind, limited reconstruction on the same physics
         rec["upwind"] = {
             "workload": "stationary bubble, coupled FP32, upwind reconstruction, one "
-                        "block-step kernel per step, replayed from HIP graphs of up to 100 steps",
-            "bubble128": timed_block_step(torch, D, c, min(args.small_steps, 5000), 100),
-            "bubble4096": timed_block_step(torch, D, W.bubble(L=4096, R=1024, steps=0),
+                        "upwind-march kernel per step, replayed from HIP graphs of up to 100 steps",
+            "bubble128": timed_recon(torch, D, c, min(args.small_steps, 5000), 100),
+            "bubble4096": timed_recon(torch, D, W.bubble(L=4096, R=1024, steps=0),
                                            args.upwind_steps, 5)}
         progress("upwind done")
         # stretched tensor-product mesh, both reconstructions
@@ -535,8 +539,8 @@ def main():
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
                         "both axes), coupled FP32, one block-step kernel per step, replayed "
                         "from HIP graphs of up to 100 steps",
-            "central": timed_block_step(torch, D, cm, args.upwind_steps, 5, "central", mesh),
-            "upwind": timed_block_step(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
+            "central": timed_recon(torch, D, cm, args.upwind_steps, 5, "central", mesh),
+            "upwind": timed_recon(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
         progress("mesh done")
         if args.serve_requests > 0:
             rec["served"] = served_stream(torch, D, W, args.serve_requests, args.serve_sample)

@@ -87,6 +87,29 @@ int fit_seg_rows(const std::vector<StripShape>& cs, long long budget) {
 // than the device caches) eight rounds of shorter tiles, which keeps the
 // rows in flight closer together and measured faster on MI355X (4096^2
 // FP32 coupled: 23.4k MLUPS with 137-row segments, 26.8k with 17).
+// The upwind march takes one round of resident waves with its own strips
+// (60 columns) and capacity; where that needs segments longer than 64 rows,
+// the shortest segments that number at most 32 waves per CU. Measured on
+// MI355X (microseconds per step, upwind bubble): 4096^2 FP32 18 rows 655,
+// 24 638, 32 634, 48 641, 64 699; FP64 16 rows 1613, 35 1484, 48 1494,
+// 64 1635; the one-round choice is the fastest at 1024^2 (10 rows), 128^2
+// (1 row) and 256 x 1024 with walls (3 rows).
+int auto_upm_rows(const dugks_handle* h) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  long long cus = 256, cap = 2048;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    cus = prop.multiProcessorCount;
+    cap = cus * dugks::upm_waves_per_cu(h->fp64(), h->coupled(), h->params.bc_y == DUGKS_BC_WALLS);
+  } else {
+    (void)hipGetLastError();
+  }
+  const std::vector<StripShape> cs = {
+      StripShape{(h->nx + dugks::kUpmCols - 1) / dugks::kUpmCols, h->ny}};
+  const int a = fit_seg_rows(cs, cap);
+  return a > 64 ? fit_seg_rows(cs, 32 * cus) : a;
+}
+
 int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity, bool fp64, bool walls) {
   const int a = fit_seg_rows(cs, capacity);
   if (a > 64) return fit_seg_rows(cs, 8 * capacity);
@@ -238,6 +261,24 @@ int upload_case(dugks_handle* h) {
   }
   HIPCHK(h, hipMemcpyAsync(h->items, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice,
                            h->stream));
+  std::vector<Item> ut;
+  if (h->upm()) {
+    h->upm_rows = h->seg_rows ? std::min(h->seg_rows, h->ny) : auto_upm_rows(h);
+    const int ns = (h->nx + dugks::kUpmCols - 1) / dugks::kUpmCols;
+    const int nseg = (h->ny + h->upm_rows - 1) / h->upm_rows;
+    ut.reserve((size_t)ns * nseg);
+    for (int s = 0; s < nseg; ++s)
+      for (int x = 0; x < ns; ++x) ut.push_back(Item{0, x, s, 0});
+    if ((int)ut.size() != h->nuitems) {
+      if (h->uitems) (void)hipFree(h->uitems);
+      h->uitems = nullptr;
+      h->nuitems = 0;
+      HIPCHK(h, hipMalloc(&h->uitems, ut.size() * sizeof(Item)));
+      h->nuitems = (int)ut.size();
+    }
+    HIPCHK(h, hipMemcpyAsync(h->uitems, ut.data(), ut.size() * sizeof(Item), hipMemcpyHostToDevice,
+                             h->stream));
+  }
   // the pinned-host source of the copies above is a local: wait here
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->dirty_case = false;
@@ -304,6 +345,20 @@ int numeric_fail(dugks_handle* h) {
 }
 
 int launch_steps(dugks_handle* h, int nsteps) {
+  if (h->upm()) {
+    StepArgs a{};
+    a.cases = h->dc;
+    a.items = h->uitems;
+    a.nitems = h->nuitems;
+    a.step_base = h->step_base;
+    a.upm_rows = h->upm_rows;
+    for (int k = 0; k < nsteps; ++k) {
+      a.kofs = k;
+      HIPCHK(h, dugks::launch_step_upm(h->fp64(), h->coupled(), h->hc.walls != 0, a, h->stream));
+    }
+    HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
+    return DUGKS_OK;
+  }
   if (h->general()) {
     UpArgs u{h->dc, h->step_base, 0};
     for (int k = 0; k < nsteps; ++k) {
@@ -336,7 +391,8 @@ std::vector<long long> launch_sig(const dugks_handle* h) {
   return {h->general() ? 1 : 0, h->upwind() ? 1 : 0, h->mesh ? 1 : 0, (long long)h->hc.walls,
           h->fp64() ? 1 : 0, h->coupled() ? 1 : 0, (long long)(uintptr_t)h->items,
           (long long)h->nitems, (long long)h->hc.seg_rows, (long long)(uintptr_t)h->dc,
-          (long long)(uintptr_t)h->step_base, (long long)h->nx,
+          (long long)(uintptr_t)h->step_base, (long long)(uintptr_t)h->uitems,
+          (long long)h->nuitems, (long long)h->upm_rows, (long long)h->nx,
           (long long)h->ny};
 }
 
@@ -454,7 +510,10 @@ int dugks_set_tile(dugks_handle* h, int seg_rows) {
   return DUGKS_OK;
 }
 
-int dugks_get_tile(const dugks_handle* h) { return h ? h->hc.seg_rows : -1; }
+int dugks_get_tile(const dugks_handle* h) {
+  if (!h) return -1;
+  return h->upm() ? h->upm_rows : h->hc.seg_rows;
+}
 
 int dugks_set_mesh(dugks_handle* h, const double* dx, const double* dy) {
   if (!h) return fail(h, DUGKS_EINVAL, "NULL handle");
@@ -755,6 +814,7 @@ int dugks_destroy(dugks_handle* h) {
   if (h->step_base) (void)hipFree(h->step_base);
   if (h->dflag) (void)hipFree(h->dflag);
   if (h->scratch) (void)hipFree(h->scratch);
+  if (h->uitems) (void)hipFree(h->uitems);
   if (h->dmesh) (void)hipFree(h->dmesh);
   drop_graphs(h);
   delete h;

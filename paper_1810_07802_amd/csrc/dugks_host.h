@@ -11,6 +11,10 @@
 #include "../../include/dugks.h"
 #include "dugks_impl.h"
 
+#ifndef DUGKS_UPM
+#define DUGKS_UPM 1
+#endif
+
 struct dugks_handle {
   int nx = 0, ny = 0, precision = 0, model = 0;
   dugks_params params{};
@@ -22,6 +26,10 @@ struct dugks_handle {
   dugks::CaseDev* dc = nullptr;
   dugks::Item* items = nullptr;
   int nitems = 0;
+  // work items of the upwind march (upwind reconstruction on the unit mesh)
+  dugks::Item* uitems = nullptr;
+  int nuitems = 0;
+  int upm_rows = 0;  // rows per segment of the upwind march in use
   int seg_rows = 0;  // 0: automatic
   long long* step_base = nullptr;  // device: steps done
   long long steps = 0;             // host mirror
@@ -47,6 +55,14 @@ struct dugks_handle {
   // steps run as the block step (upwind reconstruction or stretched mesh)
   // instead of the march
   bool general() const { return upwind() || mesh; }
+  // the upwind reconstruction on the unit mesh runs as the upwind march
+  bool upm() const {
+#if DUGKS_UPM
+    return upwind() && !mesh;
+#else
+    return false;
+#endif
+  }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
   size_t n() const { return (size_t)nx * ny; }
   size_t elem() const { return fp64() ? 8 : 4; }
@@ -82,6 +98,8 @@ int fit_seg_rows(const std::vector<StripShape>& cs, long long budget);
 // Automatic segment length of a group of cases (fp64, walls: the group's
 // precision and boundary, which decide whether the two-row kernel applies).
 int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity, bool fp64, bool walls);
+// Automatic segment length of the upwind march of a handle.
+int auto_upm_rows(const dugks_handle* h);
 // Compute units of the current device.
 long long cu_count();
 

@@ -138,7 +138,12 @@ struct StepArgs {
   int one_row;                 // every item is one row (seg_rows == 1): row kernel
   int two_row;                 // every item is two rows (seg_rows == 2): the two-row kernel
                                // for periodic FP32 cases, else the march
+  int upm_rows;                // rows per segment of the upwind march
 };
+
+// The upwind march (unit mesh): strips of kUpmCols columns (a 64-lane wave
+// with two halo lanes on each side); segments of StepArgs::upm_rows rows.
+constexpr int kUpmCols = 60;
 
 // Bar-plus planes of the block step's LDS tile (upwind reconstruction,
 // stretched mesh): f0..f8 and (coupled) g0..g8.
@@ -163,6 +168,11 @@ struct UpArgs {
 hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
                               int nx, int ny, const UpArgs& a, hipStream_t s);
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
+// the upwind march (upwind reconstruction on the unit mesh; items of
+// kUpmCols-column strips and a.upm_rows-row segments) and its resident waves
+// per CU
+hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
+int upm_waves_per_cu(bool fp64, bool coupled, bool walls);
 int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);
 // step_base[0] = value (if not null) and flag[0] = 0 (if not null)

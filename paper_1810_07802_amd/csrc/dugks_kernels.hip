@@ -2184,6 +2184,362 @@ void k_up_step(UpArgs A) {
   flag_nonfinite(C, phin + v[val_hist(CPL, 0)] + v[val_hist(CPL, 1)]);
 }
 
+// ------------------------------ upwind march (unit mesh)
+
+// The upwind reconstruction on the unit mesh as a march, like k_step: one
+// 64-lane wave owns a strip of kUpmCols = 60 columns (lanes 2..61; two halo
+// lanes on each side, since an x-face reads the limited x slopes of both its
+// cells and a slope reads the cell's neighbours) and marches up a segment of
+// rows. Each row's limited slopes are formed once and kept in its record:
+// the x slopes from the neighbouring lanes (DPP), the y slopes from the rows
+// below and above when the row above is staged. Output row k needs rows
+// k-2..k+2 staged, so the pass that stages row s also forms the y slopes of
+// row s-1, the y-face between rows s-2 and s-1, the x-faces of row s-1 and
+// the update of row s-2. The reconstruction, face macros, face distributions
+// and wall faces are the block step's (UpBars::face, up_face, up_wall), with
+// the same expressions, so both kernels give the same bits.
+template <typename T, bool CPL>
+struct URow {
+  Cell<T> cell;
+  T lxf[9], lxg[9];  // limited x slopes of the planes with e_x != 0
+  T lyf[9], lyg[9];  // limited y slopes of the planes with e_y != 0
+  T txf[9], txg[9];  // x central differences of the diagonal planes (wall faces)
+  T fsf[9], fsg[9];  // the face below the row (populations with e_y != 0)
+  // the row's part of the y-face above it: the upwind traces of the
+  // populations with e_y > 0, formed as soon as the row's y slopes exist
+  T tdf[9], tdg[9];
+};
+
+template <typename T, bool CPL, bool WALLS>
+__device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long long n,
+                                          int seg_rows) {
+  const int lane = threadIdx.x;
+  const int nx = C.nx, ny = C.ny;
+  constexpr int walls = WALLS ? 1 : 0;
+  const int i0 = it.strip * kUpmCols;
+  const int col = i0 - 2 + lane;
+  const int ci = wrap(col, nx);
+  const int cx = lane == 0 ? wrap(col - 1, nx) : (lane == 63 ? wrap(col + 1, nx) : ci);
+  const bool store = lane >= 2 && lane <= kUpmCols + 1 && col < nx;
+  const int cur = (C.cur0 + (int)(n & 1)) & 1;
+  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
+  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
+  const long long RB = C.row_vals * (long long)sizeof(T);
+  const long long PB = (long long)nx * sizeof(T);
+  constexpr int NV = num_grouped(CPL);
+  const unsigned es = sizeof(T);
+  const double tn = C.t0 + (double)n * C.dt;
+  const double xc = (double)ci + 0.5;
+  const int j0 = it.seg * seg_rows;
+  const int j1 = min(j0 + seg_rows, ny);
+  const T h = T(C.h), hal = T(0.5) - h;
+
+  __shared__ T stash[3][18][64];  // tilde-plus of the rows staged by the last three passes
+  __shared__ T fxs[2][12][64];    // x-faces of the last two rows formed (crossing populations)
+  __shared__ T topn[6][64];       // row ny - 2, populations 2..4 (f, g): the top wall face
+
+  struct Raw {
+    T f[9], g[9], hx, hy, po, pe;
+  };
+  auto fetch = [&](int r, Raw& R) {
+    T v[NV];
+    load_groups<T, NV, true>(row_ptr(in, row_idx(r, ny, walls), RB), PB, (unsigned)ci, v);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) R.f[q] = v[val_f(q)];
+    if (CPL) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) R.g[q] = v[val_g(q)];
+    }
+    R.hx = v[val_hist(CPL, 0)];
+    R.hy = v[val_hist(CPL, 1)];
+    const char* prow = row_ptr(in, row_idx(r + 1, ny, walls), RB) + NV * PB;
+    R.po = gload<T>(prow, lane_off((unsigned)ci * es));
+    R.pe = gload<T>(prow, lane_off((unsigned)cx * es));
+  };
+  auto phi_lr = [&](T own, T ext, T (&o)[3]) {
+    T left = nbr_l(own), right = nbr_r(own);
+    if (lane == 0) left = ext;
+    if (lane == 63) right = ext;
+    o[0] = left; o[1] = own; o[2] = right;
+  };
+  auto phi_row = [&](int r, T (&o)[3]) {
+    const char* prow = row_ptr(in, row_idx(r, ny, walls), RB) + NV * PB;
+    phi_lr(gload<T>(prow, lane_off((unsigned)ci * es)), gload<T>(prow, lane_off((unsigned)cx * es)), o);
+  };
+  // stage row r into rd (cell stage, tilde-plus to the stash slot, limited x
+  // slopes, x central differences)
+  auto stage = [&](int r, int slot, const Raw& R, const T (&pm)[3], const T (&p0)[3],
+                   const T (&pp)[3], URow<T, CPL>& rd) {
+    const int rr = row_idx(r, ny, walls);
+    T ph[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { ph[0][k] = pm[k]; ph[1][k] = p0[k]; ph[2][k] = pp[k]; }
+    T tp[18];
+    cell_stage<T, CPL>(C, ph, R.f, R.g, R.hx, R.hy, xc, (double)rr + 0.5, tn, rd.cell, tp);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) stash[slot][q][lane] = tp[q];
+    if (WALLS && r == ny - 2) {  // every segment that outputs row ny - 1 stages row ny - 2
+#pragma unroll
+      for (int q = 2; q <= 4; ++q) {
+        topn[q - 2][lane] = rd.cell.fb[q];
+        topn[1 + q][lane] = rd.cell.gb[q];
+      }
+    }
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (EX[q] == 0) continue;
+      const T c = rd.cell.fb[q];
+      rd.lxf[q] = van_leer(c - nbr_l(c), nbr_r(c) - c);
+      if (CPL) {
+        const T cg = rd.cell.gb[q];
+        rd.lxg[q] = van_leer(cg - nbr_l(cg), nbr_r(cg) - cg);
+      }
+      if (WALLS && EY[q] != 0) {
+        rd.txf[q] = nbr_r(c) - nbr_l(c);
+        if (CPL) rd.txg[q] = nbr_r(rd.cell.gb[q]) - nbr_l(rd.cell.gb[q]);
+      }
+    }
+  };
+  // limited y slopes of row r (record m) from the rows below (d) and above
+  // (u); one-sided and unlimited at a wall row
+  auto yslopes = [&](int r, const URow<T, CPL>& d, URow<T, CPL>& m, const URow<T, CPL>& u) {
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (EY[q] == 0) continue;
+      const T c = m.cell.fb[q];
+      const T cg = CPL ? m.cell.gb[q] : T(0);
+      if (WALLS && r == 0) {
+        m.lyf[q] = u.cell.fb[q] - c;
+        if (CPL) m.lyg[q] = u.cell.gb[q] - cg;
+      } else if (WALLS && r == ny - 1) {
+        m.lyf[q] = c - d.cell.fb[q];
+        if (CPL) m.lyg[q] = cg - d.cell.gb[q];
+      } else {
+        m.lyf[q] = van_leer(c - d.cell.fb[q], u.cell.fb[q] - c);
+        if (CPL) m.lyg[q] = van_leer(cg - d.cell.gb[q], u.cell.gb[q] - cg);
+      }
+      if (EY[q] > 0) {  // the lower cell's traces of the y-face above the row
+        T v = c + hal * m.lyf[q];
+        if (EX[q] != 0) v -= h * T(EX[q]) * m.lxf[q];
+        m.tdf[q] = v;
+        if (CPL) {
+          T w = cg + hal * m.lyg[q];
+          if (EX[q] != 0) w -= h * T(EX[q]) * m.lxg[q];
+          m.tdg[q] = w;
+        }
+      }
+    }
+  };
+  // the x-face east of each cell of row r (record m; the east cell is lane + 1)
+  // into the LDS slot xs
+  auto xface = [&](int r, int xs, const URow<T, CPL>& m) {
+    T fbar[9], gbar[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int en = EX[q], et = EY[q];
+      auto rec = [&](const T& a, const T& lx, const T& ly) {
+        if (en > 0) {
+          T v = a + hal * lx;
+          if (et != 0) v -= h * T(et) * ly;
+          return v;
+        }
+        if (en < 0) {
+          T v = nbr_r(a) - hal * nbr_r(lx);
+          if (et != 0) v -= h * T(et) * nbr_r(ly);
+          return v;
+        }
+        T v = T(0.5) * (a + nbr_r(a));
+        if (et != 0) v -= h * T(et) * (T(0.5) * (ly + nbr_r(ly)));
+        return v;
+      };
+      fbar[q] = rec(m.cell.fb[q], m.lxf[q], m.lyf[q]);
+      gbar[q] = (CPL && q > 0) ? rec(m.cell.gb[q], m.lxg[q], m.lyg[q]) : T(0);
+    }
+    const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
+                   ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
+    T N0f = T(0), Jxf = T(0), Jyf = T(0);
+    if (CPL) {
+      N0f = ((gbar[1] + gbar[2]) + (gbar[3] + gbar[4])) + ((gbar[5] + gbar[6]) + (gbar[7] + gbar[8]));
+      Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
+      Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
+    }
+    const Cell<T>& a = m.cell;
+    T fo[9], go[9];
+    face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, T(0.5) * (a.gx + nbr_r(a.gx)),
+                       T(0.5) * (a.gy + nbr_r(a.gy)), T(0.5) * (a.mu + nbr_r(a.mu)),
+                       T(0.5) * (a.Dx + nbr_r(a.Dx)), T(0.5) * (a.Dy + nbr_r(a.Dy)), fbar, gbar,
+                       (double)ci + 1.0, (double)row_idx(r, ny, walls) + 0.5, tn + C.h, fo, go);
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (EX[q] == 0) continue;
+      fxs[xs][up_xslot(q)][lane] = fo[q];
+      if (CPL) fxs[xs][6 + up_xslot(q)][lane] = go[q];
+    }
+  };
+  // the y-face between rows r (record d, below) and r + 1 (record u), into
+  // u's face below
+  auto yface = [&](int r, const URow<T, CPL>& d, URow<T, CPL>& u) {
+    T fbar[9], gbar[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      const int en = EY[q], et = EX[q];
+      auto rec = [&](const T& tD, const T& aD, const T& lxD, const T& aU, const T& lyU,
+                     const T& lxU) {
+        if (en > 0) return tD;  // formed with the lower row's y slopes
+        if (en < 0) {
+          T v = aU - hal * lyU;
+          if (et != 0) v -= h * T(et) * lxU;
+          return v;
+        }
+        T v = T(0.5) * (aD + aU);
+        if (et != 0) v -= h * T(et) * (T(0.5) * (lxD + lxU));
+        return v;
+      };
+      fbar[q] = rec(d.tdf[q], d.cell.fb[q], d.lxf[q], u.cell.fb[q], u.lyf[q], u.lxf[q]);
+      gbar[q] = (CPL && q > 0)
+                    ? rec(d.tdg[q], d.cell.gb[q], d.lxg[q], u.cell.gb[q], u.lyg[q], u.lxg[q])
+                    : T(0);
+    }
+    const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
+                   ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
+    T N0f = T(0), Jxf = T(0), Jyf = T(0);
+    if (CPL) {
+      N0f = ((gbar[1] + gbar[2]) + (gbar[3] + gbar[4])) + ((gbar[5] + gbar[6]) + (gbar[7] + gbar[8]));
+      Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
+      Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
+    }
+    const Cell<T>& a = d.cell;
+    const Cell<T>& b = u.cell;
+    face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, T(0.5) * (a.gx + b.gx), T(0.5) * (a.gy + b.gy),
+                       T(0.5) * (a.mu + b.mu), T(0.5) * (a.Dx + b.Dx), T(0.5) * (a.Dy + b.Dy),
+                       fbar, gbar, xc, (double)row_idx(r, ny, walls) + 1.0, tn + C.h, u.fsf,
+                       u.fsg);
+  };
+  // update of output row r (record m) from its faces: east m.fx, west the
+  // left lane's, below m.fs, above (fnf, fng)
+  auto update = [&](int r, int slot, int xs, const URow<T, CPL>& m, const T (&fnf)[9],
+                    const T (&fng)[9]) {
+    char* orow = row_ptr(out, row_idx(r, ny, walls), RB);
+    const T dt = T(C.dt);
+    T nv[NV];
+    T phin = T(0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      T J = T(0);
+      if (EX[q] != 0) {
+        const T e = fxs[xs][up_xslot(q)][lane];
+        J += T(EX[q]) * (e - nbr_l(e));
+      }
+      if (EY[q] != 0) J += T(EY[q]) * (fnf[q] - m.fsf[q]);
+      nv[val_f(q)] = stash[slot][q][lane] - dt * J;
+      phin += nv[val_f(q)];
+    }
+    if (CPL) {
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        T J = T(0);
+        if (EX[q] != 0) {
+          const T e = fxs[xs][6 + up_xslot(q)][lane];
+          J += T(EX[q]) * (e - nbr_l(e));
+        }
+        if (EY[q] != 0) J += T(EY[q]) * (fng[q] - m.fsg[q]);
+        nv[val_g(q)] = stash[slot][9 + q][lane] - dt * J;
+      }
+    }
+    nv[val_hist(CPL, 0)] = m.cell.hx;
+    nv[val_hist(CPL, 1)] = m.cell.hy;
+    if (store) {
+      store_groups<T, NV, true>(orow, PB, (unsigned)ci, nv);
+      gstore<T>(orow + NV * PB, lane_off((unsigned)ci * es), phin);
+      flag_nonfinite(C, phin + m.cell.hx + m.cell.hy);
+    }
+  };
+
+  // One pass: stage row s into R1; y slopes of row s - 1 (R0); the y-face
+  // between rows s - 2 (Rm) and s - 1; the x-faces of row s - 1; the update
+  // of row s - 2. p is the pass index (stash slots rotate by three).
+  auto pass = [&](int s, int p, Raw& raw, URow<T, CPL>& Rm, URow<T, CPL>& R0, URow<T, CPL>& R1,
+                  const T (&pa)[3], const T (&pb)[3], T (&pc)[3]) {
+    const int slot = p % 3;
+    phi_lr(raw.po, raw.pe, pc);
+    const bool ex1 = !(walls && (s < 0 || s >= ny));
+    if (ex1) stage(s, slot, raw, pa, pb, pc, R1);
+    fetch(min(s + 2, j1 + 1), raw);
+    const int r0 = s - 1, rm = s - 2;
+    const bool ex0 = !(walls && (r0 < 0 || r0 >= ny));
+    const bool exm = !(walls && (rm < 0 || rm >= ny));
+    if (ex0 && r0 >= j0 - 1) {
+      yslopes(r0, Rm, R0, R1);
+      if (r0 >= j0 && r0 < j1) xface(r0, p & 1, R0);
+    }
+    // the face below row s - 1: between rows s - 2 and s - 1, or the bottom wall
+    if (rm >= j0 - 1 && rm < j1) {
+      if (ex0 && exm) {
+        yface(rm, Rm, R0);
+      } else if (WALLS && rm == -1) {
+        wall_face<T, true>(C, R0.cell, R1.cell, R0.txf, R0.txg, R0.fsf, R0.fsg);
+      }
+    }
+    if (rm >= j0 && rm < j1) {
+      const int ms = (p + 1) % 3;  // slot of row s - 2
+      if (WALLS && rm == ny - 1) {
+        // top wall: the next row inward (row ny - 2) from LDS
+        Cell<T> cn;
+#pragma unroll
+        for (int q = 2; q <= 4; ++q) {
+          cn.fb[q] = topn[q - 2][lane];
+          cn.gb[q] = topn[1 + q][lane];
+        }
+        T fnf[9], fng[9];
+        wall_face<T, false>(C, Rm.cell, cn, Rm.txf, Rm.txg, fnf, fng);
+        update(rm, ms, (p + 1) & 1, Rm, fnf, fng);
+      } else {
+        update(rm, ms, (p + 1) & 1, Rm, R0.fsf, R0.fsg);
+      }
+    }
+  };
+
+  URow<T, CPL> R0, R1, R2;
+  T P0[3], P1[3], P2[3];
+  auto rotate = [&]() {
+    R0 = R1;
+    R1 = R2;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      P0[m] = P1[m];
+      P1[m] = P2[m];
+    }
+  };
+  Raw ra, rb;
+  const int kb = j0 - 2;
+  const int npass = j1 - j0 + 4;
+  phi_row(kb - 1, P0);
+  phi_row(kb, P1);
+  fetch(kb, ra);
+  fetch(kb + 1, rb);
+  for (int m = 0; m < npass; m += 2) {
+    pass(kb + m, m, ra, R0, R1, R2, P0, P1, P2);
+    rotate();
+    if (m + 1 < npass) {
+      pass(kb + m + 1, m + 1, rb, R0, R1, R2, P0, P1, P2);
+      rotate();
+    }
+  }
+}
+
+template <typename T, bool CPL, bool WALLS>
+__global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) {
+  const int nb = gridDim.x;
+  const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
+  const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (idx >= A.nitems) return;
+  const Item it = A.items[idx];
+  const CaseDev C = A.cases[it.c];
+  const long long n = *A.step_base + A.kofs - C.step0;
+  if (n < 0 || n >= C.nsteps) return;
+  upm_march<T, CPL, WALLS>(C, it, n, A.upm_rows);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- launchers
@@ -2254,6 +2610,37 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
     else launch_up_modes<float, true, false>(upwind, mesh, nx, ny, a, s);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s) {
+  if (a.nitems <= 0) return hipSuccess;
+  if (walls && !coupled) return hipErrorInvalidValue;
+  const dim3 grid((a.nitems + 7) / 8 * 8), block(kWave);
+  if (fp64) {
+    if (!coupled) hipLaunchKernelGGL((k_upm<double, false, false>), grid, block, 0, s, a);
+    else if (walls) hipLaunchKernelGGL((k_upm<double, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_upm<double, true, false>), grid, block, 0, s, a);
+  } else {
+    if (!coupled) hipLaunchKernelGGL((k_upm<float, false, false>), grid, block, 0, s, a);
+    else if (walls) hipLaunchKernelGGL((k_upm<float, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_upm<float, true, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+int upm_waves_per_cu(bool fp64, bool coupled, bool walls) {
+  int nb = 0;
+  hipError_t e;
+  if (fp64) {
+    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<double, false, false>, kWave, 0);
+    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<double, true, true>, kWave, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<double, true, false>, kWave, 0);
+  } else {
+    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<float, false, false>, kWave, 0);
+    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<float, true, true>, kWave, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<float, true, false>, kWave, 0);
+  }
+  return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 // Resident waves per CU of the step kernel (one wave per work group).

@@ -7,8 +7,10 @@ reading: trace back by h xi into the upwind cell, van Leer limited slopes).
 Tolerances are those of the central path: FP64 relative L2 <= 1e-12 after
 hundreds of steps (the same double formulas in another order; van Leer's
 limiter is Lipschitz, so rounding does not grow through its branches), FP32
-relative L2 <= 1e-5 on phi. Sizes span several 64 x 4 thread blocks with a
-ragged last block in x and y, and periodic and wall-bounded y.
+relative L2 <= 1e-5 on phi. On the unit mesh the step is the upwind march
+(60-column strips, segments of rows); sizes span several strips and
+segments with a ragged last strip and segment, and periodic and
+wall-bounded y.
 """
 import numpy as np
 import pytest
@@ -155,6 +157,28 @@ def test_switching_the_reconstruction_between_steps():
     g, r = s.macros(), o.macros()
     for k in ("phi", "u", "v", "p"):
         assert rel(g[k], r[k]) < 1e-12, k
+
+
+@pytest.mark.parametrize("precision,walls", [("fp32", False), ("fp32", True), ("fp64", False),
+                                              ("fp64", True)])
+def test_march_segments_give_the_same_bits(precision, walls):
+    """The upwind march's segment length (dugks_set_tile) changes only the
+    work decomposition: one-row segments, short ones that leave a ragged last
+    segment, the automatic choice and one segment of the whole height give
+    the same state bit for bit (halo rows go through the same code as output
+    rows). 130 columns are three strips, the last of 10 columns."""
+    c = upwind(W.random_coupled(130, 37, seed=11, rho_ratio=100.0, walls_y=walls))
+    states = {}
+    for seg in (1, 2, 5, 0, 37):
+        print(f"[upwind march] segments {seg} {precision} walls={walls}", flush=True)
+        s = D.Solver(c["nx"], c["ny"], c["params"], c["model"], precision, seg or None)
+        s.init(c["phi"], c["u"], c["v"], c["p"])
+        s.step(7)
+        assert s.seg_rows == (seg if seg else s.seg_rows)
+        states[seg] = s.get_state()[0]
+    ref = states[1]
+    for seg, st in states.items():
+        assert np.array_equal(st, ref), f"segments of {seg} rows differ from one-row segments"
 
 
 def test_batches_pools_and_autotune_reject_upwind():
