@@ -2203,7 +2203,6 @@ struct URow {
   Cell<T> cell;
   T lxf[9], lxg[9];  // limited x slopes of the planes with e_x != 0
   T lyf[9], lyg[9];  // limited y slopes of the planes with e_y != 0
-  T txf[9], txg[9];  // x central differences of the diagonal planes (wall faces)
   T fsf[9], fsg[9];  // the face below the row (populations with e_y != 0)
   // the row's part of the y-face above it: the upwind traces of the
   // populations with e_y > 0, formed as soon as the row's y slopes exist
@@ -2235,7 +2234,12 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   const T h = T(C.h), hal = T(0.5) - h;
 
   __shared__ T stash[3][18][64];  // tilde-plus of the rows staged by the last three passes
-  __shared__ T fxs[2][12][64];    // x-faces of the last two rows formed (crossing populations)
+  // x-faces of the last rows formed (crossing populations): two slots by
+  // pass parity, or with walls one slot (the update of a row then reads its
+  // x-faces before the next row's replace them; it saves the LDS of an
+  // eighth wave per CU there)
+  constexpr int XS = WALLS ? 1 : 2;
+  __shared__ T fxs[XS][12][64];
   __shared__ T topn[6][64];       // row ny - 2, populations 2..4 (f, g): the top wall face
 
   struct Raw {
@@ -2294,10 +2298,17 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         const T cg = rd.cell.gb[q];
         rd.lxg[q] = van_leer(cg - nbr_l(cg), nbr_r(cg) - cg);
       }
-      if (WALLS && EY[q] != 0) {
-        rd.txf[q] = nbr_r(c) - nbr_l(c);
-        if (CPL) rd.txg[q] = nbr_r(rd.cell.gb[q]) - nbr_l(rd.cell.gb[q]);
-      }
+    }
+  };
+  // x central differences of the diagonal planes of a wall row (wall faces)
+  auto xdiffs = [&](const Cell<T>& c, T (&txf)[9], T (&txg)[9]) {
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      txf[q] = T(0);
+      txg[q] = T(0);
+      if (EX[q] == 0 || EY[q] == 0) continue;
+      txf[q] = nbr_r(c.fb[q]) - nbr_l(c.fb[q]);
+      if (CPL) txg[q] = nbr_r(c.gb[q]) - nbr_l(c.gb[q]);
     }
   };
   // limited y slopes of row r (record m) from the rows below (d) and above
@@ -2331,7 +2342,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     }
   };
   // the x-face east of each cell of row r (record m; the east cell is lane + 1)
-  // into the LDS slot xs
+  // into LDS
   auto xface = [&](int r, int xs, const URow<T, CPL>& m) {
     T fbar[9], gbar[9];
 #pragma unroll
@@ -2468,20 +2479,23 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int r0 = s - 1, rm = s - 2;
     const bool ex0 = !(walls && (r0 < 0 || r0 >= ny));
     const bool exm = !(walls && (rm < 0 || rm >= ny));
-    if (ex0 && r0 >= j0 - 1) {
-      yslopes(r0, Rm, R0, R1);
-      if (r0 >= j0 && r0 < j1) xface(r0, p & 1, R0);
-    }
+    if (ex0 && r0 >= j0 - 1) yslopes(r0, Rm, R0, R1);
+    if (!WALLS && r0 >= j0 && r0 < j1) xface(r0, p & 1, R0);
     // the face below row s - 1: between rows s - 2 and s - 1, or the bottom wall
     if (rm >= j0 - 1 && rm < j1) {
       if (ex0 && exm) {
         yface(rm, Rm, R0);
       } else if (WALLS && rm == -1) {
-        wall_face<T, true>(C, R0.cell, R1.cell, R0.txf, R0.txg, R0.fsf, R0.fsg);
+        T txf[9], txg[9];
+        xdiffs(R0.cell, txf, txg);
+        wall_face<T, true>(C, R0.cell, R1.cell, txf, txg, R0.fsf, R0.fsg);
       }
     }
+    // the update of row s - 2 (with walls it reads its x-faces from LDS
+    // before the x-faces of row s - 1 replace them)
     if (rm >= j0 && rm < j1) {
       const int ms = (p + 1) % 3;  // slot of row s - 2
+      const int xs = WALLS ? 0 : (p + 1) & 1;
       if (WALLS && rm == ny - 1) {
         // top wall: the next row inward (row ny - 2) from LDS
         Cell<T> cn;
@@ -2490,13 +2504,15 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
           cn.fb[q] = topn[q - 2][lane];
           cn.gb[q] = topn[1 + q][lane];
         }
-        T fnf[9], fng[9];
-        wall_face<T, false>(C, Rm.cell, cn, Rm.txf, Rm.txg, fnf, fng);
-        update(rm, ms, (p + 1) & 1, Rm, fnf, fng);
+        T txf[9], txg[9], fnf[9], fng[9];
+        xdiffs(Rm.cell, txf, txg);
+        wall_face<T, false>(C, Rm.cell, cn, txf, txg, fnf, fng);
+        update(rm, ms, xs, Rm, fnf, fng);
       } else {
-        update(rm, ms, (p + 1) & 1, Rm, R0.fsf, R0.fsg);
+        update(rm, ms, xs, Rm, R0.fsf, R0.fsg);
       }
     }
+    if (WALLS && ex0 && r0 >= j0 && r0 < j1) xface(r0, 0, R0);
   };
 
   URow<T, CPL> R0, R1, R2;
