@@ -28,8 +28,8 @@ The same JSON line carries:
                 (the upwind march: one kernel per step), 128^2 and 4096^2;
                 the HBM fraction at the method's 160 B per cell
   mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
-                central and upwind, through the block step (one kernel per
-                step)
+                central (the block step) and upwind (the upwind march), one
+                kernel per step
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -208,8 +208,8 @@ def roofline(cells, steps, seconds, prec, workload=None):
 
 def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
     """Steps of case `c` (coupled FP32) with the upwind reconstruction (the
-    upwind march on the unit mesh), or on a stretched mesh `mesh` = (dx, dy)
-    in either reconstruction (the block step), replayed from HIP graphs (see
+    upwind march), or on a stretched mesh `mesh` = (dx, dy) in either
+    reconstruction (central: the block step), replayed from HIP graphs (see
     timed()). The HBM fraction is quoted at the method's 160 B per cell."""
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
     s.set_stream(torch.cuda.current_stream().cuda_stream)
@@ -224,7 +224,7 @@ def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100
          "us_per_step": round(t / steps * 1e6, 3),
          "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
          "bytes_per_cell": B_PER_CELL["fp32"], "nonfinite": d["nonfinite"]}
-    if mesh is None and recon == "upwind":
+    if recon == "upwind":
         r["seg_rows"] = s.seg_rows  # segment of the upwind march
     return r
 
@@ -537,8 +537,9 @@ def main():
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         rec["mesh"] = {
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
-                        "both axes), coupled FP32, one block-step kernel per step, replayed "
-                        "from HIP graphs of up to 100 steps",
+                        "both axes), coupled FP32, one kernel per step (central: the block "
+                        "step; upwind: the upwind march), replayed from HIP graphs of up to "
+                        "100 steps",
             "central": timed_recon(torch, D, cm, args.upwind_steps, 5, "central", mesh),
             "upwind": timed_recon(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
         progress("mesh done")

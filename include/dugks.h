@@ -89,10 +89,10 @@ enum { DUGKS_RECON_CENTRAL = 0, DUGKS_RECON_UPWIND = 1 };
  *                  ab > 0, else 0; one-sided and unlimited next to a wall);
  *                  populations along the face take the mean of both cells.
  *                  Upwind runs on single handles only (EINVAL in batches and
- *                  pools); it needs no device memory beyond the state. On
- *                  the unit mesh it runs as a march like the central one
- *                  (each cell's limited slopes formed once), on a stretched
- *                  mesh as a block step (see dugks_set_mesh).
+ *                  pools); it needs no device memory beyond the state. It
+ *                  runs as a march like the central one (each cell's
+ *                  limited slopes formed once), on the unit mesh and on a
+ *                  stretched mesh (see dugks_set_mesh).
  *   eps_n          regularisation of the interface normal of the phase-field
  *                  source (Eq. 16, n of Sec. II.A):
  *                  n = grad phi / sqrt(|grad phi|^2 + eps^2) with
@@ -147,8 +147,8 @@ int dugks_set_stream(dugks_handle *h, void *stream);
  * while two-row tiles do not, two rows, run by the four-wave two-row
  * kernel). Results do not depend on it, bit for bit. A batch uses a case's
  * explicit value, and its own automatic choice for cases left at 0. With
- * the upwind reconstruction on the unit mesh the value is the segment of the
- * upwind march instead (60-column strips; automatic: one round of resident
+ * the upwind reconstruction the value is the segment of the upwind march
+ * instead (60-column strips; automatic: one round of resident
  * waves, or where that needs more than 64 rows the shortest segments that
  * number at most 32 waves per compute unit). EINVAL outside [0, 4096].
  * dugks_get_tile returns the value in use (-1 for NULL). */
@@ -173,9 +173,10 @@ int dugks_get_tile(const dugks_handle *h);
  *     one-sided difference over the cell width);
  *   - the regularisation of the unit normal is eps_n |phi_H - phi_L| over
  *     the smallest width.
- * The step then runs as a block step (one kernel over blocks of cells with a
- * two-cell halo in LDS, both reconstructions), which needs no device memory
- * beyond the state and the metrics. Cell centres start at
+ * The step then runs as the upwind march (upwind reconstruction) or as a
+ * block step (central reconstruction: one kernel over blocks of cells with
+ * a two-cell halo in LDS); neither needs device memory beyond the state and
+ * the metrics. Cell centres start at
  * x = 0, y = 0. Takes effect at the next dugks_init_fields (the state is
  * invalidated: ESTATE until then). Not for batches or pool cases (EINVAL).
  * Errors: EINVAL (widths), ENOMEM. */

@@ -100,7 +100,8 @@ int auto_upm_rows(const dugks_handle* h) {
   long long cus = 256, cap = 2048;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
     cus = prop.multiProcessorCount;
-    cap = cus * dugks::upm_waves_per_cu(h->fp64(), h->coupled(), h->params.bc_y == DUGKS_BC_WALLS);
+    cap = cus * dugks::upm_waves_per_cu(h->fp64(), h->coupled(), h->params.bc_y == DUGKS_BC_WALLS,
+                                        h->mesh);
   } else {
     (void)hipGetLastError();
   }
@@ -354,7 +355,8 @@ int launch_steps(dugks_handle* h, int nsteps) {
     a.upm_rows = h->upm_rows;
     for (int k = 0; k < nsteps; ++k) {
       a.kofs = k;
-      HIPCHK(h, dugks::launch_step_upm(h->fp64(), h->coupled(), h->hc.walls != 0, a, h->stream));
+      HIPCHK(h, dugks::launch_step_upm(h->fp64(), h->coupled(), h->hc.walls != 0, h->mesh, a,
+                                       h->stream));
     }
     HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
     return DUGKS_OK;

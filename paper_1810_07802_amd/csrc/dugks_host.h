@@ -12,7 +12,7 @@
 #include "dugks_impl.h"
 
 #ifndef DUGKS_UPM
-#define DUGKS_UPM 1
+#define DUGKS_UPM 2
 #endif
 
 struct dugks_handle {
@@ -55,10 +55,11 @@ struct dugks_handle {
   // steps run as the block step (upwind reconstruction or stretched mesh)
   // instead of the march
   bool general() const { return upwind() || mesh; }
-  // the upwind reconstruction on the unit mesh runs as the upwind march
+  // the upwind reconstruction runs as the upwind march (DUGKS_UPM 2: on
+  // unit and stretched meshes, 1: on the unit mesh only, 0: never)
   bool upm() const {
 #if DUGKS_UPM
-    return upwind() && !mesh;
+    return upwind() && (DUGKS_UPM > 1 || !mesh);
 #else
     return false;
 #endif

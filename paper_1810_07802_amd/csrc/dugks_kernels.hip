@@ -1706,6 +1706,19 @@ struct Met {
   }
 };
 
+// Limited slope on a stretched mesh: van Leer of the one-sided slopes,
+// capped at twice the smaller one-sided difference over the cell's width, so
+// that the one-dimensional reconstruction anywhere in the cell stays between
+// the neighbours (the cap never binds on linear data, nor on unit widths);
+// the divisions use the cell's precomputed reciprocals.
+template <typename T>
+__device__ __forceinline__ T lim_mesh(T b, T f, const Met<T>& m) {
+  const T s = van_leer(b * m.ihm, f * m.ihp);
+  const T ab = b < T(0) ? -b : b, af = f < T(0) ? -f : f;
+  const T cap = (ab < af ? ab : af) * m.iw2;
+  return s > cap ? cap : (s < -cap ? -cap : s);
+}
+
 // Bar-plus values, slopes and face values of the faces of one cell (ic, jc):
 // they read the cells (ic, jc), (ic + 1, jc) and (ic, jc + 1) and their
 // neighbours. Cells are addressed by unwrapped grid indices within the
@@ -1745,16 +1758,8 @@ struct UpBars {
     if (MESH) return lim_met(b, f, MY(j));
     return van_leer(b, f);
   }
-  // stretched mesh: van Leer of the one-sided slopes, capped at twice the
-  // smaller one-sided difference over the cell's width, so that the
-  // one-dimensional reconstruction anywhere in the cell stays between the
-  // neighbours (the cap never binds on linear data, nor on unit widths); the
-  // divisions use the cell's precomputed reciprocals
   __device__ __forceinline__ static T lim_met(T b, T f, const Met<T>& m) {
-    const T s = van_leer(b * m.ihm, f * m.ihp);
-    const T ab = b < T(0) ? -b : b, af = f < T(0) ? -f : f;
-    const T cap = (ab < af ? ab : af) * m.iw2;
-    return s > cap ? cap : (s < -cap ? -cap : s);
+    return lim_mesh<T>(b, f, m);
   }
   // central slopes of the stretched mesh (parabola through three centres)
   __device__ __forceinline__ T slope_x(int p, int i, int j) const {
@@ -2209,7 +2214,7 @@ struct URow {
   T tdf[9], tdg[9];
 };
 
-template <typename T, bool CPL, bool WALLS>
+template <typename T, bool CPL, bool WALLS, bool MESH>
 __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long long n,
                                           int seg_rows) {
   const int lane = threadIdx.x;
@@ -2232,6 +2237,25 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   const int j0 = it.seg * seg_rows;
   const int j1 = min(j0 + seg_rows, ny);
   const T h = T(C.h), hal = T(0.5) - h;
+  // stretched mesh: the metrics of the lane's column (its east face: half
+  // widths dAx, dBx of the two cells and 1 / (dAx + dBx); the face position),
+  // and those of a row (uniform over the wave) through ymet()
+  Met<T> mx{};
+  T dAx = T(0.5), dBx = T(0.5), iHx = T(1), axw = T(1);
+  double xcen = xc, xeast = (double)ci + 1.0;
+  MeshAxis Y{};
+  if constexpr (MESH) {
+    const MeshAxis X = mesh_axis(C.mesh, nx, ny, 0);
+    Y = mesh_axis(C.mesh, nx, ny, 1);
+    mx = Met<T>::load(X, ci);
+    dAx = T(0.5) * mx.w;
+    dBx = nbr_r(dAx);
+    iHx = T(1) / (dAx + dBx);
+    axw = T(X.iw[ci]);
+    xcen = X.c[ci];
+    xeast = X.c[ci] + 0.5 * X.w[ci];
+  }
+  auto ymet = [&](int r) { return Met<T>::load(Y, row_idx(r, ny, walls)); };
 
   __shared__ T stash[3][18][64];  // tilde-plus of the rows staged by the last three passes
   // x-faces of the last rows formed (crossing populations): two slots by
@@ -2279,7 +2303,13 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
 #pragma unroll
     for (int k = 0; k < 3; ++k) { ph[0][k] = pm[k]; ph[1][k] = p0[k]; ph[2][k] = pp[k]; }
     T tp[18];
-    cell_stage<T, CPL>(C, ph, R.f, R.g, R.hx, R.hy, xc, (double)rr + 0.5, tn, rd.cell, tp);
+    if constexpr (MESH) {
+      T gx, gy, lap;
+      mesh_stencils<T>(C, ph, ci, rr, gx, gy, lap);
+      cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, R.f, R.g, R.hx, R.hy, xcen, Y.c[rr], tn, rd.cell, tp);
+    } else {
+      cell_stage<T, CPL>(C, ph, R.f, R.g, R.hx, R.hy, xc, (double)rr + 0.5, tn, rd.cell, tp);
+    }
 #pragma unroll
     for (int q = 0; q < 18; ++q) stash[slot][q][lane] = tp[q];
     if (WALLS && r == ny - 2) {  // every segment that outputs row ny - 1 stages row ny - 2
@@ -2293,27 +2323,39 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     for (int q = 1; q < 9; ++q) {
       if (EX[q] == 0) continue;
       const T c = rd.cell.fb[q];
-      rd.lxf[q] = van_leer(c - nbr_l(c), nbr_r(c) - c);
+      rd.lxf[q] = MESH ? lim_mesh<T>(c - nbr_l(c), nbr_r(c) - c, mx)
+                       : van_leer(c - nbr_l(c), nbr_r(c) - c);
       if (CPL) {
         const T cg = rd.cell.gb[q];
-        rd.lxg[q] = van_leer(cg - nbr_l(cg), nbr_r(cg) - cg);
+        rd.lxg[q] = MESH ? lim_mesh<T>(cg - nbr_l(cg), nbr_r(cg) - cg, mx)
+                         : van_leer(cg - nbr_l(cg), nbr_r(cg) - cg);
       }
     }
   };
-  // x central differences of the diagonal planes of a wall row (wall faces)
+  // x central differences (stretched mesh: x slopes of the parabola) of the
+  // diagonal planes of a wall row (wall faces)
   auto xdiffs = [&](const Cell<T>& c, T (&txf)[9], T (&txg)[9]) {
+    auto d = [&](T v) {
+      if (MESH) return mx.cp * (nbr_r(v) - v) + mx.cm * (v - nbr_l(v));
+      return nbr_r(v) - nbr_l(v);
+    };
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       txf[q] = T(0);
       txg[q] = T(0);
       if (EX[q] == 0 || EY[q] == 0) continue;
-      txf[q] = nbr_r(c.fb[q]) - nbr_l(c.fb[q]);
-      if (CPL) txg[q] = nbr_r(c.gb[q]) - nbr_l(c.gb[q]);
+      txf[q] = d(c.fb[q]);
+      if (CPL) txg[q] = d(c.gb[q]);
     }
   };
   // limited y slopes of row r (record m) from the rows below (d) and above
   // (u); one-sided and unlimited at a wall row
   auto yslopes = [&](int r, const URow<T, CPL>& d, URow<T, CPL>& m, const URow<T, CPL>& u) {
+    Met<T> my{};
+    if (MESH) my = ymet(r);
+    // from the row's centre to its upper face, less h (the trace of a
+    // population leaving upwards)
+    const T up = MESH ? T(0.5) * my.w - h : hal;
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       if (EY[q] == 0) continue;
@@ -2322,19 +2364,30 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
       if (WALLS && r == 0) {
         m.lyf[q] = u.cell.fb[q] - c;
         if (CPL) m.lyg[q] = u.cell.gb[q] - cg;
+        if (MESH) {
+          m.lyf[q] = m.lyf[q] * my.ihp;
+          if (CPL) m.lyg[q] = m.lyg[q] * my.ihp;
+        }
       } else if (WALLS && r == ny - 1) {
         m.lyf[q] = c - d.cell.fb[q];
         if (CPL) m.lyg[q] = cg - d.cell.gb[q];
+        if (MESH) {
+          m.lyf[q] = m.lyf[q] * my.ihm;
+          if (CPL) m.lyg[q] = m.lyg[q] * my.ihm;
+        }
+      } else if (MESH) {
+        m.lyf[q] = lim_mesh<T>(c - d.cell.fb[q], u.cell.fb[q] - c, my);
+        if (CPL) m.lyg[q] = lim_mesh<T>(cg - d.cell.gb[q], u.cell.gb[q] - cg, my);
       } else {
         m.lyf[q] = van_leer(c - d.cell.fb[q], u.cell.fb[q] - c);
         if (CPL) m.lyg[q] = van_leer(cg - d.cell.gb[q], u.cell.gb[q] - cg);
       }
       if (EY[q] > 0) {  // the lower cell's traces of the y-face above the row
-        T v = c + hal * m.lyf[q];
+        T v = c + up * m.lyf[q];
         if (EX[q] != 0) v -= h * T(EX[q]) * m.lxf[q];
         m.tdf[q] = v;
         if (CPL) {
-          T w = cg + hal * m.lyg[q];
+          T w = cg + up * m.lyg[q];
           if (EX[q] != 0) w -= h * T(EX[q]) * m.lxg[q];
           m.tdg[q] = w;
         }
@@ -2349,19 +2402,38 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     for (int q = 0; q < 9; ++q) {
       const int en = EX[q], et = EY[q];
       auto rec = [&](const T& a, const T& lx, const T& ly) {
-        if (en > 0) {
-          T v = a + hal * lx;
-          if (et != 0) v -= h * T(et) * ly;
+        if constexpr (MESH) {
+          if (en > 0) {
+            T v = a + (dAx - h) * lx;
+            if (et != 0) v -= h * T(et) * ly;
+            return v;
+          }
+          if (en < 0) {
+            T v = nbr_r(a) + (h - dBx) * nbr_r(lx);
+            if (et != 0) v -= h * T(et) * nbr_r(ly);
+            return v;
+          }
+          T vA = a, vB = nbr_r(a);
+          if (et != 0) {
+            vA -= h * T(et) * ly;
+            vB -= h * T(et) * nbr_r(ly);
+          }
+          return (dBx * vA + dAx * vB) * iHx;
+        } else {
+          if (en > 0) {
+            T v = a + hal * lx;
+            if (et != 0) v -= h * T(et) * ly;
+            return v;
+          }
+          if (en < 0) {
+            T v = nbr_r(a) - hal * nbr_r(lx);
+            if (et != 0) v -= h * T(et) * nbr_r(ly);
+            return v;
+          }
+          T v = T(0.5) * (a + nbr_r(a));
+          if (et != 0) v -= h * T(et) * (T(0.5) * (ly + nbr_r(ly)));
           return v;
         }
-        if (en < 0) {
-          T v = nbr_r(a) - hal * nbr_r(lx);
-          if (et != 0) v -= h * T(et) * nbr_r(ly);
-          return v;
-        }
-        T v = T(0.5) * (a + nbr_r(a));
-        if (et != 0) v -= h * T(et) * (T(0.5) * (ly + nbr_r(ly)));
-        return v;
       };
       fbar[q] = rec(m.cell.fb[q], m.lxf[q], m.lyf[q]);
       gbar[q] = (CPL && q > 0) ? rec(m.cell.gb[q], m.lxg[q], m.lyg[q]) : T(0);
@@ -2375,11 +2447,17 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
       Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
     }
     const Cell<T>& a = m.cell;
+    // face inputs: the mean of the two cells (linear interpolation to the
+    // face on a stretched mesh)
+    auto mean = [&](T v) {
+      if (MESH) return (dBx * v + dAx * nbr_r(v)) * iHx;
+      return T(0.5) * (v + nbr_r(v));
+    };
+    const int rr = row_idx(r, ny, walls);
     T fo[9], go[9];
-    face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, T(0.5) * (a.gx + nbr_r(a.gx)),
-                       T(0.5) * (a.gy + nbr_r(a.gy)), T(0.5) * (a.mu + nbr_r(a.mu)),
-                       T(0.5) * (a.Dx + nbr_r(a.Dx)), T(0.5) * (a.Dy + nbr_r(a.Dy)), fbar, gbar,
-                       (double)ci + 1.0, (double)row_idx(r, ny, walls) + 0.5, tn + C.h, fo, go);
+    face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, mean(a.gx), mean(a.gy), mean(a.mu), mean(a.Dx),
+                       mean(a.Dy), fbar, gbar, xeast, MESH ? Y.c[rr] : (double)rr + 0.5,
+                       tn + C.h, fo, go);
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       if (EX[q] == 0) continue;
@@ -2390,6 +2468,13 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   // the y-face between rows r (record d, below) and r + 1 (record u), into
   // u's face below
   auto yface = [&](int r, const URow<T, CPL>& d, URow<T, CPL>& u) {
+    // half heights of the two rows and 1 / their sum (stretched mesh)
+    T dA = T(0.5), dB = T(0.5), iH = T(1);
+    if (MESH) {
+      dA = T(0.5) * ymet(r).w;
+      dB = T(0.5) * ymet(r + 1).w;
+      iH = T(1) / (dA + dB);
+    }
     T fbar[9], gbar[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -2397,14 +2482,28 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
       auto rec = [&](const T& tD, const T& aD, const T& lxD, const T& aU, const T& lyU,
                      const T& lxU) {
         if (en > 0) return tD;  // formed with the lower row's y slopes
-        if (en < 0) {
-          T v = aU - hal * lyU;
-          if (et != 0) v -= h * T(et) * lxU;
+        if constexpr (MESH) {
+          if (en < 0) {
+            T v = aU + (h - dB) * lyU;
+            if (et != 0) v -= h * T(et) * lxU;
+            return v;
+          }
+          T vA = aD, vB = aU;
+          if (et != 0) {
+            vA -= h * T(et) * lxD;
+            vB -= h * T(et) * lxU;
+          }
+          return (dB * vA + dA * vB) * iH;
+        } else {
+          if (en < 0) {
+            T v = aU - hal * lyU;
+            if (et != 0) v -= h * T(et) * lxU;
+            return v;
+          }
+          T v = T(0.5) * (aD + aU);
+          if (et != 0) v -= h * T(et) * (T(0.5) * (lxD + lxU));
           return v;
         }
-        T v = T(0.5) * (aD + aU);
-        if (et != 0) v -= h * T(et) * (T(0.5) * (lxD + lxU));
-        return v;
       };
       fbar[q] = rec(d.tdf[q], d.cell.fb[q], d.lxf[q], u.cell.fb[q], u.lyf[q], u.lxf[q]);
       gbar[q] = (CPL && q > 0)
@@ -2421,41 +2520,56 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     }
     const Cell<T>& a = d.cell;
     const Cell<T>& b = u.cell;
-    face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, T(0.5) * (a.gx + b.gx), T(0.5) * (a.gy + b.gy),
-                       T(0.5) * (a.mu + b.mu), T(0.5) * (a.Dx + b.Dx), T(0.5) * (a.Dy + b.Dy),
-                       fbar, gbar, xc, (double)row_idx(r, ny, walls) + 1.0, tn + C.h, u.fsf,
-                       u.fsg);
+    auto mean = [&](T va, T vb) {
+      if (MESH) return (dB * va + dA * vb) * iH;
+      return T(0.5) * (va + vb);
+    };
+    const int rr = row_idx(r, ny, walls);
+    face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, mean(a.gx, b.gx), mean(a.gy, b.gy),
+                       mean(a.mu, b.mu), mean(a.Dx, b.Dx), mean(a.Dy, b.Dy), fbar, gbar, xcen,
+                       MESH ? Y.c[rr] + 0.5 * Y.w[rr] : (double)rr + 1.0, tn + C.h, u.fsf, u.fsg);
   };
   // update of output row r (record m) from its faces: east m.fx, west the
   // left lane's, below m.fs, above (fnf, fng)
   auto update = [&](int r, int slot, int xs, const URow<T, CPL>& m, const T (&fnf)[9],
                     const T (&fng)[9]) {
-    char* orow = row_ptr(out, row_idx(r, ny, walls), RB);
+    const int rr = row_idx(r, ny, walls);
+    char* orow = row_ptr(out, rr, RB);
     const T dt = T(C.dt);
+    // face length over cell area: 1/dx and 1/dy (1 on unit cells)
+    const T ay = MESH ? T(Y.iw[rr]) : T(1);
+    // the flux difference of population q (plane off: 0 f, 6 g) from its
+    // east/west and upper/lower faces
+    auto flux = [&](int q, int off, T fn, T fs) {
+      if constexpr (MESH) {
+        T Jx = T(0), Jy = T(0);
+        if (EX[q] != 0) {
+          const T e = fxs[xs][off + up_xslot(q)][lane];
+          Jx = T(EX[q]) * (e - nbr_l(e));
+        }
+        if (EY[q] != 0) Jy = T(EY[q]) * (fn - fs);
+        return axw * Jx + ay * Jy;
+      } else {
+        T J = T(0);
+        if (EX[q] != 0) {
+          const T e = fxs[xs][off + up_xslot(q)][lane];
+          J += T(EX[q]) * (e - nbr_l(e));
+        }
+        if (EY[q] != 0) J += T(EY[q]) * (fn - fs);
+        return J;
+      }
+    };
     T nv[NV];
     T phin = T(0);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      T J = T(0);
-      if (EX[q] != 0) {
-        const T e = fxs[xs][up_xslot(q)][lane];
-        J += T(EX[q]) * (e - nbr_l(e));
-      }
-      if (EY[q] != 0) J += T(EY[q]) * (fnf[q] - m.fsf[q]);
-      nv[val_f(q)] = stash[slot][q][lane] - dt * J;
+      nv[val_f(q)] = stash[slot][q][lane] - dt * flux(q, 0, fnf[q], m.fsf[q]);
       phin += nv[val_f(q)];
     }
     if (CPL) {
 #pragma unroll
-      for (int q = 0; q < 9; ++q) {
-        T J = T(0);
-        if (EX[q] != 0) {
-          const T e = fxs[xs][6 + up_xslot(q)][lane];
-          J += T(EX[q]) * (e - nbr_l(e));
-        }
-        if (EY[q] != 0) J += T(EY[q]) * (fng[q] - m.fsg[q]);
-        nv[val_g(q)] = stash[slot][9 + q][lane] - dt * J;
-      }
+      for (int q = 0; q < 9; ++q)
+        nv[val_g(q)] = stash[slot][9 + q][lane] - dt * flux(q, 6, fng[q], m.fsg[q]);
     }
     nv[val_hist(CPL, 0)] = m.cell.hx;
     nv[val_hist(CPL, 1)] = m.cell.hy;
@@ -2488,7 +2602,13 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
       } else if (WALLS && rm == -1) {
         T txf[9], txg[9];
         xdiffs(R0.cell, txf, txg);
-        wall_face<T, true>(C, R0.cell, R1.cell, txf, txg, R0.fsf, R0.fsg);
+        T dyw = T(0), idy = T(1);
+        if (MESH) {
+          const Met<T> m0 = ymet(0);
+          dyw = T(-0.5) * m0.w;
+          idy = m0.ihp;
+        }
+        wall_face_g<T, true, MESH>(C, R0.cell, R1.cell, txf, txg, dyw, idy, R0.fsf, R0.fsg);
       }
     }
     // the update of row s - 2 (with walls it reads its x-faces from LDS
@@ -2506,7 +2626,13 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         }
         T txf[9], txg[9], fnf[9], fng[9];
         xdiffs(Rm.cell, txf, txg);
-        wall_face<T, false>(C, Rm.cell, cn, txf, txg, fnf, fng);
+        T dyw = T(0), idy = T(1);
+        if (MESH) {
+          const Met<T> mt = ymet(ny - 1);
+          dyw = T(0.5) * mt.w;
+          idy = mt.ihm;
+        }
+        wall_face_g<T, false, MESH>(C, Rm.cell, cn, txf, txg, dyw, idy, fnf, fng);
         update(rm, ms, xs, Rm, fnf, fng);
       } else {
         update(rm, ms, xs, Rm, R0.fsf, R0.fsg);
@@ -2543,7 +2669,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   }
 }
 
-template <typename T, bool CPL, bool WALLS>
+template <typename T, bool CPL, bool WALLS, bool MESH>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) {
   const int nb = gridDim.x;
   const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
@@ -2553,7 +2679,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) 
   const CaseDev C = A.cases[it.c];
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
-  upm_march<T, CPL, WALLS>(C, it, n, A.upm_rows);
+  upm_march<T, CPL, WALLS, MESH>(C, it, n, A.upm_rows);
 }
 
 }  // namespace
@@ -2628,35 +2754,40 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
   return hipGetLastError();
 }
 
-hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s) {
+template <typename T, bool M>
+static void launch_upm(bool coupled, bool walls, const StepArgs& a, hipStream_t s) {
+  const dim3 grid((a.nitems + 7) / 8 * 8), block(kWave);
+  if (!coupled) hipLaunchKernelGGL((k_upm<T, false, false, M>), grid, block, 0, s, a);
+  else if (walls) hipLaunchKernelGGL((k_upm<T, true, true, M>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_upm<T, true, false, M>), grid, block, 0, s, a);
+}
+
+hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, bool mesh, const StepArgs& a,
+                           hipStream_t s) {
   if (a.nitems <= 0) return hipSuccess;
   if (walls && !coupled) return hipErrorInvalidValue;
-  const dim3 grid((a.nitems + 7) / 8 * 8), block(kWave);
   if (fp64) {
-    if (!coupled) hipLaunchKernelGGL((k_upm<double, false, false>), grid, block, 0, s, a);
-    else if (walls) hipLaunchKernelGGL((k_upm<double, true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_upm<double, true, false>), grid, block, 0, s, a);
+    if (mesh) launch_upm<double, true>(coupled, walls, a, s);
+    else launch_upm<double, false>(coupled, walls, a, s);
   } else {
-    if (!coupled) hipLaunchKernelGGL((k_upm<float, false, false>), grid, block, 0, s, a);
-    else if (walls) hipLaunchKernelGGL((k_upm<float, true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_upm<float, true, false>), grid, block, 0, s, a);
+    if (mesh) launch_upm<float, true>(coupled, walls, a, s);
+    else launch_upm<float, false>(coupled, walls, a, s);
   }
   return hipGetLastError();
 }
 
-int upm_waves_per_cu(bool fp64, bool coupled, bool walls) {
+template <typename T, bool M>
+static int upm_occupancy(bool coupled, bool walls) {
   int nb = 0;
   hipError_t e;
-  if (fp64) {
-    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<double, false, false>, kWave, 0);
-    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<double, true, true>, kWave, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<double, true, false>, kWave, 0);
-  } else {
-    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<float, false, false>, kWave, 0);
-    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<float, true, true>, kWave, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<float, true, false>, kWave, 0);
-  }
+  if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, false, false, M>, kWave, 0);
+  else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, true, M>, kWave, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, false, M>, kWave, 0);
   return e == hipSuccess && nb > 0 ? nb : 1;
+}
+int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh) {
+  if (fp64) return mesh ? upm_occupancy<double, true>(coupled, walls) : upm_occupancy<double, false>(coupled, walls);
+  return mesh ? upm_occupancy<float, true>(coupled, walls) : upm_occupancy<float, false>(coupled, walls);
 }
 
 // Resident waves per CU of the step kernel (one wave per work group).
