@@ -101,7 +101,7 @@ int auto_upm_rows(const dugks_handle* h) {
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
     cus = prop.multiProcessorCount;
     cap = cus * dugks::upm_waves_per_cu(h->fp64(), h->coupled(), h->params.bc_y == DUGKS_BC_WALLS,
-                                        h->mesh);
+                                        h->mesh, !h->upwind());
   } else {
     (void)hipGetLastError();
   }
@@ -355,8 +355,8 @@ int launch_steps(dugks_handle* h, int nsteps) {
     a.upm_rows = h->upm_rows;
     for (int k = 0; k < nsteps; ++k) {
       a.kofs = k;
-      HIPCHK(h, dugks::launch_step_upm(h->fp64(), h->coupled(), h->hc.walls != 0, h->mesh, a,
-                                       h->stream));
+      HIPCHK(h, dugks::launch_step_upm(h->fp64(), h->coupled(), h->hc.walls != 0, h->mesh,
+                                       !h->upwind(), a, h->stream));
     }
     HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
     return DUGKS_OK;

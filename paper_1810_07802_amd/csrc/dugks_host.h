@@ -12,7 +12,7 @@
 #include "dugks_impl.h"
 
 #ifndef DUGKS_UPM
-#define DUGKS_UPM 2
+#define DUGKS_UPM 3
 #endif
 
 struct dugks_handle {
@@ -55,14 +55,13 @@ struct dugks_handle {
   // steps run as the block step (upwind reconstruction or stretched mesh)
   // instead of the march
   bool general() const { return upwind() || mesh; }
-  // the upwind reconstruction runs as the upwind march (DUGKS_UPM 2: on
-  // unit and stretched meshes, 1: on the unit mesh only, 0: never)
+  // the step runs as the upwind march: the upwind reconstruction on the unit
+  // or a stretched mesh, and the central one on a stretched mesh
+  // (DUGKS_UPM 3; 2: upwind only, 1: upwind on the unit mesh only, 0: never)
   bool upm() const {
-#if DUGKS_UPM
-    return upwind() && (DUGKS_UPM > 1 || !mesh);
-#else
-    return false;
-#endif
+    if (DUGKS_UPM >= 3 && mesh) return true;
+    if (DUGKS_UPM >= 2 && upwind()) return true;
+    return DUGKS_UPM >= 1 && upwind() && !mesh;
   }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
   size_t n() const { return (size_t)nx * ny; }

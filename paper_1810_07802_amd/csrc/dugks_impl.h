@@ -168,12 +168,12 @@ struct UpArgs {
 hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
                               int nx, int ny, const UpArgs& a, hipStream_t s);
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
-// the upwind march (upwind reconstruction, unit or stretched mesh; items of
-// kUpmCols-column strips and a.upm_rows-row segments) and its resident waves
-// per CU
-hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, bool mesh, const StepArgs& a,
-                           hipStream_t s);
-int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh);
+// the upwind march (upwind reconstruction on the unit or a stretched mesh,
+// central reconstruction on a stretched mesh; items of kUpmCols-column strips
+// and a.upm_rows-row segments) and its resident waves per CU
+hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, bool mesh, bool central,
+                           const StepArgs& a, hipStream_t s);
+int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh, bool central);
 int step_waves_per_cu(bool fp64, bool coupled, bool walls);
 hipError_t launch_advance(long long* step_base, long long by, hipStream_t s);
 // step_base[0] = value (if not null) and flag[0] = 0 (if not null)

@@ -2214,9 +2214,10 @@ struct URow {
   T tdf[9], tdg[9];
 };
 
-template <typename T, bool CPL, bool WALLS, bool MESH>
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CEN>
 __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long long n,
                                           int seg_rows) {
+  static_assert(MESH || !CEN, "the central reconstruction on the unit mesh is k_step's");
   const int lane = threadIdx.x;
   const int nx = C.nx, ny = C.ny;
   constexpr int walls = WALLS ? 1 : 0;
@@ -2321,7 +2322,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     }
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
-      if (EX[q] == 0) continue;
+      if (CEN || EX[q] == 0) continue;  // the central slopes are formed where used
       const T c = rd.cell.fb[q];
       rd.lxf[q] = MESH ? lim_mesh<T>(c - nbr_l(c), nbr_r(c) - c, mx)
                        : van_leer(c - nbr_l(c), nbr_r(c) - c);
@@ -2529,6 +2530,88 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
                        mean(a.mu, b.mu), mean(a.Dx, b.Dx), mean(a.Dy, b.Dy), fbar, gbar, xcen,
                        MESH ? Y.c[rr] + 0.5 * Y.w[rr] : (double)rr + 1.0, tn + C.h, u.fsf, u.fsg);
   };
+  // Central reconstruction on a stretched mesh (the block step's
+  // UpBars::face, CENTRAL): the face value is the interpolation of the two
+  // cells less h xi times the normal difference and the interpolated
+  // tangential slope, for every population (the zero-weighted terms
+  // included, as there). The parabola slopes are cheap, so they are formed
+  // where used: the y slopes of row r from the rows below (d) and above (u),
+  // the x slopes from the neighbouring lanes.
+  auto yslope_c = [&](int r, T dv, T cv, T uv, const Met<T>& my) {
+    if (WALLS && r == 0) return (uv - cv) * my.ihp;
+    if (WALLS && r == ny - 1) return (cv - dv) * my.ihm;
+    return my.cp * (uv - cv) + my.cm * (cv - dv);
+  };
+  auto xslope_c = [&](T v) { return mx.cp * (nbr_r(v) - v) + mx.cm * (v - nbr_l(v)); };
+  auto xface_c = [&](int r, int xs, const URow<T, CPL>& d, const URow<T, CPL>& m,
+                     const URow<T, CPL>& u) {
+    const Met<T> my = ymet(r);
+    const T dA = dAx, dB = dBx, iH = iHx;
+    auto rec = [&](int q, T dv, T a, T uv) {
+      const T st = yslope_c(r, dv, a, uv, my);
+      const T aB = nbr_r(a), stB = nbr_r(st);
+      const T af = (dB * a + dA * aB) * iH, dn = (aB - a) * iH;
+      const T dtg = (dB * st + dA * stB) * iH;
+      return af - h * (T(EX[q]) * dn + T(EY[q]) * dtg);
+    };
+    T fbar[9], gbar[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      fbar[q] = rec(q, d.cell.fb[q], m.cell.fb[q], u.cell.fb[q]);
+      gbar[q] = (CPL && q > 0) ? rec(q, d.cell.gb[q], m.cell.gb[q], u.cell.gb[q]) : T(0);
+    }
+    const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
+                   ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
+    T N0f = T(0), Jxf = T(0), Jyf = T(0);
+    if (CPL) {
+      N0f = ((gbar[1] + gbar[2]) + (gbar[3] + gbar[4])) + ((gbar[5] + gbar[6]) + (gbar[7] + gbar[8]));
+      Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
+      Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
+    }
+    const Cell<T>& a = m.cell;
+    auto mean = [&](T v) { return (dB * v + dA * nbr_r(v)) * iH; };
+    const int rr = row_idx(r, ny, walls);
+    T fo[9], go[9];
+    face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, mean(a.gx), mean(a.gy), mean(a.mu), mean(a.Dx),
+                       mean(a.Dy), fbar, gbar, xeast, Y.c[rr], tn + C.h, fo, go);
+#pragma unroll
+    for (int q = 1; q < 9; ++q) {
+      if (EX[q] == 0) continue;
+      fxs[xs][up_xslot(q)][lane] = fo[q];
+      if (CPL) fxs[xs][6 + up_xslot(q)][lane] = go[q];
+    }
+  };
+  auto yface_c = [&](int r, const URow<T, CPL>& d, URow<T, CPL>& u) {
+    const T dA = T(0.5) * ymet(r).w, dB = T(0.5) * ymet(r + 1).w;
+    const T iH = T(1) / (dA + dB);
+    auto rec = [&](int q, T aA, T aB) {
+      const T af = (dB * aA + dA * aB) * iH, dn = (aB - aA) * iH;
+      const T dtg = (dB * xslope_c(aA) + dA * xslope_c(aB)) * iH;
+      return af - h * (T(EY[q]) * dn + T(EX[q]) * dtg);
+    };
+    T fbar[9], gbar[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+      fbar[q] = rec(q, d.cell.fb[q], u.cell.fb[q]);
+      gbar[q] = (CPL && q > 0) ? rec(q, d.cell.gb[q], u.cell.gb[q]) : T(0);
+    }
+    const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
+                   ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
+    T N0f = T(0), Jxf = T(0), Jyf = T(0);
+    if (CPL) {
+      N0f = ((gbar[1] + gbar[2]) + (gbar[3] + gbar[4])) + ((gbar[5] + gbar[6]) + (gbar[7] + gbar[8]));
+      Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
+      Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
+    }
+    const Cell<T>& a = d.cell;
+    const Cell<T>& b = u.cell;
+    auto mean = [&](T va, T vb) { return (dB * va + dA * vb) * iH; };
+    const int rr = row_idx(r, ny, walls);
+    face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, mean(a.gx, b.gx), mean(a.gy, b.gy),
+                       mean(a.mu, b.mu), mean(a.Dx, b.Dx), mean(a.Dy, b.Dy), fbar, gbar, xcen,
+                       Y.c[rr] + 0.5 * Y.w[rr], tn + C.h, u.fsf, u.fsg);
+  };
+
   // update of output row r (record m) from its faces: east m.fx, west the
   // left lane's, below m.fs, above (fnf, fng)
   auto update = [&](int r, int slot, int xs, const URow<T, CPL>& m, const T (&fnf)[9],
@@ -2593,12 +2676,16 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int r0 = s - 1, rm = s - 2;
     const bool ex0 = !(walls && (r0 < 0 || r0 >= ny));
     const bool exm = !(walls && (rm < 0 || rm >= ny));
-    if (ex0 && r0 >= j0 - 1) yslopes(r0, Rm, R0, R1);
-    if (!WALLS && r0 >= j0 && r0 < j1) xface(r0, p & 1, R0);
+    if (!CEN && ex0 && r0 >= j0 - 1) yslopes(r0, Rm, R0, R1);
+    if (!WALLS && r0 >= j0 && r0 < j1) {
+      if constexpr (CEN) xface_c(r0, p & 1, Rm, R0, R1);
+      else xface(r0, p & 1, R0);
+    }
     // the face below row s - 1: between rows s - 2 and s - 1, or the bottom wall
     if (rm >= j0 - 1 && rm < j1) {
       if (ex0 && exm) {
-        yface(rm, Rm, R0);
+        if constexpr (CEN) yface_c(rm, Rm, R0);
+        else yface(rm, Rm, R0);
       } else if (WALLS && rm == -1) {
         T txf[9], txg[9];
         xdiffs(R0.cell, txf, txg);
@@ -2638,7 +2725,10 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         update(rm, ms, xs, Rm, R0.fsf, R0.fsg);
       }
     }
-    if (WALLS && ex0 && r0 >= j0 && r0 < j1) xface(r0, 0, R0);
+    if (WALLS && ex0 && r0 >= j0 && r0 < j1) {
+      if constexpr (CEN) xface_c(r0, 0, Rm, R0, R1);
+      else xface(r0, 0, R0);
+    }
   };
 
   URow<T, CPL> R0, R1, R2;
@@ -2669,7 +2759,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   }
 }
 
-template <typename T, bool CPL, bool WALLS, bool MESH>
+template <typename T, bool CPL, bool WALLS, bool MESH, bool CEN>
 __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) {
   const int nb = gridDim.x;
   const int per = nb >> 3;  // grid is a multiple of 8 (one share per XCD)
@@ -2679,7 +2769,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) 
   const CaseDev C = A.cases[it.c];
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
-  upm_march<T, CPL, WALLS, MESH>(C, it, n, A.upm_rows);
+  upm_march<T, CPL, WALLS, MESH, CEN>(C, it, n, A.upm_rows);
 }
 
 }  // namespace
@@ -2754,40 +2844,48 @@ hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, 
   return hipGetLastError();
 }
 
-template <typename T, bool M>
+template <typename T, bool M, bool CEN>
 static void launch_upm(bool coupled, bool walls, const StepArgs& a, hipStream_t s) {
   const dim3 grid((a.nitems + 7) / 8 * 8), block(kWave);
-  if (!coupled) hipLaunchKernelGGL((k_upm<T, false, false, M>), grid, block, 0, s, a);
-  else if (walls) hipLaunchKernelGGL((k_upm<T, true, true, M>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_upm<T, true, false, M>), grid, block, 0, s, a);
+  if (!coupled) hipLaunchKernelGGL((k_upm<T, false, false, M, CEN>), grid, block, 0, s, a);
+  else if (walls) hipLaunchKernelGGL((k_upm<T, true, true, M, CEN>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_upm<T, true, false, M, CEN>), grid, block, 0, s, a);
+}
+template <typename T>
+static void launch_upm_modes(bool coupled, bool walls, bool mesh, bool central, const StepArgs& a,
+                             hipStream_t s) {
+  if (!mesh) launch_upm<T, false, false>(coupled, walls, a, s);
+  else if (central) launch_upm<T, true, true>(coupled, walls, a, s);
+  else launch_upm<T, true, false>(coupled, walls, a, s);
 }
 
-hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, bool mesh, const StepArgs& a,
-                           hipStream_t s) {
+hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, bool mesh, bool central,
+                           const StepArgs& a, hipStream_t s) {
   if (a.nitems <= 0) return hipSuccess;
   if (walls && !coupled) return hipErrorInvalidValue;
-  if (fp64) {
-    if (mesh) launch_upm<double, true>(coupled, walls, a, s);
-    else launch_upm<double, false>(coupled, walls, a, s);
-  } else {
-    if (mesh) launch_upm<float, true>(coupled, walls, a, s);
-    else launch_upm<float, false>(coupled, walls, a, s);
-  }
+  if (central && !mesh) return hipErrorInvalidValue;  // k_step covers that case
+  if (fp64) launch_upm_modes<double>(coupled, walls, mesh, central, a, s);
+  else launch_upm_modes<float>(coupled, walls, mesh, central, a, s);
   return hipGetLastError();
 }
 
-template <typename T, bool M>
+template <typename T, bool M, bool CEN>
 static int upm_occupancy(bool coupled, bool walls) {
   int nb = 0;
   hipError_t e;
-  if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, false, false, M>, kWave, 0);
-  else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, true, M>, kWave, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, false, M>, kWave, 0);
+  if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, false, false, M, CEN>, kWave, 0);
+  else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, true, M, CEN>, kWave, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, false, M, CEN>, kWave, 0);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
-int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh) {
-  if (fp64) return mesh ? upm_occupancy<double, true>(coupled, walls) : upm_occupancy<double, false>(coupled, walls);
-  return mesh ? upm_occupancy<float, true>(coupled, walls) : upm_occupancy<float, false>(coupled, walls);
+template <typename T>
+static int upm_occupancy_modes(bool coupled, bool walls, bool mesh, bool central) {
+  if (!mesh) return upm_occupancy<T, false, false>(coupled, walls);
+  return central ? upm_occupancy<T, true, true>(coupled, walls) : upm_occupancy<T, true, false>(coupled, walls);
+}
+int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh, bool central) {
+  return fp64 ? upm_occupancy_modes<double>(coupled, walls, mesh, central)
+              : upm_occupancy_modes<float>(coupled, walls, mesh, central);
 }
 
 // Resident waves per CU of the step kernel (one wave per work group).

@@ -159,19 +159,23 @@ def test_switching_the_reconstruction_between_steps():
         assert rel(g[k], r[k]) < 1e-12, k
 
 
-@pytest.mark.parametrize("precision,walls", [("fp32", False), ("fp32", True), ("fp64", False),
-                                              ("fp64", True)])
-def test_march_segments_give_the_same_bits(precision, walls):
+@pytest.mark.parametrize("precision,walls,mesh", [("fp32", False, False), ("fp32", True, False),
+                                                   ("fp64", False, False), ("fp64", True, False),
+                                                   ("fp32", True, True), ("fp64", False, True)])
+def test_march_segments_give_the_same_bits(precision, walls, mesh):
     """The upwind march's segment length (dugks_set_tile) changes only the
     work decomposition: one-row segments, short ones that leave a ragged last
     segment, the automatic choice and one segment of the whole height give
     the same state bit for bit (halo rows go through the same code as output
-    rows). 130 columns are three strips, the last of 10 columns."""
+    rows), on the unit mesh and on a rough stretched mesh. 130 columns are
+    three strips, the last of 10 columns."""
     c = upwind(W.random_coupled(130, 37, seed=11, rho_ratio=100.0, walls_y=walls))
     states = {}
     for seg in (1, 2, 5, 0, 37):
-        print(f"[upwind march] segments {seg} {precision} walls={walls}", flush=True)
+        print(f"[upwind march] segments {seg} {precision} walls={walls} mesh={mesh}", flush=True)
         s = D.Solver(c["nx"], c["ny"], c["params"], c["model"], precision, seg or None)
+        if mesh:
+            s.set_mesh(W.random_widths(130, 21), W.random_widths(37, 22))
         s.init(c["phi"], c["u"], c["v"], c["p"])
         s.step(7)
         assert s.seg_rows == (seg if seg else s.seg_rows)
