@@ -25,11 +25,10 @@ The same JSON line carries:
                 requests, aggregate MLUPS, vs the plain sequential per-case
                 loop
   upwind        the bubble with the upwind, limited face reconstruction
-                (the upwind march: one kernel per step), 128^2 and 4096^2;
-                the HBM fraction at the method's 160 B per cell
+                (the reconstruction march: one kernel per step), 128^2 and
+                4096^2; the HBM fraction at the method's 160 B per cell
   mesh          the 4096^2 bubble on a stretched mesh (widths 1 +- 0.3 sin),
-                central (the block step) and upwind (the upwind march), one
-                kernel per step
+                central and upwind, through the same march
   cpu_baseline  the FP64 C oracle on the host cores, on a bounded sample
 """
 from __future__ import annotations
@@ -207,10 +206,10 @@ def roofline(cells, steps, seconds, prec, workload=None):
 
 
 def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
-    """Steps of case `c` (coupled FP32) with the upwind reconstruction (the
-    upwind march), or on a stretched mesh `mesh` = (dx, dy) in either
-    reconstruction (central: the block step), replayed from HIP graphs (see
-    timed()). The HBM fraction is quoted at the method's 160 B per cell."""
+    """Steps of case `c` (coupled FP32) with the upwind reconstruction, or
+    on a stretched mesh `mesh` = (dx, dy) in either reconstruction (the
+    reconstruction march), replayed from HIP graphs (see timed()). The HBM
+    fraction is quoted at the method's 160 B per cell."""
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
     s.set_stream(torch.cuda.current_stream().cuda_stream)
     if mesh is not None:
@@ -224,8 +223,7 @@ def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100
          "us_per_step": round(t / steps * 1e6, 3),
          "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
          "bytes_per_cell": B_PER_CELL["fp32"], "nonfinite": d["nonfinite"]}
-    if recon == "upwind":
-        r["seg_rows"] = s.seg_rows  # segment of the upwind march
+    r["seg_rows"] = s.seg_rows  # segment of the reconstruction march
     return r
 
 
@@ -527,7 +525,8 @@ def main():
         # upwind, limited reconstruction on the same physics
         rec["upwind"] = {
             "workload": "stationary bubble, coupled FP32, upwind reconstruction, one "
-                        "upwind-march kernel per step, replayed from HIP graphs of up to 100 steps",
+                        "reconstruction-march kernel per step, replayed from HIP graphs of up "
+                        "to 100 steps",
             "bubble128": timed_recon(torch, D, c, min(args.small_steps, 5000), 100),
             "bubble4096": timed_recon(torch, D, W.bubble(L=4096, R=1024, steps=0),
                                            args.upwind_steps, 5)}
@@ -537,9 +536,8 @@ def main():
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
         rec["mesh"] = {
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
-                        "both axes), coupled FP32, one kernel per step (central: the block "
-                        "step; upwind: the upwind march), replayed from HIP graphs of up to "
-                        "100 steps",
+                        "both axes), coupled FP32, one reconstruction-march kernel per step, "
+                        "replayed from HIP graphs of up to 100 steps",
             "central": timed_recon(torch, D, cm, args.upwind_steps, 5, "central", mesh),
             "upwind": timed_recon(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
         progress("mesh done")

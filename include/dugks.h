@@ -90,9 +90,9 @@ enum { DUGKS_RECON_CENTRAL = 0, DUGKS_RECON_UPWIND = 1 };
  *                  populations along the face take the mean of both cells.
  *                  Upwind runs on single handles only (EINVAL in batches and
  *                  pools); it needs no device memory beyond the state. It
- *                  runs as a march like the central one (each cell's
- *                  limited slopes formed once), on the unit mesh and on a
- *                  stretched mesh (see dugks_set_mesh).
+ *                  runs as a second march like the central one (each
+ *                  cell's limited slopes formed once), on the unit mesh and
+ *                  on a stretched mesh (see dugks_set_mesh).
  *   eps_n          regularisation of the interface normal of the phase-field
  *                  source (Eq. 16, n of Sec. II.A):
  *                  n = grad phi / sqrt(|grad phi|^2 + eps^2) with
@@ -147,8 +147,8 @@ int dugks_set_stream(dugks_handle *h, void *stream);
  * while two-row tiles do not, two rows, run by the four-wave two-row
  * kernel). Results do not depend on it, bit for bit. A batch uses a case's
  * explicit value, and its own automatic choice for cases left at 0. With
- * the upwind reconstruction the value is the segment of the upwind march
- * instead (60-column strips; automatic: one round of resident
+ * the upwind reconstruction or a stretched mesh the value is the segment of
+ * the reconstruction march instead (60-column strips; automatic: one round of resident
  * waves, or where that needs more than 64 rows the shortest segments that
  * number at most 32 waves per compute unit). EINVAL outside [0, 4096].
  * dugks_get_tile returns the value in use (-1 for NULL). */
@@ -173,10 +173,9 @@ int dugks_get_tile(const dugks_handle *h);
  *     one-sided difference over the cell width);
  *   - the regularisation of the unit normal is eps_n |phi_H - phi_L| over
  *     the smallest width.
- * The step then runs as the upwind march (upwind reconstruction) or as a
- * block step (central reconstruction: one kernel over blocks of cells with
- * a two-cell halo in LDS); neither needs device memory beyond the state and
- * the metrics. Cell centres start at
+ * The step then runs as the reconstruction march (both reconstructions; the
+ * central one forms its parabola slopes where used), which needs no device
+ * memory beyond the state and the metrics. Cell centres start at
  * x = 0, y = 0. Takes effect at the next dugks_init_fields (the state is
  * invalidated: ESTATE until then). Not for batches or pool cases (EINVAL).
  * Errors: EINVAL (widths), ENOMEM. */
@@ -277,7 +276,9 @@ int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
  * k = 1..8, 12, 16, 20, 24 the shortest segment whose tiles fit k rounds of the
  * device's resident waves) on the handle's current state, keeps the fastest as the
  * handle's tile (dugks_set_tile) and puts the state and step counter back as
- * they were. Results do not depend on the tile, bit for bit. Synchronous;
+ * they were. With the upwind reconstruction or a stretched mesh the tiles are
+ * those of the reconstruction march (60-column strips, its own resident
+ * waves). Results do not depend on the tile, bit for bit. Synchronous;
  * holds one extra copy of the state on the device while it runs. Outputs
  * (NULL to skip): the chosen seg_rows and its time per step in microseconds.
  * ESTATE before init; on EDEVICE the state is undefined. */

@@ -263,7 +263,7 @@ int upload_case(dugks_handle* h) {
   HIPCHK(h, hipMemcpyAsync(h->items, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice,
                            h->stream));
   std::vector<Item> ut;
-  if (h->upm()) {
+  if (h->general()) {
     h->upm_rows = h->seg_rows ? std::min(h->seg_rows, h->ny) : auto_upm_rows(h);
     const int ns = (h->nx + dugks::kUpmCols - 1) / dugks::kUpmCols;
     const int nseg = (h->ny + h->upm_rows - 1) / h->upm_rows;
@@ -346,7 +346,7 @@ int numeric_fail(dugks_handle* h) {
 }
 
 int launch_steps(dugks_handle* h, int nsteps) {
-  if (h->upm()) {
+  if (h->general()) {
     StepArgs a{};
     a.cases = h->dc;
     a.items = h->uitems;
@@ -357,16 +357,6 @@ int launch_steps(dugks_handle* h, int nsteps) {
       a.kofs = k;
       HIPCHK(h, dugks::launch_step_upm(h->fp64(), h->coupled(), h->hc.walls != 0, h->mesh,
                                        !h->upwind(), a, h->stream));
-    }
-    HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
-    return DUGKS_OK;
-  }
-  if (h->general()) {
-    UpArgs u{h->dc, h->step_base, 0};
-    for (int k = 0; k < nsteps; ++k) {
-      u.kofs = k;
-      HIPCHK(h, dugks::launch_step_upwind(h->fp64(), h->coupled(), h->hc.walls != 0, h->upwind(),
-                                          h->mesh, h->nx, h->ny, u, h->stream));
     }
     HIPCHK(h, dugks::launch_advance(h->step_base, nsteps, h->stream));
     return DUGKS_OK;
@@ -514,7 +504,7 @@ int dugks_set_tile(dugks_handle* h, int seg_rows) {
 
 int dugks_get_tile(const dugks_handle* h) {
   if (!h) return -1;
-  return h->upm() ? h->upm_rows : h->hc.seg_rows;
+  return h->general() ? h->upm_rows : h->hc.seg_rows;
 }
 
 int dugks_set_mesh(dugks_handle* h, const double* dx, const double* dy) {
@@ -718,16 +708,20 @@ int dugks_set_state(dugks_handle* h, const void* host_buf, size_t bytes, long lo
 int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* out_us) {
   if (!h || probe_steps < 1 || probe_steps > 1000) return fail(h, DUGKS_EINVAL, "bad arguments");
   if (!h->has_state) return fail(h, DUGKS_ESTATE, "init_fields first");
-  if (h->general())
-    return fail(h, DUGKS_EINVAL, "the upwind reconstruction and stretched meshes have no tiles to tune");
   // candidates: the shortest segments (lowest latency per step), and for
   // k = 1..8, 12, 16, 20, 24 the shortest segment whose tiles fit k rounds of resident waves
-  // (more rounds: finer load balance, more repeated halo work)
+  // (more rounds: finer load balance, more repeated halo work); for the
+  // reconstruction march (upwind or stretched mesh) with its own strips and
+  // resident waves
   const int keep = h->seg_rows;
   int rc = DUGKS_OK;
-  const int a = h->hc.seg_rows;
-  const std::vector<StripShape> shape = {StripShape{h->hc.nstrips, h->ny}};
-  const long long cap = wave_capacity(h->fp64(), h->coupled(), h->hc.walls != 0);
+  const int a = h->general() ? h->upm_rows : h->hc.seg_rows;
+  const std::vector<StripShape> shape = {
+      StripShape{h->general() ? (h->nx + dugks::kUpmCols - 1) / dugks::kUpmCols : h->hc.nstrips, h->ny}};
+  const long long cap =
+      h->general() ? cu_count() * dugks::upm_waves_per_cu(h->fp64(), h->coupled(), h->hc.walls != 0,
+                                                          h->mesh, !h->upwind())
+                   : wave_capacity(h->fp64(), h->coupled(), h->hc.walls != 0);
   std::vector<int> use = {1, 2};
   for (int k : {1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 20, 24}) {
     const int c = fit_seg_rows(shape, k * cap);

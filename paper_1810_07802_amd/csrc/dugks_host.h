@@ -11,9 +11,6 @@
 #include "../../include/dugks.h"
 #include "dugks_impl.h"
 
-#ifndef DUGKS_UPM
-#define DUGKS_UPM 3
-#endif
 
 struct dugks_handle {
   int nx = 0, ny = 0, precision = 0, model = 0;
@@ -52,17 +49,9 @@ struct dugks_handle {
 
   bool fp64() const { return precision == DUGKS_FP64; }
   bool upwind() const { return params.recon == DUGKS_RECON_UPWIND; }
-  // steps run as the block step (upwind reconstruction or stretched mesh)
-  // instead of the march
+  // steps run as the reconstruction march (k_upm: the upwind reconstruction,
+  // or a stretched mesh) instead of k_step's
   bool general() const { return upwind() || mesh; }
-  // the step runs as the upwind march: the upwind reconstruction on the unit
-  // or a stretched mesh, and the central one on a stretched mesh
-  // (DUGKS_UPM 3; 2: upwind only, 1: upwind on the unit mesh only, 0: never)
-  bool upm() const {
-    if (DUGKS_UPM >= 3 && mesh) return true;
-    if (DUGKS_UPM >= 2 && upwind()) return true;
-    return DUGKS_UPM >= 1 && upwind() && !mesh;
-  }
   bool coupled() const { return model == DUGKS_MODEL_COUPLED; }
   size_t n() const { return (size_t)nx * ny; }
   size_t elem() const { return fp64() ? 8 : 4; }

@@ -145,9 +145,6 @@ struct StepArgs {
 // with two halo lanes on each side); segments of StepArgs::upm_rows rows.
 constexpr int kUpmCols = 60;
 
-// Bar-plus planes of the block step's LDS tile (upwind reconstruction,
-// stretched mesh): f0..f8 and (coupled) g0..g8.
-__host__ __device__ constexpr int up_bar_planes(bool coupled) { return coupled ? 18 : 9; }
 // slot of population q among the six crossing an x-face / a y-face (-1: none)
 __host__ __device__ constexpr int up_xslot(int q) {
   return q == 1 ? 0 : q == 2 ? 1 : q == 8 ? 2 : q == 4 ? 3 : q == 5 ? 4 : q == 6 ? 5 : -1;
@@ -156,17 +153,7 @@ __host__ __device__ constexpr int up_yslot(int q) {
   return q == 2 ? 0 : q == 3 ? 1 : q == 4 ? 2 : q == 6 ? 3 : q == 7 ? 4 : q == 8 ? 5 : -1;
 }
 
-// Launch arguments of the block step (upwind reconstruction, or a stretched
-// mesh; one case, one step).
-struct UpArgs {
-  const CaseDev* cases;
-  const long long* step_base;
-  int kofs;
-};
-
 // host-side launchers (dugks_kernels.hip)
-hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
-                              int nx, int ny, const UpArgs& a, hipStream_t s);
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
 // the upwind march (upwind reconstruction on the unit or a stretched mesh,
 // central reconstruction on a stretched mesh; items of kUpmCols-column strips

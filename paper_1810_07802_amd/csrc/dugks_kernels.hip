@@ -23,8 +23,9 @@
 // interface) are evaluated in double and narrowed.
 //
 // The upwind, limited reconstruction and stretched tensor-product meshes run
-// as a block step (k_up_step; see the section "block step" below), which
-// shares the cell-stage, face and wall-face arithmetic with the march.
+// as a second march (k_upm; see the section "the reconstruction march"
+// below), which shares the cell-stage, face and wall-face arithmetic with
+// k_step.
 
 #include <hip/hip_runtime.h>
 
@@ -1622,59 +1623,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag_rows(const CaseDev* __res
   }
 }
 
-// ------------------------------ block step: upwind or stretched mesh
-
-// The upwind, limited reconstruction and the stretched mesh (both selected
-// per handle) do not fit the fused march. The upwind face value of each
-// population is a non-linear function of the cells, so the face macros must
-// be summed from the nine reconstructed values instead of reconstructed cell
-// moments. A face also reads the limited slopes of both its cells, a
-// radius-two stencil. On a stretched mesh every stencil carries the local
-// widths. The step then runs as one kernel over blocks of 64 x ROWS cells
-// (k_up_step): each block stages its cells and a halo of two cells into LDS,
-// forms every face of its cells once and updates them. The cell stage, face
-// distribution and wall face are the march's.
-//
-// Stretched mesh: the reconstruction interpolates linearly to the face (the
-// value, the tangential slope and the face inputs), slopes are derivatives
-// over the centre distances, the upwind trace starts from the actual half
-// width, and the update divides the fluxes by the cell's widths. On unit
-// widths every formula reduces to the unit-mesh one.
-
-// A block is 64 columns by ROWS rows of cells, one thread per cell, with a
-// register budget of WPE waves per SIMD (1: the compiler's choice). Measured
-// on the 4096^2 bubble (FP32, microseconds per step, rows/WPE):
-//   upwind           4/3: 1131  8/1: 1336  4/1: 1494  6/1: 1700  6/3: 1708
-//   mesh, upwind     4/3: 1870  8/1: 1950  4/1: 2205  6/1: 2528  6/3: 2816
-//   mesh, central    8/1: 1668  4/1: 1727  4/3: 2031  6/1: 2150  6/3: 2830
-// Four rows at three waves per SIMD fit three blocks (150 KB of LDS) per CU;
-// the central mesh kernel holds more registers (the compiler spills at that
-// budget) and runs best as one 8-row block per CU. FP64 keeps four rows at
-// one wave per SIMD.
-constexpr int kUpCols = 64;
-template <typename T, bool MESH, bool CENTRAL>
-__host__ __device__ constexpr int up_rows() {
-  return sizeof(T) == 8 ? 4 : (MESH && CENTRAL) ? 8 : 4;
-}
-template <typename T, bool MESH, bool CENTRAL>
-__host__ __device__ constexpr int up_wpe() {
-  return sizeof(T) == 8 ? 1 : (MESH && CENTRAL) ? 1 : 3;
-}
-
-// Periodic index for an index at most one period outside [0, n): a
-// conditional add or subtract (an integer remainder costs tens of
-// instructions), with the remainder kept for grids smaller than a halo.
-__device__ __forceinline__ int wrap_near(int a, int n) {
-  if (a < 0) a += n;
-  else if (a >= n) a -= n;
-  return (a >= 0 && a < n) ? a : wrap(a, n);
-}
-
-// Step index of this launch in the case's window, or -1 when outside it.
-__device__ __forceinline__ long long up_step(const CaseDev& C, const UpArgs& A) {
-  const long long n = *A.step_base + A.kofs - C.step0;
-  return (n < 0 || n >= C.nsteps) ? -1 : n;
-}
+// ----------------- upwind reconstruction and stretched meshes: pieces
 
 // van Leer's limited slope of two one-sided differences (or slopes).
 template <typename T>
@@ -1687,12 +1636,6 @@ __device__ __forceinline__ T van_leer(T a, T b) {
                              : T(2) * a * b / (a + b);
   return a * b > T(0) ? q : T(0);
 }
-
-// The block step holds the bar-plus values of its block's cells and their
-// halo (two columns/rows before, two after) in LDS: a block's faces read each
-// value several times (the limited slopes of both cells of every face). The
-// tile has kTileC columns and ROWS + 4 rows.
-constexpr int kTileC = kUpCols + 4;
 
 // Metrics of one cell along one axis of a stretched mesh: width, the
 // reciprocal centre distances to the previous and next cells, the weights of
@@ -1719,490 +1662,32 @@ __device__ __forceinline__ T lim_mesh(T b, T f, const Met<T>& m) {
   return s > cap ? cap : (s < -cap ? -cap : s);
 }
 
-// Bar-plus values, slopes and face values of the faces of one cell (ic, jc):
-// they read the cells (ic, jc), (ic + 1, jc) and (ic, jc + 1) and their
-// neighbours. Cells are addressed by unwrapped grid indices within the
-// block's tile (the halo holds the wrapped or clamped neighbours); icw, jcw,
-// ic1, jc1 are the wrapped indices of ic, jc, ic + 1, jc + 1. On a stretched
-// mesh the metrics of columns ic, ic + 1 and rows jc, jc + 1 are held in
-// registers.
-template <typename T, bool WALLS, bool MESH, int NB, int TR>
-struct UpBars {
-  const T (*L)[TR][kTileC];  // LDS tile [planes][TR][kTileC]
-  int i0, j0;                    // grid cell of tile position (2, 2)
-  int nx, ny;
-  int ic, jc, icw, jcw, ic1, jc1;
-  Met<T> mx[2], my[2];  // stretched mesh only
-  __device__ __forceinline__ T at(int p, int i, int j) const { return L[p][j - j0 + 2][i - i0 + 2]; }
-  __device__ __forceinline__ int xi(int i) const { return i == ic ? icw : ic1; }
-  __device__ __forceinline__ int yj(int j) const { return j == jc ? jcw : jc1; }
-  __device__ __forceinline__ const Met<T>& MX(int i) const { return i == ic ? mx[0] : mx[1]; }
-  __device__ __forceinline__ const Met<T>& MY(int j) const { return j == jc ? my[0] : my[1]; }
-  // one-sided y difference (derivative on a stretched mesh) next to a wall,
-  // unlimited (j is row 0 or ny-1)
-  __device__ __forceinline__ T wall_dy(int p, int i, int j) const {
-    const T d = j == 0 ? at(p, i, 1) - at(p, i, 0) : at(p, i, ny - 1) - at(p, i, ny - 2);
-    if (MESH) return d * (j == 0 ? MY(j).ihp : MY(j).ihm);
-    return d;
-  }
-  __device__ __forceinline__ T lim_x(int p, int i, int j) const {
-    const T c = at(p, i, j);
-    const T b = c - at(p, i - 1, j), f = at(p, i + 1, j) - c;
-    if (MESH) return lim_met(b, f, MX(i));
-    return van_leer(b, f);
-  }
-  __device__ __forceinline__ T lim_y(int p, int i, int j) const {
-    if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
-    const T c = at(p, i, j);
-    const T b = c - at(p, i, j - 1), f = at(p, i, j + 1) - c;
-    if (MESH) return lim_met(b, f, MY(j));
-    return van_leer(b, f);
-  }
-  __device__ __forceinline__ static T lim_met(T b, T f, const Met<T>& m) {
-    return lim_mesh<T>(b, f, m);
-  }
-  // central slopes of the stretched mesh (parabola through three centres)
-  __device__ __forceinline__ T slope_x(int p, int i, int j) const {
-    const Met<T>& m = MX(i);
-    const T c = at(p, i, j);
-    return m.cp * (at(p, i + 1, j) - c) + m.cm * (c - at(p, i - 1, j));
-  }
-  __device__ __forceinline__ T slope_y(int p, int i, int j) const {
-    if (WALLS && (j == 0 || j == ny - 1)) return wall_dy(p, i, j);
-    const Met<T>& m = MY(j);
-    const T c = at(p, i, j);
-    return m.cp * (at(p, i, j + 1) - c) + m.cm * (c - at(p, i, j - 1));
-  }
-  // half widths of cells A and B across a face of normal DIR
-  template <int DIR>
-  __device__ __forceinline__ void halves(int ia, int ja, int ib, int jb, T& dA, T& dB) const {
-    if (MESH) {
-      dA = T(0.5) * (DIR == 0 ? MX(ia).w : MY(ja).w);
-      dB = T(0.5) * (DIR == 0 ? MX(ib).w : MY(jb).w);
-    } else {
-      dA = dB = T(0.5);
-    }
-  }
-  // value of plane p's population (velocity ex, ey) at the face of normal
-  // DIR between cells A (below / left) and B. Upwind: traced back by h xi
-  // into the upwind cell, or (along the face) the interpolation of both
-  // cells. Central (stretched mesh): interpolated value minus h xi times the
-  // normal and tangential slopes at the face.
-  template <int DIR, bool CENTRAL>
-  __device__ __forceinline__ T face(int p, int ex, int ey, T h, int ia, int ja, int ib,
-                                    int jb) const {
-    const int en = DIR == 0 ? ex : ey, et = DIR == 0 ? ey : ex;
-    auto ln = [&](int i, int j) { return DIR == 0 ? lim_x(p, i, j) : lim_y(p, i, j); };
-    auto lt = [&](int i, int j) { return DIR == 0 ? lim_y(p, i, j) : lim_x(p, i, j); };
-    if constexpr (!MESH) {
-      const T hal = T(0.5) - h;
-      if (en > 0) {
-        T v = at(p, ia, ja) + hal * ln(ia, ja);
-        if (et != 0) v -= h * T(et) * lt(ia, ja);
-        return v;
-      }
-      if (en < 0) {
-        T v = at(p, ib, jb) - hal * ln(ib, jb);
-        if (et != 0) v -= h * T(et) * lt(ib, jb);
-        return v;
-      }
-      T v = T(0.5) * (at(p, ia, ja) + at(p, ib, jb));
-      if (et != 0) v -= h * T(et) * (T(0.5) * (lt(ia, ja) + lt(ib, jb)));
-      return v;
-    } else {
-      T dA, dB;
-      halves<DIR>(ia, ja, ib, jb, dA, dB);
-      // one reciprocal of the centre distance per face (shared by the
-      // populations once inlined)
-      const T iH = T(1) / (dA + dB), aA = at(p, ia, ja), aB = at(p, ib, jb);
-      if constexpr (CENTRAL) {
-        auto st = [&](int i, int j) { return DIR == 0 ? slope_y(p, i, j) : slope_x(p, i, j); };
-        const T af = (dB * aA + dA * aB) * iH, dn = (aB - aA) * iH;
-        const T dtg = (dB * st(ia, ja) + dA * st(ib, jb)) * iH;
-        return af - h * (T(en) * dn + T(et) * dtg);
-      } else {
-        if (en > 0) {
-          T v = aA + (dA - h) * ln(ia, ja);
-          if (et != 0) v -= h * T(et) * lt(ia, ja);
-          return v;
-        }
-        if (en < 0) {
-          T v = aB + (h - dB) * ln(ib, jb);
-          if (et != 0) v -= h * T(et) * lt(ib, jb);
-          return v;
-        }
-        T vA = aA, vB = aB;
-        if (et != 0) {
-          vA -= h * T(et) * lt(ia, ja);
-          vB -= h * T(et) * lt(ib, jb);
-        }
-        return (dB * vA + dA * vB) * iH;
-      }
-    }
-  }
-};
+// ------------------------------ the reconstruction march
 
-// The view of the tile for the faces of cell (ic, jc) (unwrapped), with its
-// wrapped indices and, on a stretched mesh, its metrics.
-template <typename T, bool WALLS, bool MESH, int NB, int TR>
-__device__ __forceinline__ UpBars<T, WALLS, MESH, NB, TR> up_bars(const CaseDev& C,
-                                                                 const T (*L)[TR][kTileC], int i0,
-                                                                 int j0, int ic, int jc) {
-  const int nx = C.nx, ny = C.ny;
-  UpBars<T, WALLS, MESH, NB, TR> B{L, i0, j0, nx, ny, ic, jc, wrap_near(ic, nx), wrap_near(jc, ny),
-                               wrap_near(ic + 1, nx), wrap_near(jc + 1, ny), {}, {}};
-  if (MESH) {
-    const MeshAxis X = mesh_axis(C.mesh, nx, ny, 0), Y = mesh_axis(C.mesh, nx, ny, 1);
-    const int cx[2] = {B.icw, B.ic1}, cy[2] = {B.jcw, B.jc1};
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      B.mx[k] = Met<T>::load(X, cx[k]);
-      B.my[k] = Met<T>::load(Y, cy[k]);
-    }
-  }
-  return B;
-}
-
-// Face of normal DIR between cells A and B (unwrapped indices):
-// reconstruction, face macros and the face distributions fo, go (the
-// populations that cross the face).
-template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int DIR, int NB, int TR>
-__device__ __forceinline__ void up_face(const CaseDev& C, const UpBars<T, WALLS, MESH, NB, TR>& B,
-                                        int ia, int ja, int ib, int jb, double xf, double yf,
-                                        double tf, T (&fo)[9], T (&go)[9]) {
-  const T h = T(C.h);
-  T fbar[9], gbar[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    fbar[q] = B.template face<DIR, CENTRAL>(q, EX[q], EY[q], h, ia, ja, ib, jb);
-    gbar[q] = (CPL && q > 0) ? B.template face<DIR, CENTRAL>(9 + q, EX[q], EY[q], h, ia, ja, ib, jb)
-                             : T(0);
-  }
-  const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
-                 ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
-  T N0f = T(0), Jxf = T(0), Jyf = T(0);
-  if (CPL) {
-    N0f = ((gbar[1] + gbar[2]) + (gbar[3] + gbar[4])) + ((gbar[5] + gbar[6]) + (gbar[7] + gbar[8]));
-    Jxf = (gbar[1] + gbar[2] + gbar[8]) - (gbar[4] + gbar[5] + gbar[6]);
-    Jyf = (gbar[2] + gbar[3] + gbar[4]) - (gbar[6] + gbar[7] + gbar[8]);
-  }
-  T dA, dB;
-  B.template halves<DIR>(ia, ja, ib, jb, dA, dB);
-  // gradient-type face inputs (tile planes NB ..): the mean of the two
-  // cells (linear interpolation to the face on a stretched mesh)
-  const T iH = T(1) / (dA + dB);
-  auto mean = [&](int k) {
-    if (MESH) return (dB * B.at(NB + k, ia, ja) + dA * B.at(NB + k, ib, jb)) * iH;
-    return T(0.5) * (B.at(NB + k, ia, ja) + B.at(NB + k, ib, jb));
-  };
-  face_df<T, CPL, DIR>(C, phif, N0f, Jxf, Jyf, mean(0), mean(1), mean(2), mean(3), mean(4), fbar,
-                       gbar, xf, yf, tf, fo, go);
-}
-
-// Wall face below row 0 (BOTTOM) or above row ny-1 of column i: the march's
-// face bounce-back, fed from the tile. B is the view of the wall cell; its
-// phi and p come from the registers of the thread that owns it.
-template <typename T, bool BOTTOM, bool MESH, int NB, int TR>
-__device__ __forceinline__ void up_wall(const CaseDev& C, const UpBars<T, true, MESH, NB, TR>& B,
-                                        int i, T phiw, T pw, T (&fo)[9], T (&go)[9]) {
-  const int ny = B.ny;
-  const int jw = BOTTOM ? 0 : ny - 1, jn = BOTTOM ? 1 : ny - 2;
-  Cell<T> c, cn;
-  T txf[9], txg[9];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    c.fb[q] = B.at(q, i, jw);
-    c.gb[q] = B.at(9 + q, i, jw);
-    cn.fb[q] = B.at(q, i, jn);
-    cn.gb[q] = B.at(9 + q, i, jn);
-    const bool diag = EX[q] != 0 && EY[q] != 0;
-    if (MESH) {  // x slopes
-      txf[q] = diag ? B.slope_x(q, i, jw) : T(0);
-      txg[q] = diag ? B.slope_x(9 + q, i, jw) : T(0);
-    } else {  // x central differences (halved in wall_face)
-      txf[q] = diag ? B.at(q, i + 1, jw) - B.at(q, i - 1, jw) : T(0);
-      txg[q] = diag ? B.at(9 + q, i + 1, jw) - B.at(9 + q, i - 1, jw) : T(0);
-    }
-  }
-  c.phi = phiw;
-  c.gx = B.at(NB + 0, i, jw);
-  c.mu = B.at(NB + 2, i, jw);
-  c.Dx = B.at(NB + 3, i, jw);
-  c.p = pw;
-  T dyw = T(0), idy = T(1);
-  if (MESH) {
-    const Met<T>& m = B.MY(jw);
-    dyw = BOTTOM ? T(-0.5) * m.w : T(0.5) * m.w;
-    idy = BOTTOM ? m.ihp : m.ihm;
-  }
-  wall_face_g<T, BOTTOM, MESH>(C, c, cn, txf, txg, dyw, idy, fo, go);
-}
-
-// The whole step of one 64 x ROWS block of cells. Three phases, with
-// barriers:
-//   1. stage: the cell stage (macros, equilibria, sources, bar-plus and
-//      tilde-plus; the central march's cell_stage / cell_core) of the block's
-//      cells and of a halo of two cells on each side, 68 x (ROWS + 4) cells:
-//      bar-plus and the face inputs (grad phi, mu_phi, D) go to the LDS tile,
-//      tilde-plus, the history, phi and p of the block's own cells stay in
-//      the registers of the thread that updates the cell (the halo cells skip
-//      tilde-plus);
-//   2. faces: every thread forms the x-face east and the y-face north of its
-//      cell, wave 0 also the y-face south of the block's first row, ROWS
-//      lanes of wave 1 the x-face west of its first column (reconstruction
-//      from the tile, face macros, face distributions; wall faces, by the
-//      thread that owns the wall cell);
-//   3. update (Eq. 24): the face distributions go to LDS over the tile, and
-//      every cell is updated from its four faces.
-// The two halo cells on each side are what the block's faces read: a face
-// reads the limited slopes of both its cells, and a slope reads the cell's
-// neighbours.
-template <typename T, bool CPL, bool WALLS, bool MESH, bool CENTRAL, int ROWS, int WPE>
-__global__ __launch_bounds__(kUpCols * ROWS) __attribute__((amdgpu_waves_per_eu(WPE)))
-void k_up_step(UpArgs A) {
-  constexpr int NT = kUpCols * ROWS, TR = ROWS + 4;
-  const CaseDev C = *A.cases;
-  const long long n = up_step(C, A);
-  if (n < 0) return;
-  const int nx = C.nx, ny = C.ny;
-  // block origin (blocks in XCD-contiguous order); blocks past the grid
-  // leave before the barriers, all of their threads together
-  const int nbx = (nx + kUpCols - 1) / kUpCols;
-  const int idx = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
-  const int i0 = (idx % nbx) * kUpCols, j0 = (idx / nbx) * ROWS;
-  if (j0 >= ny) return;
-  const int lane = threadIdx.x & (kUpCols - 1), wv = threadIdx.x >> 6;
-  const long long RB = C.row_vals * (long long)sizeof(T), PB = (long long)nx * sizeof(T);
-  constexpr int NB = up_bar_planes(CPL);
-  constexpr int NF = CPL ? 12 : 6;  // crossing populations of a face, f then g
-  constexpr int NV = num_grouped(CPL);
-  constexpr int walls = WALLS ? 1 : 0;
-  // bar-plus planes, then grad phi x, y, mu_phi, D x, y
-  __shared__ T tile[NB + 5][TR][kTileC];
-  static_assert(NF * (ROWS * (kUpCols + 1) + (ROWS + 1) * kUpCols) <= (NB + 5) * TR * kTileC,
-                "the face planes of phase 3 fit in the tile");
-  const int cur = (C.cur0 + (int)(n & 1)) & 1;
-  const char* in = static_cast<const char*>(cur ? C.set[1] : C.set[0]);
-  char* out = static_cast<char*>(cur ? C.set[0] : C.set[1]);
-  const double tn = C.t0 + (double)n * C.dt;
-
-  // ---- 1. stage. Tile cell (tc, tr) is grid cell (i0 - 2 + tc, j0 - 2 + tr),
-  // wrapped in x and y (periodic) or clamped to the wall rows (the clamped
-  // copies stand for rows past a wall, which no face reads).
-  auto stage = [&](int tc, int tr, Cell<T>& o, T (&tp)[18]) {
-    const int gi = wrap_near(i0 - 2 + tc, nx);
-    int gj = j0 - 2 + tr;
-    gj = WALLS ? (gj < 0 ? 0 : (gj >= ny ? ny - 1 : gj)) : wrap_near(gj, ny);
-    T ph[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      const T* prow = reinterpret_cast<const T*>(in + (long long)row_idx(gj + r - 1, ny, walls) * RB +
-                                                 NV * PB);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) ph[r][c] = prow[wrap_near(gi + c - 1, nx)];
-    }
-    T v[NV];
-    load_groups<T, NV>(in + (long long)gj * RB, PB, (unsigned)gi, v);
-    T ft[9], gt[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      ft[q] = v[val_f(q)];
-      gt[q] = CPL ? v[val_g(q)] : T(0);
-    }
-    if constexpr (MESH) {
-      T gx, gy, lap;
-      mesh_stencils<T>(C, ph, gi, gj, gx, gy, lap);
-      double xc, yc;
-      cell_centre(C, gi, gj, xc, yc);
-      cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)],
-                        xc, yc, tn, o, tp);
-    } else {
-      cell_stage<T, CPL>(C, ph, ft, gt, v[val_hist(CPL, 0)], v[val_hist(CPL, 1)], (double)gi + 0.5,
-                         (double)gj + 0.5, tn, o, tp);
-    }
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      tile[q][tr][tc] = o.fb[q];
-      if (CPL) tile[9 + q][tr][tc] = o.gb[q];
-    }
-    tile[NB + 0][tr][tc] = o.gx;
-    tile[NB + 1][tr][tc] = o.gy;
-    tile[NB + 2][tr][tc] = o.mu;
-    tile[NB + 3][tr][tc] = o.Dx;
-    tile[NB + 4][tr][tc] = o.Dy;
-  };
-  // the thread's own cell: tilde-plus and history kept for the update, phi
-  // and p for a wall face
-  T keep[NV];
-  T own_phi, own_p;
-  {
-    Cell<T> o;
-    T tp[18];
-    stage(2 + lane, 2 + wv, o, tp);
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-      keep[val_f(q)] = tp[q];
-      if (CPL) keep[val_g(q)] = tp[9 + q];
-    }
-    keep[val_hist(CPL, 0)] = o.hx;
-    keep[val_hist(CPL, 1)] = o.hy;
-    own_phi = o.phi;
-    own_p = o.p;
-  }
-  // the halo: rows 0, 1 and TR - 2, TR - 1 of the tile, then columns 0, 1,
-  // kTileC - 2, kTileC - 1 of the block's rows
-  constexpr int kHalo = kTileC * TR - NT;
-  for (int hc = (int)threadIdx.x; hc < kHalo; hc += NT) {
-    int tc, tr;
-    if (hc < 2 * kTileC) {
-      tr = hc / kTileC;
-      tc = hc - tr * kTileC;
-    } else if (hc < 4 * kTileC) {
-      const int k = hc - 2 * kTileC;
-      tr = TR - 2 + k / kTileC;
-      tc = k % kTileC;
-    } else {
-      const int k = hc - 4 * kTileC;
-      tr = 2 + (k >> 2);
-      const int m = k & 3;
-      tc = m < 2 ? m : kTileC - 4 + m;
-    }
-    Cell<T> o;
-    T tp[18];
-    stage(tc, tr, o, tp);
-  }
-  __syncthreads();
-
-  // ---- 2. faces
-  const int i = i0 + lane, j = j0 + wv;
-  const bool act = i < nx && j < ny;
-  const double tf = tn + C.h;
-  MeshAxis X{}, Y{};
-  if (MESH) {
-    X = mesh_axis(C.mesh, nx, ny, 0);
-    Y = mesh_axis(C.mesh, nx, ny, 1);
-  }
-  // face positions: the east face of column c, the north face of row r
-  // (wrapped indices)
-  auto xeast = [&](int c) { return MESH ? X.c[c] + 0.5 * X.w[c] : (double)c + 1.0; };
-  auto xmid = [&](int c) { return MESH ? X.c[c] : (double)c + 0.5; };
-  auto ynorth = [&](int r) { return MESH ? Y.c[r] + 0.5 * Y.w[r] : (double)r + 1.0; };
-  auto ymid = [&](int r) { return MESH ? Y.c[r] : (double)r + 0.5; };
-  T fx[9], gx[9], fy[9], gy[9], fe[9], ge[9];
-  if (act) {
-    const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i, j);
-    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, i, j, i + 1, j, xeast(i), ymid(j), tf, fx, gx);
-    if (WALLS && j == ny - 1) {
-      if constexpr (WALLS) up_wall<T, false, MESH, NB, TR>(C, B, i, own_phi, own_p, fy, gy);
-    } else {
-      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, i, j, i, j + 1, xmid(i), ynorth(j), tf, fy, gy);
-    }
-  }
-  // the block's extra faces
-  const bool south = wv == 0 && i < nx;
-  const bool west = wv == 1 && lane < ROWS && j0 + lane < ny;
-  if (south) {  // y-face between rows j0 - 1 and j0, or the bottom wall (of this thread's cell)
-    if (WALLS && j0 == 0) {
-      if constexpr (WALLS) {
-        const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i, 0);
-        up_wall<T, true, MESH, NB, TR>(C, B, i, own_phi, own_p, fe, ge);
-      }
-    } else {
-      const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i, j0 - 1);
-      up_face<T, CPL, WALLS, MESH, CENTRAL, 1>(C, B, i, j0 - 1, i, j0, xmid(i), ynorth(B.jcw), tf,
-                                               fe, ge);
-    }
-  }
-  if (west) {  // x-face between columns i0 - 1 and i0 of row j0 + lane
-    const int jr = j0 + lane;
-    const auto B = up_bars<T, WALLS, MESH, NB, TR>(C, tile, i0, j0, i0 - 1, jr);
-    up_face<T, CPL, WALLS, MESH, CENTRAL, 0>(C, B, i0 - 1, jr, i0, jr, xeast(B.icw), ymid(jr), tf,
-                                             fe, ge);
-  }
-  __syncthreads();  // every read of the tile is done: it now holds the faces
-
-  // ---- 3. update
-  // x-faces [NF][ROWS][kUpCols + 1] (column c: the face east of i0 - 1 + c),
-  // y-faces [NF][ROWS + 1][kUpCols] (row r: the face north of j0 - 1 + r)
-  T* FX = &tile[0][0][0];
-  T* FY = FX + NF * ROWS * (kUpCols + 1);
-  auto fxi = [&](int s, int r, int c) { return (s * ROWS + r) * (kUpCols + 1) + c; };
-  auto fyi = [&](int s, int r, int c) { return (s * (ROWS + 1) + r) * kUpCols + c; };
-#pragma unroll
-  for (int q = 1; q < 9; ++q) {
-    const int sx = up_xslot(q), sy = up_yslot(q);
-    if (act && sx >= 0) {
-      FX[fxi(sx, wv, lane + 1)] = fx[q];
-      if (CPL) FX[fxi(6 + sx, wv, lane + 1)] = gx[q];
-    }
-    if (act && sy >= 0) {
-      FY[fyi(sy, wv + 1, lane)] = fy[q];
-      if (CPL) FY[fyi(6 + sy, wv + 1, lane)] = gy[q];
-    }
-    if (south && sy >= 0) {
-      FY[fyi(sy, 0, lane)] = fe[q];
-      if (CPL) FY[fyi(6 + sy, 0, lane)] = ge[q];
-    }
-    if (west && sx >= 0) {
-      FX[fxi(sx, lane, 0)] = fe[q];
-      if (CPL) FX[fxi(6 + sx, lane, 0)] = ge[q];
-    }
-  }
-  __syncthreads();
-  if (!act) return;
-  // face length over cell area is 1/dx and 1/dy (1 on unit cells)
-  char* orow = row_ptr(out, j, RB);  // one row per wave
-  T ax = T(1), ay = T(1);
-  if (MESH) {
-    ax = T(X.iw[i]);
-    ay = T(Y.iw[j]);
-  }
-  const T dt = T(C.dt);
-  T phin = T(0);
-  auto upd = [&](int q, int off) {
-    const int sx = up_xslot(q), sy = up_yslot(q);
-    if (MESH) {
-      T Jx = T(0), Jy = T(0);
-      if (EX[q] != 0) Jx = T(EX[q]) * (FX[fxi(off + sx, wv, lane + 1)] - FX[fxi(off + sx, wv, lane)]);
-      if (EY[q] != 0) Jy = T(EY[q]) * (FY[fyi(off + sy, wv + 1, lane)] - FY[fyi(off + sy, wv, lane)]);
-      return ax * Jx + ay * Jy;
-    }
-    T J = T(0);
-    if (EX[q] != 0) J += T(EX[q]) * (FX[fxi(off + sx, wv, lane + 1)] - FX[fxi(off + sx, wv, lane)]);
-    if (EY[q] != 0) J += T(EY[q]) * (FY[fyi(off + sy, wv + 1, lane)] - FY[fyi(off + sy, wv, lane)]);
-    return J;
-  };
-  T v[NV];
-#pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    v[val_f(q)] = keep[val_f(q)] - dt * upd(q, 0);
-    phin += v[val_f(q)];
-  }
-  if (CPL) {
-#pragma unroll
-    for (int q = 0; q < 9; ++q) v[val_g(q)] = keep[val_g(q)] - dt * upd(q, 6);
-  }
-  v[val_hist(CPL, 0)] = keep[val_hist(CPL, 0)];
-  v[val_hist(CPL, 1)] = keep[val_hist(CPL, 1)];
-  store_groups<T, NV>(orow, PB, (unsigned)i, v);
-  gstore<T>(orow + NV * PB, (unsigned)i * (unsigned)sizeof(T), phin);
-  flag_nonfinite(C, phin + v[val_hist(CPL, 0)] + v[val_hist(CPL, 1)]);
-}
-
-// ------------------------------ upwind march (unit mesh)
-
-// The upwind reconstruction on the unit mesh as a march, like k_step: one
+// The upwind, limited reconstruction (on the unit and on a stretched mesh)
+// and the central one on a stretched mesh do not fit k_step's march: the
+// upwind face value of each population is a non-linear function of the
+// cells, so the face macros must be summed from the nine reconstructed
+// values instead of reconstructed cell moments, a face reads the limited
+// slopes of both its cells (a radius-two stencil), and on a stretched mesh
+// every stencil carries the local widths. k_upm marches like k_step: one
 // 64-lane wave owns a strip of kUpmCols = 60 columns (lanes 2..61; two halo
 // lanes on each side, since an x-face reads the limited x slopes of both its
-// cells and a slope reads the cell's neighbours) and marches up a segment of
-// rows. Each row's limited slopes are formed once and kept in its record:
-// the x slopes from the neighbouring lanes (DPP), the y slopes from the rows
-// below and above when the row above is staged. Output row k needs rows
-// k-2..k+2 staged, so the pass that stages row s also forms the y slopes of
-// row s-1, the y-face between rows s-2 and s-1, the x-faces of row s-1 and
-// the update of row s-2. The reconstruction, face macros, face distributions
-// and wall faces are the block step's (UpBars::face, up_face, up_wall), with
-// the same expressions, so both kernels give the same bits.
+// cells and a slope reads the cell's neighbours) and marches up a segment
+// of rows. Each row's limited slopes are formed once and kept in its
+// record: the x slopes from the neighbouring lanes (DPP), the y slopes from
+// the rows below and above when the row above is staged. Output row k needs
+// rows k-2..k+2 staged, so the pass that stages row s also forms the y
+// slopes of row s-1, the y-face between rows s-2 and s-1, the x-faces of row
+// s-1 and the update of row s-2. The cell stage, face distributions and wall
+// faces are k_step's (cell_stage / cell_core, face_df, wall_face_g).
+//
+// Stretched mesh: the reconstruction interpolates linearly to the face (the
+// value, the tangential slope and the face inputs), slopes are derivatives
+// over the centre distances, the upwind trace starts from the actual half
+// width, and the update divides the fluxes by the cell's widths. On unit
+// widths every formula reduces to the unit-mesh one. The central
+// reconstruction's parabola slopes are cheap and are formed where used.
 template <typename T, bool CPL>
 struct URow {
   Cell<T> cell;
@@ -2530,13 +2015,12 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
                        mean(a.mu, b.mu), mean(a.Dx, b.Dx), mean(a.Dy, b.Dy), fbar, gbar, xcen,
                        MESH ? Y.c[rr] + 0.5 * Y.w[rr] : (double)rr + 1.0, tn + C.h, u.fsf, u.fsg);
   };
-  // Central reconstruction on a stretched mesh (the block step's
-  // UpBars::face, CENTRAL): the face value is the interpolation of the two
-  // cells less h xi times the normal difference and the interpolated
-  // tangential slope, for every population (the zero-weighted terms
-  // included, as there). The parabola slopes are cheap, so they are formed
-  // where used: the y slopes of row r from the rows below (d) and above (u),
-  // the x slopes from the neighbouring lanes.
+  // Central reconstruction on a stretched mesh: the face value is the
+  // interpolation of the two cells less h xi times the normal difference and
+  // the interpolated tangential slope, for every population (the
+  // zero-weighted terms included). The parabola slopes are cheap, so they
+  // are formed where used: the y slopes of row r from the rows below (d) and
+  // above (u), the x slopes from the neighbouring lanes.
   auto yslope_c = [&](int r, T dv, T cv, T uv, const Met<T>& my) {
     if (WALLS && r == 0) return (uv - cv) * my.ihp;
     if (WALLS && r == ny - 1) return (cv - dv) * my.ihm;
@@ -2808,38 +2292,6 @@ hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, h
     if (!coupled) hipLaunchKernelGGL((k_step<float, false, false>), grid, block, 0, s, a);
     else if (walls) hipLaunchKernelGGL((k_step<float, true, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_step<float, true, false>), grid, block, 0, s, a);
-  }
-  return hipGetLastError();
-}
-
-// One block-step launch: blocks of 64 x ROWS cells, the grid rounded up to
-// a multiple of eight (one share per XCD; surplus blocks leave at once).
-template <typename T, bool CPL, bool W, bool M, bool CEN>
-static void launch_up(int nx, int ny, const UpArgs& a, hipStream_t s) {
-  constexpr int rows = up_rows<T, M, CEN>();
-  const long long blocks = (long long)((nx + kUpCols - 1) / kUpCols) * ((ny + rows - 1) / rows);
-  const dim3 grid((unsigned)((blocks + 7) / 8 * 8)), block(kUpCols * rows);
-  hipLaunchKernelGGL((k_up_step<T, CPL, W, M, CEN, rows, up_wpe<T, M, CEN>()>), grid, block, 0, s, a);
-}
-template <typename T, bool CPL, bool W>
-static void launch_up_modes(bool upwind, bool mesh, int nx, int ny, const UpArgs& a, hipStream_t s) {
-  if (!mesh) launch_up<T, CPL, W, false, false>(nx, ny, a, s);
-  else if (upwind) launch_up<T, CPL, W, true, false>(nx, ny, a, s);
-  else launch_up<T, CPL, W, true, true>(nx, ny, a, s);
-}
-
-hipError_t launch_step_upwind(bool fp64, bool coupled, bool walls, bool upwind, bool mesh,
-                              int nx, int ny, const UpArgs& a, hipStream_t s) {
-  if (walls && !coupled) return hipErrorInvalidValue;
-  if (!upwind && !mesh) return hipErrorInvalidValue;  // the march covers that case
-  if (fp64) {
-    if (!coupled) launch_up_modes<double, false, false>(upwind, mesh, nx, ny, a, s);
-    else if (walls) launch_up_modes<double, true, true>(upwind, mesh, nx, ny, a, s);
-    else launch_up_modes<double, true, false>(upwind, mesh, nx, ny, a, s);
-  } else {
-    if (!coupled) launch_up_modes<float, false, false>(upwind, mesh, nx, ny, a, s);
-    else if (walls) launch_up_modes<float, true, true>(upwind, mesh, nx, ny, a, s);
-    else launch_up_modes<float, true, false>(upwind, mesh, nx, ny, a, s);
   }
   return hipGetLastError();
 }

@@ -151,7 +151,7 @@ def test_saved_state_follows_the_documented_layout(prec, model, nx, ny):
 def test_largest_grids_evolve_like_a_narrow_grid(prec, nx, ny, walls, mode):
     """Grids at the size limit of the C ABI (2^28 cells in FP32, 2^27 in
     FP64), as rows of up to 5.6 GB or as 22 GB buffers of many rows; the
-    fused march, and the block step (upwind reconstruction, a mesh
+    fused march, and the reconstruction march (upwind reconstruction, a mesh
     stretched along y). The initial state
     varies along y only, so every cell of a row sees the same inputs and must
     end with the bits of the same row of a 64-column grid (whose kernels give

@@ -155,8 +155,9 @@ def test_time_step_and_state_rules():
     s.init(c["phi"])
     s.step(10)
     assert s.time == pytest.approx(10 * c["params"]["cfl"] * dx.min())
-    with pytest.raises(D.DugksError):
-        s.autotune(2)
+    st0 = s.get_state()[0]
+    seg, _ = s.autotune(2)  # segments of the reconstruction march, on a copy of the state
+    assert s.seg_rows == seg and np.array_equal(s.get_state()[0], st0)
     with pytest.raises(D.DugksError):
         D.Batch([s])
     with pytest.raises(D.DugksError):

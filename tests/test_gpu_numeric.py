@@ -31,7 +31,7 @@ def _poisoned(c):
 
 
 # every step kernel: one-row, two-row, march (periodic and walls), FP64, and
-# the block step (upwind reconstruction)
+# the reconstruction march (upwind reconstruction)
 KERNELS = [
     ("fp32", 1, "central", False), ("fp32", 2, "central", False), ("fp32", 6, "central", False),
     ("fp32", 6, "central", True), ("fp64", 4, "central", False), ("fp32", None, "upwind", False),

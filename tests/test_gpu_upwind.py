@@ -7,7 +7,7 @@ reading: trace back by h xi into the upwind cell, van Leer limited slopes).
 Tolerances are those of the central path: FP64 relative L2 <= 1e-12 after
 hundreds of steps (the same double formulas in another order; van Leer's
 limiter is Lipschitz, so rounding does not grow through its branches), FP32
-relative L2 <= 1e-5 on phi. On the unit mesh the step is the upwind march
+relative L2 <= 1e-5 on phi. The step is the reconstruction march
 (60-column strips, segments of rows); sizes span several strips and
 segments with a ragged last strip and segment, and periodic and
 wall-bounded y.
@@ -163,7 +163,7 @@ def test_switching_the_reconstruction_between_steps():
                                                    ("fp64", False, False), ("fp64", True, False),
                                                    ("fp32", True, True), ("fp64", False, True)])
 def test_march_segments_give_the_same_bits(precision, walls, mesh):
-    """The upwind march's segment length (dugks_set_tile) changes only the
+    """The reconstruction march's segment length (dugks_set_tile) changes only the
     work decomposition: one-row segments, short ones that leave a ragged last
     segment, the automatic choice and one segment of the whole height give
     the same state bit for bit (halo rows go through the same code as output
@@ -172,7 +172,7 @@ def test_march_segments_give_the_same_bits(precision, walls, mesh):
     c = upwind(W.random_coupled(130, 37, seed=11, rho_ratio=100.0, walls_y=walls))
     states = {}
     for seg in (1, 2, 5, 0, 37):
-        print(f"[upwind march] segments {seg} {precision} walls={walls} mesh={mesh}", flush=True)
+        print(f"[reconstruction march] segments {seg} {precision} walls={walls} mesh={mesh}", flush=True)
         s = D.Solver(c["nx"], c["ny"], c["params"], c["model"], precision, seg or None)
         if mesh:
             s.set_mesh(W.random_widths(130, 21), W.random_widths(37, 22))
@@ -185,13 +185,17 @@ def test_march_segments_give_the_same_bits(precision, walls, mesh):
         assert np.array_equal(st, ref), f"segments of {seg} rows differ from one-row segments"
 
 
-def test_batches_pools_and_autotune_reject_upwind():
+def test_batches_and_pools_reject_upwind_and_autotune_tunes_its_march():
     c = upwind(W.random_coupled(40, 20, seed=2, rho_ratio=10.0))
     s = gpu(c, 1)
     with pytest.raises(D.DugksError):
         D.Batch([s])
-    with pytest.raises(D.DugksError):
-        s.autotune(2)
+    # the autotuner times segment lengths of the reconstruction march on a copy of
+    # the state and keeps the fastest
+    st0 = s.get_state()[0]
+    seg, us = s.autotune(2)
+    assert seg >= 1 and us > 0 and s.seg_rows == seg
+    assert np.array_equal(s.get_state()[0], st0)
     pool = D.Pool(1 << 26, max_cases=2, max_cells=40 * 20)
     with pytest.raises(D.DugksError):
         pool.admit(c, 10)
