@@ -87,7 +87,7 @@ int fit_seg_rows(const std::vector<StripShape>& cs, long long budget) {
 // than the device caches) eight rounds of shorter tiles, which keeps the
 // rows in flight closer together and measured faster on MI355X (4096^2
 // FP32 coupled: 23.4k MLUPS with 137-row segments, 26.8k with 17).
-// The upwind march takes one round of resident waves with its own strips
+// The reconstruction march takes one round of resident waves with its own strips
 // (60 columns) and capacity; where that needs segments longer than 64 rows,
 // the shortest segments that number at most 32 waves per CU. Measured on
 // MI355X (microseconds per step, upwind bubble): 4096^2 FP32 18 rows 655,

@@ -23,10 +23,10 @@ struct dugks_handle {
   dugks::CaseDev* dc = nullptr;
   dugks::Item* items = nullptr;
   int nitems = 0;
-  // work items of the upwind march (upwind reconstruction on the unit mesh)
+  // work items of the reconstruction march (general() handles)
   dugks::Item* uitems = nullptr;
   int nuitems = 0;
-  int upm_rows = 0;  // rows per segment of the upwind march in use
+  int upm_rows = 0;  // rows per segment of the reconstruction march in use
   int seg_rows = 0;  // 0: automatic
   long long* step_base = nullptr;  // device: steps done
   long long steps = 0;             // host mirror
@@ -87,7 +87,7 @@ int fit_seg_rows(const std::vector<StripShape>& cs, long long budget);
 // Automatic segment length of a group of cases (fp64, walls: the group's
 // precision and boundary, which decide whether the two-row kernel applies).
 int auto_seg_rows(const std::vector<StripShape>& cs, long long capacity, bool fp64, bool walls);
-// Automatic segment length of the upwind march of a handle.
+// Automatic segment length of the reconstruction march of a handle.
 int auto_upm_rows(const dugks_handle* h);
 // Compute units of the current device.
 long long cu_count();

@@ -85,9 +85,8 @@ struct CaseDev {
   // equilibrium weights of the relaxation: cell (Eq. 29) 3h/(2tau+dt), face
   // (Eq. 28) h/(2tau+h); for f, and for g when tau_g is uniform
   double fb, ffb, gb, gfb;
-  // stretched mesh (nullptr: unit cells): per axis, x then y, four arrays
-  // of the axis length: width, distance to the previous centre, distance to
-  // the next centre, centre position (layout in mesh_axis())
+  // stretched mesh (nullptr: unit cells): per axis, x then y, kMeshArrays
+  // arrays of the axis length (layout in mesh_axis())
   const double* mesh;
   // non-finite flag of the case (device word): a step that produces a
   // non-finite phi, phi u or p in one of its cells stores 1 there; the host
@@ -138,11 +137,12 @@ struct StepArgs {
   int one_row;                 // every item is one row (seg_rows == 1): row kernel
   int two_row;                 // every item is two rows (seg_rows == 2): the two-row kernel
                                // for periodic FP32 cases, else the march
-  int upm_rows;                // rows per segment of the upwind march
+  int upm_rows;                // rows per segment of the reconstruction march
 };
 
-// The upwind march (unit mesh): strips of kUpmCols columns (a 64-lane wave
-// with two halo lanes on each side); segments of StepArgs::upm_rows rows.
+// The reconstruction march (upwind reconstruction, or a stretched mesh):
+// strips of kUpmCols columns (a 64-lane wave with two halo lanes on each
+// side); segments of StepArgs::upm_rows rows.
 constexpr int kUpmCols = 60;
 
 // slot of population q among the six crossing an x-face / a y-face (-1: none)
@@ -155,8 +155,8 @@ __host__ __device__ constexpr int up_yslot(int q) {
 
 // host-side launchers (dugks_kernels.hip)
 hipError_t launch_step(bool fp64, bool coupled, bool walls, const StepArgs& a, hipStream_t s);
-// the upwind march (upwind reconstruction on the unit or a stretched mesh,
-// central reconstruction on a stretched mesh; items of kUpmCols-column strips
+// the reconstruction march (upwind reconstruction on the unit or a stretched
+// mesh, central reconstruction on a stretched mesh; items of kUpmCols-column strips
 // and a.upm_rows-row segments) and its resident waves per CU
 hipError_t launch_step_upm(bool fp64, bool coupled, bool walls, bool mesh, bool central,
                            const StepArgs& a, hipStream_t s);
