@@ -158,6 +158,8 @@ void fill_case(dugks_handle* h) {
   C.dt = P.cfl * dl;
   C.h = 0.5 * C.dt;
   C.mesh = h->mesh ? h->dmesh : nullptr;
+  C.meshf = h->mesh ? reinterpret_cast<const float*>(h->dmesh + dugks::kMeshArrays * (size_t)(h->nx + h->ny))
+                    : nullptr;
   C.flag = h->dflag;
   C.t0 = 0.0;
   const double D = P.phi_H - P.phi_L;
@@ -241,9 +243,12 @@ int upload_case(dugks_handle* h) {
   fill_case(h);
   if (h->mesh) {  // the metrics depend on the y boundary
     const std::vector<double> m = mesh_metrics(h, h->hc.walls != 0);
+    const std::vector<float> mf(m.begin(), m.end());  // rounded to nearest
     HIPCHK(h, hipMemcpyAsync(h->dmesh, m.data(), m.size() * sizeof(double), hipMemcpyHostToDevice,
                              h->stream));
-    HIPCHK(h, hipStreamSynchronize(h->stream));  // m is a local
+    HIPCHK(h, hipMemcpyAsync(h->dmesh + m.size(), mf.data(), mf.size() * sizeof(float),
+                             hipMemcpyHostToDevice, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));  // m and mf are locals
   }
   HIPCHK(h, hipMemcpyAsync(h->dc, &h->hc, sizeof(CaseDev), hipMemcpyHostToDevice, h->stream));
   if (h->borrowed) {  // a pool case: the pool launches it with its own items, and
@@ -528,7 +533,9 @@ int dugks_set_mesh(dugks_handle* h, const double* dx, const double* dy) {
   for (double w : wy)
     if (!(w > 0.0 && std::isfinite(w))) return fail(h, DUGKS_EINVAL, "cell widths must be finite and > 0");
   if (!h->dmesh) {
-    hipError_t e = hipMalloc(&h->dmesh, dugks::kMeshArrays * (size_t)(h->nx + h->ny) * sizeof(double));
+    // the metric arrays in double, then rounded to float
+    hipError_t e = hipMalloc(&h->dmesh, dugks::kMeshArrays * (size_t)(h->nx + h->ny) *
+                                            (sizeof(double) + sizeof(float)));
     if (e != hipSuccess) {
       h->dmesh = nullptr;
       (void)hipGetLastError();

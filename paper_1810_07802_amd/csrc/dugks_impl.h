@@ -86,8 +86,10 @@ struct CaseDev {
   // (Eq. 28) h/(2tau+h); for f, and for g when tau_g is uniform
   double fb, ffb, gb, gfb;
   // stretched mesh (nullptr: unit cells): per axis, x then y, kMeshArrays
-  // arrays of the axis length (layout in mesh_axis())
+  // arrays of the axis length (layout in mesh_axis()); meshf holds the same
+  // arrays rounded to float, read by the FP32 kernels
   const double* mesh;
+  const float* meshf;
   // non-finite flag of the case (device word): a step that produces a
   // non-finite phi, phi u or p in one of its cells stores 1 there; the host
   // clears it at initialisation and reads it after synchronising
@@ -104,14 +106,17 @@ struct CaseDev {
 // and the interpolation weights of the next and previous centres at the
 // cell centre's mirror point, wp = hm / (hm + hp), wm = hp / (hm + hp).
 constexpr int kMeshArrays = 13;
-struct MeshAxis {
-  const double *w, *hm, *hp, *c, *iw, *ihm, *ihp, *cp, *cm, *ep, *em, *wp, *wm;
+template <typename S>
+struct MeshAxisT {
+  const S *w, *hm, *hp, *c, *iw, *ihm, *ihp, *cp, *cm, *ep, *em, *wp, *wm;
 };
-__host__ __device__ inline MeshAxis mesh_axis(const double* mesh, int nx, int ny, int axis) {
-  const double* b = mesh + (axis == 0 ? 0 : kMeshArrays * (long long)nx);
+using MeshAxis = MeshAxisT<double>;
+template <typename S>
+__host__ __device__ inline MeshAxisT<S> mesh_axis(const S* mesh, int nx, int ny, int axis) {
+  const S* b = mesh + (axis == 0 ? 0 : kMeshArrays * (long long)nx);
   const long long n = axis == 0 ? nx : ny;
-  return MeshAxis{b,         b + n,     b + 2 * n, b + 3 * n,  b + 4 * n,  b + 5 * n, b + 6 * n,
-                  b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
+  return MeshAxisT<S>{b,         b + n,     b + 2 * n, b + 3 * n,  b + 4 * n,  b + 5 * n, b + 6 * n,
+                      b + 7 * n, b + 8 * n, b + 9 * n, b + 10 * n, b + 11 * n, b + 12 * n};
 }
 
 enum VelKind { kVelUniform = 0, kVelRotation = 1, kVelShear = 2, kVelDeform = 3 };

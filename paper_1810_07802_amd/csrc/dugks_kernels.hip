@@ -1311,15 +1311,40 @@ __global__ void k_reset(long long* step_base, long long value, int* flag) {
 // the neighbouring rows weighted by the opposite distance so that the sum is
 // centred on the cell: exact on quadratics, and the unit-mesh stencils on
 // unit widths.
+// Metric arrays in the kernel's precision: FP32 kernels read the float copy
+// (one load and no conversion per value; a row's metrics stay uniform).
+template <typename T>
+__device__ __forceinline__ const T* mesh_of(const CaseDev& C);
+template <>
+__device__ __forceinline__ const float* mesh_of<float>(const CaseDev& C) { return C.meshf; }
+template <>
+__device__ __forceinline__ const double* mesh_of<double>(const CaseDev& C) { return C.mesh; }
+
+// The metric arrays are read through the constant address space: they do
+// not change during a launch, so a row's metrics (uniform over the wave)
+// load into scalar registers, and a column's load with global rather than
+// flat instructions.
+template <typename S>
+struct KMem {
+  typedef __attribute__((address_space(4))) S type;
+};
+template <typename S>
+using KAxis = MeshAxisT<typename KMem<S>::type>;
+template <typename S>
+__device__ __forceinline__ KAxis<S> kaxis(const S* mesh, int nx, int ny, int axis) {
+  return mesh_axis((const typename KMem<S>::type*)mesh, nx, ny, axis);
+}
+
 template <typename T>
 __device__ __forceinline__ void mesh_stencils(const CaseDev& C, const T (&ph)[3][3], int i, int j,
                                               T& gx, T& gy, T& lap) {
-  const MeshAxis X = mesh_axis(C.mesh, C.nx, C.ny, 0), Y = mesh_axis(C.mesh, C.nx, C.ny, 1);
+  const KAxis<T> X = kaxis(mesh_of<T>(C), C.nx, C.ny, 0);
+  const KAxis<T> Y = kaxis(mesh_of<T>(C), C.nx, C.ny, 1);
   // parabola weights of column i (x) and row j (y), and the weights of the
   // neighbouring rows (columns) in the centred sum
-  const T cpx = T(X.cp[i]), cmx = T(X.cm[i]), epx = T(X.ep[i]), emx = T(X.em[i]);
-  const T cpy = T(Y.cp[j]), cmy = T(Y.cm[j]), epy = T(Y.ep[j]), emy = T(Y.em[j]);
-  const T wpx = T(X.wp[i]), wmx = T(X.wm[i]), wpy = T(Y.wp[j]), wmy = T(Y.wm[j]);
+  const T cpx = X.cp[i], cmx = X.cm[i], epx = X.ep[i], emx = X.em[i];
+  const T cpy = Y.cp[j], cmy = Y.cm[j], epy = Y.ep[j], emy = Y.em[j];
+  const T wpx = X.wp[i], wmx = X.wm[i], wpy = Y.wp[j], wmy = Y.wm[j];
   T dxr[3], dxxr[3], dyc[3], dyyc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1644,10 +1669,17 @@ __device__ __forceinline__ T van_leer(T a, T b) {
 template <typename T>
 struct Met {
   T w, ihm, ihp, cp, cm, iw2;  // iw2 = 2 / w
-  __device__ static Met load(const MeshAxis& A, int k) {
-    return Met{T(A.w[k]), T(A.ihm[k]), T(A.ihp[k]), T(A.cp[k]), T(A.cm[k]), T(2.0 * A.iw[k])};
+  template <typename A>
+  __device__ static Met load(const A& ax, int k) {
+    return Met{ax.w[k], ax.ihm[k], ax.ihp[k], ax.cp[k], ax.cm[k], T(2) * ax.iw[k]};
   }
 };
+
+// s clamped to [-cap, cap] (cap >= 0): one median-of-three in float
+__device__ __forceinline__ float clamp_sym(float s, float cap) {
+  return __builtin_amdgcn_fmed3f(s, -cap, cap);
+}
+__device__ __forceinline__ double clamp_sym(double s, double cap) { return fmin(fmax(s, -cap), cap); }
 
 // Limited slope on a stretched mesh: van Leer of the one-sided slopes,
 // capped at twice the smaller one-sided difference over the cell's width, so
@@ -1657,9 +1689,7 @@ struct Met {
 template <typename T>
 __device__ __forceinline__ T lim_mesh(T b, T f, const Met<T>& m) {
   const T s = van_leer(b * m.ihm, f * m.ihp);
-  const T ab = b < T(0) ? -b : b, af = f < T(0) ? -f : f;
-  const T cap = (ab < af ? ab : af) * m.iw2;
-  return s > cap ? cap : (s < -cap ? -cap : s);
+  return clamp_sym(s, fmin(fabs(b), fabs(f)) * m.iw2);
 }
 
 // ------------------------------ the reconstruction march
@@ -1729,17 +1759,22 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   Met<T> mx{};
   T dAx = T(0.5), dBx = T(0.5), iHx = T(1), axw = T(1);
   double xcen = xc, xeast = (double)ci + 1.0;
-  MeshAxis Y{};
+  // Y: the metrics in the kernel's precision; Yd: the double arrays, for
+  // positions (a prescribed velocity)
+  KAxis<T> Y{};
+  KAxis<double> Yd{};
   if constexpr (MESH) {
-    const MeshAxis X = mesh_axis(C.mesh, nx, ny, 0);
-    Y = mesh_axis(C.mesh, nx, ny, 1);
+    const KAxis<T> X = kaxis(mesh_of<T>(C), nx, ny, 0);
+    const KAxis<double> Xd = kaxis(C.mesh, nx, ny, 0);
+    Y = kaxis(mesh_of<T>(C), nx, ny, 1);
+    Yd = kaxis(C.mesh, nx, ny, 1);
     mx = Met<T>::load(X, ci);
     dAx = T(0.5) * mx.w;
     dBx = nbr_r(dAx);
-    iHx = T(1) / (dAx + dBx);
-    axw = T(X.iw[ci]);
-    xcen = X.c[ci];
-    xeast = X.c[ci] + 0.5 * X.w[ci];
+    iHx = mx.ihp;  // 1 / (dAx + dBx), the distance to the next centre
+    axw = X.iw[ci];
+    xcen = Xd.c[ci];
+    xeast = Xd.c[ci] + 0.5 * Xd.w[ci];
   }
   auto ymet = [&](int r) { return Met<T>::load(Y, row_idx(r, ny, walls)); };
 
@@ -1792,7 +1827,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     if constexpr (MESH) {
       T gx, gy, lap;
       mesh_stencils<T>(C, ph, ci, rr, gx, gy, lap);
-      cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, R.f, R.g, R.hx, R.hy, xcen, Y.c[rr], tn, rd.cell, tp);
+      cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, R.f, R.g, R.hx, R.hy, xcen, Yd.c[rr], tn, rd.cell, tp);
     } else {
       cell_stage<T, CPL>(C, ph, R.f, R.g, R.hx, R.hy, xc, (double)rr + 0.5, tn, rd.cell, tp);
     }
@@ -1942,7 +1977,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int rr = row_idx(r, ny, walls);
     T fo[9], go[9];
     face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, mean(a.gx), mean(a.gy), mean(a.mu), mean(a.Dx),
-                       mean(a.Dy), fbar, gbar, xeast, MESH ? Y.c[rr] : (double)rr + 0.5,
+                       mean(a.Dy), fbar, gbar, xeast, MESH ? Yd.c[rr] : (double)rr + 0.5,
                        tn + C.h, fo, go);
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
@@ -1957,9 +1992,10 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     // half heights of the two rows and 1 / their sum (stretched mesh)
     T dA = T(0.5), dB = T(0.5), iH = T(1);
     if (MESH) {
-      dA = T(0.5) * ymet(r).w;
+      const Met<T> ma = ymet(r);
+      dA = T(0.5) * ma.w;
       dB = T(0.5) * ymet(r + 1).w;
-      iH = T(1) / (dA + dB);
+      iH = ma.ihp;  // 1 / (dA + dB)
     }
     T fbar[9], gbar[9];
 #pragma unroll
@@ -2013,14 +2049,14 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int rr = row_idx(r, ny, walls);
     face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, mean(a.gx, b.gx), mean(a.gy, b.gy),
                        mean(a.mu, b.mu), mean(a.Dx, b.Dx), mean(a.Dy, b.Dy), fbar, gbar, xcen,
-                       MESH ? Y.c[rr] + 0.5 * Y.w[rr] : (double)rr + 1.0, tn + C.h, u.fsf, u.fsg);
+                       MESH ? Yd.c[rr] + 0.5 * Yd.w[rr] : (double)rr + 1.0, tn + C.h, u.fsf, u.fsg);
   };
   // Central reconstruction on a stretched mesh: the face value is the
   // interpolation of the two cells less h xi times the normal difference and
-  // the interpolated tangential slope, for every population (the
-  // zero-weighted terms included). The parabola slopes are cheap, so they
-  // are formed where used: the y slopes of row r from the rows below (d) and
-  // above (u), the x slopes from the neighbouring lanes.
+  // the interpolated tangential slope (terms whose velocity component is
+  // zero are left out). The parabola slopes are cheap, so they are formed
+  // where used: the y slopes of row r from the rows below (d) and above (u),
+  // the x slopes from the neighbouring lanes.
   auto yslope_c = [&](int r, T dv, T cv, T uv, const Met<T>& my) {
     if (WALLS && r == 0) return (uv - cv) * my.ihp;
     if (WALLS && r == ny - 1) return (cv - dv) * my.ihm;
@@ -2032,10 +2068,14 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const Met<T> my = ymet(r);
     const T dA = dAx, dB = dBx, iH = iHx;
     auto rec = [&](int q, T dv, T a, T uv) {
+      const T aB = nbr_r(a);
+      const T af = (dB * a + dA * aB) * iH;
+      if (EX[q] == 0 && EY[q] == 0) return af;
+      const T dn = (aB - a) * iH;
+      if (EY[q] == 0) return af - h * (T(EX[q]) * dn);
       const T st = yslope_c(r, dv, a, uv, my);
-      const T aB = nbr_r(a), stB = nbr_r(st);
-      const T af = (dB * a + dA * aB) * iH, dn = (aB - a) * iH;
-      const T dtg = (dB * st + dA * stB) * iH;
+      const T dtg = (dB * st + dA * nbr_r(st)) * iH;
+      if (EX[q] == 0) return af - h * (T(EY[q]) * dtg);
       return af - h * (T(EX[q]) * dn + T(EY[q]) * dtg);
     };
     T fbar[9], gbar[9];
@@ -2057,7 +2097,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int rr = row_idx(r, ny, walls);
     T fo[9], go[9];
     face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, mean(a.gx), mean(a.gy), mean(a.mu), mean(a.Dx),
-                       mean(a.Dy), fbar, gbar, xeast, Y.c[rr], tn + C.h, fo, go);
+                       mean(a.Dy), fbar, gbar, xeast, Yd.c[rr], tn + C.h, fo, go);
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       if (EX[q] == 0) continue;
@@ -2066,11 +2106,16 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     }
   };
   auto yface_c = [&](int r, const URow<T, CPL>& d, URow<T, CPL>& u) {
-    const T dA = T(0.5) * ymet(r).w, dB = T(0.5) * ymet(r + 1).w;
-    const T iH = T(1) / (dA + dB);
+    const Met<T> ma = ymet(r);
+    const T dA = T(0.5) * ma.w, dB = T(0.5) * ymet(r + 1).w;
+    const T iH = ma.ihp;  // 1 / (dA + dB)
     auto rec = [&](int q, T aA, T aB) {
-      const T af = (dB * aA + dA * aB) * iH, dn = (aB - aA) * iH;
+      const T af = (dB * aA + dA * aB) * iH;
+      if (EX[q] == 0 && EY[q] == 0) return af;
+      const T dn = (aB - aA) * iH;
+      if (EX[q] == 0) return af - h * (T(EY[q]) * dn);
       const T dtg = (dB * xslope_c(aA) + dA * xslope_c(aB)) * iH;
+      if (EY[q] == 0) return af - h * (T(EX[q]) * dtg);
       return af - h * (T(EY[q]) * dn + T(EX[q]) * dtg);
     };
     T fbar[9], gbar[9];
@@ -2093,7 +2138,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int rr = row_idx(r, ny, walls);
     face_df<T, CPL, 1>(C, phif, N0f, Jxf, Jyf, mean(a.gx, b.gx), mean(a.gy, b.gy),
                        mean(a.mu, b.mu), mean(a.Dx, b.Dx), mean(a.Dy, b.Dy), fbar, gbar, xcen,
-                       Y.c[rr] + 0.5 * Y.w[rr], tn + C.h, u.fsf, u.fsg);
+                       Yd.c[rr] + 0.5 * Yd.w[rr], tn + C.h, u.fsf, u.fsg);
   };
 
   // update of output row r (record m) from its faces: east m.fx, west the
@@ -2104,7 +2149,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     char* orow = row_ptr(out, rr, RB);
     const T dt = T(C.dt);
     // face length over cell area: 1/dx and 1/dy (1 on unit cells)
-    const T ay = MESH ? T(Y.iw[rr]) : T(1);
+    const T ay = MESH ? Y.iw[rr] : T(1);
     // the flux difference of population q (plane off: 0 f, 6 g) from its
     // east/west and upper/lower faces
     auto flux = [&](int q, int off, T fn, T fs) {
