@@ -1335,16 +1335,22 @@ __device__ __forceinline__ KAxis<S> kaxis(const S* mesh, int nx, int ny, int axi
   return mesh_axis((const typename KMem<S>::type*)mesh, nx, ny, axis);
 }
 
+// The stencil weights of one cell along one axis: the parabola weights and
+// the weights of the neighbouring rows (columns) in the centred sum.
 template <typename T>
-__device__ __forceinline__ void mesh_stencils(const CaseDev& C, const T (&ph)[3][3], int i, int j,
+struct StW {
+  T cp, cm, ep, em, wp, wm;
+  template <typename A>
+  __device__ static StW load(const A& ax, int k) {
+    return StW{ax.cp[k], ax.cm[k], ax.ep[k], ax.em[k], ax.wp[k], ax.wm[k]};
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ void mesh_stencils(const StW<T>& x, const StW<T>& y, const T (&ph)[3][3],
                                               T& gx, T& gy, T& lap) {
-  const KAxis<T> X = kaxis(mesh_of<T>(C), C.nx, C.ny, 0);
-  const KAxis<T> Y = kaxis(mesh_of<T>(C), C.nx, C.ny, 1);
-  // parabola weights of column i (x) and row j (y), and the weights of the
-  // neighbouring rows (columns) in the centred sum
-  const T cpx = X.cp[i], cmx = X.cm[i], epx = X.ep[i], emx = X.em[i];
-  const T cpy = Y.cp[j], cmy = Y.cm[j], epy = Y.ep[j], emy = Y.em[j];
-  const T wpx = X.wp[i], wmx = X.wm[i], wpy = Y.wp[j], wmy = Y.wm[j];
+  const T cpx = x.cp, cmx = x.cm, epx = x.ep, emx = x.em, wpx = x.wp, wmx = x.wm;
+  const T cpy = y.cp, cmy = y.cm, epy = y.ep, emy = y.em, wpy = y.wp, wmy = y.wm;
   T dxr[3], dxxr[3], dyc[3], dyyc[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -1359,6 +1365,13 @@ __device__ __forceinline__ void mesh_stencils(const CaseDev& C, const T (&ph)[3]
   gy = T(2.0 / 3.0) * dyc[1] + T(1.0 / 3.0) * (wpx * dyc[2] + wmx * dyc[0]);
   lap = T(5.0 / 6.0) * (dxxr[1] + dyyc[1]) + T(1.0 / 6.0) * (wpy * dxxr[2] + wmy * dxxr[0]) +
         T(1.0 / 6.0) * (wpx * dyyc[2] + wmx * dyyc[0]);
+}
+// ... of cell (i, j), the weights read from the metric arrays
+template <typename T>
+__device__ __forceinline__ void mesh_stencils(const CaseDev& C, const T (&ph)[3][3], int i, int j,
+                                              T& gx, T& gy, T& lap) {
+  mesh_stencils<T>(StW<T>::load(kaxis(mesh_of<T>(C), C.nx, C.ny, 0), i),
+                   StW<T>::load(kaxis(mesh_of<T>(C), C.nx, C.ny, 1), j), ph, gx, gy, lap);
 }
 
 // Gradient and Laplacian of the init and readout kernels: the unit-mesh
@@ -1753,37 +1766,76 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   const int j0 = it.seg * seg_rows;
   const int j1 = min(j0 + seg_rows, ny);
   const T h = T(C.h), hal = T(0.5) - h;
-  // stretched mesh: the metrics of the lane's column (its east face: half
-  // widths dAx, dBx of the two cells and 1 / (dAx + dBx); the face position),
-  // and those of a row (uniform over the wave) through ymet()
-  Met<T> mx{};
-  T dAx = T(0.5), dBx = T(0.5), iHx = T(1), axw = T(1);
+  // stretched mesh: the metrics of the lane's column (1/hm, 1/hp, 2/w, w/2
+  // and the stencil weights cp, cm, ep, em, wp, wm) through xmv(). The
+  // upwind march keeps them in LDS (xm, one row per value, written once and
+  // read where used through an offset the compiler cannot hoist, so that
+  // they hold no registers across the march; the LDS comes from a second
+  // x-face slot), the central one in registers, as does the FP64 march with
+  // walls, whose LDS would then hold one wave less per CU (both measured
+  // slower with the LDS copy). Those of a row (uniform over the wave) come
+  // through ymet(). Y: the row metrics in the kernel's precision; Yd: the
+  // double arrays, for positions (a prescribed velocity).
+  constexpr bool XLDS = MESH && !CEN && !(WALLS && sizeof(T) == 8);
   double xcen = xc, xeast = (double)ci + 1.0;
-  // Y: the metrics in the kernel's precision; Yd: the double arrays, for
-  // positions (a prescribed velocity)
   KAxis<T> Y{};
   KAxis<double> Yd{};
+  __shared__ T xm[XLDS ? 10 : 1][64];
+  T xr[10] = {};
+  T dBr = T(0.5);  // the east neighbour's half width (metrics in registers)
   if constexpr (MESH) {
     const KAxis<T> X = kaxis(mesh_of<T>(C), nx, ny, 0);
     const KAxis<double> Xd = kaxis(C.mesh, nx, ny, 0);
     Y = kaxis(mesh_of<T>(C), nx, ny, 1);
     Yd = kaxis(C.mesh, nx, ny, 1);
-    mx = Met<T>::load(X, ci);
-    dAx = T(0.5) * mx.w;
-    dBx = nbr_r(dAx);
-    iHx = mx.ihp;  // 1 / (dAx + dBx), the distance to the next centre
-    axw = X.iw[ci];
+    xr[0] = X.ihm[ci];
+    xr[1] = X.ihp[ci];
+    xr[2] = T(2) * X.iw[ci];
+    xr[3] = T(0.5) * X.w[ci];
+    xr[4] = X.cp[ci];
+    xr[5] = X.cm[ci];
+    xr[6] = X.ep[ci];
+    xr[7] = X.em[ci];
+    xr[8] = X.wp[ci];
+    xr[9] = X.wm[ci];
+    if constexpr (XLDS) {
+#pragma unroll
+      for (int k = 0; k < 10; ++k) xm[k][lane] = xr[k];
+    } else {
+      dBr = nbr_r(xr[3]);
+    }
     xcen = Xd.c[ci];
     xeast = Xd.c[ci] + 0.5 * Xd.w[ci];
   }
+  auto xmv = [&](int k) {
+    if constexpr (XLDS) {
+      unsigned off = (unsigned)lane * (unsigned)sizeof(T);
+      asm volatile("" : "+v"(off));
+      return *(const T*)((const char*)&xm[k][0] + off);
+    } else {
+      return xr[k];
+    }
+  };
+  // the limiter metrics of the lane's column (1/hm, 1/hp, 2/w)
+  auto xmet = [&]() { return Met<T>{T(0), xmv(0), xmv(1), T(0), T(0), xmv(2)}; };
   auto ymet = [&](int r) { return Met<T>::load(Y, row_idx(r, ny, walls)); };
+  // the east face of the lane's cell: the half widths of the two cells and
+  // 1 / their sum (the distance to the next centre)
+  struct XFace {
+    T dA, dB, iH;
+  };
+  auto xfm = [&]() {
+    if (!MESH) return XFace{T(0.5), T(0.5), T(1)};
+    const T dA = xmv(3);
+    return XFace{dA, XLDS ? nbr_r(dA) : dBr, xmv(1)};
+  };
 
   __shared__ T stash[3][18][64];  // tilde-plus of the rows staged by the last three passes
   // x-faces of the last rows formed (crossing populations): two slots by
-  // pass parity, or with walls one slot (the update of a row then reads its
-  // x-faces before the next row's replace them; it saves the LDS of an
-  // eighth wave per CU there)
-  constexpr int XS = WALLS ? 1 : 2;
+  // pass parity, or one slot with walls or the column metrics in LDS (the
+  // update of a row then reads its x-faces before the next row's replace
+  // them; it saves the LDS of an eighth wave per CU)
+  constexpr int XS = (WALLS || XLDS) ? 1 : 2;
   __shared__ T fxs[XS][12][64];
   __shared__ T topn[6][64];       // row ny - 2, populations 2..4 (f, g): the top wall face
 
@@ -1826,7 +1878,8 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     T tp[18];
     if constexpr (MESH) {
       T gx, gy, lap;
-      mesh_stencils<T>(C, ph, ci, rr, gx, gy, lap);
+      const StW<T> wx{xmv(4), xmv(5), xmv(6), xmv(7), xmv(8), xmv(9)};
+      mesh_stencils<T>(wx, StW<T>::load(Y, rr), ph, gx, gy, lap);
       cell_core<T, CPL>(C, ph[1][1], gx, gy, lap, R.f, R.g, R.hx, R.hy, xcen, Yd.c[rr], tn, rd.cell, tp);
     } else {
       cell_stage<T, CPL>(C, ph, R.f, R.g, R.hx, R.hy, xc, (double)rr + 0.5, tn, rd.cell, tp);
@@ -1840,6 +1893,8 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         topn[1 + q][lane] = rd.cell.gb[q];
       }
     }
+    Met<T> mx{};
+    if (MESH && !CEN) mx = xmet();
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
       if (CEN || EX[q] == 0) continue;  // the central slopes are formed where used
@@ -1856,8 +1911,9 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   // x central differences (stretched mesh: x slopes of the parabola) of the
   // diagonal planes of a wall row (wall faces)
   auto xdiffs = [&](const Cell<T>& c, T (&txf)[9], T (&txg)[9]) {
+    const T cpx = MESH ? xmv(4) : T(0), cmx = MESH ? xmv(5) : T(0);
     auto d = [&](T v) {
-      if (MESH) return mx.cp * (nbr_r(v) - v) + mx.cm * (v - nbr_l(v));
+      if (MESH) return cpx * (nbr_r(v) - v) + cmx * (v - nbr_l(v));
       return nbr_r(v) - nbr_l(v);
     };
 #pragma unroll
@@ -1918,6 +1974,8 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   // the x-face east of each cell of row r (record m; the east cell is lane + 1)
   // into LDS
   auto xface = [&](int r, int xs, const URow<T, CPL>& m) {
+    const XFace xf = xfm();
+    const T dAx = xf.dA, dBx = xf.dB, iHx = xf.iH;
     T fbar[9], gbar[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -2062,11 +2120,12 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     if (WALLS && r == ny - 1) return (cv - dv) * my.ihm;
     return my.cp * (uv - cv) + my.cm * (cv - dv);
   };
-  auto xslope_c = [&](T v) { return mx.cp * (nbr_r(v) - v) + mx.cm * (v - nbr_l(v)); };
+  auto xslope_c = [&](T v) { return xmv(4) * (nbr_r(v) - v) + xmv(5) * (v - nbr_l(v)); };
   auto xface_c = [&](int r, int xs, const URow<T, CPL>& d, const URow<T, CPL>& m,
                      const URow<T, CPL>& u) {
     const Met<T> my = ymet(r);
-    const T dA = dAx, dB = dBx, iH = iHx;
+    const XFace xf = xfm();
+    const T dA = xf.dA, dB = xf.dB, iH = xf.iH;
     auto rec = [&](int q, T dv, T a, T uv) {
       const T aB = nbr_r(a);
       const T af = (dB * a + dA * aB) * iH;
@@ -2150,6 +2209,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const T dt = T(C.dt);
     // face length over cell area: 1/dx and 1/dy (1 on unit cells)
     const T ay = MESH ? Y.iw[rr] : T(1);
+    const T axw = MESH ? T(0.5) * xmv(2) : T(1);  // 1 / w of the lane's column
     // the flux difference of population q (plane off: 0 f, 6 g) from its
     // east/west and upper/lower faces
     auto flux = [&](int q, int off, T fn, T fs) {
@@ -2206,7 +2266,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const bool ex0 = !(walls && (r0 < 0 || r0 >= ny));
     const bool exm = !(walls && (rm < 0 || rm >= ny));
     if (!CEN && ex0 && r0 >= j0 - 1) yslopes(r0, Rm, R0, R1);
-    if (!WALLS && r0 >= j0 && r0 < j1) {
+    if (XS == 2 && r0 >= j0 && r0 < j1) {
       if constexpr (CEN) xface_c(r0, p & 1, Rm, R0, R1);
       else xface(r0, p & 1, R0);
     }
@@ -2227,11 +2287,11 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         wall_face_g<T, true, MESH>(C, R0.cell, R1.cell, txf, txg, dyw, idy, R0.fsf, R0.fsg);
       }
     }
-    // the update of row s - 2 (with walls it reads its x-faces from LDS
-    // before the x-faces of row s - 1 replace them)
+    // the update of row s - 2 (with one x-face slot it reads its x-faces
+    // from LDS before the x-faces of row s - 1 replace them)
     if (rm >= j0 && rm < j1) {
       const int ms = (p + 1) % 3;  // slot of row s - 2
-      const int xs = WALLS ? 0 : (p + 1) & 1;
+      const int xs = XS == 1 ? 0 : (p + 1) & 1;
       if (WALLS && rm == ny - 1) {
         // top wall: the next row inward (row ny - 2) from LDS
         Cell<T> cn;
@@ -2254,7 +2314,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         update(rm, ms, xs, Rm, R0.fsf, R0.fsg);
       }
     }
-    if (WALLS && ex0 && r0 >= j0 && r0 < j1) {
+    if (XS == 1 && ex0 && r0 >= j0 && r0 < j1) {
       if constexpr (CEN) xface_c(r0, 0, Rm, R0, R1);
       else xface(r0, 0, R0);
     }
