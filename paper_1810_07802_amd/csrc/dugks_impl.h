@@ -90,6 +90,13 @@ struct CaseDev {
   // arrays rounded to float, read by the FP32 kernels
   const double* mesh;
   const float* meshf;
+  // the constants the FP32 kernels use, rounded to float on the host (they
+  // then load into scalar registers instead of being converted into vector
+  // ones); hdt = dt / 2, beta4 = 4 beta
+  struct F32 {
+    float h, dt, hdt, phi_L, phi_H, phibar, drho, gx, gy, Gx, Gy, theta_c, tau_f, kappa, beta4, ffb,
+        fb, eps_n2;
+  } f32;
   // non-finite flag of the case (device word): a step that produces a
   // non-finite phi, phi u or p in one of its cells stores 1 there; the host
   // clears it at initialisation and reads it after synchronising

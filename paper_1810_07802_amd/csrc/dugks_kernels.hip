@@ -43,6 +43,29 @@ __device__ constexpr int EY[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
 // one ulp of 4/9, 1/9, 1/36 so that they sum to exactly 1 (w1 = 4 w2 and
 // w0 = 1 - 4 w1 - 4 w2 are exact); with the rounded weights the zeroth moment
 // of every equilibrium would carry a 7e-9 bias per step into sum phi.
+// A case constant in the kernel's precision: its float copy (rounded on
+// the host) in FP32 kernels, the double field in FP64 ones.
+template <typename T>
+__device__ __forceinline__ T ck(float f, double d);
+template <>
+__device__ __forceinline__ float ck<float>(float f, double) { return f; }
+template <>
+__device__ __forceinline__ double ck<double>(float, double d) { return d; }
+
+// Kernels whose vector registers are not the limit narrow the constants
+// themselves (vector conversions at the kernel's start) instead of taking
+// the float copies into scalar registers: measured faster where scalar
+// registers are the scarcer ones (the unit-mesh kernels; the copies pay off
+// in the stretched-mesh marches, whose upwind form otherwise spills vector
+// registers).
+__device__ __forceinline__ void narrow_in_kernel(CaseDev& C) {
+  C.f32 = CaseDev::F32{float(C.h),       float(C.dt),      float(0.5 * C.dt), float(C.phi_L),
+                       float(C.phi_H),   float(C.phibar),  float(C.drho),     float(C.gx),
+                       float(C.gy),      float(C.Gx),      float(C.Gy),       float(C.theta_c),
+                       float(C.tau_f),   float(C.kappa),   float(4.0 * C.beta), float(C.ffb),
+                       float(C.fb),      float(C.eps_n2)};
+}
+
 template <typename T>
 __device__ __forceinline__ constexpr T wq(int q);
 template <>
@@ -143,7 +166,7 @@ __device__ __forceinline__ void g_relax(const CaseDev& C, double phi, double rho
 // unit vector, and 0 where the gradient is exactly 0).
 template <typename T>
 __device__ __forceinline__ void normal(const CaseDev& C, T gx, T gy, T& nx, T& ny) {
-  const T m2 = gx * gx + gy * gy + T(C.eps_n2);
+  const T m2 = gx * gx + gy * gy + ck<T>(C.f32.eps_n2, C.eps_n2);
   const T inv = m2 > T(0) ? rsqrt_t(m2) : T(0);
   nx = gx * inv;
   ny = gy * inv;
@@ -252,12 +275,12 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
                                           const T (&ft)[9], const T (&gt)[9],
                                           T hist_x, T hist_y, double xc, double yc,
                                           double tn, Cell<T>& o, T (&tp)[18]) {
-  const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
-  const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;  // Eq. 4
-  const T theta = T(C.theta_c) * dA * dB;                                            // Eq. 6
+  const T dA = phi - ck<T>(C.f32.phi_H, C.phi_H), dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
+  const T mu = ck<T>(C.f32.beta4, 4.0 * C.beta) * dA * dB * (phi - ck<T>(C.f32.phibar, C.phibar)) - ck<T>(C.f32.kappa, C.kappa) * lap;  // Eq. 4
+  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * dA * dB;                                            // Eq. 6
   T nxv, nyv;
   normal<T>(C, gx, gy, nxv, nyv);
-  const T dt = T(C.dt);
+  const T dt = ck<T>(C.f32.dt, C.dt);
 
   T u, v, p = T(0);
   double rhoD = rho_of(C, (double)phi);
@@ -265,14 +288,14 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
     const T rho = T(rhoD);
     const T irho = T(inv_rho<T>(rhoD));
     const T rg = T(rhoD - C.rho_ref);
-    const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
-    const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
+    const T Fx = mu * gx + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
+    const T Fy = mu * gy + (ck<T>(C.f32.Gy, C.Gy) + rg * ck<T>(C.f32.gy, C.gy));
     const T mx = (gt[1] + gt[2] + gt[8]) - (gt[4] + gt[5] + gt[6]);
     const T my = (gt[2] + gt[3] + gt[4]) - (gt[6] + gt[7] + gt[8]);
     const T m0 = ((gt[1] + gt[2]) + (gt[3] + gt[4])) + ((gt[5] + gt[6]) + (gt[7] + gt[8]));
     u = (mx + T(0.5) * dt * Fx) * irho;  // Eq. 32
     v = (my + T(0.5) * dt * Fy) * irho;
-    const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
+    const T drx = ck<T>(C.f32.drho, C.drho) * gx, dry = ck<T>(C.f32.drho, C.drho) * gy;
     const T uu = u * u + v * v;
     p = T(0.6) * m0 + T(0.3) * dt * (u * drx + v * dry) - T(0.4) * rho * uu;  // Eq. 33
     // g: equilibrium (Eq. 17) and source (Eq. 19), bar-plus and tilde-plus
@@ -305,7 +328,7 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
   const T Dx = (hx - hist_x) * T(1.0 / C.dt), Dy = (hy - hist_y) * T(1.0 / C.dt);
   {
     // f^eq + tau_f S^f = w (phi + xi . V) with V = 3 phi u + tau_f (theta n + 3 D)
-    const T fbc = T(C.fb), fbc43 = T(4.0 / 3.0 * C.fb), tauf = T(C.tau_f);
+    const T fbc = ck<T>(C.f32.fb, C.fb), fbc43 = T(4.0 / 3.0 * C.fb), tauf = ck<T>(C.f32.tau_f, C.tau_f);
     const T Vx = T(3) * phi * u + tauf * (theta * nxv + T(3) * Dx);
     const T Vy = T(3) * phi * v + tauf * (theta * nyv + T(3) * Dy);
     auto relax = [&](int q, T target) {
@@ -373,8 +396,8 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
                                         const T (&fbar)[9], const T (&gbar)[9],
                                         double xf, double yf, double tf,
                                         T (&fo)[9], T (&go)[9]) {
-  const T h = T(C.h);
-  const T theta = T(C.theta_c) * (phif - T(C.phi_H)) * (phif - T(C.phi_L));
+  const T h = ck<T>(C.f32.h, C.h);
+  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * (phif - ck<T>(C.f32.phi_H, C.phi_H)) * (phif - ck<T>(C.f32.phi_L, C.phi_L));
   T nxv, nyv;
   normal<T>(C, gxf, gyf, nxv, nyv);
   T u, v;
@@ -382,11 +405,11 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
     const double rhoD = rho_of(C, (double)phif);
     const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
     const T rg = T(rhoD - C.rho_ref);
-    const T Fx = muf * gxf + (T(C.Gx) + rg * T(C.gx));
-    const T Fy = muf * gyf + (T(C.Gy) + rg * T(C.gy));
+    const T Fx = muf * gxf + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
+    const T Fy = muf * gyf + (ck<T>(C.f32.Gy, C.Gy) + rg * ck<T>(C.f32.gy, C.gy));
     u = (Jxf + T(0.5) * h * Fx) * irho;
     v = (Jyf + T(0.5) * h * Fy) * irho;
-    const T drx = T(C.drho) * gxf, dry = T(C.drho) * gyf;
+    const T drx = ck<T>(C.f32.drho, C.drho) * gxf, dry = ck<T>(C.f32.drho, C.drho) * gyf;
     const T uu = u * u + v * v;
     const T p = T(0.6) * N0f + T(0.3) * h * (u * drx + v * dry) - T(0.4) * rho * uu;
     double gbD, tauD;
@@ -405,7 +428,7 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
   } else {
     presc_vel<T>(C, xf, yf, tf, u, v);
   }
-  const T fbc = T(C.ffb), tauf = T(C.tau_f);
+  const T fbc = ck<T>(C.f32.ffb, C.ffb), tauf = ck<T>(C.f32.tau_f, C.tau_f);
   const T Vx = T(3) * phif * u + tauf * (theta * nxv + T(3) * Dxf);
   const T Vy = T(3) * phif * v + tauf * (theta * nyv + T(3) * Dyf);
 #pragma unroll
@@ -432,21 +455,21 @@ __device__ __forceinline__ void wall_face_g(const CaseDev& C, const Cell<T>& c,
                                             const Cell<T>& cn, const T (&txf)[9],
                                             const T (&txg)[9], T dyw_m, T idy, T (&fo)[9],
                                             T (&go)[9]) {
-  const T h = T(C.h);
+  const T h = ck<T>(C.f32.h, C.h);
   const T dyw = MESH ? dyw_m : (BOTTOM ? T(-0.5) : T(0.5));
   const T phiw = c.phi;
   const double rhoD = rho_of(C, (double)phiw);
-  const T theta = T(C.theta_c) * (phiw - T(C.phi_H)) * (phiw - T(C.phi_L));
+  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * (phiw - ck<T>(C.f32.phi_H, C.phi_H)) * (phiw - ck<T>(C.f32.phi_L, C.phi_L));
   const T gxw = c.gx;
   T nxv, nyv;
   normal<T>(C, gxw, T(0), nxv, nyv);
   const T rg = T(rhoD - C.rho_ref);
-  const T Fx = c.mu * gxw + (T(C.Gx) + rg * T(C.gx));
-  const T Fy = T(C.Gy) + rg * T(C.gy);
+  const T Fx = c.mu * gxw + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
+  const T Fy = ck<T>(C.f32.Gy, C.Gy) + rg * ck<T>(C.f32.gy, C.gy);
   double gbD, tauD;
   g_relax<true>(C, (double)phiw, rhoD, gbD, tauD);
   const T gb = T(gbD), tau = T(tauD);
-  const T fbc = T(C.ffb), tauf = T(C.tau_f);
+  const T fbc = ck<T>(C.f32.ffb, C.ffb), tauf = ck<T>(C.f32.tau_f, C.tau_f);
   const T Vx = tauf * (theta * nxv + T(3) * c.Dx);
 #pragma unroll
   for (int q = 1; q < 9; ++q) {
@@ -616,7 +639,7 @@ template <typename T, bool CPL>
 __device__ __forceinline__ void y_face(const CaseDev& C, const RowData<T, CPL>& D,
                                        const RowData<T, CPL>& U, double xf, double yf,
                                        double tf, T (&fo)[9], T (&go)[9]) {
-  const T h = T(C.h), hq = T(0.25) * T(C.h);
+  const T h = ck<T>(C.f32.h, C.h), hq = T(0.25) * ck<T>(C.f32.h, C.h);
   // mean minus h e_y times the normal slope, as weights of the two cells:
   // (1/2 + h e_y) below + (1/2 - h e_y) above
   const T cp = T(0.5) + h, cm = T(0.5) - h;
@@ -691,7 +714,7 @@ __device__ __forceinline__ void row_xface(const CaseDev& C, int k, int ny, int c
   // x-face east of the own cell: L = own lane, R = lane + 1
   {
     const Cell<T>& L = cur_r.cell;
-    const T h = T(C.h), hq = T(0.25) * T(C.h);
+    const T h = ck<T>(C.f32.h, C.h), hq = T(0.25) * ck<T>(C.f32.h, C.h);
     // (1/2 + h e_x) own + (1/2 - h e_x) right neighbour (mean minus h e_x
     // times the normal slope)
     const T cp = T(0.5) + h, cm = T(0.5) - h;
@@ -752,7 +775,7 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
   const T(&fs_f)[9] = prv.fnf;
   const T(&fs_g)[9] = prv.fng;
   char* orow = row_ptr(out, row_idx(k, ny, walls), RB);
-  const T dt = T(C.dt);
+  const T dt = ck<T>(C.f32.dt, C.dt);
   T nv[NV];  // new tilde f, tilde g, history
   T phin = T(0);
 #pragma unroll
@@ -949,7 +972,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   // descriptor pointer, they would be re-read after every store of the march
   // (the stores could alias them as far as the compiler knows).
   const CaseDev* Cg = A.cases + it.c;
-  const CaseDev C = *Cg;
+  CaseDev C = *Cg;
+  narrow_in_kernel(C);
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
   // wall cases march upwards only (see item_dir): one copy of the march
@@ -1008,7 +1032,8 @@ __global__ __launch_bounds__(192, sizeof(T) == 4 ? 2 : 1) void k_step_row(StepAr
   const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (idx >= A.nitems) return;  // uniform over the work group
   const Item it = A.items[idx];
-  const CaseDev C = A.cases[it.c];
+  CaseDev C = A.cases[it.c];
+  narrow_in_kernel(C);
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;  // uniform over the work group
 
@@ -1151,7 +1176,8 @@ __global__ __launch_bounds__(256) void k_step_row2(StepArgs A) {
   const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (idx >= A.nitems) return;  // uniform over the work group
   const Item it = A.items[idx];
-  const CaseDev C = A.cases[it.c];
+  CaseDev C = A.cases[it.c];
+  narrow_in_kernel(C);
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;  // uniform over the work group
 
@@ -1430,12 +1456,12 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
   T gx, gy, lap;
   cell_stencils<T>(C, ph, i, j, gx, gy, lap);
   const T phi = ph[1][1];
-  const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
-  const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
-  const T theta = T(C.theta_c) * dA * dB;
+  const T dA = phi - ck<T>(C.f32.phi_H, C.phi_H), dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
+  const T mu = ck<T>(C.f32.beta4, 4.0 * C.beta) * dA * dB * (phi - ck<T>(C.f32.phibar, C.phibar)) - ck<T>(C.f32.kappa, C.kappa) * lap;
+  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * dA * dB;
   T nxv, nyv;
   normal<T>(C, gx, gy, nxv, nyv);
-  const T hdt = T(0.5 * C.dt);
+  const T hdt = ck<T>(C.f32.hdt, 0.5 * C.dt);
   T u, v;
   if (CPL) {
     u = u0 ? T(u0[c]) : T(0);
@@ -1444,9 +1470,9 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
     const double rhoD = rho_of(C, (double)phi);
     const T rho = T(rhoD);
     const T rg = T(rhoD - C.rho_ref);
-    const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
-    const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
-    const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
+    const T Fx = mu * gx + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
+    const T Fy = mu * gy + (ck<T>(C.f32.Gy, C.Gy) + rg * ck<T>(C.f32.gy, C.gy));
+    const T drx = ck<T>(C.f32.drho, C.drho) * gx, dry = ck<T>(C.f32.drho, C.drho) * gy;
     const T uu = u * u + v * v;
     const T a0 = u * drx + v * dry, b0 = u * Fx + v * Fy;
 #pragma unroll
@@ -1497,22 +1523,22 @@ __device__ __forceinline__ void cell_macros(const CaseDev& C, const T* __restric
   if (CPL) {
     T gx, gy, lap;
     cell_stencils<T>(C, ph, i, j, gx, gy, lap);
-    const T dA = phi - T(C.phi_H), dB = phi - T(C.phi_L);
-    const T mu = T(4.0 * C.beta) * dA * dB * (phi - T(C.phibar)) - T(C.kappa) * lap;
+    const T dA = phi - ck<T>(C.f32.phi_H, C.phi_H), dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
+    const T mu = ck<T>(C.f32.beta4, 4.0 * C.beta) * dA * dB * (phi - ck<T>(C.f32.phibar, C.phibar)) - ck<T>(C.f32.kappa, C.kappa) * lap;
     const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
     const T rg = T(rhoD - C.rho_ref);
-    const T Fx = mu * gx + (T(C.Gx) + rg * T(C.gx));
-    const T Fy = mu * gy + (T(C.Gy) + rg * T(C.gy));
+    const T Fx = mu * gx + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
+    const T Fy = mu * gy + (ck<T>(C.f32.Gy, C.Gy) + rg * ck<T>(C.f32.gy, C.gy));
     T g[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) g[q] = st[state_index(val_g(q), i, j, C.nx, rv, CPL)];
     const T mx = (g[1] + g[2] + g[8]) - (g[4] + g[5] + g[6]);
     const T my = (g[2] + g[3] + g[4]) - (g[6] + g[7] + g[8]);
     const T m0 = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
-    const T dt = T(C.dt);
+    const T dt = ck<T>(C.f32.dt, C.dt);
     u = (mx + T(0.5) * dt * Fx) * irho;
     v = (my + T(0.5) * dt * Fy) * irho;
-    const T drx = T(C.drho) * gx, dry = T(C.drho) * gy;
+    const T drx = ck<T>(C.f32.drho, C.drho) * gx, dry = ck<T>(C.f32.drho, C.drho) * gy;
     p = T(0.6) * m0 + T(0.3) * dt * (u * drx + v * dry) - T(0.4) * rho * (u * u + v * v);
   } else {
     double xc, yc;
@@ -1765,7 +1791,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   const double xc = (double)ci + 0.5;
   const int j0 = it.seg * seg_rows;
   const int j1 = min(j0 + seg_rows, ny);
-  const T h = T(C.h), hal = T(0.5) - h;
+  const T h = ck<T>(C.f32.h, C.h), hal = T(0.5) - h;
   // stretched mesh: the metrics of the lane's column (1/hm, 1/hp, 2/w, w/2
   // and the stencil weights cp, cm, ep, em, wp, wm) through xmv(). The
   // upwind march keeps them in LDS (xm, one row per value, written once and
@@ -2206,7 +2232,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
                     const T (&fng)[9]) {
     const int rr = row_idx(r, ny, walls);
     char* orow = row_ptr(out, rr, RB);
-    const T dt = T(C.dt);
+    const T dt = ck<T>(C.f32.dt, C.dt);
     // face length over cell area: 1/dx and 1/dy (1 on unit cells)
     const T ay = MESH ? Y.iw[rr] : T(1);
     const T axw = MESH ? T(0.5) * xmv(2) : T(1);  // 1 / w of the lane's column
@@ -2355,7 +2381,8 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) 
   const int idx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (idx >= A.nitems) return;
   const Item it = A.items[idx];
-  const CaseDev C = A.cases[it.c];
+  CaseDev C = A.cases[it.c];
+  if (!MESH) narrow_in_kernel(C);
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
   upm_march<T, CPL, WALLS, MESH, CEN>(C, it, n, A.upm_rows);
