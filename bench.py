@@ -72,8 +72,9 @@ def parse():
                     help="run only the timed 4096x4096 workload (for profilers)")
     ap.add_argument("--profile-upwind", action="store_true",
                     help="only the upwind leg on 4096^2 (for rocprofv3)")
-    ap.add_argument("--profile-mesh", action="store_true",
-                    help="only the stretched-mesh central leg on 4096^2 (for rocprofv3)")
+    ap.add_argument("--profile-mesh", nargs="?", const="central", choices=("central", "upwind"),
+                    help="only the stretched-mesh leg on 4096^2 in this reconstruction "
+                         "(default central; for rocprofv3)")
     ap.add_argument("--upwind-steps", type=int, default=50)
     ap.add_argument("--profile-copy", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (calibrates the "
@@ -205,11 +206,12 @@ def roofline(cells, steps, seconds, prec, workload=None):
             "bytes_per_launch": per_launch, "launch_us": round(t_launch * 1e6, 3)}
 
 
-def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100):
+def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100, workload=None):
     """Steps of case `c` (coupled FP32) with the upwind reconstruction, or
     on a stretched mesh `mesh` = (dx, dy) in either reconstruction (the
     reconstruction march), replayed from HIP graphs (see timed()). The HBM
-    fraction is quoted at the method's 160 B per cell."""
+    fraction is quoted at the method's 160 B per cell; `workload` names the
+    committed counter line whose bytes per cell are reported beside it."""
     s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", "fp32")
     s.set_stream(torch.cuda.current_stream().cuda_stream)
     if mesh is not None:
@@ -224,6 +226,9 @@ def timed_recon(torch, D, c, steps, warmup, recon="upwind", mesh=None, chunk=100
          "achieved_GBps": round(ach, 1), "frac_hbm": round(ach / HBM_PEAK_GBS, 4),
          "bytes_per_cell": B_PER_CELL["fp32"], "nonfinite": d["nonfinite"]}
     r["seg_rows"] = s.seg_rows  # segment of the reconstruction march
+    if workload is not None:
+        tr = counter_traffic(workload)
+        r["counter_bytes_per_cell"] = None if tr is None else round(tr / cells, 1)
     return r
 
 
@@ -397,8 +402,9 @@ def main():
     if args.profile_mesh:
         cl = W.bubble(L=4096, R=1024, steps=0)
         mesh = (W.stretched_widths(4096, 0.3), W.stretched_widths(4096, 0.3, phase=1.0))
-        print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, stretched mesh, central",
-                          **timed_recon(torch, D, cl, args.upwind_steps, 3, "central", mesh)}),
+        print(json.dumps({"workload": f"bubble 4096x4096 coupled FP32, stretched mesh, {args.profile_mesh}",
+                          **timed_recon(torch, D, cl, args.upwind_steps, 3, args.profile_mesh, mesh,
+                                        workload=f"mesh4096_{args.profile_mesh}")}),
               flush=True)
         return
     if args.profile_batch:
@@ -418,7 +424,8 @@ def main():
     if args.profile_upwind:
         cl = W.bubble(L=4096, R=1024, steps=0)
         print(json.dumps({"workload": "bubble 4096x4096 coupled FP32, upwind reconstruction",
-                          **timed_recon(torch, D, cl, args.upwind_steps, 3)}), flush=True)
+                          **timed_recon(torch, D, cl, args.upwind_steps, 3, workload="upwind4096")}),
+              flush=True)
         return
     if args.profile_kernel:
         c = W.bubble(L=128, R=32)
@@ -529,7 +536,7 @@ def main():
                         "to 100 steps",
             "bubble128": timed_recon(torch, D, c, min(args.small_steps, 5000), 100),
             "bubble4096": timed_recon(torch, D, W.bubble(L=4096, R=1024, steps=0),
-                                           args.upwind_steps, 5)}
+                                           args.upwind_steps, 5, workload="upwind4096")}
         progress("upwind done")
         # stretched tensor-product mesh, both reconstructions
         cm = W.bubble(L=4096, R=1024, steps=0)
@@ -538,8 +545,10 @@ def main():
             "workload": "stationary bubble 4096x4096 on a stretched mesh (widths 1 + 0.3 sin, "
                         "both axes), coupled FP32, one reconstruction-march kernel per step, "
                         "replayed from HIP graphs of up to 100 steps",
-            "central": timed_recon(torch, D, cm, args.upwind_steps, 5, "central", mesh),
-            "upwind": timed_recon(torch, D, cm, args.upwind_steps, 5, "upwind", mesh)}
+            "central": timed_recon(torch, D, cm, args.upwind_steps, 5, "central", mesh,
+                                   workload="mesh4096_central"),
+            "upwind": timed_recon(torch, D, cm, args.upwind_steps, 5, "upwind", mesh,
+                                  workload="mesh4096_upwind")}
         progress("mesh done")
         if args.serve_requests > 0:
             rec["served"] = served_stream(torch, D, W, args.serve_requests, args.serve_sample)
