@@ -194,10 +194,7 @@ void fill_case(dugks_handle* h) {
   C.ffb = C.h / (2.0 * C.tau_f + C.h);
   C.gb = 3.0 * C.h / (2.0 * C.tau_g_uniform + C.dt);
   C.gfb = C.h / (2.0 * C.tau_g_uniform + C.h);
-  auto f = [](double v) { return (float)v; };
-  C.f32 = CaseDev::F32{f(C.h),       f(C.dt),    f(0.5 * C.dt), f(C.phi_L), f(C.phi_H), f(C.phibar),
-                       f(C.drho),    f(C.gx),    f(C.gy),       f(C.Gx),    f(C.Gy),    f(C.theta_c),
-                       f(C.tau_f),   f(C.kappa), f(4.0 * C.beta), f(C.ffb), f(C.fb),    f(C.eps_n2)};
+  C.f32 = dugks::narrow_constants(C);
   C.step0 = 0;
   C.nsteps = LLONG_MAX;
 }

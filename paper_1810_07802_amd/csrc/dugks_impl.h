@@ -103,6 +103,17 @@ struct CaseDev {
   int* flag;
 };
 
+// The float copies of a case's constants (CaseDev::f32), rounded to nearest
+// from the double fields: the host fills them once, and kernels that keep
+// their constants in vector registers form them the same way at their start.
+__host__ __device__ inline CaseDev::F32 narrow_constants(const CaseDev& C) {
+  return CaseDev::F32{float(C.h),     float(C.dt),     float(0.5 * C.dt),   float(C.phi_L),
+                      float(C.phi_H), float(C.phibar), float(C.drho),       float(C.gx),
+                      float(C.gy),    float(C.Gx),     float(C.Gy),         float(C.theta_c),
+                      float(C.tau_f), float(C.kappa),  float(4.0 * C.beta), float(C.ffb),
+                      float(C.fb),    float(C.eps_n2)};
+}
+
 // Metric arrays of one axis of a stretched mesh, each of the axis length,
 // in this order: the width w, the distances hm and hp to the previous and
 // next centres, the centre c, and what the stencils derive from them (once,

@@ -58,13 +58,7 @@ __device__ __forceinline__ double ck<double>(float, double d) { return d; }
 // registers are the scarcer ones (the unit-mesh kernels; the copies pay off
 // in the stretched-mesh marches, whose upwind form otherwise spills vector
 // registers).
-__device__ __forceinline__ void narrow_in_kernel(CaseDev& C) {
-  C.f32 = CaseDev::F32{float(C.h),       float(C.dt),      float(0.5 * C.dt), float(C.phi_L),
-                       float(C.phi_H),   float(C.phibar),  float(C.drho),     float(C.gx),
-                       float(C.gy),      float(C.Gx),      float(C.Gy),       float(C.theta_c),
-                       float(C.tau_f),   float(C.kappa),   float(4.0 * C.beta), float(C.ffb),
-                       float(C.fb),      float(C.eps_n2)};
-}
+__device__ __forceinline__ void narrow_in_kernel(CaseDev& C) { C.f32 = narrow_constants(C); }
 
 template <typename T>
 __device__ __forceinline__ constexpr T wq(int q);
