@@ -1887,8 +1887,11 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const char* prow = row_ptr(in, row_idx(r, ny, walls), RB) + NV * PB;
     phi_lr(gload<T>(prow, lane_off((unsigned)ci * es)), gload<T>(prow, lane_off((unsigned)cx * es)), o);
   };
+  // x slope of the parabola through the lane's cell and its neighbours
+  // (central reconstruction on a stretched mesh)
+  auto xslope_c = [&](T v) { return xmv(4) * (nbr_r(v) - v) + xmv(5) * (v - nbr_l(v)); };
   // stage row r into rd (cell stage, tilde-plus to the stash slot, limited x
-  // slopes, x central differences)
+  // slopes, or with the central reconstruction the parabola ones)
   auto stage = [&](int r, int slot, const Raw& R, const T (&pm)[3], const T (&p0)[3],
                    const T (&pp)[3], URow<T, CPL>& rd) {
     const int rr = row_idx(r, ny, walls);
@@ -1917,7 +1920,12 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     if (MESH && !CEN) mx = xmet();
 #pragma unroll
     for (int q = 1; q < 9; ++q) {
-      if (CEN || EX[q] == 0) continue;  // the central slopes are formed where used
+      if (EX[q] == 0) continue;
+      if constexpr (CEN) {
+        rd.lxf[q] = xslope_c(rd.cell.fb[q]);
+        if (CPL) rd.lxg[q] = xslope_c(rd.cell.gb[q]);
+        continue;
+      }
       const T c = rd.cell.fb[q];
       rd.lxf[q] = MESH ? lim_mesh<T>(c - nbr_l(c), nbr_r(c) - c, mx)
                        : van_leer(c - nbr_l(c), nbr_r(c) - c);
@@ -2140,7 +2148,6 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     if (WALLS && r == ny - 1) return (cv - dv) * my.ihm;
     return my.cp * (uv - cv) + my.cm * (cv - dv);
   };
-  auto xslope_c = [&](T v) { return xmv(4) * (nbr_r(v) - v) + xmv(5) * (v - nbr_l(v)); };
   auto xface_c = [&](int r, int xs, const URow<T, CPL>& d, const URow<T, CPL>& m,
                      const URow<T, CPL>& u) {
     const Met<T> my = ymet(r);
@@ -2188,20 +2195,20 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const Met<T> ma = ymet(r);
     const T dA = T(0.5) * ma.w, dB = T(0.5) * ymet(r + 1).w;
     const T iH = ma.ihp;  // 1 / (dA + dB)
-    auto rec = [&](int q, T aA, T aB) {
+    auto rec = [&](int q, T aA, T aB, T sA, T sB) {
       const T af = (dB * aA + dA * aB) * iH;
       if (EX[q] == 0 && EY[q] == 0) return af;
       const T dn = (aB - aA) * iH;
       if (EX[q] == 0) return af - h * (T(EY[q]) * dn);
-      const T dtg = (dB * xslope_c(aA) + dA * xslope_c(aB)) * iH;
+      const T dtg = (dB * sA + dA * sB) * iH;
       if (EY[q] == 0) return af - h * (T(EX[q]) * dtg);
       return af - h * (T(EY[q]) * dn + T(EX[q]) * dtg);
     };
     T fbar[9], gbar[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-      fbar[q] = rec(q, d.cell.fb[q], u.cell.fb[q]);
-      gbar[q] = (CPL && q > 0) ? rec(q, d.cell.gb[q], u.cell.gb[q]) : T(0);
+      fbar[q] = rec(q, d.cell.fb[q], u.cell.fb[q], d.lxf[q], u.lxf[q]);
+      gbar[q] = (CPL && q > 0) ? rec(q, d.cell.gb[q], u.cell.gb[q], d.lxg[q], u.lxg[q]) : T(0);
     }
     const T phif = (fbar[0] + ((fbar[1] + fbar[2]) + (fbar[3] + fbar[4]))) +
                    ((fbar[5] + fbar[6]) + (fbar[7] + fbar[8]));
@@ -2280,11 +2287,16 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     const int slot = p % 3;
     phi_lr(raw.po, raw.pe, pc);
     const bool ex1 = !(walls && (s < 0 || s >= ny));
-    if (ex1) stage(s, slot, raw, pa, pb, pc, R1);
-    fetch(min(s + 2, j1 + 1), raw);
     const int r0 = s - 1, rm = s - 2;
     const bool ex0 = !(walls && (r0 < 0 || r0 >= ny));
     const bool exm = !(walls && (rm < 0 || rm >= ny));
+    // central: the y-face between rows s - 2 and s - 1 needs neither row s
+    // nor its slopes, so it comes first and the lower row's x slopes die
+    // before row s's are formed
+    const bool yf = rm >= j0 - 1 && rm < j1 && ex0 && exm;
+    if (CEN && yf) yface_c(rm, Rm, R0);
+    if (ex1) stage(s, slot, raw, pa, pb, pc, R1);
+    fetch(min(s + 2, j1 + 1), raw);
     if (!CEN && ex0 && r0 >= j0 - 1) yslopes(r0, Rm, R0, R1);
     if (XS == 2 && r0 >= j0 && r0 < j1) {
       if constexpr (CEN) xface_c(r0, p & 1, Rm, R0, R1);
@@ -2293,8 +2305,7 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
     // the face below row s - 1: between rows s - 2 and s - 1, or the bottom wall
     if (rm >= j0 - 1 && rm < j1) {
       if (ex0 && exm) {
-        if constexpr (CEN) yface_c(rm, Rm, R0);
-        else yface(rm, Rm, R0);
+        if constexpr (!CEN) yface(rm, Rm, R0);
       } else if (WALLS && rm == -1) {
         T txf[9], txg[9];
         xdiffs(R0.cell, txf, txg);
