@@ -1797,6 +1797,11 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   // through ymet(). Y: the row metrics in the kernel's precision; Yd: the
   // double arrays, for positions (a prescribed velocity).
   constexpr bool XLDS = MESH && !CEN && !(WALLS && sizeof(T) == 8);
+  // Values that a lane takes from its neighbour are mostly formed on the
+  // neighbour and moved once (x differences, east traces); the FP64
+  // periodic mesh march moves the inputs instead: the same bits, and
+  // measured, it then does not spill.
+  constexpr bool MOVE_IN = MESH && sizeof(T) == 8 && !WALLS;
   double xcen = xc, xeast = (double)ci + 1.0;
   KAxis<T> Y{};
   KAxis<double> Yd{};
@@ -1926,14 +1931,15 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
         if (CPL) rd.lxg[q] = xslope_c(rd.cell.gb[q]);
         continue;
       }
-      const T c = rd.cell.fb[q];
-      rd.lxf[q] = MESH ? lim_mesh<T>(c - nbr_l(c), nbr_r(c) - c, mx)
-                       : van_leer(c - nbr_l(c), nbr_r(c) - c);
-      if (CPL) {
-        const T cg = rd.cell.gb[q];
-        rd.lxg[q] = MESH ? lim_mesh<T>(cg - nbr_l(cg), nbr_r(cg) - cg, mx)
-                         : van_leer(cg - nbr_l(cg), nbr_r(cg) - cg);
-      }
+      // the backward difference of a lane is the forward one of the lane
+      // before it (the same subtraction, taken from that lane; see MOVE_IN)
+      auto lim = [&](T c) {
+        const T fwd = nbr_r(c) - c;
+        const T bwd = MOVE_IN ? c - nbr_l(c) : nbr_l(fwd);
+        return MESH ? lim_mesh<T>(bwd, fwd, mx) : van_leer(bwd, fwd);
+      };
+      rd.lxf[q] = lim(rd.cell.fb[q]);
+      if (CPL) rd.lxg[q] = lim(rd.cell.gb[q]);
     }
   };
   // x central differences (stretched mesh: x slopes of the parabola) of the
@@ -2008,8 +2014,25 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       const int en = EX[q], et = EY[q];
+      // a trace that starts in the east cell is formed on the east lane
+      // and moved over once (the same arithmetic as on this lane; see
+      // MOVE_IN)
       auto rec = [&](const T& a, const T& lx, const T& ly) {
-        if constexpr (MESH) {
+        if constexpr (MESH && !MOVE_IN) {
+          if (en > 0) {
+            T v = a + (dAx - h) * lx;
+            if (et != 0) v -= h * T(et) * ly;
+            return v;
+          }
+          if (en < 0) {
+            T v = a + (h - dAx) * lx;
+            if (et != 0) v -= h * T(et) * ly;
+            return nbr_r(v);
+          }
+          T vA = a;
+          if (et != 0) vA -= h * T(et) * ly;
+          return (dBx * vA + dAx * nbr_r(vA)) * iHx;
+        } else if constexpr (MESH) {
           if (en > 0) {
             T v = a + (dAx - h) * lx;
             if (et != 0) v -= h * T(et) * ly;
@@ -2033,9 +2056,9 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
             return v;
           }
           if (en < 0) {
-            T v = nbr_r(a) - hal * nbr_r(lx);
-            if (et != 0) v -= h * T(et) * nbr_r(ly);
-            return v;
+            T v = a - hal * lx;
+            if (et != 0) v -= h * T(et) * ly;
+            return nbr_r(v);
           }
           T v = T(0.5) * (a + nbr_r(a));
           if (et != 0) v -= h * T(et) * (T(0.5) * (ly + nbr_r(ly)));
