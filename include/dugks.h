@@ -286,7 +286,8 @@ int dugks_autotune(dugks_handle *h, int probe_steps, int *seg_rows,
                    double *us_per_step);
 
 /* Device bytes a handle of this shape holds (both state buffers). A
- * stretched mesh adds 104 (nx + ny) bytes of metrics. */
+ * stretched mesh adds 156 (nx + ny) bytes of metrics (13 arrays per axis in
+ * double and again in float). */
 size_t dugks_footprint_bytes(int nx, int ny, int precision, int model);
 
 /* Message of the last error on h (or of the last failed create when h is
