@@ -52,6 +52,25 @@ __device__ __forceinline__ float ck<float>(float f, double) { return f; }
 template <>
 __device__ __forceinline__ double ck<double>(float, double d) { return d; }
 
+// The phase-field terms of a cell: dA = phi - phi_H, dB = phi - phi_L, the
+// chemical potential (Eq. 4) and theta (Eq. 6).
+template <typename T>
+__device__ __forceinline__ void phase_terms(const CaseDev& C, T phi, T lap, T& dA, T& dB, T& mu,
+                                            T& theta) {
+  const T b4 = ck<T>(C.f32.beta4, 4.0 * C.beta), pbar = ck<T>(C.f32.phibar, C.phibar);
+  const T kap = ck<T>(C.f32.kappa, C.kappa), thc = ck<T>(C.f32.theta_c, C.theta_c);
+  dA = phi - ck<T>(C.f32.phi_H, C.phi_H);
+  dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
+  mu = b4 * dA * dB * (phi - pbar) - kap * lap;
+  theta = thc * dA * dB;
+}
+// theta (Eq. 6) of a face or wall value of phi
+template <typename T>
+__device__ __forceinline__ T theta_of(const CaseDev& C, T phi) {
+  const T thc = ck<T>(C.f32.theta_c, C.theta_c);
+  return thc * (phi - ck<T>(C.f32.phi_H, C.phi_H)) * (phi - ck<T>(C.f32.phi_L, C.phi_L));
+}
+
 // Kernels whose vector registers are not the limit narrow the constants
 // themselves (vector conversions at the kernel's start) instead of taking
 // the float copies into scalar registers: measured faster where scalar
@@ -269,9 +288,8 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
                                           const T (&ft)[9], const T (&gt)[9],
                                           T hist_x, T hist_y, double xc, double yc,
                                           double tn, Cell<T>& o, T (&tp)[18]) {
-  const T dA = phi - ck<T>(C.f32.phi_H, C.phi_H), dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
-  const T mu = ck<T>(C.f32.beta4, 4.0 * C.beta) * dA * dB * (phi - ck<T>(C.f32.phibar, C.phibar)) - ck<T>(C.f32.kappa, C.kappa) * lap;  // Eq. 4
-  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * dA * dB;                                            // Eq. 6
+  T dA, dB, mu, theta;  // Eqs. 4, 6
+  phase_terms<T>(C, phi, lap, dA, dB, mu, theta);
   T nxv, nyv;
   normal<T>(C, gx, gy, nxv, nyv);
   const T dt = ck<T>(C.f32.dt, C.dt);
@@ -391,7 +409,7 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
                                         double xf, double yf, double tf,
                                         T (&fo)[9], T (&go)[9]) {
   const T h = ck<T>(C.f32.h, C.h);
-  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * (phif - ck<T>(C.f32.phi_H, C.phi_H)) * (phif - ck<T>(C.f32.phi_L, C.phi_L));
+  const T theta = theta_of<T>(C, phif);
   T nxv, nyv;
   normal<T>(C, gxf, gyf, nxv, nyv);
   T u, v;
@@ -453,7 +471,7 @@ __device__ __forceinline__ void wall_face_g(const CaseDev& C, const Cell<T>& c,
   const T dyw = MESH ? dyw_m : (BOTTOM ? T(-0.5) : T(0.5));
   const T phiw = c.phi;
   const double rhoD = rho_of(C, (double)phiw);
-  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * (phiw - ck<T>(C.f32.phi_H, C.phi_H)) * (phiw - ck<T>(C.f32.phi_L, C.phi_L));
+  const T theta = theta_of<T>(C, phiw);
   const T gxw = c.gx;
   T nxv, nyv;
   normal<T>(C, gxw, T(0), nxv, nyv);
@@ -1450,9 +1468,8 @@ __global__ void k_init(const CaseDev* __restrict__ Cd, int buf, const double* __
   T gx, gy, lap;
   cell_stencils<T>(C, ph, i, j, gx, gy, lap);
   const T phi = ph[1][1];
-  const T dA = phi - ck<T>(C.f32.phi_H, C.phi_H), dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
-  const T mu = ck<T>(C.f32.beta4, 4.0 * C.beta) * dA * dB * (phi - ck<T>(C.f32.phibar, C.phibar)) - ck<T>(C.f32.kappa, C.kappa) * lap;
-  const T theta = ck<T>(C.f32.theta_c, C.theta_c) * dA * dB;
+  T dA, dB, mu, theta;
+  phase_terms<T>(C, phi, lap, dA, dB, mu, theta);
   T nxv, nyv;
   normal<T>(C, gx, gy, nxv, nyv);
   const T hdt = ck<T>(C.f32.hdt, 0.5 * C.dt);
@@ -1517,8 +1534,8 @@ __device__ __forceinline__ void cell_macros(const CaseDev& C, const T* __restric
   if (CPL) {
     T gx, gy, lap;
     cell_stencils<T>(C, ph, i, j, gx, gy, lap);
-    const T dA = phi - ck<T>(C.f32.phi_H, C.phi_H), dB = phi - ck<T>(C.f32.phi_L, C.phi_L);
-    const T mu = ck<T>(C.f32.beta4, 4.0 * C.beta) * dA * dB * (phi - ck<T>(C.f32.phibar, C.phibar)) - ck<T>(C.f32.kappa, C.kappa) * lap;
+    T dA, dB, mu, theta;
+    phase_terms<T>(C, phi, lap, dA, dB, mu, theta);
     const T rho = T(rhoD), irho = T(inv_rho<T>(rhoD));
     const T rg = T(rhoD - C.rho_ref);
     const T Fx = mu * gx + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
@@ -2163,9 +2180,10 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
   // Central reconstruction on a stretched mesh: the face value is the
   // interpolation of the two cells less h xi times the normal difference and
   // the interpolated tangential slope (terms whose velocity component is
-  // zero are left out). The parabola slopes are cheap, so they are formed
-  // where used: the y slopes of row r from the rows below (d) and above (u),
-  // the x slopes from the neighbouring lanes.
+  // zero are left out). The parabola slopes: the x slopes of a row are
+  // formed once when it is staged (in its record, for the y-faces below and
+  // above it), the y slopes of row r from the rows below (d) and above (u)
+  // where its x-face uses them.
   auto yslope_c = [&](int r, T dv, T cv, T uv, const Met<T>& my) {
     if (WALLS && r == 0) return (uv - cv) * my.ihp;
     if (WALLS && r == ny - 1) return (cv - dv) * my.ihm;
@@ -2485,15 +2503,19 @@ template <typename T, bool M, bool CEN>
 static int upm_occupancy(bool coupled, bool walls) {
   int nb = 0;
   hipError_t e;
-  if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, false, false, M, CEN>, kWave, 0);
-  else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, true, M, CEN>, kWave, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_upm<T, true, false, M, CEN>, kWave, 0);
+  auto occ = [&](const void* k) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kWave, 0);
+  };
+  if (!coupled) e = occ((const void*)k_upm<T, false, false, M, CEN>);
+  else if (walls) e = occ((const void*)k_upm<T, true, true, M, CEN>);
+  else e = occ((const void*)k_upm<T, true, false, M, CEN>);
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
 template <typename T>
 static int upm_occupancy_modes(bool coupled, bool walls, bool mesh, bool central) {
   if (!mesh) return upm_occupancy<T, false, false>(coupled, walls);
-  return central ? upm_occupancy<T, true, true>(coupled, walls) : upm_occupancy<T, true, false>(coupled, walls);
+  return central ? upm_occupancy<T, true, true>(coupled, walls)
+                 : upm_occupancy<T, true, false>(coupled, walls);
 }
 int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh, bool central) {
   return fp64 ? upm_occupancy_modes<double>(coupled, walls, mesh, central)
@@ -2504,14 +2526,15 @@ int upm_waves_per_cu(bool fp64, bool coupled, bool walls, bool mesh, bool centra
 int step_waves_per_cu(bool fp64, bool coupled, bool walls) {
   int nb = 0;
   hipError_t e;
+  auto occ = [&](const void* k) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kWave, 0); };
   if (fp64) {
-    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<double, false, false>, kWave, 0);
-    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<double, true, true>, kWave, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<double, true, false>, kWave, 0);
+    if (!coupled) e = occ((const void*)k_step<double, false, false>);
+    else if (walls) e = occ((const void*)k_step<double, true, true>);
+    else e = occ((const void*)k_step<double, true, false>);
   } else {
-    if (!coupled) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, false, false>, kWave, 0);
-    else if (walls) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, true, true>, kWave, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_step<float, true, false>, kWave, 0);
+    if (!coupled) e = occ((const void*)k_step<float, false, false>);
+    else if (walls) e = occ((const void*)k_step<float, true, true>);
+    else e = occ((const void*)k_step<float, true, false>);
   }
   return e == hipSuccess && nb > 0 ? nb : 1;
 }
@@ -2545,12 +2568,15 @@ hipError_t launch_macros(bool fp64, const CaseDev* dcase, const CaseDev& hc, lon
   dim3 block(128), grid((hc.nx + 127) / 128, hc.ny);
   const int buf = (hc.cur0 + (int)(local_step & 1)) & 1;
   const double t = hc.t0 + (double)local_step * hc.dt;
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+  };
   if (fp64) {
-    if (hc.coupled) hipLaunchKernelGGL((k_macros<double, true>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
-    else hipLaunchKernelGGL((k_macros<double, false>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+    if (hc.coupled) go(k_macros<double, true>);
+    else go(k_macros<double, false>);
   } else {
-    if (hc.coupled) hipLaunchKernelGGL((k_macros<float, true>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
-    else hipLaunchKernelGGL((k_macros<float, false>), grid, block, 0, s, dcase, buf, t, phi, u, v, p, rho);
+    if (hc.coupled) go(k_macros<float, true>);
+    else go(k_macros<float, false>);
   }
   return hipGetLastError();
 }
