@@ -1707,9 +1707,9 @@ __device__ __forceinline__ T van_leer(T a, T b) {
   // select where a b <= 0 (a + b may then be 0). In float the hardware
   // reciprocal (1 ulp) replaces the correctly rounded division, which takes
   // ten instructions and, as the arm of a branch, a divergent jump.
-  const T q = sizeof(T) == 4 ? T(2) * a * b * T(__builtin_amdgcn_rcpf(float(a + b)))
-                             : T(2) * a * b / (a + b);
-  return a * b > T(0) ? q : T(0);
+  const T ab = a * b;  // 2 a b below is exactly ab + ab
+  const T q = sizeof(T) == 4 ? (ab + ab) * T(__builtin_amdgcn_rcpf(float(a + b))) : (ab + ab) / (a + b);
+  return ab > T(0) ? q : T(0);
 }
 
 // Metrics of one cell along one axis of a stretched mesh: width, the
