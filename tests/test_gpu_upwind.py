@@ -78,6 +78,15 @@ def test_fp64_interface_only(vel):
     assert e["phi"] < 1e-12
 
 
+def test_fp32_interface_only():
+    """The interface-only model in FP32 with the upwind reconstruction: phi
+    within 1e-5 of the oracle after 400 steps of the smoothed deformation."""
+    c = W.smoothed_deformation(L0=96, Pe=96, M=0.02)
+    c["params"] = dict(c["params"], vel="deform", T_period=400.0, U0=0.02)
+    e, _, _ = compare("ac fp32", upwind(c), 400, "fp32")
+    assert e["phi"] < 1e-5
+
+
 def test_fp64_density_ratio_1000_driven_flow():
     c = upwind(W.random_coupled(100, 40, seed=5, rho_ratio=1000.0, U=0.01))
     e, _, _ = compare("ratio1000", c, 100)
