@@ -64,6 +64,26 @@ def test_nan_in_the_initial_phi_is_reported_at_the_next_sync(prec, seg, recon, w
     assert d["status"] == D.OK and d["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("recon", ["central", "upwind"])
+def test_nan_on_a_stretched_mesh_is_reported(prec, recon):
+    """The stretched-mesh marches flag a NaN in the initial phi the same way."""
+    c = W.bubble(L=48, R=12, steps=0)
+    print(f"numeric flag: {prec} {recon} stretched mesh", flush=True)
+    s = D.Solver(c["nx"], c["ny"], dict(c["params"], recon=recon), "coupled", prec)
+    s.set_stream(_stream().cuda_stream)
+    s.set_mesh(W.stretched_widths(48, 0.3), W.stretched_widths(48, 0.3, phase=1.0))
+    s.init(_poisoned(c))
+    s.step(3)
+    with pytest.raises(D.DugksError) as e:
+        s.sync()
+    assert e.value.code == D.ENUMERIC
+    s.init(c["phi"])
+    s.step(3)
+    s.sync()
+    assert s.diagnostics()["status"] == D.OK
+
+
 def test_a_clean_run_never_reports():
     c = W.bubble(L=64, R=16, steps=0)
     s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
