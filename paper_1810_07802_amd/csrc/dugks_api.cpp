@@ -847,6 +847,15 @@ struct dugks_batch {
   std::vector<CaseDev> hcases;
   std::map<int, hipGraphExec_t> graphs;
   std::string err = "no error";
+  // The cases run as two independent chains of launches: cases [0, half) on
+  // the batch's stream and [half, n) on `side`, forked from and joined to
+  // the batch's stream once per recorded sequence, so that the two chains'
+  // kernels overlap each other's start and drain. ofs[w][j] is where chain
+  // j's items of boundary group w start (items are case-major).
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  int half = 0;
+  int ofs[2][3] = {{0, 0, 0}, {0, 0, 0}};
 };
 
 namespace {
@@ -891,14 +900,37 @@ hipError_t build_items(dugks_batch* b) {
   std::vector<Item> it[2];
   b->one_row[0] = b->one_row[1] = 1;
   b->two_row[0] = b->two_row[1] = 1;
-  for (size_t k = 0; k < b->cases.size(); ++k) {
+  // the chains: the first case at which the running cell count reaches half
+  // of the batch's (none for a single case)
+  const size_t n = b->cases.size();
+  long long total = 0, run = 0;
+  for (auto* h : b->cases) total += h->n();
+  b->half = (int)n;
+  for (size_t k = 0; k + 1 < n && n >= 2; ++k) {
+    run += b->cases[k]->n();
+    if (2 * run >= total) {
+      b->half = (int)k + 1;
+      break;
+    }
+  }
+  if (n >= 2 && b->half == (int)n) b->half = (int)n - 1;
+  for (size_t k = 0; k < n; ++k) {
     const CaseDev& c = b->cases[k]->hc;
     const int w = c.walls ? 1 : 0;
+    if ((int)k == b->half) {
+      b->ofs[0][1] = (int)it[0].size();
+      b->ofs[1][1] = (int)it[1].size();
+    }
     if (b->seg[k] != 1) b->one_row[w] = 0;
     if (b->seg[k] != 2) b->two_row[w] = 0;
     const int nsegs = (c.ny + b->seg[k] - 1) / b->seg[k];
     for (int s = 0; s < nsegs; ++s)
       for (int x = 0; x < c.nstrips; ++x) it[w].push_back(Item{(int)k, x, s, dugks::item_dir(s, w == 1)});
+  }
+  for (int w = 0; w < 2; ++w) {
+    b->ofs[w][0] = 0;
+    if (b->half >= (int)n) b->ofs[w][1] = (int)it[w].size();
+    b->ofs[w][2] = (int)it[w].size();
   }
   for (int w = 0; w < 2; ++w) {
     if (b->items[w]) (void)hipFree(b->items[w]);
@@ -965,6 +997,12 @@ int ensure_built(dugks_batch* b) {
     e = hipMalloc(&b->step_base, sizeof(long long));
     if (e == hipSuccess) e = hipMemcpy(b->step_base, &b->gstep, sizeof(long long), hipMemcpyHostToDevice);
   }
+  if (e == hipSuccess && b->cases.size() >= 2 && !b->side) {
+    // default priority, like every stream here
+    e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming);
+  }
   if (e == hipSuccess) e = build_items(b);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -988,16 +1026,28 @@ int record_steps(dugks_batch* b, int nsteps) {
   StepArgs a{};
   a.cases = b->dcases;
   a.step_base = b->step_base;
+  const bool two = b->side && b->half < (int)b->cases.size();
+  if (two) {
+    BHIPCHK(b, hipEventRecord(b->fork, b->stream));
+    BHIPCHK(b, hipStreamWaitEvent(b->side, b->fork, 0));
+  }
   for (int k = 0; k < nsteps; ++k) {
     a.kofs = k;
-    for (int w = 0; w < 2; ++w) {
-      if (b->nitems[w] == 0) continue;
-      a.items = b->items[w];
-      a.nitems = b->nitems[w];
-      a.one_row = b->one_row[w];
-      a.two_row = b->two_row[w];
-      BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, w == 1, a, b->stream));
+    for (int j = 0; j < (two ? 2 : 1); ++j) {
+      for (int w = 0; w < 2; ++w) {
+        const int i0 = two ? b->ofs[w][j] : 0, i1 = two ? b->ofs[w][j + 1] : b->nitems[w];
+        if (i1 <= i0) continue;
+        a.items = b->items[w] + i0;
+        a.nitems = i1 - i0;
+        a.one_row = b->one_row[w];
+        a.two_row = b->two_row[w];
+        BHIPCHK(b, dugks::launch_step(b->fp64, b->coupled, w == 1, a, j ? b->side : b->stream));
+      }
     }
+  }
+  if (two) {
+    BHIPCHK(b, hipEventRecord(b->join, b->side));
+    BHIPCHK(b, hipStreamWaitEvent(b->stream, b->join, 0));
   }
   BHIPCHK(b, dugks::launch_advance(b->step_base, nsteps, b->stream));
   return DUGKS_OK;
@@ -1264,6 +1314,12 @@ int dugks_batch_destroy(dugks_batch* b) {
   for (int w = 0; w < 2; ++w)
     if (b->items[w]) (void)hipFree(b->items[w]);
   if (b->step_base) (void)hipFree(b->step_base);
+  if (b->side) {
+    (void)hipStreamSynchronize(b->side);
+    (void)hipStreamDestroy(b->side);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
   if (b->owns)
     for (auto* h : b->cases) dugks_destroy(h);
   delete b;
