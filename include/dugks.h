@@ -300,11 +300,15 @@ int dugks_destroy(dugks_handle *h);
 /* ---------------------------------------------------------------- batches
  * A batch advances several cases of the same precision and model together
  * (independent grids of uneven sizes, e.g. the spinodal runs of Sec. IV.C):
- * one kernel launch per step covers all of them (work items are the (case,
- * column strip, row segment) tiles of every case), and a step sequence can be
- * recorded once in a HIP graph and replayed. The cases are handles and stay
- * usable on their own (set_params, init, get_macros) between batch calls;
- * the batch works on the batch's stream. Work items are built at the first
+ * work items are the (case, column strip, row segment) tiles of every case,
+ * and a step sequence can be recorded once in a HIP graph and replayed. The
+ * cases are handles and stay usable on their own (set_params, init,
+ * get_macros) between batch calls; the batch works on the batch's stream.
+ * With two or more cases they run as two independent chains of launches,
+ * one per half of the cells (split between cases): one chain on the batch's
+ * stream, the other on a stream the batch owns (default priority), forked
+ * from and joined back to the batch's stream within each dugks_batch_step,
+ * so that work after the call on the batch's stream sees all cases done. Work items are built at the first
  * dugks_batch_step or dugks_batch_autotune, and again when a case's boundary
  * or explicit tile changes. Every case needs its parameters and state then
  * (ESTATE otherwise); the upwind reconstruction and stretched meshes are
