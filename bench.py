@@ -522,6 +522,8 @@ def main():
         rec["batched"] = {"workload": "spinodal decomposition, 64 cases of 64^2..512^2 "
                                       "(seed 1810), rho 1000:1, coupled FP32",
                           "cells": bc, "steps": args.batch_steps,
+                          "launch": "HIP graphs of 100 steps, each two independent chains of "
+                                    "step launches (the cases split at half the cells)",
                           "batched_graph_mlups": round(bc * args.batch_steps / tb / 1e6, 1),
                           "batched_graph_auto_tile_mlups": round(bc * args.batch_steps / tb_auto / 1e6, 1),
                           "tile_seg_rows": bt.tiles,
