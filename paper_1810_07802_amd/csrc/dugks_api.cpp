@@ -1309,15 +1309,13 @@ int dugks_batch_sync(dugks_batch* b) {
 int dugks_batch_destroy(dugks_batch* b) {
   if (!b) return DUGKS_OK;
   (void)hipStreamSynchronize(b->stream);
+  if (b->side) (void)hipStreamSynchronize(b->side);  // work left unjoined by an error
   for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.second);
   if (b->dcases) (void)hipFree(b->dcases);
   for (int w = 0; w < 2; ++w)
     if (b->items[w]) (void)hipFree(b->items[w]);
   if (b->step_base) (void)hipFree(b->step_base);
-  if (b->side) {
-    (void)hipStreamSynchronize(b->side);
-    (void)hipStreamDestroy(b->side);
-  }
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->fork) (void)hipEventDestroy(b->fork);
   if (b->join) (void)hipEventDestroy(b->join);
   if (b->owns)
