@@ -17,6 +17,7 @@ The same JSON line carries:
                 the counter bytes of the committed rocprofv3 profile
   copy_ceiling  what a plain device copy of the same bytes reaches
   small_grid    the 128^2 bubble (2.6 MB: cache-resident, latency-bound)
+  interface_only  the 100^2 diagonal translation, interface-only model, FP64
   rayleigh_taylor  the 256 x 1024 Rayleigh-Taylor case with walls (Sec. IV.D)
   batched       the spinodal batch (64 cases of 64^2..512^2): one graph of
                 batched launches vs one launch per case per step
@@ -494,6 +495,19 @@ def main():
             "fp64_mlups": round(cells * n64 / t64 / 1e6, 1)}
         del s, s64
         progress(f"small grid: {rec['small_grid']['mlups']} MLUPS")
+        # the interface-only model in FP64 (diagonal translation, 100^2)
+        c1 = W.diag_translation()
+        s1 = D.Solver(c1["nx"], c1["ny"], c1["params"], "ac", "fp64")
+        s1.set_stream(stream)
+        s1.init(c1["phi"], c1["u"], c1["v"], c1["p"])
+        t1, _ = timed(torch, s1.step, 2000, 200, 1000)
+        rec["interface_only"] = {
+            "workload": "diagonal translation 100x100, interface-only model (Sec. III.A), FP64 "
+                        "(cache-resident, latency-bound)",
+            "mlups": round(c1["nx"] * c1["ny"] * 2000 / t1 / 1e6, 1), "steps": 2000,
+            "us_per_step": round(t1 / 2000 * 1e6, 3), "seg_rows": s1.seg_rows}
+        del s1
+        progress(f"interface-only FP64: {rec['interface_only']['mlups']} MLUPS")
         # Rayleigh-Taylor with walls
         cr = W.rayleigh_taylor(steps=0)
         sr = D.Solver(cr["nx"], cr["ny"], cr["params"], "coupled", "fp32")
