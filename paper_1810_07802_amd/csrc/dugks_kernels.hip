@@ -131,8 +131,11 @@ __device__ __forceinline__ T nbr_l(T v) { return rot<0x13C>(v); }  // value of l
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
 
-// 1/rho in double. The float path refines a float reciprocal with one
-// Newton-Raphson step (relative error ~1e-14); the double path divides.
+// 1/r in double, for a positive r well inside the float range (a density,
+// a relaxation denominator). The float path refines a float reciprocal with
+// one Newton-Raphson step (relative error ~1e-14, far below what it is
+// narrowed to), a third of the instructions of a correctly rounded double
+// divide; the double path divides.
 template <typename T>
 __device__ __forceinline__ double inv_rho(double r);
 template <>
@@ -143,6 +146,12 @@ __device__ __forceinline__ double inv_rho<float>(double r) {
 template <>
 __device__ __forceinline__ double inv_rho<double>(double r) {
   return 1.0 / r;
+}
+// a / r with the reciprocal above
+template <typename T>
+__device__ __forceinline__ double div_pos(double a, double r) {
+  if constexpr (sizeof(T) == 4) return a * inv_rho<float>(r);
+  else return a / r;
 }
 
 // Density (Eq. 10) with s clamped to [0,1], in double.
@@ -156,8 +165,8 @@ __device__ __forceinline__ double rho_of(const CaseDev& C, double phi) {
 // equilibrium weight b and tau: cell (Eq. 29) b = 3h/(2tau+dt), face (Eq. 28)
 // b = h/(2tau+h); the source weight is tau b in both, and the weight of the
 // distribution itself is 1 - b, which the kernels use in the increment form
-// psi + b (psi^eq + tau S - psi).
-template <bool FACE>
+// psi + b (psi^eq + tau S - psi). The FP32 kernels divide with div_pos.
+template <typename T, bool FACE>
 __device__ __forceinline__ void g_relax(const CaseDev& C, double phi, double rho,
                                         double& b, double& tau) {
   if (C.visc_mode == kViscUniformNu) {
@@ -168,10 +177,10 @@ __device__ __forceinline__ void g_relax(const CaseDev& C, double phi, double rho
   double s = (phi - C.phi_L) * C.inv_dphi;
   s = fmin(fmax(s, 0.0), 1.0);
   double mu = (C.visc_mode == kViscReciprocal)
-                  ? 1.0 / (s * C.inv_mu_H + (1.0 - s) * C.inv_mu_L)
+                  ? inv_rho<T>(s * C.inv_mu_H + (1.0 - s) * C.inv_mu_L)
                   : s * C.mu_H + (1.0 - s) * C.mu_L;
-  tau = 3.0 * mu / rho;
-  b = FACE ? C.h / (2.0 * tau + C.h) : 3.0 * C.h / (2.0 * tau + C.dt);
+  tau = div_pos<T>(3.0 * mu, rho);
+  b = FACE ? div_pos<T>(C.h, 2.0 * tau + C.h) : div_pos<T>(3.0 * C.h, 2.0 * tau + C.dt);
 }
 
 // Unit normal n = grad phi / sqrt(|grad phi|^2 + eps^2): zero for a uniform
@@ -312,7 +321,7 @@ __device__ __forceinline__ void cell_core(const CaseDev& C, T phi, T gx, T gy, T
     p = T(0.6) * m0 + T(0.3) * dt * (u * drx + v * dry) - T(0.4) * rho * uu;  // Eq. 33
     // g: equilibrium (Eq. 17) and source (Eq. 19), bar-plus and tilde-plus
     double gbD, tauD;
-    g_relax<false>(C, (double)phi, rhoD, gbD, tauD);
+    g_relax<T, false>(C, (double)phi, rhoD, gbD, tauD);
     const T gb = T(gbD);
     const GTerms<T> s = g_terms<T>(u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy);
     // Eq. 29-30 as increments: bar+ = g + b e, tilde+ = g + (4/3) b e with
@@ -425,7 +434,7 @@ __device__ __forceinline__ void face_df(const CaseDev& C, T phif, T N0f, T Jxf, 
     const T uu = u * u + v * v;
     const T p = T(0.6) * N0f + T(0.3) * h * (u * drx + v * dry) - T(0.4) * rho * uu;
     double gbD, tauD;
-    g_relax<true>(C, (double)phif, rhoD, gbD, tauD);
+    g_relax<T, true>(C, (double)phif, rhoD, gbD, tauD);
     const T gb = T(gbD);
     const GTerms<T> s = g_terms<T>(u, v, uu, p, rho, T(tauD), drx, dry, Fx, Fy);
     // Eq. 28 in increment form, for the pairs of directions crossing the face
@@ -479,7 +488,7 @@ __device__ __forceinline__ void wall_face_g(const CaseDev& C, const Cell<T>& c,
   const T Fx = c.mu * gxw + (ck<T>(C.f32.Gx, C.Gx) + rg * ck<T>(C.f32.gx, C.gx));
   const T Fy = ck<T>(C.f32.Gy, C.Gy) + rg * ck<T>(C.f32.gy, C.gy);
   double gbD, tauD;
-  g_relax<true>(C, (double)phiw, rhoD, gbD, tauD);
+  g_relax<T, true>(C, (double)phiw, rhoD, gbD, tauD);
   const T gb = T(gbD), tau = T(tauD);
   const T fbc = ck<T>(C.f32.ffb, C.ffb), tauf = ck<T>(C.f32.tau_f, C.tau_f);
   const T Vx = tauf * (theta * nxv + T(3) * c.Dx);
