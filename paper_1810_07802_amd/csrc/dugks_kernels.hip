@@ -74,9 +74,10 @@ __device__ __forceinline__ T theta_of(const CaseDev& C, T phi) {
 // Kernels whose vector registers are not the limit narrow the constants
 // themselves (vector conversions at the kernel's start) instead of taking
 // the float copies into scalar registers: measured faster where scalar
-// registers are the scarcer ones (the unit-mesh kernels; the copies pay off
-// in the stretched-mesh marches, whose upwind form otherwise spills vector
-// registers).
+// registers are the scarcer ones (the periodic unit-mesh kernels). The
+// copies pay off where vector registers would otherwise spill: the
+// stretched-mesh marches and the central march with walls, whose spill
+// reloads inside the loop wait for the prefetched rows.
 __device__ __forceinline__ void narrow_in_kernel(CaseDev& C) { C.f32 = narrow_constants(C); }
 
 template <typename T>
@@ -994,7 +995,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_step(StepArgs A)
   // (the stores could alias them as far as the compiler knows).
   const CaseDev* Cg = A.cases + it.c;
   CaseDev C = *Cg;
-  narrow_in_kernel(C);
+  if (!WALLS) narrow_in_kernel(C);
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
   // wall cases march upwards only (see item_dir): one copy of the march
