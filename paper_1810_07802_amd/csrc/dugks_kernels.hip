@@ -76,8 +76,8 @@ __device__ __forceinline__ T theta_of(const CaseDev& C, T phi) {
 // the float copies into scalar registers: measured faster where scalar
 // registers are the scarcer ones (the periodic unit-mesh kernels). The
 // copies pay off where vector registers would otherwise spill: the
-// stretched-mesh marches and the central march with walls, whose spill
-// reloads inside the loop wait for the prefetched rows.
+// stretched-mesh marches and the marches with walls, whose spill reloads
+// inside the loop wait for the prefetched rows.
 __device__ __forceinline__ void narrow_in_kernel(CaseDev& C) { C.f32 = narrow_constants(C); }
 
 template <typename T>
@@ -2438,7 +2438,7 @@ __global__ __launch_bounds__(64, sizeof(T) == 4 ? 2 : 1) void k_upm(StepArgs A) 
   if (idx >= A.nitems) return;
   const Item it = A.items[idx];
   CaseDev C = A.cases[it.c];
-  if (!MESH) narrow_in_kernel(C);
+  if (!MESH && !WALLS) narrow_in_kernel(C);
   const long long n = *A.step_base + A.kofs - C.step0;
   if (n < 0 || n >= C.nsteps) return;
   upm_march<T, CPL, WALLS, MESH, CEN>(C, it, n, A.upm_rows);
