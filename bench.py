@@ -362,7 +362,7 @@ def large_solver(D, W, seg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
+        print("bench.py runs on one GPU: the library has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
