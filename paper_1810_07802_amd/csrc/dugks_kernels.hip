@@ -128,6 +128,30 @@ template <typename T>
 __device__ __forceinline__ T nbr_r(T v) { return rot<0x134>(v); }  // value of lane + 1
 template <typename T>
 __device__ __forceinline__ T nbr_l(T v) { return rot<0x13C>(v); }  // value of lane - 1
+// The same moves through the LDS unit's crossbar (ds_bpermute) where BP is
+// set (FP32): they take no VALU issue slot, at the LDS unit's latency. That
+// pays in the central march of the coupled model, whose issue is nearly
+// full. The interface-only march has far less arithmetic to hide the
+// latency behind, the reconstruction marches keep metrics in LDS and the
+// small-grid kernels are latency-bound: there the DPP moves are faster.
+template <bool BP, typename T>
+__device__ __forceinline__ T xr(T v) {  // value of lane + 1
+  if constexpr (BP && sizeof(T) == 4) {
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 1) & 63) << 2, __float_as_int(v)));
+  } else {
+    return nbr_r(v);
+  }
+}
+template <bool BP, typename T>
+__device__ __forceinline__ T xl(T v) {  // value of lane - 1
+  if constexpr (BP && sizeof(T) == 4) {
+    const int lane = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 63) & 63) << 2, __float_as_int(v)));
+  } else {
+    return nbr_l(v);
+  }
+}
 
 __device__ __forceinline__ float rsqrt_t(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double rsqrt_t(double x) { return 1.0 / sqrt(x); }
@@ -639,20 +663,20 @@ struct RowData {
   T fnf[9], fng[9];  // face distributions of the face above this row
 };
 
-template <typename T, bool CPL>
+template <typename T, bool CPL, bool BP = false>
 __device__ __forceinline__ void x_diffs(RowData<T, CPL>& r) {
   const int diag[4] = {2, 4, 6, 8};
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int q = diag[k];
-    r.txf[q] = nbr_r(r.cell.fb[q]) - nbr_l(r.cell.fb[q]);
-    if (CPL) r.txg[q] = nbr_r(r.cell.gb[q]) - nbr_l(r.cell.gb[q]);
+    r.txf[q] = xr<BP>(r.cell.fb[q]) - xl<BP>(r.cell.fb[q]);
+    if (CPL) r.txg[q] = xr<BP>(r.cell.gb[q]) - xl<BP>(r.cell.gb[q]);
   }
-  r.txMx = nbr_r(r.cell.Mx) - nbr_l(r.cell.Mx);
+  r.txMx = xr<BP>(r.cell.Mx) - xl<BP>(r.cell.Mx);
   if (CPL) {
-    r.txJx = nbr_r(r.cell.Jx) - nbr_l(r.cell.Jx);
-    r.txPxx = nbr_r(r.cell.Pxx) - nbr_l(r.cell.Pxx);
-    r.txPxy = nbr_r(r.cell.Pxy) - nbr_l(r.cell.Pxy);
+    r.txJx = xr<BP>(r.cell.Jx) - xl<BP>(r.cell.Jx);
+    r.txPxx = xr<BP>(r.cell.Pxx) - xl<BP>(r.cell.Pxx);
+    r.txPxy = xr<BP>(r.cell.Pxy) - xl<BP>(r.cell.Pxy);
   }
 }
 
@@ -722,7 +746,7 @@ __device__ __forceinline__ void y_diffs(const RowData<T, CPL>& up, const RowData
 // and k+1 (nxt); a bottom
 // wall face lands in prv.fnf/fng (the face below row k), a top one in
 // cur.fnf/fng (the face above).
-template <typename T, bool CPL, bool WALLS>
+template <typename T, bool CPL, bool WALLS, bool BP = false>
 __device__ __forceinline__ void row_xface(const CaseDev& C, int k, int ny, int ci, double tn,
                                           RowData<T, CPL>& prv, RowData<T, CPL>& cur_r,
                                           const RowData<T, CPL>& nxt, T (&fx_f)[9], T (&fx_g)[9]) {
@@ -746,31 +770,31 @@ __device__ __forceinline__ void row_xface(const CaseDev& C, int k, int ny, int c
       if (EX[q] == 0) continue;
       const T ey = T(EY[q]);
       const T cL = EX[q] > 0 ? cp : cm, cR = EX[q] > 0 ? cm : cp;
-      T vf = cL * L.fb[q] + cR * nbr_r(L.fb[q]);
-      if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + nbr_r(ty.f[q]));
+      T vf = cL * L.fb[q] + cR * xr<BP>(L.fb[q]);
+      if (EY[q] != 0) vf -= hq * ey * (ty.f[q] + xr<BP>(ty.f[q]));
       fbar[q] = vf;
       if (CPL) {
-        T vg = cL * L.gb[q] + cR * nbr_r(L.gb[q]);
-        if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + nbr_r(ty.g[q]));
+        T vg = cL * L.gb[q] + cR * xr<BP>(L.gb[q]);
+        if (EY[q] != 0) vg -= hq * ey * (ty.g[q] + xr<BP>(ty.g[q]));
         gbar[q] = vg;
       }
     }
-    const T phif = T(0.5) * (L.M0 + nbr_r(L.M0)) - h * (nbr_r(L.Mx) - L.Mx) -
-                   hq * (ty.My + nbr_r(ty.My));
+    const T phif = T(0.5) * (L.M0 + xr<BP>(L.M0)) - h * (xr<BP>(L.Mx) - L.Mx) -
+                   hq * (ty.My + xr<BP>(ty.My));
     T N0f = T(0), Jxf = T(0), Jyf = T(0);
     if (CPL) {
-      N0f = T(0.5) * (L.N0 + nbr_r(L.N0)) - h * (nbr_r(L.Jx) - L.Jx) -
-            hq * (ty.Jy + nbr_r(ty.Jy));
-      Jxf = T(0.5) * (L.Jx + nbr_r(L.Jx)) - h * (nbr_r(L.Pxx) - L.Pxx) -
-            hq * (ty.Pxy + nbr_r(ty.Pxy));
-      Jyf = T(0.5) * (L.Jy + nbr_r(L.Jy)) - h * (nbr_r(L.Pxy) - L.Pxy) -
-            hq * (ty.Pyy + nbr_r(ty.Pyy));
+      N0f = T(0.5) * (L.N0 + xr<BP>(L.N0)) - h * (xr<BP>(L.Jx) - L.Jx) -
+            hq * (ty.Jy + xr<BP>(ty.Jy));
+      Jxf = T(0.5) * (L.Jx + xr<BP>(L.Jx)) - h * (xr<BP>(L.Pxx) - L.Pxx) -
+            hq * (ty.Pxy + xr<BP>(ty.Pxy));
+      Jyf = T(0.5) * (L.Jy + xr<BP>(L.Jy)) - h * (xr<BP>(L.Pxy) - L.Pxy) -
+            hq * (ty.Pyy + xr<BP>(ty.Pyy));
     }
-    const T gxf = T(0.5) * (L.gx + nbr_r(L.gx));
-    const T gyf = T(0.5) * (L.gy + nbr_r(L.gy));
-    const T muf = T(0.5) * (L.mu + nbr_r(L.mu));
-    const T Dxf = T(0.5) * (L.Dx + nbr_r(L.Dx));
-    const T Dyf = T(0.5) * (L.Dy + nbr_r(L.Dy));
+    const T gxf = T(0.5) * (L.gx + xr<BP>(L.gx));
+    const T gyf = T(0.5) * (L.gy + xr<BP>(L.gy));
+    const T muf = T(0.5) * (L.mu + xr<BP>(L.mu));
+    const T Dxf = T(0.5) * (L.Dx + xr<BP>(L.Dx));
+    const T Dyf = T(0.5) * (L.Dy + xr<BP>(L.Dy));
     const int kr = row_idx(k, ny, walls);
     face_df<T, CPL, 0>(C, phif, N0f, Jxf, Jyf, gxf, gyf, muf, Dxf, Dyf, fbar, gbar,
                        (double)ci + 1.0, (double)kr + 0.5, tn + C.h, fx_f, fx_g);
@@ -784,7 +808,7 @@ __device__ __forceinline__ void row_xface(const CaseDev& C, int k, int ny, int c
 // Update of output row k (Eq. 24) and its stores. cur.fnf/fng hold the face
 // above the row, prv.fnf/fng the face below, fx the x-faces east of each
 // cell (the west face is the left lane's), tp(q) the tilde-plus values.
-template <typename T, bool CPL, bool OPQ, typename TP>
+template <typename T, bool CPL, bool OPQ, bool BP = false, typename TP>
 __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int nx, int walls,
                                            int ci, bool store, char* out, long long RB,
                                            long long PB,
@@ -803,7 +827,7 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
 #pragma unroll
   for (int q = 0; q < 9; ++q) {
     T J = T(0);
-    if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - nbr_l(fx_f[q]));
+    if (EX[q] != 0) J += T(EX[q]) * (fx_f[q] - xl<BP>(fx_f[q]));
     if (EY[q] != 0) J += T(EY[q]) * (fn_f[q] - fs_f[q]);
     nv[val_f(q)] = tp(q) - dt * J;
     phin += nv[val_f(q)];
@@ -812,7 +836,7 @@ __device__ __forceinline__ void row_update(const CaseDev& C, int k, int ny, int 
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
       T J = T(0);
-      if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - nbr_l(fx_g[q]));
+      if (EX[q] != 0) J += T(EX[q]) * (fx_g[q] - xl<BP>(fx_g[q]));
       if (EY[q] != 0) J += T(EY[q]) * (fn_g[q] - fs_g[q]);
       nv[val_g(q)] = tp(9 + q) - dt * J;
     }
@@ -839,6 +863,7 @@ template <typename T, bool CPL, bool WALLS, bool DOWN>
 __device__ __forceinline__ void march(const CaseDev& C, const Item& it, long long n) {
   constexpr int sgn = DOWN ? -1 : 1;  // marching direction in rows
   const int lane = threadIdx.x;
+  constexpr bool BP = sizeof(T) == 4 && CPL;  // neighbour moves through the LDS crossbar (xr, xl)
   const int nx = C.nx, ny = C.ny;
   constexpr int walls = WALLS ? 1 : 0;
   const int i0 = it.strip * kStripCols;
@@ -885,7 +910,7 @@ __device__ __forceinline__ void march(const CaseDev& C, const Item& it, long lon
   };
   // phi of one row for (left, own, right) columns from own and extra values
   auto phi_lr = [&](T own, T ext, T (&o)[3]) {
-    T left = nbr_l(own), right = nbr_r(own);
+    T left = xl<BP>(own), right = xr<BP>(own);
     if (lane == 0) left = ext;
     if (lane == 63) right = ext;
     o[0] = left; o[1] = own; o[2] = right;
@@ -906,7 +931,7 @@ __device__ __forceinline__ void march(const CaseDev& C, const Item& it, long lon
     const int slot = r & 1;
 #pragma unroll
     for (int q = 0; q < 18; ++q) stash[slot][q][lane] = tp[q];
-    x_diffs<T, CPL>(rd);
+    x_diffs<T, CPL, BP>(rd);
   };
 
   // One pass of the march for output row k. With the records of the rows
@@ -944,9 +969,9 @@ __device__ __forceinline__ void march(const CaseDev& C, const Item& it, long lon
     RowData<T, CPL>& below = DOWN ? nxt : prv;
     RowData<T, CPL>& above = DOWN ? prv : nxt;
     T fx_f[9], fx_g[9];
-    row_xface<T, CPL, WALLS>(C, k, ny, ci, tn, below, cur_r, above, fx_f, fx_g);
+    row_xface<T, CPL, WALLS, BP>(C, k, ny, ci, tn, below, cur_r, above, fx_f, fx_g);
     const int slot = k & 1;
-    row_update<T, CPL, true>(C, k, ny, nx, walls, ci, store, out, RB, PB, below, cur_r, fx_f,
+    row_update<T, CPL, true, BP>(C, k, ny, nx, walls, ci, store, out, RB, PB, below, cur_r, fx_f,
                              fx_g, [&](int q) { return stash[slot][q][lane]; });
   };
 
