@@ -155,7 +155,7 @@ def batch_timed(torch, D, solvers, steps, warmup, chunk=100, autotune=False):
     picked by the library's autotuner first (outside the timed region)."""
     b = D.Batch(solvers)
     b.set_stream(torch.cuda.current_stream().cuda_stream)
-    b.tiles = b.autotune(5) if autotune else None
+    b.tiles = b.autotune(25) if autotune else None
     t, _ = timed(torch, lambda n: b.step(n, use_graph=True), steps, warmup, chunk)
     return t, b
 
