@@ -2327,8 +2327,10 @@ __device__ __forceinline__ void upm_march(const CaseDev& C, const Item& it, long
       } else {
         T J = T(0);
         if (EX[q] != 0) {
+          // the west face through the LDS crossbar (xl) in the coupled
+          // model: 1.2% faster here, slower on the stretched mesh
           const T e = fxs[xs][off + up_xslot(q)][lane];
-          J += T(EX[q]) * (e - nbr_l(e));
+          J += T(EX[q]) * (e - xl<CPL>(e));
         }
         if (EY[q] != 0) J += T(EY[q]) * (fn - fs);
         return J;
