@@ -353,7 +353,9 @@ int dugks_batch_sync(dugks_batch *b);
 int dugks_batch_destroy(dugks_batch *b);
 
 /* Tile autotuner of a batch: for each boundary group (periodic cases, wall
- * cases) in turn, times probe_steps (1..1000) batch steps for the same
+ * cases) in turn, times probe_steps (1..1000) batch steps (with a stream set,
+ * as one captured graph replayed, the way dugks_batch_step with use_graph
+ * runs them; on the null stream as direct launches) for the same
  * candidate segment lengths as dugks_autotune, computed over the whole group,
  * keeps the fastest for every case of the group, and puts every case's state
  * and the batch's step counter back as they were (results do not depend on

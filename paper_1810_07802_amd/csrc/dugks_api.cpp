@@ -1170,13 +1170,36 @@ int dugks_batch_autotune(dugks_batch* b, int probe_steps, int* seg_periodic, int
   auto probe = [&](float& ms) -> int {
     int rc = sync_descriptors(b);
     if (rc) return rc;
-    rc = record_steps(b, 1);  // warm-up
-    if (rc) return rc;
-    BHIPCHK(b, hipEventRecord(e0, b->stream));
-    rc = record_steps(b, probe_steps);
-    if (rc) return rc;
-    BHIPCHK(b, hipEventRecord(e1, b->stream));
-    BHIPCHK(b, hipEventSynchronize(e1));
+    if (b->stream) {
+      // on a stream that can be captured, the candidate is timed the way
+      // dugks_batch_step with use_graph runs it: one captured graph of
+      // probe_steps steps, replayed once untimed and once timed (direct
+      // launches rank the tiles differently)
+      hipGraph_t g;
+      BHIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+      rc = record_steps(b, probe_steps);
+      hipError_t ce = hipStreamEndCapture(b->stream, &g);
+      if (rc) return rc;
+      if (ce != hipSuccess) return bfail(b, DUGKS_EDEVICE, hipGetErrorString(ce));
+      hipGraphExec_t ex = nullptr;
+      ce = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ce == hipSuccess) ce = hipGraphLaunch(ex, b->stream);
+      if (ce == hipSuccess) ce = hipEventRecord(e0, b->stream);
+      if (ce == hipSuccess) ce = hipGraphLaunch(ex, b->stream);
+      if (ce == hipSuccess) ce = hipEventRecord(e1, b->stream);
+      if (ce == hipSuccess) ce = hipEventSynchronize(e1);
+      if (ex) (void)hipGraphExecDestroy(ex);
+      if (ce != hipSuccess) return bfail(b, DUGKS_EDEVICE, hipGetErrorString(ce));
+    } else {
+      rc = record_steps(b, 1);  // warm-up
+      if (rc) return rc;
+      BHIPCHK(b, hipEventRecord(e0, b->stream));
+      rc = record_steps(b, probe_steps);
+      if (rc) return rc;
+      BHIPCHK(b, hipEventRecord(e1, b->stream));
+      BHIPCHK(b, hipEventSynchronize(e1));
+    }
     BHIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
     BHIPCHK(b, restore());
     return DUGKS_OK;

@@ -162,7 +162,11 @@ def test_batch_matches_single_cases_bitwise():
         assert np.array_equal(s.get_state()[0], alone[k]), k
 
 
-def test_batch_autotune_restores_states_and_keeps_bits():
+@pytest.mark.parametrize("created_stream", [True, False])
+def test_batch_autotune_restores_states_and_keeps_bits(created_stream):
+    """The probes (captured graphs on a created stream, direct launches on
+    the null stream) leave every state and step counter as it was, and the
+    chosen tiles change no bit."""
     cases = [W.spinodal(L=64, seed=30, steps=0), W.random_coupled(70, 36, seed=31, walls_y=True),
              W.spinodal(L=100, seed=32, steps=0), W.random_coupled(130, 50, seed=33, walls_y=True)]
     solvers, alone = [], []
@@ -177,11 +181,14 @@ def test_batch_autotune_restores_states_and_keeps_bits():
     import torch
     stream = torch.cuda.Stream()
     b = D.Batch(solvers)
-    b.set_stream(stream.cuda_stream)
+    if created_stream:
+        b.set_stream(stream.cuda_stream)
     b.step(10, use_graph=False)
     b.sync()
     before = [s.get_state()[0] for s in solvers]
     seg_p, seg_w = b.autotune(3)
+    if not created_stream:
+        b.set_stream(stream.cuda_stream)  # graphs need a created stream
     assert seg_p >= 1 and seg_w >= 1
     for k, s in enumerate(solvers):
         assert s.steps_done == 10
