@@ -271,7 +271,9 @@ int dugks_get_state(dugks_handle *h, void *host_buf, size_t bytes,
 int dugks_set_state(dugks_handle *h, const void *host_buf, size_t bytes,
                     long long steps);
 
-/* Tile autotuner: times probe_steps (1..1000) steps for each of a few
+/* Tile autotuner: times probe_steps (1..1000) steps (with a stream set, as
+ * one captured graph replayed; on the null stream as direct launches) for
+ * each of a few
  * segment lengths (1 and 2 rows, for the lowest latency per step, and for
  * k = 1..8, 12, 16, 20, 24 the shortest segment whose tiles fit k rounds of the
  * device's resident waves) on the handle's current state, keeps the fastest as the

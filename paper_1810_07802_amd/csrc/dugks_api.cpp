@@ -753,13 +753,37 @@ int dugks_autotune(dugks_handle* h, int probe_steps, int* out_seg_rows, double* 
     h->dirty_case = true;
     rc = upload_case(h);
     if (rc) break;
-    rc = launch_steps(h, 1);  // warm-up
-    if (rc) break;
-    e = hipEventRecord(e0, h->stream);
-    if (e == hipSuccess) rc = launch_steps(h, probe_steps);
-    if (rc) break;
-    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (h->stream) {
+      // on a stream that can be captured, timed the way dugks_step runs
+      // longer sequences there: one captured graph, replayed once untimed
+      // and once timed (direct launches can rank the tiles differently)
+      hipGraph_t g = nullptr;
+      hipGraphExec_t ex = nullptr;
+      e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) break;
+      rc = launch_steps(h, probe_steps);
+      e = hipStreamEndCapture(h->stream, &g);  // always ends the capture
+      if (rc) {
+        if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+        break;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e == hipSuccess) e = hipGraphLaunch(ex, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+      if (e == hipSuccess) e = hipGraphLaunch(ex, h->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (ex) (void)hipGraphExecDestroy(ex);
+    } else {
+      rc = launch_steps(h, 1);  // warm-up
+      if (rc) break;
+      e = hipEventRecord(e0, h->stream);
+      if (e == hipSuccess) rc = launch_steps(h, probe_steps);
+      if (rc) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+    }
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e == hipSuccess && (k == 0 || ms < best_ms)) {

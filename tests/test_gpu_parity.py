@@ -122,12 +122,20 @@ def test_checkpoint_resume_bitwise(prec):
     assert np.array_equal(a.get_state()[0], b.get_state()[0])
 
 
-def test_autotune_restores_state_and_keeps_bits():
+@pytest.mark.parametrize("created_stream", [False, True])
+def test_autotune_restores_state_and_keeps_bits(created_stream):
+    """The probes (direct launches on the null stream, captured graphs on a
+    created one) leave the state and step counter as they were, and the
+    chosen tile changes no bit."""
+    import torch
     c = W.random_coupled(130, 50, seed=11, rho_ratio=50.0)
     ref = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
     ref.init(c["phi"], c["u"], c["v"])
     ref.step(25)
     s = D.Solver(c["nx"], c["ny"], c["params"], "coupled", "fp32")
+    stream = torch.cuda.Stream()
+    if created_stream:
+        s.set_stream(stream.cuda_stream)
     s.init(c["phi"], c["u"], c["v"])
     s.step(10)
     before, n0 = s.get_state()
